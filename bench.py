@@ -1,0 +1,286 @@
+#!/usr/bin/env python3
+"""Throughput of batched segmented NCC on one MI355X.
+
+A step is one pass of the whole hot path over one batch held in HBM: sum
+tables of every frame, FP32-compensated scoring of every (frame, template)
+pair at every offset with top-k selection, and FP64 re-scoring of the
+candidates' neighbourhoods with the fine approximation (one graph launch).
+
+Default workload ("coarse-fine"): 256 frames 1280x720 x 32 templates with
+sides U{24..96}, coarse sigma_max 16 (top-32 per pair), fine sigma_max 4 on
++-2 px neighbourhoods.  `--workload batched` runs 16 frames 1920x1080 x 64
+templates (sides U{16..192}, sigma_max U{4,8,12,16}, top-5) instead.
+
+Prints one JSON line.  value = coarse offset x segment evaluations per
+second of the whole step.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "offset×segment evals/sec + frames/sec, batched FP32 vs plain FP64, |Δρ|≤1e-5"
+UNIT = "offset×segment evals/s"
+
+# VALU lane operations of the method per offset x segment evaluation: 3 integer
+# add/sub for the box sum (Eq. (11)), 1 integer multiply-add for the mean term
+# of Eq. (12), 1 int->float conversion, 1 FMA with c_i, 3 add/sub of the
+# compensated sum.
+OPS_PER_EVAL = 9
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: non-packed VALU lane operations/s
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# LDS: 128 bytes/clock/CU x 256 CUs x 2.4 GHz; 16 bytes (4 corners) per eval
+LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2502_01286_amd", "csrc", "kernels.hip"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload):
+    """HBM bytes per scoring launch from committed rocprofv3 --pmc summaries
+    (FETCH_SIZE, WRITE_SIZE, scaled by a copy kernel of known size), or None
+    when they were taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"tile_kernel_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernels_hip_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def make_workload(name):
+    from workloads import synth
+    if name == "coarse-fine":
+        return synth.cfg4()
+    if name == "batched":
+        return synth.cfg3()
+    if name == "coarse-fine-small":
+        return synth.cfg4(n_frames=16, n_templates=8)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(wl, coarse_segs_k, budget_s=15.0, max_pairs=1024):
+    """The oracle (NumPy FP64), as it stands, on a seeded sample of pairs of
+    the same workload, one pair per worker process."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    rng = np.random.default_rng(12345)
+    order = rng.permutation(len(wl.pairs))
+    # bound the sample: estimated cost ~ offsets x K per pair
+    est = lambda p: (wl.M - wl.templates[wl.pairs[p][1]].shape[1] + 1) * \
+        (wl.N - wl.templates[wl.pairs[p][1]].shape[0] + 1) * coarse_segs_k[wl.pairs[p][1]]
+    chosen, work = [], 0.0
+    rate_guess = 4e7 * cores          # evals/s of the NumPy oracle (rough, for sizing only)
+    for p in order:
+        if len(chosen) >= max_pairs or work / rate_guess > budget_s:
+            break
+        chosen.append(int(p))
+        work += est(p)
+    jobs = [(wl.frames[wl.pairs[p][0]], wl.templates[wl.pairs[p][1]], wl.sigmas[wl.pairs[p][1]],
+             wl.fine_sigma, wl.k) for p in chosen]
+    # template preparation happens before timing, as in the paper's split
+    with ProcessPoolExecutor(max_workers=cores) as ex:
+        preps = list(ex.map(_cpu_prep, jobs))
+        t0 = time.perf_counter()
+        evals = sum(ex.map(_cpu_pair, jobs, preps))
+        dt = time.perf_counter() - t0
+    return {"value": evals / dt, "unit": UNIT, "cores": cores, "kind": "oracle",
+            "sample": f"{len(chosen)} seeded (frame, template) pairs of the same workload: "
+                      f"full coarse rho map (FP64) + top-{wl.k}"
+                      + (" + FP64 fine re-score of the +-2 px neighbourhoods" if wl.fine_sigma else "")
+                      + f", {dt:.1f} s wall on {cores} processes"}
+
+
+def _cpu_prep(job):
+    import oracle as O
+    f, t, sc, sf, k = job
+    c = O.precompute_template_approximation(t, sc)
+    fi = O.precompute_template_approximation(t, sf) if sf else None
+    return c, fi
+
+
+def _cpu_pair(job, prep):
+    import oracle as O
+    f, t, sc, sf, k = job
+    c, fi = prep
+    tables = O.sum_tables(f)
+    N, M = f.shape
+    cmap = O.rho_map(f, c, tables=tables)
+    if fi is not None:
+        O.coarse_fine(*tables, c, fi, M, N, k=k, radius=2, coarse_map=cmap)
+    else:
+        O.topk(cmap, k)
+    return cmap.size * c.K
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="coarse-fine")
+    ap.add_argument("--tune", type=int, default=1)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("this build measures one GPU only: run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2502_01286_amd as S
+
+    log(f"[bench] generating workload {args.workload}")
+    t0 = time.perf_counter()
+    wl = make_workload(args.workload)
+    B, N, M = len(wl.frames), wl.N, wl.M
+    log(f"[bench] {B} frames {M}x{N}, {len(wl.templates)} templates, {len(wl.pairs)} pairs "
+        f"({time.perf_counter() - t0:.1f} s)")
+
+    # template preparation (host C++), reported separately
+    t0 = time.perf_counter()
+    coarse_l, fine_l = [], []
+    for t, sg in zip(wl.templates, wl.sigmas):
+        coarse_l.append(S.sncc_segment_template(t, sg, wl.k_max)[0])
+        if wl.fine_sigma:
+            fine_l.append(S.sncc_segment_template(t, wl.fine_sigma, wl.k_max)[0])
+    prep_ms = (time.perf_counter() - t0) * 1e3
+    Kc = [len(a) for a in coarse_l]
+    log(f"[bench] prep {prep_ms:.1f} ms, K coarse {min(Kc)}..{max(Kc)}"
+        + (f", K fine {min(map(len, fine_l))}..{max(map(len, fine_l))}" if fine_l else ""))
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = S.sncc_ctx_create(0)
+    Ws = [t.shape[1] for t in wl.templates]
+    Hs = [t.shape[0] for t in wl.templates]
+    coarse = S.sncc_upload_templates(ctx, coarse_l, Ws, Hs)
+    fine = S.sncc_upload_templates(ctx, fine_l, Ws, Hs) if fine_l else None
+    f = torch.from_numpy(np.stack(wl.frames)).to(dev)
+    P = S.sncc_sat_pitch(M)
+    s = torch.empty((B, N + 1, P), dtype=torch.int32, device=dev)
+    s2 = torch.empty_like(s)
+    n_pairs = len(wl.pairs)
+    topk = torch.zeros((n_pairs, wl.k, 3), dtype=torch.int32, device=dev)
+    best = torch.zeros((n_pairs, 4), dtype=torch.int32, device=dev) if fine else None
+    cnt = torch.zeros(n_pairs, dtype=torch.int32, device=dev) if fine else None
+    t0 = time.perf_counter()
+    batch = S.sncc_batch_create(ctx, coarse, s, s2, B, M, N, wl.pairs, wl.k, topk, fine=fine,
+                                radius=2, best_out=best, count_out=cnt, frames=f,
+                                tune=args.tune)
+    st = batch.stats()
+    log(f"[bench] batch planned in {time.perf_counter() - t0:.2f} s: {st['work_items']} items, "
+        f"tile {st['tile_u']}x{st['tile_v']}, {st['wg_threads']} threads, LDS {st['lds_bytes']} B")
+
+    for i in range(args.warmup):
+        batch.run()
+        torch.cuda.synchronize()
+    log(f"[bench] warmup done")
+
+    stages = {k: [] for k in ("ms_sat", "ms_score", "ms_select", "ms_refine", "ms_total")}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        batch.run()
+        torch.cuda.synchronize()
+        st = batch.stats()
+        for k in stages:
+            stages[k].append(st[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    avg = {k: (float(np.mean(v)) if v and min(v) >= 0 else None) for k, v in stages.items()}
+    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, stages {avg}")
+    evals = st["coarse_evals"]
+    fine_offsets = int(cnt.sum().item()) if cnt is not None else 0
+    value = evals / (ms_per_step / 1e3)
+
+    roof = None
+    if avg["ms_score"]:
+        ops_tops = OPS_PER_EVAL * evals / (avg["ms_score"] / 1e3) / 1e12
+        lds_tbs = 16 * evals / (avg["ms_score"] / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": round(ops_tops, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "TOP/s (VALU lane ops)", "frac": round(ops_tops / VALU_PEAK_TOPS, 4),
+                "traffic": load_traffic(args.workload),
+                "kernel": "tile_kernel (scoring)", "kernel_ms": round(avg["ms_score"], 4),
+                "ops_per_eval": OPS_PER_EVAL, "evals_per_launch": evals,
+                "lds": {"achieved_TBps": round(lds_tbs, 3), "peak_TBps": round(LDS_PEAK_TBS, 2),
+                        "frac": round(lds_tbs / LDS_PEAK_TBS, 4), "bytes_per_eval": 16}}
+        if avg["ms_sat"]:
+            px = B * M * N
+            roof["sat"] = {"bound": "hbm", "achieved_GBps": round(9 * px / (avg["ms_sat"] / 1e3) / 1e9, 1),
+                           "peak_GBps": 8000, "bytes_per_px": 9, "ms": round(avg["ms_sat"], 4)}
+
+    plain = None
+    if not args.no_plain:
+        log("[bench] plain FP64 comparator (one launch per pair)")
+        out64 = torch.zeros_like(topk)
+        S.sncc_topk(ctx, coarse, s, s2, B, M, N, wl.pairs, wl.k, S.SNCC_FP64, out64)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 2
+        e0.record()
+        for _ in range(reps):
+            S.sncc_topk(ctx, coarse, s, s2, B, M, N, wl.pairs, wl.k, S.SNCC_FP64, out64)
+        e1.record()
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1) / reps
+        plain = {"value": evals / (pms / 1e3), "unit": UNIT, "ms": round(pms, 3),
+                 "speedup_batched_fp32": round((evals / (avg["ms_score"] / 1e3)) / (evals / (pms / 1e3)), 3)
+                 if avg["ms_score"] else None,
+                 "form": "one plain FP64 scoring launch per pair (+ per-pair top-k), no graph"}
+        log(f"[bench] plain {pms:.2f} ms")
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(wl, Kc, budget_s=args.cpu_budget)
+        log(f"[bench] cpu {cpu}")
+
+    batch.destroy()
+    S.sncc_tmpl_destroy(coarse)
+    if fine:
+        S.sncc_tmpl_destroy(fine)
+    S.sncc_ctx_destroy(ctx)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "frames": B, "width": M, "height": N,
+                   "templates": len(wl.templates), "pairs": n_pairs, "top_k": wl.k,
+                   "coarse_sigma": sorted(set(wl.sigmas)), "fine_sigma": wl.fine_sigma,
+                   "K_coarse": [min(Kc), max(Kc)], "coarse_evals": evals,
+                   "fine_offsets_scored": fine_offsets,
+                   "arith": "u32 box sums, f32 compensated accumulation, f64 epilogue/refine"},
+        "frames_per_s": B / (ms_per_step / 1e3),
+        "stage_ms": avg, "prep_ms_host": prep_ms,
+        "roofline": roof, "plain_fp64": plain, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

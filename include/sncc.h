@@ -1,0 +1,296 @@
+/*
+ * sncc.h - segmented normalized cross-correlation template matching on MI355X.
+ *
+ * Method: Marusic, Popovic, Kalafatic, "Template Matching in Images using
+ * Segmented Normalized Cross-Correlation", arXiv:2502.01286.  A template is
+ * approximated by axis-aligned rectangles of constant value (Section 3,
+ * Eqs. (2)-(7)); the NCC of Eq. (1) between the image and that approximation is
+ * computed at every offset segment by segment through sum tables
+ * (Section 4, Eqs. (8)-(18)).
+ *
+ * Conventions for every entry point
+ *  - Return value: SNCC_OK (0) or a negative SNCC_E* code.  Nothing throws or
+ *    aborts across this interface.  On error a message is kept for the
+ *    calling thread and returned by sncc_last_error().
+ *  - Argument checks are synchronous.  Device work is enqueued on the stream
+ *    bound to the context and runs asynchronously; HIP errors of that work
+ *    surface at a later call on the context or at sncc_sync().
+ *  - Ownership: the caller owns every host array and every device buffer it
+ *    passes (e.g. PyTorch tensors).  The library copies what it keeps (segment
+ *    lists, pair lists) and owns only its handles and the scratch memory those
+ *    handles hold; *_destroy frees them.  Device buffers must stay alive while
+ *    work that uses them is pending.
+ *  - Device pointers must be 16-byte aligned.  Pitches are in elements.
+ *  - Image f is M pixels wide (x, columns) and N tall (y, rows), uint8,
+ *    row-major (Section 2).  A template is W x H.  Offsets are
+ *    u in [0, M-W], v in [0, N-H]; maps over offsets are row-major over v.
+ */
+#ifndef SNCC_H
+#define SNCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define SNCC_OK 0
+#define SNCC_EINVAL (-1)      /* bad argument (NULL, size, pitch, alignment)   */
+#define SNCC_ENOMEM (-2)      /* host or device allocation failed               */
+#define SNCC_ENOSPC (-3)      /* output capacity too small                      */
+#define SNCC_ERANGE (-4)      /* exact 32-bit window sums not guaranteed        */
+#define SNCC_EDEGENERATE (-5) /* uniform template approximation (Section 2)     */
+#define SNCC_EDEVICE (-6)     /* HIP runtime error (text in sncc_last_error)    */
+
+/* accumulation precision of the per-segment numerator (Eq. (12)) */
+#define SNCC_FP32_KAHAN 0     /* integer box sums, FP32 compensated sum        */
+#define SNCC_FP64 1           /* integer box sums, FP64 sum                    */
+
+/* Largest template area n = W*H for which every window sum of f^2 is below
+ * 2^32 (255^2 * n < 2^32), so that differences of the modulo-2^32 sum
+ * tables are exact. */
+#define SNCC_MAX_TEMPLATE_AREA 66051
+
+/* One rectangle of the approximation: the 5-tuple of Eq. (6) with the mean
+ * k_i = sum / area kept as an exact integer ratio (Eq. (4)). */
+typedef struct sncc_segment {
+  int32_t x, y;      /* top-left template pixel                         */
+  int32_t w, h;      /* W_i, H_i                                        */
+  int64_t sum;       /* sum of template pixels over the rectangle       */
+  int32_t area;      /* W_i * H_i                                       */
+  int32_t reserved;  /* zero                                            */
+} sncc_segment;
+
+/* A match triplet (u, v, rho) of the algorithm's output (Section 5). */
+typedef struct sncc_match {
+  int32_t u, v;
+  float rho;
+} sncc_match;
+
+typedef struct sncc_match64 {
+  int32_t u, v;
+  double rho;
+} sncc_match64;
+
+typedef struct sncc_ctx sncc_ctx;
+typedef struct sncc_tmpl sncc_tmpl;
+typedef struct sncc_batch sncc_batch;
+
+/* --------------------------------------------------------------- utilities */
+const char *sncc_status_string(int status);
+/* Message of the last failing call on this thread ("" if none). */
+const char *sncc_last_error(void);
+/* Library version as 10000*major + 100*minor + patch. */
+int sncc_version(void);
+
+/* -------------------------------------------------- template preparation */
+/*
+ * precompute_template_approximation of Section 5 (host only, no device).
+ *
+ * Splits the template recursively (split_segment: keep a rectangle whose
+ * population standard deviation is below sigma_max, Eq. (2); else halve its
+ * larger side, width when w > h, first half ceil), raising sigma_max by 1 and
+ * splitting again while more than K_max rectangles result (counted before
+ * merging), then merges aligned neighbours with equal exact means
+ * (merge_redundant_segments).  The deviation test is decided exactly.
+ *
+ *   t          host, H rows of W bytes, row stride t_stride >= W bytes
+ *   sigma_max  threshold (> 0 to get any rectangle larger than one pixel)
+ *   K_max      >= 1
+ *   out        host array of cap entries; receives the K rectangles in the
+ *              final (y, x) order of the merge
+ *   K_out      receives K (also when SNCC_ENOSPC is returned)
+ *   sigma_used receives the threshold of the accepted split (nullable)
+ *   rho_max    receives the NCC between t and its approximation, steps 4-7 of
+ *              the function, with the area-weighted sum of Eq. (17) (nullable)
+ * Errors: SNCC_EINVAL (NULL, sizes < 1, stride < W, K_max < 1),
+ *         SNCC_ENOSPC (cap < K), SNCC_EDEGENERATE (approximation uniform).
+ */
+int sncc_segment_template(const uint8_t *t, int W, int H, int t_stride,
+                          double sigma_max, int K_max, sncc_segment *out,
+                          int cap, int *K_out, double *sigma_used,
+                          double *rho_max);
+
+/* ---------------------------------------------------------------- context */
+/*
+ * Binds a device and a HIP stream (hipStream_t passed as an integer, e.g.
+ * torch.cuda.current_stream().cuda_stream; 0 is the null stream).  All
+ * device work of calls taking this context is enqueued on that stream.
+ * Errors: SNCC_EINVAL, SNCC_EDEVICE, SNCC_ENOMEM.
+ */
+int sncc_ctx_create(int device, uintptr_t hip_stream, sncc_ctx **out);
+int sncc_ctx_destroy(sncc_ctx *ctx);
+/* Waits for the context's stream; reports pending HIP errors. */
+int sncc_sync(sncc_ctx *ctx);
+
+/* ------------------------------------------------------------- sum tables */
+/* Minimum pitch (elements) of a sum table for images M pixels wide:
+ * M + 1 rounded up to a multiple of 64. */
+int sncc_sat_pitch(int M, int *pitch_elems);
+
+/*
+ * compute_sum_tables (Section 5, step 6): s of Eq. (10) and s^2 of Eq. (14)
+ * for B frames, zero-padded: entry [y + 1][x + 1] is the sum over columns
+ * 0..x and rows 0..y; row 0 and column 0 are zero (the values at index -1
+ * in Eqs. (11), (13), (15)).  Values are stored modulo 2^32; any box sum
+ * taken as a difference of four entries is exact while its true value is
+ * below 2^32 (so for f^2 windows of area <= SNCC_MAX_TEMPLATE_AREA).
+ *
+ *   d_f        device, B frames of N rows x f_pitch bytes, frames contiguous
+ *   d_s, d_s2  device, B frames of (N + 1) rows x sat_pitch uint32, frames
+ *              contiguous; columns M+1 .. sat_pitch-1 are written with zeros
+ * Errors: SNCC_EINVAL (NULL, B/M/N < 1, f_pitch < M, sat_pitch too small,
+ *         misaligned), SNCC_EDEVICE, SNCC_ENOMEM (scratch).
+ */
+int sncc_build_sats(sncc_ctx *ctx, const uint8_t *d_f, int B, int M, int N,
+                    int f_pitch, uint32_t *d_s, uint32_t *d_s2, int sat_pitch);
+
+/* ------------------------------------------------------ segment lists */
+/*
+ * Copies T segment lists to the device together with the constants the
+ * matching phase precomputes (Section 5, steps 3-4): k_bar (Eq. (7)),
+ * c_i = k_i - k_bar in FP64 and FP32, and q_k = sum_i W_i H_i c_i^2
+ * (area-weighted Eq. (17)).  Segments of each list must partition its
+ * W x H template.
+ *
+ *   segs[i]    host array of K[i] segments of template i
+ * Errors: SNCC_EINVAL (NULL, sizes, segments outside the template or not
+ *         covering it exactly once), SNCC_ERANGE (W*H above
+ *         SNCC_MAX_TEMPLATE_AREA), SNCC_EDEGENERATE (q_k == 0),
+ *         SNCC_ENOMEM, SNCC_EDEVICE.
+ */
+int sncc_upload_templates(sncc_ctx *ctx, int T, const sncc_segment *const *segs,
+                          const int *K, const int *W, const int *H,
+                          sncc_tmpl **out);
+int sncc_tmpl_destroy(sncc_tmpl *tm);
+/* W, H, K and q_k of template `index` (any pointer nullable). */
+int sncc_tmpl_info(const sncc_tmpl *tm, int index, int *W, int *H, int *K,
+                   double *q_k);
+
+/* ------------------------------------------------------------- scoring */
+/*
+ * rho(u, v; f, k) of Eq. (18) at every offset of one frame for template
+ * `index` (Section 5, step 7a-e): window sums by Eqs. (13) and (15), the
+ * exact window energy n*sum f^2 - (sum f)^2 in 64-bit integers (Eq. (16)
+ * times n), the numerator of Eq. (12) from integer box sums (Eq. (11)) and
+ * the area-weighted denominator of Eq. (17).
+ *
+ *   precision  SNCC_FP32_KAHAN: d_rho is float; box sums minus (area x the
+ *              window mean rounded to an integer) are accumulated in FP32
+ *              with compensated summation.  SNCC_FP64: d_rho is double; box
+ *              sums are accumulated in FP64, one launch per call.
+ *   d_rho      device, (N-H+1) rows x rho_pitch elements (>= M-W+1)
+ *   d_degenerate  device, nullable, (N-H+1) x rho_pitch bytes: 1 where the
+ *              window is uniform (rho written as 0), else 0
+ * Errors: SNCC_EINVAL (NULL, template larger than image, pitches),
+ *         SNCC_EDEVICE, SNCC_ENOMEM.
+ */
+int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index,
+               const uint32_t *d_s, const uint32_t *d_s2, int M, int N,
+               int sat_pitch, int precision, void *d_rho, int rho_pitch,
+               uint8_t *d_degenerate);
+
+/*
+ * The k highest-scoring offsets of each (frame, template) pair (Section 2:
+ * the match is the offset with the highest rho).  Ordering: higher rho
+ * first, ties to the smaller v, then smaller u; no suppression of
+ * neighbours.  SNCC_FP32_KAHAN runs every pair in one persistent launch
+ * over a cost-ordered work list; SNCC_FP64 runs one launch per pair.
+ *
+ *   d_s, d_s2  sum tables of B frames (layout of sncc_build_sats)
+ *   pairs      host, n_pairs x {frame, template}
+ *   k          1 .. 64
+ *   d_out      device, n_pairs x k matches; slots beyond the number of
+ *              offsets get u = v = -1, rho = -infinity
+ * Errors: SNCC_EINVAL, SNCC_EDEVICE, SNCC_ENOMEM.
+ */
+int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s,
+              const uint32_t *d_s2, int B, int M, int N, int sat_pitch,
+              int n_pairs, const int32_t *pairs, int k, int precision,
+              sncc_match *d_out);
+/* sncc_topk with k = 1. */
+int sncc_argmax(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s,
+                const uint32_t *d_s2, int B, int M, int N, int sat_pitch,
+                int n_pairs, const int32_t *pairs, int precision,
+                sncc_match *d_out);
+
+/*
+ * Fine step of the coarse-to-fine search (Section 5, steps 7f-i, with the
+ * coarse threshold replaced by a candidate list): for each pair, rho with
+ * the fine approximation `fine` (same template indices as the coarse set)
+ * is computed in FP64 at every offset within Chebyshev distance `radius` of
+ * one of the pair's candidates (clipped to valid offsets, duplicates
+ * scored once), and the best of them is returned (ties: smaller v, then u).
+ *
+ *   d_cand     device, n_pairs x n_cand candidates (e.g. sncc_topk output);
+ *              entries with u < 0 are ignored
+ *   radius     0 .. 7; n_cand * (2 radius + 1)^2 <= 4096
+ *   d_out      device, n_pairs results; a pair without candidates gets
+ *              u = v = -1, rho = -infinity
+ *   d_count    device, nullable, n_pairs int32: offsets scored per pair
+ * Errors: SNCC_EINVAL, SNCC_EDEVICE.
+ */
+int sncc_refine(sncc_ctx *ctx, const sncc_tmpl *fine, const uint32_t *d_s,
+                const uint32_t *d_s2, int B, int M, int N, int sat_pitch,
+                int n_pairs, const int32_t *pairs, const sncc_match *d_cand,
+                int n_cand, int radius, sncc_match64 *d_out, int32_t *d_count);
+
+/* ------------------------------------------------------------ batches */
+typedef struct sncc_batch_desc {
+  const sncc_tmpl *coarse;   /* scored at every offset (FP32 compensated)  */
+  const sncc_tmpl *fine;     /* nullable: FP64 refinement when given       */
+  const uint8_t *d_f;        /* nullable: frames; sum tables built per run */
+  int f_pitch;
+  uint32_t *d_s, *d_s2;      /* sum tables (written when d_f is given)     */
+  int sat_pitch;
+  int B, M, N;
+  int n_pairs;
+  const int32_t *pairs;      /* host, n_pairs x {frame, template}          */
+  int k;                     /* top-k per pair, 1 .. 64                    */
+  int radius;                /* refinement radius (used when fine != NULL) */
+  sncc_match *d_topk;        /* device, n_pairs x k                        */
+  sncc_match64 *d_best;      /* device, n_pairs (when fine != NULL)        */
+  int32_t *d_count;          /* device, nullable, n_pairs (refine counts)  */
+  int tune;                  /* 0: default tile shape; 1: time candidates  */
+  const char *tune_cache;    /* nullable: JSON file read/written by tuner  */
+} sncc_batch_desc;
+
+typedef struct sncc_batch_stats {
+  int64_t coarse_evals;      /* sum over pairs of offsets x K (coarse)     */
+  int64_t n_offsets;         /* sum over pairs of offsets                  */
+  int64_t work_items;
+  int n_launch_classes;      /* persistent scoring launches per run        */
+  int tile_u, tile_v;        /* offsets per tile (u, v)                    */
+  int wg_threads;
+  int lds_bytes;
+  int timed;                 /* 1 when the graph records per-stage events  */
+  float ms_sat;              /* last run, from events in the graph; -1 if  */
+  float ms_score;            /* not recorded                                */
+  float ms_select;
+  float ms_refine;
+  float ms_total;
+} sncc_batch_stats;
+
+/*
+ * Plans a batch: builds the cost-ordered work list of (pair, offset tiles)
+ * items, chooses the tile shape (default, or timed candidates when
+ * desc->tune is set), and captures sum-table construction, the persistent
+ * scoring launches, top-k selection and (optionally) FP64 refinement into
+ * one HIP graph on the context's stream.  The descriptor's buffers are
+ * bound at this point.  Errors: as for the calls it combines.
+ */
+int sncc_batch_create(sncc_ctx *ctx, const sncc_batch_desc *desc,
+                      sncc_batch **out);
+/* One launch of the captured graph on the context's stream. */
+int sncc_batch_run(sncc_batch *b);
+/* Statistics and, after the run has completed, per-stage device times. */
+int sncc_batch_stats_get(sncc_batch *b, sncc_batch_stats *st);
+int sncc_batch_destroy(sncc_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNCC_H */

@@ -1,0 +1,345 @@
+"""ctypes binding of libsncc.so (include/sncc.h).
+
+Argument marshalling only: every function keeps the C name, checks that
+tensors are on the right device with the right dtype and layout, passes raw
+pointers and sizes, and raises ``SnccError`` on a negative status.  All device
+work happens in the library's HIP kernels.  Importing this module fails loudly
+when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsncc.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "sncc.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2502_01286_amd.build` "
+        "(the HIP library is required; there is no fallback)")
+
+lib = C.CDLL(LIB_PATH)
+
+SNCC_OK = 0
+SNCC_EINVAL = -1
+SNCC_ENOMEM = -2
+SNCC_ENOSPC = -3
+SNCC_ERANGE = -4
+SNCC_EDEGENERATE = -5
+SNCC_EDEVICE = -6
+SNCC_FP32_KAHAN = 0
+SNCC_FP64 = 1
+SNCC_MAX_TEMPLATE_AREA = 66051
+
+
+class sncc_segment(C.Structure):
+    _fields_ = [("x", C.c_int32), ("y", C.c_int32), ("w", C.c_int32), ("h", C.c_int32),
+                ("sum", C.c_int64), ("area", C.c_int32), ("reserved", C.c_int32)]
+
+
+SEGMENT_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("w", "<i4"), ("h", "<i4"),
+                          ("sum", "<i8"), ("area", "<i4"), ("reserved", "<i4")])
+assert SEGMENT_DTYPE.itemsize == C.sizeof(sncc_segment) == 32
+
+
+class sncc_batch_desc(C.Structure):
+    _fields_ = [("coarse", C.c_void_p), ("fine", C.c_void_p),
+                ("d_f", C.c_void_p), ("f_pitch", C.c_int),
+                ("d_s", C.c_void_p), ("d_s2", C.c_void_p), ("sat_pitch", C.c_int),
+                ("B", C.c_int), ("M", C.c_int), ("N", C.c_int),
+                ("n_pairs", C.c_int), ("pairs", C.c_void_p),
+                ("k", C.c_int), ("radius", C.c_int),
+                ("d_topk", C.c_void_p), ("d_best", C.c_void_p), ("d_count", C.c_void_p),
+                ("tune", C.c_int), ("tune_cache", C.c_char_p)]
+
+
+class sncc_batch_stats(C.Structure):
+    _fields_ = [("coarse_evals", C.c_int64), ("n_offsets", C.c_int64),
+                ("work_items", C.c_int64), ("n_launch_classes", C.c_int),
+                ("tile_u", C.c_int), ("tile_v", C.c_int), ("wg_threads", C.c_int),
+                ("lds_bytes", C.c_int), ("timed", C.c_int),
+                ("ms_sat", C.c_float), ("ms_score", C.c_float), ("ms_select", C.c_float),
+                ("ms_refine", C.c_float), ("ms_total", C.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_vp, _i, _d, _u = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+_SIGS = {
+    "sncc_status_string": (C.c_char_p, [_i]),
+    "sncc_last_error": (C.c_char_p, []),
+    "sncc_version": (_i, []),
+    "sncc_segment_template": (_i, [_vp, _i, _i, _i, _d, _i, _vp, _i, _vp, _vp, _vp]),
+    "sncc_ctx_create": (_i, [_i, C.c_size_t, _vp]),
+    "sncc_ctx_destroy": (_i, [_vp]),
+    "sncc_sync": (_i, [_vp]),
+    "sncc_sat_pitch": (_i, [_i, _vp]),
+    "sncc_build_sats": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _i]),
+    "sncc_upload_templates": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
+    "sncc_tmpl_destroy": (_i, [_vp]),
+    "sncc_tmpl_info": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
+    "sncc_score": (_i, [_vp, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _i, _vp]),
+    "sncc_topk": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _i, _i, _vp]),
+    "sncc_argmax": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _i, _vp]),
+    "sncc_refine": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _vp, _i, _i, _vp, _vp]),
+    "sncc_batch_create": (_i, [_vp, _vp, _vp]),
+    "sncc_batch_run": (_i, [_vp]),
+    "sncc_batch_stats_get": (_i, [_vp, _vp]),
+    "sncc_batch_destroy": (_i, [_vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def header_functions():
+    """Names of the functions declared in include/sncc.h."""
+    with open(HEADER_PATH) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(sncc_\w+)\s*\(", text, re.M)))
+
+
+class SnccError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{lib.sncc_status_string(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != SNCC_OK:
+        raise SnccError(rc, lib.sncc_last_error().decode())
+
+
+def sncc_status_string(code: int) -> str:
+    return lib.sncc_status_string(code).decode()
+
+
+def sncc_last_error() -> str:
+    return lib.sncc_last_error().decode()
+
+
+def sncc_version() -> int:
+    return lib.sncc_version()
+
+
+# ----------------------------------------------------------- host (no device)
+def sncc_segment_template(t, sigma_max: float, K_max: int = 5000):
+    """Returns (segments as a SEGMENT_DTYPE array, sigma_used, rho_max)."""
+    t = np.ascontiguousarray(t, dtype=np.uint8)
+    if t.ndim != 2:
+        raise ValueError("template must be 2-D")
+    H, W = t.shape
+    cap = W * H
+    out = np.zeros(cap, dtype=SEGMENT_DTYPE)
+    K = C.c_int(0)
+    su = C.c_double(0)
+    rm = C.c_double(0)
+    _check(lib.sncc_segment_template(t.ctypes.data, W, H, W, float(sigma_max), int(K_max),
+                                     out.ctypes.data, cap, C.byref(K), C.byref(su), C.byref(rm)))
+    return out[:K.value].copy(), su.value, rm.value
+
+
+def sncc_sat_pitch(M: int) -> int:
+    p = C.c_int(0)
+    _check(lib.sncc_sat_pitch(int(M), C.byref(p)))
+    return p.value
+
+
+# ------------------------------------------------------------------ device
+def _ptr(t, dtype=None, name="tensor"):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def sncc_ctx_create(device: int = 0, stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device).cuda_stream
+    h = C.c_void_p()
+    _check(lib.sncc_ctx_create(int(device), int(stream), C.byref(h)))
+    return h
+
+
+def sncc_ctx_destroy(ctx):
+    _check(lib.sncc_ctx_destroy(ctx))
+
+
+def sncc_sync(ctx):
+    _check(lib.sncc_sync(ctx))
+
+
+def sncc_build_sats(ctx, f, s, s2):
+    """f: uint8 (B, N, M) or (N, M); s, s2: int32 (B, N+1, pitch) or (N+1, pitch)
+    device tensors holding the uint32 tables."""
+    import torch
+    if f.dim() == 2:
+        f = f.unsqueeze(0)
+    B, N, M = f.shape
+    P = s.shape[-1]
+    _check(lib.sncc_build_sats(ctx, _ptr(f, torch.uint8, "f"), B, M, N, M,
+                               _ptr(s, torch.int32, "s"), _ptr(s2, torch.int32, "s2"), P))
+
+
+def sncc_upload_templates(ctx, seg_lists, W, H):
+    """seg_lists: list of SEGMENT_DTYPE arrays; W, H: sizes per template."""
+    T = len(seg_lists)
+    arrs = [np.ascontiguousarray(a, dtype=SEGMENT_DTYPE) for a in seg_lists]
+    ptrs = (C.c_void_p * T)(*[a.ctypes.data for a in arrs])
+    K = (C.c_int * T)(*[len(a) for a in arrs])
+    Wa = (C.c_int * T)(*[int(w) for w in W])
+    Ha = (C.c_int * T)(*[int(h) for h in H])
+    h = C.c_void_p()
+    _check(lib.sncc_upload_templates(ctx, T, ptrs, K, Wa, Ha, C.byref(h)))
+    return h
+
+
+def sncc_tmpl_destroy(tm):
+    _check(lib.sncc_tmpl_destroy(tm))
+
+
+def sncc_tmpl_info(tm, index):
+    W, H, K, q = C.c_int(), C.c_int(), C.c_int(), C.c_double()
+    _check(lib.sncc_tmpl_info(tm, int(index), C.byref(W), C.byref(H), C.byref(K), C.byref(q)))
+    return W.value, H.value, K.value, q.value
+
+
+def sncc_score(ctx, tm, index, s, s2, M, N, precision, rho, degen=None):
+    import torch
+    want = torch.float32 if precision == SNCC_FP32_KAHAN else torch.float64
+    _check(lib.sncc_score(ctx, tm, int(index), _ptr(s, torch.int32, "s"),
+                          _ptr(s2, torch.int32, "s2"), int(M), int(N), s.shape[-1],
+                          int(precision), _ptr(rho, want, "rho"), rho.shape[-1],
+                          _ptr(degen, torch.uint8, "degen")))
+
+
+def _pairs_array(pairs):
+    p = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    return p
+
+
+def sncc_topk(ctx, tm, s, s2, B, M, N, pairs, k, precision, out):
+    """out: int32 device tensor (n_pairs, k, 3) = {u, v, rho bits}."""
+    import torch
+    p = _pairs_array(pairs)
+    _check(lib.sncc_topk(ctx, tm, _ptr(s, torch.int32, "s"), _ptr(s2, torch.int32, "s2"),
+                         int(B), int(M), int(N), s.shape[-1], len(p), p.ctypes.data, int(k),
+                         int(precision), _ptr(out, torch.int32, "out")))
+
+
+def sncc_argmax(ctx, tm, s, s2, B, M, N, pairs, precision, out):
+    import torch
+    p = _pairs_array(pairs)
+    _check(lib.sncc_argmax(ctx, tm, _ptr(s, torch.int32, "s"), _ptr(s2, torch.int32, "s2"),
+                           int(B), int(M), int(N), s.shape[-1], len(p), p.ctypes.data,
+                           int(precision), _ptr(out, torch.int32, "out")))
+
+
+def sncc_refine(ctx, fine, s, s2, B, M, N, pairs, cand, radius, out, count=None):
+    """cand: int32 (n_pairs, n_cand, 3); out: int32 (n_pairs, 4) = {u, v, rho f64}."""
+    import torch
+    p = _pairs_array(pairs)
+    _check(lib.sncc_refine(ctx, fine, _ptr(s, torch.int32, "s"), _ptr(s2, torch.int32, "s2"),
+                           int(B), int(M), int(N), s.shape[-1], len(p), p.ctypes.data,
+                           _ptr(cand, torch.int32, "cand"), cand.shape[1], int(radius),
+                           _ptr(out, torch.int32, "out"), _ptr(count, torch.int32, "count")))
+
+
+class Batch:
+    """Owns a sncc_batch handle and the host copies its descriptor points to."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def run(self):
+        _check(lib.sncc_batch_run(self.handle))
+
+    def stats(self):
+        st = sncc_batch_stats()
+        _check(lib.sncc_batch_stats_get(self.handle, C.byref(st)))
+        return st.as_dict()
+
+    def destroy(self):
+        if self.handle:
+            _check(lib.sncc_batch_destroy(self.handle))
+            self.handle = None
+
+
+def sncc_batch_create(ctx, coarse, s, s2, B, M, N, pairs, k, topk_out, fine=None,
+                      radius=2, best_out=None, count_out=None, frames=None, tune=0,
+                      tune_cache=None):
+    import torch
+    p = _pairs_array(pairs)
+    d = sncc_batch_desc()
+    d.coarse = coarse
+    d.fine = fine
+    d.d_f = _ptr(frames, torch.uint8, "frames") if frames is not None else None
+    d.f_pitch = int(M)
+    d.d_s = _ptr(s, torch.int32, "s")
+    d.d_s2 = _ptr(s2, torch.int32, "s2")
+    d.sat_pitch = s.shape[-1]
+    d.B, d.M, d.N = int(B), int(M), int(N)
+    d.n_pairs = len(p)
+    d.pairs = p.ctypes.data
+    d.k = int(k)
+    d.radius = int(radius)
+    d.d_topk = _ptr(topk_out, torch.int32, "topk_out")
+    d.d_best = _ptr(best_out, torch.int32, "best_out") if best_out is not None else None
+    d.d_count = _ptr(count_out, torch.int32, "count_out") if count_out is not None else None
+    d.tune = int(tune)
+    cache = tune_cache.encode() if tune_cache else None
+    d.tune_cache = cache
+    h = C.c_void_p()
+    _check(lib.sncc_batch_create(ctx, C.byref(d), C.byref(h)))
+    return Batch(h, (p, cache))
+
+
+def sncc_batch_run(batch: Batch):
+    batch.run()
+
+
+def sncc_batch_stats_get(batch: Batch):
+    return batch.stats()
+
+
+def sncc_batch_destroy(batch: Batch):
+    batch.destroy()
+
+
+# ------------------------------------------------------------ decoding helpers
+def decode_matches(out) -> np.ndarray:
+    """(n_pairs, k, 3) int32 match buffer -> structured numpy (u, v, rho)."""
+    a = out.detach().cpu().numpy().astype(np.int32, copy=False)
+    res = np.zeros(a.shape[:-1], dtype=[("u", "<i4"), ("v", "<i4"), ("rho", "<f4")])
+    res["u"] = a[..., 0]
+    res["v"] = a[..., 1]
+    res["rho"] = a[..., 2].view(np.float32)
+    return res
+
+
+def decode_matches64(out) -> np.ndarray:
+    """(n_pairs, 4) int32 buffer -> structured numpy (u, v, rho float64)."""
+    a = np.ascontiguousarray(out.detach().cpu().numpy().astype(np.int32, copy=False))
+    res = np.zeros(a.shape[0], dtype=[("u", "<i4"), ("v", "<i4"), ("rho", "<f8")])
+    res["u"] = a[:, 0]
+    res["v"] = a[:, 1]
+    res["rho"] = a[:, 2:4].copy().view(np.float64)[:, 0]
+    return res

@@ -1,0 +1,1142 @@
+// C-ABI of libsncc: argument checks, device memory of handles, the tile
+// planner (LDS passes, work list) and the graph-captured batch.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "sncc_internal.hpp"
+
+namespace sncc {
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+}  // namespace sncc
+
+using namespace sncc;
+
+#define SNCC_FAIL(code, ...)  \
+  do {                        \
+    set_error(__VA_ARGS__);   \
+    return (code);            \
+  } while (0)
+
+#define HIPCHK(x)                                                                  \
+  do {                                                                             \
+    hipError_t e_ = (x);                                                           \
+    if (e_ != hipSuccess) SNCC_FAIL(SNCC_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHK(x)                 \
+  do {                         \
+    int r_ = (x);              \
+    if (r_ != SNCC_OK) return r_; \
+  } while (0)
+
+namespace {
+
+// Device buffer owned by a handle; grows on demand, freed on destruction.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  int reserve(size_t n) {
+    if (n <= bytes) return SNCC_OK;
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+      bytes = 0;
+    }
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      SNCC_FAIL(SNCC_ENOMEM, "hipMalloc(%zu): %s", n, hipGetErrorString(e));
+    }
+    bytes = n;
+    return SNCC_OK;
+  }
+  template <class T>
+  int upload(const std::vector<T> &v, hipStream_t st) {
+    const size_t n = std::max<size_t>(v.size() * sizeof(T), 16);
+    CHK(reserve(n));
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T),
+                                          hipMemcpyHostToDevice, st));
+    return SNCC_OK;
+  }
+  template <class T>
+  T *as() const {
+    return static_cast<T *>(p);
+  }
+};
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ handles
+struct PlanDev;
+
+struct sncc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 0;
+  DevBuf sat_scratch;
+  DevBuf map_scratch;
+  std::vector<std::unique_ptr<PlanDev>> retired;  // awaiting completion
+};
+
+struct sncc_tmpl {
+  sncc_ctx *ctx = nullptr;
+  int T = 0;
+  std::vector<int> W, H, K, seg_off;
+  std::vector<std::vector<Seg>> segs;
+  std::vector<std::vector<double>> c64;
+  std::vector<double> q_k, r64;
+  std::vector<DevTmpl> dev;  // generic (plain / refine) descriptors
+  DevBuf d_geom, d_c64, d_area, d_dev;
+};
+
+namespace {
+
+// ------------------------------------------------------------- tile plans
+struct PlanHost {
+  int cfg = 0;
+  TileCfg tc{2, 4, 8};
+  int lds_bytes = 0;
+  int grid = 0;
+  bool map_sink = false;
+  int k = 0;
+  std::vector<DevTmpl> tmpls;
+  std::vector<PassDesc> passes;
+  std::vector<Interval> ivs;
+  std::vector<TileRec> recs;
+  std::vector<PairDesc> pairs;
+  std::vector<WorkItem> items;
+  std::vector<int> order;
+  int64_t coarse_evals = 0, n_offsets = 0;
+};
+
+int lp_class_for(int width) {
+  for (int i = 0; i < kNumLpClasses; ++i)
+    if (kLpClasses[i] >= width) return i;
+  return -1;
+}
+
+// Rows (template-relative, zero-padded coordinates) that the corner rows of
+// a segment need for a tile of bv offset rows: [y, y+bv) and [y+h, y+h+bv).
+void mark_rows(std::vector<char> &cov, const Seg &g, int bv, int &count) {
+  for (int r = g.y; r < g.y + bv; ++r)
+    if (!cov[r]) cov[r] = 1, ++count;
+  for (int r = g.y + g.h; r < g.y + g.h + bv; ++r)
+    if (!cov[r]) cov[r] = 1, ++count;
+}
+
+int rows_needed(const std::vector<char> &cov, const Seg &g, int bv) {
+  int add = 0;
+  for (int r = g.y; r < g.y + bv; ++r) add += !cov[r];
+  for (int r = std::max(g.y + g.h, g.y + bv); r < g.y + g.h + bv; ++r) add += !cov[r];
+  return add;
+}
+
+// Splits a template's segment list into passes whose staged rows fit
+// `rows_budget` LDS rows of pitch LP; appends passes, intervals, records.
+// Returns the largest number of rows any pass stages, or -1.
+int plan_template(const sncc_tmpl *tm, int t, const TileCfg &tc, int LP, int rows_budget,
+                  PlanHost &ph, DevTmpl &d) {
+  const int H = tm->H[t], bv = tc.bv();
+  const int span = H + bv;  // rows 0 .. H + bv - 1
+  const std::vector<Seg> &segs = tm->segs[t];
+  d.pass_begin = (int)ph.passes.size();
+  int max_rows = 0;
+  size_t i = 0;
+  while (i < segs.size()) {
+    std::vector<char> cov(span, 0);
+    int count = 0;
+    size_t j = i;
+    if (span <= rows_budget) {
+      std::fill(cov.begin(), cov.end(), 1);
+      count = span;
+      j = segs.size();
+    } else {
+      while (j < segs.size()) {
+        const int add = rows_needed(cov, segs[j], bv);
+        if (count + add > rows_budget) break;
+        mark_rows(cov, segs[j], bv, count);
+        ++j;
+      }
+      if (j == i) return -1;  // one segment does not fit
+    }
+    PassDesc ps;
+    ps.iv_begin = (int)ph.ivs.size();
+    std::vector<int> slot(span, -1);
+    int lds_row = 0;
+    for (int r = 0; r < span;) {
+      if (!cov[r]) {
+        ++r;
+        continue;
+      }
+      int e = r;
+      while (e < span && cov[e]) ++e;
+      Interval iv{r, e - r, lds_row, 0};
+      ph.ivs.push_back(iv);
+      for (int q = r; q < e; ++q) slot[q] = lds_row + (q - r);
+      lds_row += e - r;
+      r = e;
+    }
+    ps.iv_end = (int)ph.ivs.size();
+    ps.seg_begin = (int)ph.recs.size();
+    for (size_t q = i; q < j; ++q) {
+      const Seg &g = segs[q];
+      TileRec rc;
+      rc.off_tl = slot[g.y] * LP + g.x;
+      rc.off_bl = slot[g.y + g.h] * LP + g.x;
+      rc.w_area = (int)((uint32_t)g.w | ((uint32_t)g.area << 12));
+      rc.c = (float)tm->c64[t][q];
+      ph.recs.push_back(rc);
+    }
+    ps.seg_end = (int)ph.recs.size();
+    ph.passes.push_back(ps);
+    max_rows = std::max(max_rows, lds_row);
+    i = j;
+  }
+  d.pass_end = (int)ph.passes.size();
+  return max_rows;
+}
+
+int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
+               const int32_t *pairs, int k, bool map_sink, int num_cu, PlanHost &ph) {
+  if (cfg < 0 || cfg >= tile_cfg_count()) SNCC_FAIL(SNCC_EINVAL, "bad tile config %d", cfg);
+  ph = PlanHost();
+  ph.cfg = cfg;
+  ph.tc = tile_cfg(cfg);
+  ph.map_sink = map_sink;
+  ph.k = k;
+  const TileCfg tc = ph.tc;
+  const int bu = tc.bu(), bv = tc.bv();
+  std::vector<char> used(tm->T, 0);
+  for (int p = 0; p < n_pairs; ++p) used[pairs[2 * p + 1]] = 1;
+
+  // LDS budget: two workgroups per CU when every template allows it
+  const int topk_bytes = map_sink ? 0 : tc.nw * std::max(k, 1) * 8;
+  int budget = 80 * 1024 - 256;
+  for (int pass = 0; pass < 2; ++pass) {
+    ph.tmpls.assign(tm->T, DevTmpl{});
+    ph.passes.clear();
+    ph.ivs.clear();
+    ph.recs.clear();
+    bool ok = true;
+    int max_bytes = topk_bytes;
+    for (int t = 0; t < tm->T; ++t) {
+      DevTmpl d = tm->dev[t];
+      d.pass_begin = d.pass_end = 0;
+      if (used[t]) {
+        const int cls = lp_class_for(bu + tm->W[t] + 1);
+        if (cls < 0) SNCC_FAIL(SNCC_ERANGE, "template %d too wide (W=%d) for the tile kernel", t, tm->W[t]);
+        const int LP = kLpClasses[cls];
+        d.lp_class = cls;
+        const int rows_budget = budget / (LP * 4);
+        const int rows = plan_template(tm, t, tc, LP, rows_budget, ph, d);
+        if (rows < 0) {
+          ok = false;
+          break;
+        }
+        max_bytes = std::max(max_bytes, rows * LP * 4);
+      }
+      ph.tmpls[t] = d;
+    }
+    if (ok) {
+      ph.lds_bytes = (max_bytes + 255) & ~255;
+      break;
+    }
+    if (pass == 1) SNCC_FAIL(SNCC_ERANGE, "a template needs more LDS rows than available");
+    budget = tile_max_lds() - 1024;
+  }
+
+  // pairs and work items
+  const int occ = std::max(1, tile_occupancy(cfg, map_sink, ph.lds_bytes));
+  const int slots = std::max(1, num_cu) * occ;
+  std::vector<double> tile_cost(n_pairs);
+  double total = 0;
+  ph.pairs.resize(n_pairs);
+  for (int p = 0; p < n_pairs; ++p) {
+    const int t = pairs[2 * p + 1];
+    PairDesc &pd = ph.pairs[p];
+    pd.frame = pairs[2 * p];
+    pd.tmpl = t;
+    pd.nu = M - tm->W[t] + 1;
+    pd.nv = N - tm->H[t] + 1;
+    pd.ntu = (pd.nu + bu - 1) / bu;
+    pd.ntv = (pd.nv + bv - 1) / bv;
+    const double staged = (double)(bu + tm->W[t] + 1) * (double)(bv + tm->H[t] + 1);
+    tile_cost[p] = (double)bu * bv * (tm->K[t] + 8.0) + 0.5 * staged;
+    total += tile_cost[p] * pd.ntu * pd.ntv;
+    ph.coarse_evals += (int64_t)pd.nu * pd.nv * tm->K[t];
+    ph.n_offsets += (int64_t)pd.nu * pd.nv;
+  }
+  const double target = total / (slots * 6.0);
+  std::vector<double> item_cost;
+  for (int p = 0; p < n_pairs; ++p) {
+    PairDesc &pd = ph.pairs[p];
+    const int ntiles = pd.ntu * pd.ntv;
+    int per = (int)std::max(1.0, std::floor(target / tile_cost[p]));
+    per = std::min(per, ntiles);
+    const int nitems = (ntiles + per - 1) / per;
+    per = (ntiles + nitems - 1) / nitems;  // even out
+    pd.item_begin = (int)ph.items.size();
+    for (int a = 0; a < ntiles; a += per) {
+      WorkItem it{p, a, std::min(ntiles, a + per), 0};
+      ph.items.push_back(it);
+      item_cost.push_back(tile_cost[p] * (it.tile_end - it.tile_begin));
+    }
+    pd.item_end = (int)ph.items.size();
+  }
+  ph.order.resize(ph.items.size());
+  for (size_t i = 0; i < ph.order.size(); ++i) ph.order[i] = (int)i;
+  std::stable_sort(ph.order.begin(), ph.order.end(),
+                   [&](int a, int b) { return item_cost[a] > item_cost[b]; });
+  ph.grid = (int)std::min<size_t>(ph.items.size(), (size_t)slots);
+  if (ph.grid < 1) ph.grid = 1;
+  return SNCC_OK;
+}
+
+}  // namespace
+
+// Device copy of a plan plus its completion event.
+struct PlanDev {
+  PlanHost h;
+  DevBuf d_tmpls, d_passes, d_ivs, d_recs, d_pairs, d_items, d_order, d_queue, d_partial;
+  hipEvent_t done = nullptr;
+  ~PlanDev() {
+    if (done) (void)hipEventDestroy(done);
+  }
+  int upload(hipStream_t st) {
+    CHK(d_tmpls.upload(h.tmpls, st));
+    CHK(d_passes.upload(h.passes, st));
+    CHK(d_ivs.upload(h.ivs, st));
+    CHK(d_recs.upload(h.recs, st));
+    CHK(d_pairs.upload(h.pairs, st));
+    CHK(d_items.upload(h.items, st));
+    CHK(d_order.upload(h.order, st));
+    CHK(d_queue.reserve(256));
+    if (!h.map_sink) CHK(d_partial.reserve(std::max<size_t>(16, h.items.size() * h.k * 8)));
+    return SNCC_OK;
+  }
+  TileArgs args(const uint32_t *s, const uint32_t *s2, long long fs, int P, int M, int N) {
+    TileArgs a;
+    a.s = s;
+    a.s2 = s2;
+    a.frame_stride = fs;
+    a.sat_pitch = P;
+    a.M = M;
+    a.N = N;
+    a.tmpls = d_tmpls.as<DevTmpl>();
+    a.passes = d_passes.as<PassDesc>();
+    a.ivs = d_ivs.as<Interval>();
+    a.recs = d_recs.as<TileRec>();
+    a.pairs = d_pairs.as<PairDesc>();
+    a.items = d_items.as<WorkItem>();
+    a.order = d_order.as<int>();
+    a.n_items = (int)h.items.size();
+    a.queue = d_queue.as<int>();
+    a.k = h.k;
+    a.partial = d_partial.as<unsigned long long>();
+    a.rho = nullptr;
+    a.rho_pitch = 0;
+    a.degen = nullptr;
+    return a;
+  }
+};
+
+namespace {
+
+// Frees retired plans whose work has completed (all of them when `wait`).
+void reap(sncc_ctx *ctx, bool wait) {
+  auto &v = ctx->retired;
+  for (size_t i = 0; i < v.size();) {
+    bool finished = true;
+    if (v[i]->done) {
+      if (wait)
+        (void)hipEventSynchronize(v[i]->done);
+      else
+        finished = hipEventQuery(v[i]->done) == hipSuccess;
+    }
+    if (finished) {
+      v.erase(v.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
+
+int retire(sncc_ctx *ctx, std::unique_ptr<PlanDev> pd) {
+  HIPCHK(hipEventCreateWithFlags(&pd->done, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(pd->done, ctx->stream));
+  ctx->retired.push_back(std::move(pd));
+  if (ctx->retired.size() > 32) reap(ctx, false);
+  return SNCC_OK;
+}
+
+int check_ctx(sncc_ctx *ctx) {
+  if (!ctx) SNCC_FAIL(SNCC_EINVAL, "NULL context");
+  HIPCHK(hipSetDevice(ctx->device));
+  return SNCC_OK;
+}
+
+int check_sats(const uint32_t *s, const uint32_t *s2, int M, int N, int P) {
+  if (!s || !s2) SNCC_FAIL(SNCC_EINVAL, "NULL sum table");
+  if (!aligned16(s) || !aligned16(s2)) SNCC_FAIL(SNCC_EINVAL, "sum tables must be 16-byte aligned");
+  if (M < 1 || N < 1) SNCC_FAIL(SNCC_EINVAL, "bad image size %dx%d", M, N);
+  int need = 0;
+  sncc_sat_pitch(M, &need);
+  if (P < need || P % 64 != 0)
+    SNCC_FAIL(SNCC_EINVAL, "sat_pitch %d: need a multiple of 64 >= %d", P, need);
+  return SNCC_OK;
+}
+
+int check_pairs(const sncc_tmpl *tm, int B, int M, int N, int n_pairs, const int32_t *pairs) {
+  if (!tm) SNCC_FAIL(SNCC_EINVAL, "NULL template set");
+  if (n_pairs < 1 || !pairs) SNCC_FAIL(SNCC_EINVAL, "no pairs");
+  for (int p = 0; p < n_pairs; ++p) {
+    const int f = pairs[2 * p], t = pairs[2 * p + 1];
+    if (f < 0 || f >= B || t < 0 || t >= tm->T)
+      SNCC_FAIL(SNCC_EINVAL, "pair %d = (%d, %d) out of range", p, f, t);
+    if (tm->W[t] > M || tm->H[t] > N)
+      SNCC_FAIL(SNCC_EINVAL, "template %d (%dx%d) larger than image %dx%d", t, tm->W[t],
+                tm->H[t], M, N);
+  }
+  return SNCC_OK;
+}
+
+}  // namespace
+
+// ================================================================ C-ABI
+extern "C" {
+
+const char *sncc_status_string(int status) {
+  switch (status) {
+    case SNCC_OK: return "ok";
+    case SNCC_EINVAL: return "invalid argument";
+    case SNCC_ENOMEM: return "out of memory";
+    case SNCC_ENOSPC: return "output capacity too small";
+    case SNCC_ERANGE: return "size outside the exact range";
+    case SNCC_EDEGENERATE: return "uniform template approximation";
+    case SNCC_EDEVICE: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char *sncc_last_error(void) { return g_err.c_str(); }
+
+int sncc_version(void) { return 10000; }
+
+int sncc_segment_template(const uint8_t *t, int W, int H, int t_stride, double sigma_max,
+                          int K_max, sncc_segment *out, int cap, int *K_out,
+                          double *sigma_used, double *rho_max) {
+  g_err.clear();
+  if (!t || !K_out) SNCC_FAIL(SNCC_EINVAL, "NULL argument");
+  if (W < 1 || H < 1 || t_stride < W) SNCC_FAIL(SNCC_EINVAL, "bad template size %dx%d stride %d", W, H, t_stride);
+  if (K_max < 1) SNCC_FAIL(SNCC_EINVAL, "K_max must be >= 1");
+  if (std::isnan(sigma_max)) SNCC_FAIL(SNCC_EINVAL, "sigma_max is NaN");
+  std::vector<Seg> segs;
+  int kbm = 0;
+  double su = 0, rm = 0;
+  const int st = segment_template(t, W, H, t_stride, sigma_max, K_max, segs, &kbm, &su, &rm);
+  *K_out = (int)segs.size();
+  if (sigma_used) *sigma_used = su;
+  if (st != SNCC_OK) SNCC_FAIL(st, "uniform template approximation (all segment means equal)");
+  if (rho_max) *rho_max = rm;
+  if (cap < (int)segs.size() || (!out && !segs.empty()))
+    SNCC_FAIL(SNCC_ENOSPC, "need %zu segments, capacity %d", segs.size(), cap);
+  for (size_t i = 0; i < segs.size(); ++i) {
+    out[i].x = segs[i].x;
+    out[i].y = segs[i].y;
+    out[i].w = segs[i].w;
+    out[i].h = segs[i].h;
+    out[i].sum = segs[i].sum;
+    out[i].area = (int32_t)segs[i].area;
+    out[i].reserved = 0;
+  }
+  return SNCC_OK;
+}
+
+int sncc_ctx_create(int device, uintptr_t hip_stream, sncc_ctx **out) {
+  g_err.clear();
+  if (!out) SNCC_FAIL(SNCC_EINVAL, "NULL output");
+  *out = nullptr;
+  int n = 0;
+  HIPCHK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) SNCC_FAIL(SNCC_EINVAL, "device %d of %d", device, n);
+  HIPCHK(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, device));
+  sncc_ctx *c = new (std::nothrow) sncc_ctx();
+  if (!c) SNCC_FAIL(SNCC_ENOMEM, "context allocation");
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->num_cu = prop.multiProcessorCount;
+  *out = c;
+  return SNCC_OK;
+}
+
+int sncc_ctx_destroy(sncc_ctx *ctx) {
+  g_err.clear();
+  if (!ctx) return SNCC_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  reap(ctx, true);
+  delete ctx;
+  return SNCC_OK;
+}
+
+int sncc_sync(sncc_ctx *ctx) {
+  g_err.clear();
+  CHK(check_ctx(ctx));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  reap(ctx, true);
+  HIPCHK(hipGetLastError());
+  return SNCC_OK;
+}
+
+int sncc_sat_pitch(int M, int *pitch_elems) {
+  if (M < 1 || !pitch_elems) SNCC_FAIL(SNCC_EINVAL, "bad width");
+  *pitch_elems = ((M + 1) + 63) / 64 * 64;
+  return SNCC_OK;
+}
+
+int sncc_build_sats(sncc_ctx *ctx, const uint8_t *d_f, int B, int M, int N, int f_pitch,
+                    uint32_t *d_s, uint32_t *d_s2, int sat_pitch) {
+  g_err.clear();
+  CHK(check_ctx(ctx));
+  if (!d_f) SNCC_FAIL(SNCC_EINVAL, "NULL frames");
+  if (B < 1) SNCC_FAIL(SNCC_EINVAL, "B must be >= 1");
+  if (f_pitch < M) SNCC_FAIL(SNCC_EINVAL, "f_pitch %d < M %d", f_pitch, M);
+  CHK(check_sats(d_s, d_s2, M, N, sat_pitch));
+  CHK(ctx->sat_scratch.reserve(sat_scratch_words(B, M, N) * 4));
+  if (launch_sat(d_f, B, M, N, f_pitch, d_s, d_s2, sat_pitch,
+                 ctx->sat_scratch.as<uint32_t>(), ctx->stream) != 0)
+    SNCC_FAIL(SNCC_EDEVICE, "sum-table launch: %s", hipGetErrorString(hipGetLastError()));
+  return SNCC_OK;
+}
+
+int sncc_upload_templates(sncc_ctx *ctx, int T, const sncc_segment *const *segs, const int *K,
+                          const int *W, const int *H, sncc_tmpl **out) {
+  g_err.clear();
+  CHK(check_ctx(ctx));
+  if (!out || !segs || !K || !W || !H || T < 1) SNCC_FAIL(SNCC_EINVAL, "bad template arguments");
+  *out = nullptr;
+  std::unique_ptr<sncc_tmpl> tm(new (std::nothrow) sncc_tmpl());
+  if (!tm) SNCC_FAIL(SNCC_ENOMEM, "template allocation");
+  tm->ctx = ctx;
+  tm->T = T;
+  std::vector<int4> geom;
+  std::vector<double> c64all;
+  std::vector<int> areas;
+  for (int t = 0; t < T; ++t) {
+    const int w = W[t], h = H[t], k = K[t];
+    if (w < 1 || h < 1 || k < 1 || !segs[t]) SNCC_FAIL(SNCC_EINVAL, "template %d: bad size or list", t);
+    const long long n = (long long)w * h;
+    if (n > SNCC_MAX_TEMPLATE_AREA)
+      SNCC_FAIL(SNCC_ERANGE, "template %d: area %lld above %d (f^2 window sums would exceed 2^32)",
+                t, n, SNCC_MAX_TEMPLATE_AREA);
+    std::vector<char> cover((size_t)n, 0);
+    std::vector<Seg> list;
+    int64_t total = 0;
+    for (int i = 0; i < k; ++i) {
+      const sncc_segment &g = segs[t][i];
+      if (g.w < 1 || g.h < 1 || g.x < 0 || g.y < 0 || g.x + g.w > w || g.y + g.h > h ||
+          g.area != g.w * g.h || g.sum < 0 || g.sum > 255LL * g.area)
+        SNCC_FAIL(SNCC_EINVAL, "template %d segment %d invalid", t, i);
+      for (int y = g.y; y < g.y + g.h; ++y)
+        for (int x = g.x; x < g.x + g.w; ++x) {
+          if (cover[(size_t)y * w + x]) SNCC_FAIL(SNCC_EINVAL, "template %d: segments overlap", t);
+          cover[(size_t)y * w + x] = 1;
+        }
+      list.push_back(Seg{g.x, g.y, g.w, g.h, g.sum, g.area});
+      total += g.sum;
+    }
+    for (char c : cover)
+      if (!c) SNCC_FAIL(SNCC_EINVAL, "template %d: segments do not cover the template", t);
+    bool uniform = true;
+    for (const Seg &g : list)
+      if ((__int128)g.sum * n != (__int128)total * g.area) uniform = false;
+    if (uniform) SNCC_FAIL(SNCC_EDEGENERATE, "template %d: uniform approximation (q_k = 0)", t);
+    // Eq. (7) and the zero-mean values of step 3; q_k of step 4 (area-weighted)
+    double kbar = 0;
+    for (const Seg &g : list) kbar += (double)g.area * ((double)g.sum / (double)g.area);
+    kbar /= (double)n;
+    std::vector<double> c(k);
+    double qk = 0, r = 0;
+    for (int i = 0; i < k; ++i) {
+      c[i] = (double)list[i].sum / (double)list[i].area - kbar;
+      qk += (double)list[i].area * c[i] * c[i];
+      r += (double)list[i].area * c[i];
+    }
+    DevTmpl d{};
+    d.W = w;
+    d.H = h;
+    d.K = k;
+    d.n = (int)n;
+    d.q_k = qk;
+    d.r64 = r;
+    d.seg_off = (int)geom.size();
+    tm->W.push_back(w);
+    tm->H.push_back(h);
+    tm->K.push_back(k);
+    tm->seg_off.push_back(d.seg_off);
+    tm->q_k.push_back(qk);
+    tm->r64.push_back(r);
+    for (int i = 0; i < k; ++i) {
+      geom.push_back(make_int4(list[i].x, list[i].y, list[i].w, list[i].h));
+      c64all.push_back(c[i]);
+      areas.push_back((int)list[i].area);
+    }
+    tm->segs.push_back(std::move(list));
+    tm->c64.push_back(std::move(c));
+    tm->dev.push_back(d);
+  }
+  CHK(tm->d_geom.upload(geom, ctx->stream));
+  CHK(tm->d_c64.upload(c64all, ctx->stream));
+  CHK(tm->d_area.upload(areas, ctx->stream));
+  CHK(tm->d_dev.upload(tm->dev, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  *out = tm.release();
+  return SNCC_OK;
+}
+
+int sncc_tmpl_destroy(sncc_tmpl *tm) {
+  g_err.clear();
+  if (!tm) return SNCC_OK;
+  if (tm->ctx) {
+    (void)hipSetDevice(tm->ctx->device);
+    (void)hipStreamSynchronize(tm->ctx->stream);
+  }
+  delete tm;
+  return SNCC_OK;
+}
+
+int sncc_tmpl_info(const sncc_tmpl *tm, int index, int *W, int *H, int *K, double *q_k) {
+  g_err.clear();
+  if (!tm || index < 0 || index >= tm->T) SNCC_FAIL(SNCC_EINVAL, "bad template index");
+  if (W) *W = tm->W[index];
+  if (H) *H = tm->H[index];
+  if (K) *K = tm->K[index];
+  if (q_k) *q_k = tm->q_k[index];
+  return SNCC_OK;
+}
+
+int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint32_t *d_s,
+               const uint32_t *d_s2, int M, int N, int sat_pitch, int precision, void *d_rho,
+               int rho_pitch, uint8_t *d_degenerate) {
+  g_err.clear();
+  CHK(check_ctx(ctx));
+  CHK(check_sats(d_s, d_s2, M, N, sat_pitch));
+  if (!tm || index < 0 || index >= tm->T) SNCC_FAIL(SNCC_EINVAL, "bad template index");
+  if (!d_rho || !aligned16(d_rho)) SNCC_FAIL(SNCC_EINVAL, "NULL or misaligned rho map");
+  const int nu = M - tm->W[index] + 1, nv = N - tm->H[index] + 1;
+  if (nu < 1 || nv < 1) SNCC_FAIL(SNCC_EINVAL, "template larger than image");
+  if (rho_pitch < nu) SNCC_FAIL(SNCC_EINVAL, "rho_pitch %d < %d", rho_pitch, nu);
+  if (precision == SNCC_FP64) {
+    PlainArgs a;
+    a.s = d_s;
+    a.s2 = d_s2;
+    a.sat_pitch = sat_pitch;
+    a.nu = nu;
+    a.nv = nv;
+    a.W = tm->W[index];
+    a.H = tm->H[index];
+    a.K = tm->K[index];
+    a.q_k = tm->q_k[index];
+    a.r64 = tm->r64[index];
+    a.geom = tm->d_geom.as<int4>() + tm->seg_off[index];
+    a.c64 = tm->d_c64.as<double>() + tm->seg_off[index];
+    a.area = tm->d_area.as<int>() + tm->seg_off[index];
+    a.rho = static_cast<double *>(d_rho);
+    a.rho_pitch = rho_pitch;
+    a.degen = d_degenerate;
+    if (launch_plain(a, ctx->stream) != 0)
+      SNCC_FAIL(SNCC_EDEVICE, "plain launch: %s", hipGetErrorString(hipGetLastError()));
+    return SNCC_OK;
+  }
+  if (precision != SNCC_FP32_KAHAN) SNCC_FAIL(SNCC_EINVAL, "unknown precision %d", precision);
+  std::unique_ptr<PlanDev> pd(new PlanDev());
+  const int32_t pair[2] = {0, index};
+  CHK(build_plan(tm, 0, M, N, 1, pair, 0, true, ctx->num_cu, pd->h));
+  CHK(pd->upload(ctx->stream));
+  TileArgs a = pd->args(d_s, d_s2, (long long)(N + 1) * sat_pitch, sat_pitch, M, N);
+  a.rho = d_rho;
+  a.rho_pitch = rho_pitch;
+  a.degen = d_degenerate;
+  if (launch_zero(a.queue, 1, ctx->stream) != 0 ||
+      launch_tile(pd->h.cfg, true, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0)
+    SNCC_FAIL(SNCC_EDEVICE, "tile launch: %s", hipGetErrorString(hipGetLastError()));
+  return retire(ctx, std::move(pd));
+}
+
+int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uint32_t *d_s2,
+              int B, int M, int N, int sat_pitch, int n_pairs, const int32_t *pairs, int k,
+              int precision, sncc_match *d_out) {
+  g_err.clear();
+  CHK(check_ctx(ctx));
+  CHK(check_sats(d_s, d_s2, M, N, sat_pitch));
+  if (B < 1) SNCC_FAIL(SNCC_EINVAL, "B must be >= 1");
+  CHK(check_pairs(tm, B, M, N, n_pairs, pairs));
+  if (k < 1 || k > 64) SNCC_FAIL(SNCC_EINVAL, "k must be in 1..64");
+  if (!d_out || !aligned16(d_out)) SNCC_FAIL(SNCC_EINVAL, "NULL or misaligned output");
+  const long long fs = (long long)(N + 1) * sat_pitch;
+  std::unique_ptr<PlanDev> pd(new PlanDev());
+  if (precision == SNCC_FP32_KAHAN) {
+    CHK(build_plan(tm, 0, M, N, n_pairs, pairs, k, false, ctx->num_cu, pd->h));
+    CHK(pd->upload(ctx->stream));
+    TileArgs a = pd->args(d_s, d_s2, fs, sat_pitch, M, N);
+    if (launch_zero(a.queue, 1, ctx->stream) != 0 ||
+        launch_tile(pd->h.cfg, false, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0 ||
+        launch_merge(pd->d_pairs.as<PairDesc>(), n_pairs, a.partial, k, d_out, ctx->stream) != 0)
+      SNCC_FAIL(SNCC_EDEVICE, "top-k launch: %s", hipGetErrorString(hipGetLastError()));
+    return retire(ctx, std::move(pd));
+  }
+  if (precision != SNCC_FP64) SNCC_FAIL(SNCC_EINVAL, "unknown precision %d", precision);
+  // plain form: one FP64 map per pair, then chunked top-k and the merge
+  const int chunk = 64 * 1024;
+  PlanHost &h = pd->h;
+  h.k = k;
+  size_t max_map = 0;
+  int n_chunks = 0;
+  h.pairs.resize(n_pairs);
+  for (int p = 0; p < n_pairs; ++p) {
+    const int t = pairs[2 * p + 1];
+    PairDesc &q = h.pairs[p];
+    q.frame = pairs[2 * p];
+    q.tmpl = t;
+    q.nu = M - tm->W[t] + 1;
+    q.nv = N - tm->H[t] + 1;
+    q.ntu = q.ntv = 0;
+    const long long tot = (long long)q.nu * q.nv;
+    q.item_begin = n_chunks;
+    n_chunks += (int)((tot + chunk - 1) / chunk);
+    q.item_end = n_chunks;
+    max_map = std::max(max_map, (size_t)tot);
+  }
+  CHK(ctx->map_scratch.reserve(max_map * sizeof(double)));
+  CHK(pd->d_pairs.upload(h.pairs, ctx->stream));
+  CHK(pd->d_partial.reserve((size_t)n_chunks * k * 8));
+  unsigned long long *partial = pd->d_partial.as<unsigned long long>();
+  for (int p = 0; p < n_pairs; ++p) {
+    const PairDesc &q = h.pairs[p];
+    const int t = q.tmpl;
+    PlainArgs a;
+    a.s = d_s + (long long)q.frame * fs;
+    a.s2 = d_s2 + (long long)q.frame * fs;
+    a.sat_pitch = sat_pitch;
+    a.nu = q.nu;
+    a.nv = q.nv;
+    a.W = tm->W[t];
+    a.H = tm->H[t];
+    a.K = tm->K[t];
+    a.q_k = tm->q_k[t];
+    a.r64 = tm->r64[t];
+    a.geom = tm->d_geom.as<int4>() + tm->seg_off[t];
+    a.c64 = tm->d_c64.as<double>() + tm->seg_off[t];
+    a.area = tm->d_area.as<int>() + tm->seg_off[t];
+    a.rho = ctx->map_scratch.as<double>();
+    a.rho_pitch = q.nu;
+    a.degen = nullptr;
+    if (launch_plain(a, ctx->stream) != 0 ||
+        launch_map_topk(a.rho, q.nu, q.nu, q.nv, chunk, k, partial + (size_t)q.item_begin * k,
+                        ctx->stream) != 0)
+      SNCC_FAIL(SNCC_EDEVICE, "plain top-k launch: %s", hipGetErrorString(hipGetLastError()));
+  }
+  if (launch_merge(pd->d_pairs.as<PairDesc>(), n_pairs, partial, k, d_out, ctx->stream) != 0)
+    SNCC_FAIL(SNCC_EDEVICE, "merge launch: %s", hipGetErrorString(hipGetLastError()));
+  return retire(ctx, std::move(pd));
+}
+
+int sncc_argmax(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uint32_t *d_s2,
+                int B, int M, int N, int sat_pitch, int n_pairs, const int32_t *pairs,
+                int precision, sncc_match *d_out) {
+  return sncc_topk(ctx, tm, d_s, d_s2, B, M, N, sat_pitch, n_pairs, pairs, 1, precision, d_out);
+}
+
+static int check_fine(const sncc_tmpl *fine, int B, int M, int N, int n_pairs,
+                      const int32_t *pairs, int n_cand, int radius) {
+  CHK(check_pairs(fine, B, M, N, n_pairs, pairs));
+  if (n_cand < 1 || radius < 0 || radius > 7)
+    SNCC_FAIL(SNCC_EINVAL, "bad candidate count %d or radius %d", n_cand, radius);
+  if (n_cand * (2 * radius + 1) * (2 * radius + 1) > 4096)
+    SNCC_FAIL(SNCC_EINVAL, "n_cand * (2 radius + 1)^2 must be <= 4096");
+  return SNCC_OK;
+}
+
+int sncc_refine(sncc_ctx *ctx, const sncc_tmpl *fine, const uint32_t *d_s, const uint32_t *d_s2,
+                int B, int M, int N, int sat_pitch, int n_pairs, const int32_t *pairs,
+                const sncc_match *d_cand, int n_cand, int radius, sncc_match64 *d_out,
+                int32_t *d_count) {
+  g_err.clear();
+  CHK(check_ctx(ctx));
+  CHK(check_sats(d_s, d_s2, M, N, sat_pitch));
+  if (B < 1) SNCC_FAIL(SNCC_EINVAL, "B must be >= 1");
+  CHK(check_fine(fine, B, M, N, n_pairs, pairs, n_cand, radius));
+  if (!d_cand || !d_out || !aligned16(d_out)) SNCC_FAIL(SNCC_EINVAL, "NULL or misaligned buffers");
+  std::unique_ptr<PlanDev> pd(new PlanDev());
+  PlanHost &h = pd->h;
+  h.pairs.resize(n_pairs);
+  for (int p = 0; p < n_pairs; ++p) {
+    const int t = pairs[2 * p + 1];
+    PairDesc &q = h.pairs[p];
+    q = PairDesc{};
+    q.frame = pairs[2 * p];
+    q.tmpl = t;
+    q.nu = M - fine->W[t] + 1;
+    q.nv = N - fine->H[t] + 1;
+  }
+  CHK(pd->d_pairs.upload(h.pairs, ctx->stream));
+  if (launch_refine(d_s, d_s2, (long long)(N + 1) * sat_pitch, sat_pitch,
+                    fine->d_dev.as<DevTmpl>(), fine->d_geom.as<int4>(), fine->d_c64.as<double>(),
+                    fine->d_area.as<int>(), pd->d_pairs.as<PairDesc>(), n_pairs, d_cand, n_cand,
+                    radius, d_out, d_count, ctx->stream) != 0)
+    SNCC_FAIL(SNCC_EDEVICE, "refine launch: %s", hipGetErrorString(hipGetLastError()));
+  return retire(ctx, std::move(pd));
+}
+
+}  // extern "C"
+
+// ================================================================= batches
+struct sncc_batch {
+  sncc_ctx *ctx = nullptr;
+  sncc_batch_desc d{};
+  std::vector<int32_t> pairs;
+  std::unique_ptr<PlanDev> plan;
+  DevBuf sat_scratch;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev[5] = {};
+  bool timed = false;
+  std::string capture_note;  // why the timed graph was not built, if it was not
+  ~sncc_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+namespace {
+
+// Enqueues stage `stage` of one run of the batch on stream `st`:
+// 0 sum tables, 1 scoring, 2 top-k merge, 3 FP64 refinement.
+int enqueue_stage(sncc_batch *b, int stage, hipStream_t st) {
+  const sncc_batch_desc &d = b->d;
+  PlanDev &pd = *b->plan;
+  const long long fs = (long long)(d.N + 1) * d.sat_pitch;
+  TileArgs a = pd.args(d.d_s, d.d_s2, fs, d.sat_pitch, d.M, d.N);
+  switch (stage) {
+    case 0:
+      if (d.d_f && launch_sat(d.d_f, d.B, d.M, d.N, d.f_pitch, d.d_s, d.d_s2, d.sat_pitch,
+                              b->sat_scratch.as<uint32_t>(), st) != 0)
+        SNCC_FAIL(SNCC_EDEVICE, "sum-table launch");
+      return SNCC_OK;
+    case 1:
+      if (launch_zero(a.queue, 1, st) != 0 ||
+          launch_tile(pd.h.cfg, false, a, pd.h.grid, pd.h.lds_bytes, st) != 0)
+        SNCC_FAIL(SNCC_EDEVICE, "scoring launch");
+      return SNCC_OK;
+    case 2:
+      if (launch_merge(pd.d_pairs.as<PairDesc>(), d.n_pairs, a.partial, d.k, d.d_topk, st) != 0)
+        SNCC_FAIL(SNCC_EDEVICE, "merge launch");
+      return SNCC_OK;
+    case 3:
+      if (d.fine &&
+          launch_refine(d.d_s, d.d_s2, fs, d.sat_pitch, d.fine->d_dev.as<DevTmpl>(),
+                        d.fine->d_geom.as<int4>(), d.fine->d_c64.as<double>(),
+                        d.fine->d_area.as<int>(), pd.d_pairs.as<PairDesc>(), d.n_pairs, d.d_topk,
+                        d.k, d.radius, d.d_best, d.d_count, st) != 0)
+        SNCC_FAIL(SNCC_EDEVICE, "refine launch");
+      return SNCC_OK;
+  }
+  return SNCC_OK;
+}
+
+bool stage_used(const sncc_batch *b, int stage) {
+  return stage == 1 || stage == 2 || (stage == 0 && b->d.d_f) || (stage == 3 && b->d.fine);
+}
+
+int capture_stage(sncc_batch *b, int stage, hipGraph_t *out) {
+  *out = nullptr;
+  HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  const int st = enqueue_stage(b, stage, b->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->cap, &g);
+  if (st != SNCC_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    SNCC_FAIL(st != SNCC_OK ? st : SNCC_EDEVICE, "capture of stage %d failed: %s", stage,
+              hipGetErrorString(e));
+  }
+  *out = g;
+  return SNCC_OK;
+}
+
+// One graph per run: each stage captured as a child graph; with `timed`,
+// event-record nodes between the stages give per-stage device times.
+int capture(sncc_batch *b, bool timed) {
+  hipGraph_t parent = nullptr;
+  HIPCHK(hipGraphCreate(&parent, 0));
+  hipGraphNode_t prev = nullptr;
+  int rc = SNCC_OK;
+  auto fail = [&](int code) {
+    (void)hipGraphDestroy(parent);
+    (void)hipGetLastError();
+    return code;
+  };
+  auto add_event = [&](hipEvent_t e) -> int {
+    hipGraphNode_t n = nullptr;
+    if (hipGraphAddEventRecordNode(&n, parent, prev ? &prev : nullptr, prev ? 1 : 0, e) !=
+        hipSuccess)
+      SNCC_FAIL(SNCC_EDEVICE, "event-record node: %s", hipGetErrorString(hipGetLastError()));
+    prev = n;
+    return SNCC_OK;
+  };
+  if (timed && (rc = add_event(b->ev[0])) != SNCC_OK) return fail(rc);
+  for (int stage = 0; stage < 4; ++stage) {
+    if (stage_used(b, stage)) {
+      hipGraph_t g = nullptr;
+      if ((rc = capture_stage(b, stage, &g)) != SNCC_OK) return fail(rc);
+      hipGraphNode_t n = nullptr;
+      const hipError_t e =
+          hipGraphAddChildGraphNode(&n, parent, prev ? &prev : nullptr, prev ? 1 : 0, g);
+      (void)hipGraphDestroy(g);  // the child node holds its own copy
+      if (e != hipSuccess) {
+        set_error("child graph node: %s", hipGetErrorString(e));
+        return fail(SNCC_EDEVICE);
+      }
+      prev = n;
+    }
+    if (timed && (rc = add_event(b->ev[stage + 1])) != SNCC_OK) return fail(rc);
+  }
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, parent, nullptr, nullptr, 0) != hipSuccess) {
+    set_error("graph instantiation: %s", hipGetErrorString(hipGetLastError()));
+    return fail(SNCC_EDEVICE);
+  }
+  b->graph = parent;
+  b->exec = x;
+  b->timed = timed;
+  return SNCC_OK;
+}
+
+std::string tune_key(const sncc_batch_desc &d) {
+  std::ostringstream os;
+  os << "gfx950|M" << d.M << "|N" << d.N << "|B" << d.B << "|P" << d.n_pairs << "|k" << d.k;
+  unsigned long long h = 1469598103934665603ull;
+  for (int t = 0; t < d.coarse->T; ++t) {
+    for (long long v : {(long long)d.coarse->W[t], (long long)d.coarse->H[t],
+                        (long long)d.coarse->K[t]}) {
+      h ^= (unsigned long long)v;
+      h *= 1099511628211ull;
+    }
+  }
+  os << "|h" << std::hex << h;
+  return os.str();
+}
+
+int read_cache(const char *path, const std::string &key) {
+  if (!path) return -1;
+  std::ifstream in(path);
+  if (!in) return -1;
+  std::string line;
+  while (std::getline(in, line)) {
+    const size_t a = line.find('"' + key + '"');
+    if (a == std::string::npos) continue;
+    const size_t c = line.find(':', a);
+    if (c == std::string::npos) continue;
+    return std::atoi(line.c_str() + c + 1);
+  }
+  return -1;
+}
+
+void write_cache(const char *path, const std::string &key, int cfg) {
+  if (!path) return;
+  std::vector<std::string> lines;
+  {
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line))
+      if (line.find('"') != std::string::npos && line.find('"' + key + '"') == std::string::npos)
+        lines.push_back(line);
+  }
+  std::ofstream out(path);
+  out << "{\n";
+  for (auto &l : lines) {
+    std::string s = l;
+    while (!s.empty() && (s.back() == ',' || s.back() == ' ')) s.pop_back();
+    out << s << ",\n";
+  }
+  out << "  \"" << key << "\": " << cfg << "\n}\n";
+}
+
+// Times the scoring launch of each tile configuration on this batch and
+// returns the fastest.
+int autotune(sncc_batch *b, int *best_cfg) {
+  const sncc_batch_desc &d = b->d;
+  const long long fs = (long long)(d.N + 1) * d.sat_pitch;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  *best_cfg = 0;
+  for (int c = 0; c < tile_cfg_count(); ++c) {
+    PlanDev pd;
+    if (build_plan(d.coarse, c, d.M, d.N, d.n_pairs, b->pairs.data(), d.k, false,
+                   b->ctx->num_cu, pd.h) != SNCC_OK)
+      continue;
+    if (pd.upload(b->ctx->stream) != SNCC_OK) continue;
+    TileArgs a = pd.args(d.d_s, d.d_s2, fs, d.sat_pitch, d.M, d.N);
+    float ms = 0;
+    for (int rep = 0; rep < 2; ++rep) {
+      launch_zero(a.queue, 1, b->ctx->stream);
+      HIPCHK(hipEventRecord(e0, b->ctx->stream));
+      launch_tile(c, false, a, pd.h.grid, pd.h.lds_bytes, b->ctx->stream);
+      HIPCHK(hipEventRecord(e1, b->ctx->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    }
+    if (ms < best) {
+      best = ms;
+      *best_cfg = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return SNCC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sncc_batch_create(sncc_ctx *ctx, const sncc_batch_desc *desc, sncc_batch **out) {
+  g_err.clear();
+  CHK(check_ctx(ctx));
+  if (!desc || !out) SNCC_FAIL(SNCC_EINVAL, "NULL argument");
+  *out = nullptr;
+  const sncc_batch_desc &d = *desc;
+  CHK(check_sats(d.d_s, d.d_s2, d.M, d.N, d.sat_pitch));
+  if (d.B < 1) SNCC_FAIL(SNCC_EINVAL, "B must be >= 1");
+  CHK(check_pairs(d.coarse, d.B, d.M, d.N, d.n_pairs, d.pairs));
+  if (d.k < 1 || d.k > 64) SNCC_FAIL(SNCC_EINVAL, "k must be in 1..64");
+  if (!d.d_topk || !aligned16(d.d_topk)) SNCC_FAIL(SNCC_EINVAL, "NULL or misaligned d_topk");
+  if (d.d_f && d.f_pitch < d.M) SNCC_FAIL(SNCC_EINVAL, "f_pitch < M");
+  if (d.fine) {
+    CHK(check_fine(d.fine, d.B, d.M, d.N, d.n_pairs, d.pairs, d.k, d.radius));
+    if (!d.d_best || !aligned16(d.d_best)) SNCC_FAIL(SNCC_EINVAL, "NULL or misaligned d_best");
+    if (d.fine->T != d.coarse->T) SNCC_FAIL(SNCC_EINVAL, "fine and coarse sets differ in size");
+    for (int t = 0; t < d.coarse->T; ++t)
+      if (d.fine->W[t] != d.coarse->W[t] || d.fine->H[t] != d.coarse->H[t])
+        SNCC_FAIL(SNCC_EINVAL, "fine template %d differs in size from the coarse one", t);
+  }
+  std::unique_ptr<sncc_batch> b(new (std::nothrow) sncc_batch());
+  if (!b) SNCC_FAIL(SNCC_ENOMEM, "batch allocation");
+  b->ctx = ctx;
+  b->d = d;
+  b->pairs.assign(d.pairs, d.pairs + 2 * (size_t)d.n_pairs);
+  b->d.pairs = b->pairs.data();
+  if (d.d_f) CHK(b->sat_scratch.reserve(sat_scratch_words(d.B, d.M, d.N) * 4));
+
+  int cfg = 0;
+  if (d.tune) {
+    const std::string key = tune_key(d);
+    cfg = read_cache(d.tune_cache, key);
+    if (cfg < 0 || cfg >= tile_cfg_count()) {
+      if (d.d_f) {  // the candidates are timed on real sum tables
+        if (launch_sat(d.d_f, d.B, d.M, d.N, d.f_pitch, d.d_s, d.d_s2, d.sat_pitch,
+                       b->sat_scratch.as<uint32_t>(), ctx->stream) != 0)
+          SNCC_FAIL(SNCC_EDEVICE, "sum-table launch");
+      }
+      CHK(autotune(b.get(), &cfg));
+      write_cache(d.tune_cache, key, cfg);
+    }
+  }
+  b->plan.reset(new PlanDev());
+  CHK(build_plan(d.coarse, cfg, d.M, d.N, d.n_pairs, b->pairs.data(), d.k, false, ctx->num_cu,
+                 b->plan->h));
+  CHK(b->plan->upload(ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+
+  HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  for (auto &e : b->ev) HIPCHK(hipEventCreate(&e));
+  if (capture(b.get(), true) != SNCC_OK) {
+    b->capture_note = sncc_last_error();
+    CHK(capture(b.get(), false));
+  }
+  *out = b.release();
+  return SNCC_OK;
+}
+
+int sncc_batch_run(sncc_batch *b) {
+  g_err.clear();
+  if (!b) SNCC_FAIL(SNCC_EINVAL, "NULL batch");
+  CHK(check_ctx(b->ctx));
+  HIPCHK(hipGraphLaunch(b->exec, b->ctx->stream));
+  return SNCC_OK;
+}
+
+int sncc_batch_stats_get(sncc_batch *b, sncc_batch_stats *st) {
+  g_err.clear();
+  if (!b || !st) SNCC_FAIL(SNCC_EINVAL, "NULL argument");
+  const PlanHost &h = b->plan->h;
+  memset(st, 0, sizeof *st);
+  st->coarse_evals = h.coarse_evals;
+  st->n_offsets = h.n_offsets;
+  st->work_items = (int64_t)h.items.size();
+  st->n_launch_classes = 1;
+  st->tile_u = h.tc.bu();
+  st->tile_v = h.tc.bv();
+  st->wg_threads = h.tc.threads();
+  st->lds_bytes = h.lds_bytes;
+  st->timed = b->timed ? 1 : 0;
+  st->ms_sat = st->ms_score = st->ms_select = st->ms_refine = st->ms_total = -1.f;
+  if (b->timed && hipEventQuery(b->ev[4]) == hipSuccess) {
+    hipEventElapsedTime(&st->ms_sat, b->ev[0], b->ev[1]);
+    hipEventElapsedTime(&st->ms_score, b->ev[1], b->ev[2]);
+    hipEventElapsedTime(&st->ms_select, b->ev[2], b->ev[3]);
+    hipEventElapsedTime(&st->ms_refine, b->ev[3], b->ev[4]);
+    hipEventElapsedTime(&st->ms_total, b->ev[0], b->ev[4]);
+    (void)hipGetLastError();
+  }
+  return SNCC_OK;
+}
+
+int sncc_batch_destroy(sncc_batch *b) {
+  g_err.clear();
+  if (!b) return SNCC_OK;
+  (void)hipSetDevice(b->ctx->device);
+  (void)hipStreamSynchronize(b->ctx->stream);
+  delete b;
+  return SNCC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,880 @@
+// HIP kernels for segmented NCC on gfx950 (CDNA4, wave64).
+//
+//  * Sum tables (Eqs. (10), (14)): three launches.  Per 64 x 256 tile,
+//    sat_totals writes column totals, row totals and the tile total;
+//    sat_prefix turns them into the carries each tile needs (sum of the
+//    rows above per column, of the columns to the left per row, and of the
+//    tiles above-left); sat_scan rebuilds the tile with running column sums
+//    and one wavefront scan per row and writes s and s^2.  f is read twice,
+//    s and s^2 written once: about 10 bytes of HBM traffic per pixel.
+//  * Scoring (Eqs. (11)-(18)): a persistent kernel pulls work items
+//    (pair, range of offset tiles) from an atomic counter.  For each tile the
+//    rows of the sum table that the template's corner rows touch are staged
+//    in LDS; every lane then owns RU x RV offsets, streams the segment list
+//    (wave-uniform scalar loads) and forms each box sum from four LDS reads in
+//    32-bit modular arithmetic (exact), subtracts area x (window mean rounded
+//    to an integer) in integers and accumulates the product with c_i in FP32
+//    with Kahan compensation.  The epilogue takes the window energy in 64-bit
+//    integers and rho in FP64.  Results go either to a map or to a per-wave
+//    register-resident top-k list.
+//  * Plain FP64 kernel: one thread per offset, segments from global memory,
+//    FP64 accumulation; used for the FP64 map, the per-pair baseline and the
+//    fine re-scoring.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sncc_internal.hpp"
+
+namespace sncc {
+
+typedef unsigned long long u64;
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  // Hillis-Steele within rows of 16 lanes, then row broadcasts (GFX9 DPP).
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), 63);
+}
+
+__device__ __forceinline__ u64 shfl_u64(u64 x, int src) {
+  unsigned lo = (unsigned)__shfl((int)(unsigned)x, src);
+  unsigned hi = (unsigned)__shfl((int)(unsigned)(x >> 32), src);
+  return ((u64)hi << 32) | lo;
+}
+
+__device__ __forceinline__ u64 shfl_up_u64(u64 x, int d) {
+  unsigned lo = (unsigned)__shfl_up((int)(unsigned)x, d);
+  unsigned hi = (unsigned)__shfl_up((int)(unsigned)(x >> 32), d);
+  return ((u64)hi << 32) | lo;
+}
+
+__device__ __forceinline__ u64 wave_max_u64(u64 x) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    unsigned lo = (unsigned)__shfl_xor((int)(unsigned)x, m);
+    unsigned hi = (unsigned)__shfl_xor((int)(unsigned)(x >> 32), m);
+    u64 y = ((u64)hi << 32) | lo;
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+// Order-preserving map of a float to uint32 (larger float -> larger code).
+__device__ __forceinline__ uint32_t float_order(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float float_unorder(uint32_t o) {
+  uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+  return __uint_as_float(u);
+}
+
+// Selection key: higher rho first, then smaller row-major offset index.
+__device__ __forceinline__ u64 make_key(float rho, int idx) {
+  return ((u64)float_order(rho) << 32) | (u64)(0xffffffffu - (uint32_t)idx);
+}
+
+// Per-wave top-k list: lane j < k holds the j-th best key (0 = empty).
+// Inserts a wave-uniform key that beats the current k-th entry.
+__device__ __forceinline__ void topk_insert(u64 &lkey, u64 key, int k, int lane) {
+  const bool better = lane < k && lkey > key;
+  const int pos = __popcll(__ballot(better));
+  const u64 up = shfl_up_u64(lkey, 1);
+  if (lane == pos)
+    lkey = key;
+  else if (lane > pos && lane < k)
+    lkey = up;
+}
+
+// Offers R candidate keys per lane (0 = none) to the wave's list.
+template <int R>
+__device__ __forceinline__ void topk_offer(u64 &lkey, u64 (&cand)[R], int k, int lane) {
+  u64 thr = shfl_u64(lkey, k - 1);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (cand[r] <= thr) cand[r] = 0;
+  for (;;) {
+    u64 best = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) best = cand[r] > best ? cand[r] : best;
+    if (__ballot(best != 0) == 0) break;
+    best = wave_max_u64(best);
+    topk_insert(lkey, best, k, lane);
+    thr = shfl_u64(lkey, k - 1);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (cand[r] == best || cand[r] <= thr) cand[r] = 0;
+  }
+}
+
+// ---------------------------------------------------------------- sum tables
+constexpr int SAT_TY = 64;
+constexpr int SAT_TX = 256;
+
+struct SatScratch {
+  uint32_t *colT, *rowT, *T, *corner;
+  int nTX, nTY;
+};
+
+__host__ __device__ inline SatScratch sat_layout(uint32_t *base, int B, int M, int N) {
+  SatScratch sc;
+  sc.nTX = (M + SAT_TX - 1) / SAT_TX;
+  sc.nTY = (N + SAT_TY - 1) / SAT_TY;
+  sc.colT = base;                                          // [2][B][nTY][M]
+  sc.rowT = sc.colT + (size_t)2 * B * sc.nTY * M;          // [2][B][N][nTX]
+  sc.T = sc.rowT + (size_t)2 * B * N * sc.nTX;             // [2][B][nTY][nTX]
+  sc.corner = sc.T + (size_t)2 * B * sc.nTY * sc.nTX;      // [2][B][nTY][nTX]
+  return sc;
+}
+
+size_t sat_scratch_words(int B, int M, int N) {
+  size_t nTX = (M + SAT_TX - 1) / SAT_TX, nTY = (N + SAT_TY - 1) / SAT_TY;
+  return (size_t)2 * B * (nTY * (size_t)M + (size_t)N * nTX + 2 * nTY * nTX);
+}
+
+__device__ __forceinline__ void load_px4(const uint8_t *row, int x0, int M,
+                                         uint32_t (&v)[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = (x0 + q < M) ? (uint32_t)row[x0 + q] : 0u;
+}
+
+__global__ __launch_bounds__(64) void sat_totals(const uint8_t *__restrict__ f,
+                                                 int B, int M, int N, int f_pitch,
+                                                 uint32_t *__restrict__ scratch) {
+  SatScratch sc = sat_layout(scratch, B, M, N);
+  const int lane = threadIdx.x, J = blockIdx.x, I = blockIdx.y, b = blockIdx.z;
+  const int x0 = J * SAT_TX + 4 * lane;
+  const int y0 = I * SAT_TY;
+  const int rows = min(SAT_TY, N - y0);
+  const uint8_t *fb = f + (size_t)b * N * f_pitch;
+  uint32_t cs[4] = {0, 0, 0, 0}, cs2[4] = {0, 0, 0, 0};
+  const size_t plane_row = (size_t)B * N * sc.nTX;
+  for (int r = 0; r < rows; ++r) {
+    const int y = y0 + r;
+    uint32_t v[4];
+    load_px4(fb + (size_t)y * f_pitch, x0, M, v);
+    uint32_t rs = 0, rs2 = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cs[q] += v[q];
+      cs2[q] += v[q] * v[q];
+      rs += v[q];
+      rs2 += v[q] * v[q];
+    }
+    rs = wave_sum(rs);
+    rs2 = wave_sum(rs2);
+    if (lane == 0) {
+      const size_t o = ((size_t)b * N + y) * sc.nTX + J;
+      sc.rowT[o] = rs;
+      sc.rowT[plane_row + o] = rs2;
+    }
+  }
+  const size_t plane_col = (size_t)B * sc.nTY * M;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (x0 + q < M) {
+      const size_t o = ((size_t)b * sc.nTY + I) * M + x0 + q;
+      sc.colT[o] = cs[q];
+      sc.colT[plane_col + o] = cs2[q];
+    }
+  }
+  uint32_t tt = wave_sum(cs[0] + cs[1] + cs[2] + cs[3]);
+  uint32_t tt2 = wave_sum(cs2[0] + cs2[1] + cs2[2] + cs2[3]);
+  if (lane == 0) {
+    const size_t o = ((size_t)b * sc.nTY + I) * sc.nTX + J;
+    const size_t plane_t = (size_t)B * sc.nTY * sc.nTX;
+    sc.T[o] = tt;
+    sc.T[plane_t + o] = tt2;
+  }
+}
+
+// Carries: exclusive prefix over tile rows of the column totals, over tile
+// columns of the row totals, and the 2-D exclusive prefix of tile totals.
+__global__ __launch_bounds__(256) void sat_prefix(int B, int M, int N,
+                                                  uint32_t *__restrict__ scratch) {
+  SatScratch sc = sat_layout(scratch, B, M, N);
+  const long long job = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nA = (long long)B * M, nB = (long long)B * N, nC = (long long)B * sc.nTX;
+  if (job < nA) {
+    const int b = (int)(job / M), x = (int)(job % M);
+    const size_t plane = (size_t)B * sc.nTY * M;
+    for (int p = 0; p < 2; ++p) {
+      uint32_t run = 0;
+      for (int I = 0; I < sc.nTY; ++I) {
+        const size_t o = p * plane + ((size_t)b * sc.nTY + I) * M + x;
+        const uint32_t t = sc.colT[o];
+        sc.colT[o] = run;
+        run += t;
+      }
+    }
+  } else if (job < nA + nB) {
+    const long long j = job - nA;
+    const int b = (int)(j / N), y = (int)(j % N);
+    const size_t plane = (size_t)B * N * sc.nTX;
+    for (int p = 0; p < 2; ++p) {
+      uint32_t run = 0;
+      for (int J = 0; J < sc.nTX; ++J) {
+        const size_t o = p * plane + ((size_t)b * N + y) * sc.nTX + J;
+        const uint32_t t = sc.rowT[o];
+        sc.rowT[o] = run;
+        run += t;
+      }
+    }
+  } else if (job < nA + nB + nC) {
+    const long long j = job - nA - nB;
+    const int b = (int)(j / sc.nTX), J = (int)(j % sc.nTX);
+    const size_t plane = (size_t)B * sc.nTY * sc.nTX;
+    for (int p = 0; p < 2; ++p) {
+      uint32_t acc = 0;
+      for (int I = 0; I < sc.nTY; ++I) {
+        const size_t row = p * plane + ((size_t)b * sc.nTY + I) * sc.nTX;
+        sc.corner[row + J] = acc;
+        for (int Jp = 0; Jp < J; ++Jp) acc += sc.T[row + Jp];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void sat_scan(const uint8_t *__restrict__ f,
+                                               int B, int M, int N, int f_pitch,
+                                               const uint32_t *__restrict__ scratch,
+                                               uint32_t *__restrict__ s,
+                                               uint32_t *__restrict__ s2,
+                                               int P) {
+  SatScratch sc = sat_layout(const_cast<uint32_t *>(scratch), B, M, N);
+  const int lane = threadIdx.x, J = blockIdx.x, I = blockIdx.y, b = blockIdx.z;
+  const int x0 = J * SAT_TX + 4 * lane;
+  const int y0 = I * SAT_TY;
+  const int rows = min(SAT_TY, N - y0);
+  const uint8_t *fb = f + (size_t)b * N * f_pitch;
+  uint32_t *sb = s + (size_t)b * (N + 1) * P;
+  uint32_t *s2b = s2 + (size_t)b * (N + 1) * P;
+
+  // running column sums start at the sum of all rows above the tile
+  uint32_t cs[4], cs2[4];
+  const size_t plane_col = (size_t)B * sc.nTY * M;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const size_t o = ((size_t)b * sc.nTY + I) * M + x0 + q;
+    cs[q] = (x0 + q < M) ? sc.colT[o] : 0u;
+    cs2[q] = (x0 + q < M) ? sc.colT[plane_col + o] : 0u;
+  }
+  // left carry of row y0 + r (held by lane r): tile corner + rows' left sums
+  const size_t plane_row = (size_t)B * N * sc.nTX;
+  uint32_t rl = 0, rl2 = 0;
+  if (lane < rows) {
+    const size_t o = ((size_t)b * N + y0 + lane) * sc.nTX + J;
+    rl = sc.rowT[o];
+    rl2 = sc.rowT[plane_row + o];
+  }
+  const size_t oc = ((size_t)b * sc.nTY + I) * sc.nTX + J;
+  const size_t plane_t = (size_t)B * sc.nTY * sc.nTX;
+  const uint32_t L = sc.corner[oc] + wave_incl_scan(rl);
+  const uint32_t L2 = sc.corner[plane_t + oc] + wave_incl_scan(rl2);
+
+  for (int r = 0; r < rows; ++r) {
+    const int y = y0 + r;
+    uint32_t v[4];
+    load_px4(fb + (size_t)y * f_pitch, x0, M, v);
+    uint32_t p[4], p2[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cs[q] += v[q];
+      cs2[q] += v[q] * v[q];
+      p[q] = (q ? p[q - 1] : 0u) + cs[q];
+      p2[q] = (q ? p2[q - 1] : 0u) + cs2[q];
+    }
+    const uint32_t ex = wave_incl_scan(p[3]) - p[3];
+    const uint32_t ex2 = wave_incl_scan(p2[3]) - p2[3];
+    const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)L, r) + ex;
+    const uint32_t base2 = (uint32_t)__builtin_amdgcn_readlane((int)L2, r) + ex2;
+    uint32_t *o = sb + (size_t)(y + 1) * P + 1;
+    uint32_t *o2 = s2b + (size_t)(y + 1) * P + 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (x0 + q < M) {
+        o[x0 + q] = base + p[q];
+        o2[x0 + q] = base2 + p2[q];
+      }
+    }
+    if (J == 0 && lane == 0) {  // padded column 0
+      sb[(size_t)(y + 1) * P] = 0;
+      s2b[(size_t)(y + 1) * P] = 0;
+    }
+    if (J == sc.nTX - 1) {  // padding columns M+1 .. P-1
+      for (int c = M + 1 + lane; c < P; c += 64) {
+        sb[(size_t)(y + 1) * P + c] = 0;
+        s2b[(size_t)(y + 1) * P + c] = 0;
+      }
+    }
+  }
+  if (I == 0) {  // padded row 0
+    for (int c = J * SAT_TX + lane; c < (J + 1) * SAT_TX + (J == sc.nTX - 1 ? P : 0) && c < P;
+         c += 64) {
+      sb[c] = 0;
+      s2b[c] = 0;
+    }
+  }
+}
+
+int launch_sat(const uint8_t *f, int B, int M, int N, int f_pitch, uint32_t *s,
+               uint32_t *s2, int sat_pitch, uint32_t *scratch, hipStream_t st) {
+  const int nTX = (M + SAT_TX - 1) / SAT_TX, nTY = (N + SAT_TY - 1) / SAT_TY;
+  dim3 grid(nTX, nTY, B);
+  hipLaunchKernelGGL(sat_totals, grid, dim3(64), 0, st, f, B, M, N, f_pitch, scratch);
+  const long long jobs = (long long)B * M + (long long)B * N + (long long)B * nTX;
+  hipLaunchKernelGGL(sat_prefix, dim3((unsigned)((jobs + 255) / 256)), dim3(256), 0, st,
+                     B, M, N, scratch);
+  hipLaunchKernelGGL(sat_scan, grid, dim3(64), 0, st, f, B, M, N, f_pitch, scratch, s,
+                     s2, sat_pitch);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ------------------------------------------------------------ tile scoring
+template <int LP, int NW>
+__device__ __forceinline__ void stage_pass(const uint32_t *__restrict__ sat, int P, int N,
+                                           const Interval *__restrict__ ivs, int iv_begin,
+                                           int iv_end, int u0, int v0, int stage_w4,
+                                           uint32_t *lds, int wave, int lane) {
+  for (int iv = iv_begin; iv < iv_end; ++iv) {
+    const Interval I = ivs[iv];
+    for (int j = wave; j < I.n_rows; j += NW) {
+      const int sr = v0 + I.rel_row + j;
+      uint4 *dst = reinterpret_cast<uint4 *>(lds + (I.lds_row + j) * LP);
+      if (sr <= N) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(sat + (long long)sr * P + u0);
+        for (int c4 = lane; c4 < stage_w4; c4 += 64)
+          dst[c4] = (u0 + 4 * c4 + 3 < P) ? src[c4] : make_uint4(0, 0, 0, 0);
+      } else {
+        for (int c4 = lane; c4 < stage_w4; c4 += 64) dst[c4] = make_uint4(0, 0, 0, 0);
+      }
+    }
+  }
+}
+
+template <int RU, int RV, int NW, int LP, bool MAP>
+__device__ __forceinline__ void run_item(
+    const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
+    int P, int N, const PassDesc *__restrict__ passes, const Interval *__restrict__ ivs,
+    const TileRec *__restrict__ recs, const WorkItem &it, const PairDesc &pd,
+    const DevTmpl &td, u64 &lkey, int k, float *__restrict__ rho_out, int rho_pitch,
+    uint8_t *__restrict__ degen, uint32_t *lds, int wave, int lane) {
+  constexpr int BU = 64 * RU, BV = NW * RV, R = RU * RV;
+  const uint32_t *S = s + (long long)pd.frame * frame_stride;
+  const uint32_t *S2 = s2 + (long long)pd.frame * frame_stride;
+  const int W = td.W, H = td.H, n = td.n;
+  const float inv_n = 1.0f / (float)n;
+  const double q_k = td.q_k;
+  const int stage_w4 = (BU + W + 1 + 3) >> 2;
+  const int lbase = wave * RV * LP + lane;
+
+  for (int tile = it.tile_begin; tile < it.tile_end; ++tile) {
+    const int tv = tile / pd.ntu, tu = tile - tv * pd.ntu;
+    const int u0 = tu * BU, v0 = tv * BV;
+
+    // window sums (Eqs. (13), (15)) and the integer bias per offset
+    uint32_t sf[R], sf2[R];
+    int nb[R];
+    float acc[R], cmp[R];
+#pragma unroll
+    for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+      for (int du = 0; du < RU; ++du) {
+        const int r = dv * RU + du;
+        const int u = u0 + lane + 64 * du, v = v0 + wave * RV + dv;
+        sf[r] = 0;
+        sf2[r] = 0;
+        if (u < pd.nu && v < pd.nv) {
+          const uint32_t *a0 = S + (long long)v * P + u;
+          const uint32_t *a1 = a0 + (long long)H * P;
+          sf[r] = (a1[W] - a1[0]) - (a0[W] - a0[0]);
+          const uint32_t *b0 = S2 + (long long)v * P + u;
+          const uint32_t *b1 = b0 + (long long)H * P;
+          sf2[r] = (b1[W] - b1[0]) - (b0[W] - b0[0]);
+        }
+        nb[r] = -(int)__builtin_rintf((float)sf[r] * inv_n);
+        acc[r] = 0.f;
+        cmp[r] = 0.f;
+      }
+
+    // per-segment terms (Eqs. (11), (12)), pass by pass
+    for (int p = td.pass_begin; p < td.pass_end; ++p) {
+      const PassDesc ps = passes[p];
+      __syncthreads();
+      stage_pass<LP, NW>(S, P, N, ivs, ps.iv_begin, ps.iv_end, u0, v0, stage_w4, lds, wave,
+                         lane);
+      __syncthreads();
+      const TileRec *rp = recs + ps.seg_begin;
+      const int nseg = ps.seg_end - ps.seg_begin;
+#pragma unroll 2
+      for (int i = 0; i < nseg; ++i) {
+        const TileRec rec = rp[i];
+        const uint32_t wa = (uint32_t)rec.w_area;
+        const int w = (int)(wa & 0xfffu);
+        const int A = (int)(wa >> 12);
+        const float c = rec.c;
+        const uint32_t *tl = lds + lbase + rec.off_tl;
+        const uint32_t *bl = lds + lbase + rec.off_bl;
+        const uint32_t *tr = tl + w;
+        const uint32_t *br = bl + w;
+#pragma unroll
+        for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+          for (int du = 0; du < RU; ++du) {
+            const int o = dv * LP + du * 64;
+            const int r = dv * RU + du;
+            const uint32_t F = (br[o] - bl[o]) - (tr[o] - tl[o]);
+            const int G = (int)F + __mul24(A, nb[r]);
+            const float y = __builtin_fmaf((float)G, c, -cmp[r]);
+            const float t = acc[r] + y;
+            cmp[r] = (t - acc[r]) - y;
+            acc[r] = t;
+          }
+      }
+    }
+
+    // epilogue: exact window energy (Eq. (16) x n), rho (Eqs. (17), (18))
+    u64 cand[R];
+#pragma unroll
+    for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+      for (int du = 0; du < RU; ++du) {
+        const int r = dv * RU + du;
+        const int u = u0 + lane + 64 * du, v = v0 + wave * RV + dv;
+        cand[r] = 0;
+        if (u < pd.nu && v < pd.nv) {
+          const long long V = (long long)((u64)(uint32_t)n * sf2[r] - (u64)sf[r] * sf[r]);
+          const double num = (double)acc[r] - (double)cmp[r];
+          const double rho = V == 0 ? 0.0 : num / sqrt((double)V / (double)n * q_k);
+          if (MAP) {
+            rho_out[(long long)v * rho_pitch + u] = (float)rho;
+            if (degen) degen[(long long)v * rho_pitch + u] = V == 0 ? 1 : 0;
+          } else {
+            cand[r] = make_key((float)rho, v * pd.nu + u);
+          }
+        }
+      }
+    if (!MAP) topk_offer<R>(lkey, cand, k, lane);
+  }
+}
+
+template <int RU, int RV, int NW, bool MAP>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void tile_kernel(
+    const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
+    int P, int N, const DevTmpl *__restrict__ tmpls, const PassDesc *__restrict__ passes,
+    const Interval *__restrict__ ivs, const TileRec *__restrict__ recs,
+    const PairDesc *__restrict__ pairs, const WorkItem *__restrict__ items,
+    const int *__restrict__ order, int n_items, int *__restrict__ queue, int k,
+    u64 *__restrict__ partial, float *__restrict__ rho_out, int rho_pitch,
+    uint8_t *__restrict__ degen) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ int item_sh;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = atomicAdd(queue, 1);
+    __syncthreads();
+    const int q = item_sh;
+    __syncthreads();
+    if (q >= n_items) break;
+    const int item = order[q];
+    const WorkItem it = items[item];
+    const PairDesc pd = pairs[it.pair];
+    const DevTmpl td = tmpls[pd.tmpl];
+    u64 lkey = 0;
+#define SNCC_RUN(LPV)                                                                    \
+  run_item<RU, RV, NW, LPV, MAP>(s, s2, frame_stride, P, N, passes, ivs, recs, it, pd, td, \
+                                 lkey, k, rho_out, rho_pitch, degen, lds, wave, lane)
+    switch (td.lp_class) {
+      case 0: SNCC_RUN(192); break;
+      case 1: SNCC_RUN(256); break;
+      case 2: SNCC_RUN(320); break;
+      case 3: SNCC_RUN(384); break;
+      case 4: SNCC_RUN(448); break;
+      default: SNCC_RUN(576); break;
+    }
+#undef SNCC_RUN
+    if (!MAP) {
+      // merge the waves' lists into wave 0's and write the item's partial
+      u64 *buf = reinterpret_cast<u64 *>(lds);
+      __syncthreads();
+      if (lane < k) buf[wave * k + lane] = lkey;
+      __syncthreads();
+      if (wave == 0) {
+        u64 thr = shfl_u64(lkey, k - 1);
+        for (int w = 1; w < NW; ++w) {
+          for (int j = 0; j < k; ++j) {
+            const u64 key = buf[w * k + j];
+            if (key <= thr) break;
+            topk_insert(lkey, key, k, lane);
+            thr = shfl_u64(lkey, k - 1);
+          }
+        }
+        if (lane < k) partial[(long long)item * k + lane] = lkey;
+      }
+    }
+  }
+}
+
+struct TileEntry {
+  TileCfg cfg;
+  const void *fn_map;
+  const void *fn_topk;
+};
+
+#define SNCC_TILE_ENTRY(RU, RV, NW)                                                   \
+  TileEntry {                                                                         \
+    TileCfg{RU, RV, NW}, reinterpret_cast<const void *>(&tile_kernel<RU, RV, NW, true>), \
+        reinterpret_cast<const void *>(&tile_kernel<RU, RV, NW, false>)                 \
+  }
+
+static const TileEntry kTileEntries[] = {
+    SNCC_TILE_ENTRY(2, 4, 8),
+    SNCC_TILE_ENTRY(2, 4, 4),
+    SNCC_TILE_ENTRY(1, 8, 8),
+    SNCC_TILE_ENTRY(2, 2, 8),
+};
+static const int kNumTileEntries = sizeof(kTileEntries) / sizeof(kTileEntries[0]);
+
+int tile_cfg_count() { return kNumTileEntries; }
+
+int tile_occupancy(int cfg, bool map_sink, int lds_bytes) {
+  if (cfg < 0 || cfg >= kNumTileEntries) return 0;
+  const TileEntry &e = kTileEntries[cfg];
+  const void *fn = map_sink ? e.fn_map : e.fn_topk;
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, tile_max_lds() - 64);
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, e.cfg.threads(),
+                                                   (size_t)lds_bytes) != hipSuccess)
+    return 0;
+  return blocks;
+}
+TileCfg tile_cfg(int i) { return kTileEntries[i].cfg; }
+int tile_max_lds() { return 160 * 1024; }
+
+int launch_tile(int cfg, bool map_sink, const TileArgs &a, int grid, int lds_bytes,
+                hipStream_t st) {
+  if (cfg < 0 || cfg >= kNumTileEntries) return -1;
+  const TileEntry &e = kTileEntries[cfg];
+  const void *fn = map_sink ? e.fn_map : e.fn_topk;
+  static bool attr_done[2][16] = {};
+  if (!attr_done[map_sink][cfg]) {
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            tile_max_lds() - 64) != hipSuccess)
+      return -1;
+    attr_done[map_sink][cfg] = true;
+  }
+  long long fs = a.frame_stride;
+  int P = a.sat_pitch, N = a.N, n_items = a.n_items, k = a.k, rp = a.rho_pitch;
+  const uint32_t *s = a.s, *s2 = a.s2;
+  const DevTmpl *tm = a.tmpls;
+  const PassDesc *ps = a.passes;
+  const Interval *iv = a.ivs;
+  const TileRec *rc = a.recs;
+  const PairDesc *pr = a.pairs;
+  const WorkItem *it = a.items;
+  const int *ord = a.order;
+  int *queue = a.queue;
+  u64 *partial = a.partial;
+  float *rho = static_cast<float *>(a.rho);
+  uint8_t *dg = a.degen;
+  void *args[] = {&s,  &s2, &fs, &P,  &N,     &tm,      &ps,  &iv,  &rc,  &pr,
+                  &it, &ord, &n_items, &queue, &k, &partial, &rho, &rp, &dg};
+  hipError_t err = hipLaunchKernel(fn, dim3(grid), dim3(e.cfg.threads()), args,
+                                   (size_t)lds_bytes, st);
+  return err == hipSuccess ? 0 : -1;
+}
+
+// --------------------------------------------------------------- plain FP64
+// rho at one offset, segments read from global memory, FP64 accumulation of
+// box_i * c_i; Eq. (12)'s mean term is fbar * sum_i A_i c_i.
+__device__ __forceinline__ double rho_plain(const uint32_t *__restrict__ S,
+                                            const uint32_t *__restrict__ S2, int P, int u,
+                                            int v, int W, int H, int K, double q_k,
+                                            double r64, const int4 *__restrict__ geom,
+                                            const double *__restrict__ c64, bool &flat) {
+  const uint32_t *a0 = S + (long long)v * P + u;
+  const uint32_t *a1 = a0 + (long long)H * P;
+  const uint32_t sf = (a1[W] - a1[0]) - (a0[W] - a0[0]);
+  const uint32_t *b0 = S2 + (long long)v * P + u;
+  const uint32_t *b1 = b0 + (long long)H * P;
+  const uint32_t sf2 = (b1[W] - b1[0]) - (b0[W] - b0[0]);
+  const int n = W * H;
+  const long long V = (long long)((u64)(uint32_t)n * sf2 - (u64)sf * sf);
+  double acc = 0.0;
+  for (int i = 0; i < K; ++i) {
+    const int4 g = geom[i];  // x, y, width, height
+    const uint32_t *q0 = a0 + (long long)g.y * P + g.x;
+    const uint32_t *q2 = q0 + (long long)g.w * P;
+    const uint32_t F = (q2[g.z] - q2[0]) - (q0[g.z] - q0[0]);
+    acc = __builtin_fma((double)F, c64[i], acc);
+  }
+  flat = V == 0;
+  const double fbar = (double)sf / (double)n;
+  const double num = acc - fbar * r64;
+  return flat ? 0.0 : num / sqrt((double)V / (double)n * q_k);
+}
+
+__global__ __launch_bounds__(256) void plain_kernel(
+    const uint32_t *__restrict__ S, const uint32_t *__restrict__ S2, int P, int nu, int nv,
+    int W, int H, int K, double q_k, double r64, const int4 *__restrict__ geom,
+    const double *__restrict__ c64, double *__restrict__ rho, int rho_pitch,
+    uint8_t *__restrict__ degen) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int u = blockIdx.x * 64 + lane, v = blockIdx.y * 4 + wave;
+  if (u >= nu || v >= nv) return;
+  bool flat;
+  const double r = rho_plain(S, S2, P, u, v, W, H, K, q_k, r64, geom, c64, flat);
+  rho[(long long)v * rho_pitch + u] = r;
+  if (degen) degen[(long long)v * rho_pitch + u] = flat ? 1 : 0;
+}
+
+int launch_plain(const PlainArgs &a, hipStream_t st) {
+  dim3 grid((a.nu + 63) / 64, (a.nv + 3) / 4);
+  hipLaunchKernelGGL(plain_kernel, grid, dim3(256), 0, st, a.s, a.s2, a.sat_pitch, a.nu,
+                     a.nv, a.W, a.H, a.K, a.q_k, a.r64, a.geom, a.c64, a.rho, a.rho_pitch,
+                     a.degen);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ---------------------------------------------------------- small kernels
+__global__ void zero_kernel(int *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+int launch_zero(int *p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// One wave per pair: merges the pair's item partials into the final top-k.
+__global__ __launch_bounds__(256) void merge_kernel(const PairDesc *__restrict__ pairs,
+                                                    int n_pairs,
+                                                    const u64 *__restrict__ partial, int k,
+                                                    sncc_match *__restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (p >= n_pairs) return;
+  const PairDesc pd = pairs[p];
+  u64 lkey = 0, thr = 0;
+  for (int item = pd.item_begin; item < pd.item_end; ++item) {
+    const u64 mine = lane < k ? partial[(long long)item * k + lane] : 0;
+    for (int j = 0; j < k; ++j) {
+      const u64 key = shfl_u64(mine, j);
+      if (key <= thr) break;
+      topk_insert(lkey, key, k, lane);
+      thr = shfl_u64(lkey, k - 1);
+    }
+  }
+  if (lane < k) {
+    sncc_match m;
+    if (lkey == 0) {
+      m.u = -1;
+      m.v = -1;
+      m.rho = -__builtin_inff();
+    } else {
+      const int idx = (int)(0xffffffffu - (uint32_t)(lkey & 0xffffffffu));
+      m.v = idx / pd.nu;
+      m.u = idx - m.v * pd.nu;
+      m.rho = float_unorder((uint32_t)(lkey >> 32));
+    }
+    out[(long long)p * k + lane] = m;
+  }
+}
+
+int launch_merge(const PairDesc *pairs, int n_pairs, const u64 *partial, int k,
+                 sncc_match *out, hipStream_t st) {
+  hipLaunchKernelGGL(merge_kernel, dim3((n_pairs + 3) / 4), dim3(256), 0, st, pairs,
+                     n_pairs, partial, k, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Top-k over a double map, one chunk of `chunk` offsets per workgroup.
+__global__ __launch_bounds__(256) void map_topk_kernel(const double *__restrict__ map,
+                                                       int pitch, int nu, int nv, int chunk,
+                                                       int k, u64 *__restrict__ partial) {
+  __shared__ u64 buf[4 * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long total = (long long)nu * nv;
+  const long long c0 = (long long)blockIdx.x * chunk;
+  const long long c1 = min(total, c0 + chunk);
+  u64 lkey = 0;
+  for (long long e0 = c0 + wave * 64; e0 < c1; e0 += 4 * 256) {
+    u64 cand[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long long e = e0 + lane + 256 * q;
+      cand[q] = 0;
+      if (e < c1) {
+        const int v = (int)(e / nu), u = (int)(e - (long long)v * nu);
+        cand[q] = make_key((float)map[(long long)v * pitch + u], (int)e);
+      }
+    }
+    topk_offer<4>(lkey, cand, k, lane);
+  }
+  if (lane < k) buf[wave * k + lane] = lkey;
+  __syncthreads();
+  if (wave == 0) {
+    u64 thr = shfl_u64(lkey, k - 1);
+    for (int w = 1; w < 4; ++w)
+      for (int j = 0; j < k; ++j) {
+        const u64 key = buf[w * k + j];
+        if (key <= thr) break;
+        topk_insert(lkey, key, k, lane);
+        thr = shfl_u64(lkey, k - 1);
+      }
+    if (lane < k) partial[(long long)blockIdx.x * k + lane] = lkey;
+  }
+}
+
+int launch_map_topk(const double *map, int pitch, int nu, int nv, int chunk, int k,
+                    u64 *partial, hipStream_t st) {
+  const long long total = (long long)nu * nv;
+  const int blocks = (int)((total + chunk - 1) / chunk);
+  hipLaunchKernelGGL(map_topk_kernel, dim3(blocks), dim3(256), 0, st, map, pitch, nu, nv,
+                     chunk, k, partial);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ------------------------------------------------------------- FP64 refine
+constexpr int REFINE_CAP = 4096;
+
+__global__ __launch_bounds__(256) void refine_kernel(
+    const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
+    int P, const DevTmpl *__restrict__ tmpls, const int4 *__restrict__ geom,
+    const double *__restrict__ c64, const PairDesc *__restrict__ pairs,
+    const sncc_match *__restrict__ cand, int n_cand, int radius,
+    sncc_match64 *__restrict__ out, int *__restrict__ count) {
+  __shared__ int list[REFINE_CAP];
+  __shared__ int wsum[4];
+  __shared__ double best_r[4];
+  __shared__ int best_i[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int p = blockIdx.x;
+  const PairDesc pd = pairs[p];
+  const DevTmpl td = tmpls[pd.tmpl];
+  const int side = 2 * radius + 1, area = side * side;
+  const int total = n_cand * area;
+  int np = 1;
+  while (np < total) np <<= 1;
+  // candidate neighbourhoods, clipped; INT_MAX marks an empty slot
+  for (int e = tid; e < np; e += 256) {
+    int val = 0x7fffffff;
+    if (e < total) {
+      const int j = e / area, d = e - j * area;
+      const sncc_match c = cand[(long long)p * n_cand + j];
+      const int u = c.u + d % side - radius, v = c.v + d / side - radius;
+      if (c.u >= 0 && u >= 0 && u < pd.nu && v >= 0 && v < pd.nv) val = v * pd.nu + u;
+    }
+    list[e] = val;
+  }
+  __syncthreads();
+  // bitonic sort ascending
+  for (int size = 2; size <= np; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < np; i += 256) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const int a = list[i], b = list[j];
+          const bool up = (i & size) == 0;
+          if ((a > b) == up) {
+            list[i] = b;
+            list[j] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  // unique values: each thread owns a contiguous run of the sorted list
+  const int per = (np + 255) / 256;
+  const int r0 = min(np, tid * per), r1 = min(np, r0 + per);
+  int cnt = 0;
+  for (int i = r0; i < r1; ++i)
+    if (list[i] != 0x7fffffff && (i == 0 || list[i] != list[i - 1])) ++cnt;
+  const uint32_t incl = wave_incl_scan((uint32_t)cnt);
+  if (lane == 63) wsum[wave] = (int)incl;
+  __syncthreads();
+  int off = (int)incl - cnt;
+  for (int w = 0; w < wave; ++w) off += wsum[w];
+  const int L = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  // gather unique entries into registers before compacting in place
+  int mine[16];
+  int m = 0;
+  for (int i = r0; i < r1 && m < 16; ++i)
+    if (list[i] != 0x7fffffff && (i == 0 || list[i] != list[i - 1])) mine[m++] = list[i];
+  __syncthreads();
+  for (int q = 0; q < m; ++q) list[off + q] = mine[q];
+  __syncthreads();
+  // FP64 scores with the fine approximation
+  const uint32_t *S = s + (long long)pd.frame * frame_stride;
+  const uint32_t *S2 = s2 + (long long)pd.frame * frame_stride;
+  double br = -__builtin_inf();
+  int bi = 0x7fffffff;
+  for (int i = tid; i < L; i += 256) {
+    const int idx = list[i];
+    const int v = idx / pd.nu, u = idx - v * pd.nu;
+    bool flat;
+    const double r = rho_plain(S, S2, P, u, v, td.W, td.H, td.K, td.q_k, td.r64,
+                               geom + td.seg_off, c64 + td.seg_off, flat);
+    if (r > br || (r == br && idx < bi)) {
+      br = r;
+      bi = idx;
+    }
+  }
+  for (int msk = 32; msk >= 1; msk >>= 1) {
+    const double orr = __shfl_xor(br, msk);
+    const int oi = __shfl_xor(bi, msk);
+    if (orr > br || (orr == br && oi < bi)) {
+      br = orr;
+      bi = oi;
+    }
+  }
+  if (lane == 0) {
+    best_r[wave] = br;
+    best_i[wave] = bi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 4; ++w)
+      if (best_r[w] > br || (best_r[w] == br && best_i[w] < bi)) {
+        br = best_r[w];
+        bi = best_i[w];
+      }
+    sncc_match64 o;
+    if (L == 0) {
+      o.u = -1;
+      o.v = -1;
+      o.rho = -__builtin_inf();
+    } else {
+      o.v = bi / pd.nu;
+      o.u = bi - o.v * pd.nu;
+      o.rho = br;
+    }
+    out[p] = o;
+    if (count) count[p] = L;
+  }
+}
+
+int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride, int P,
+                  const DevTmpl *tmpls, const int4 *geom, const double *c64, const int *area,
+                  const PairDesc *pairs, int n_pairs, const sncc_match *cand, int n_cand,
+                  int radius, sncc_match64 *out, int *count, hipStream_t st) {
+  (void)area;
+  if (n_cand * (2 * radius + 1) * (2 * radius + 1) > REFINE_CAP) return -1;
+  hipLaunchKernelGGL(refine_kernel, dim3(n_pairs), dim3(256), 0, st, s, s2, frame_stride,
+                     P, tmpls, geom, c64, pairs, cand, n_cand, radius, out, count);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace sncc

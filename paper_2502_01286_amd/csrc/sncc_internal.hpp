@@ -1,0 +1,149 @@
+// Internal structures shared by the host planner and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/sncc.h"
+
+namespace sncc {
+
+// ---------------------------------------------------------------- host side
+struct Seg {
+  int x, y, w, h;
+  int64_t sum;
+  int64_t area;
+};
+
+bool std_below(int64_t S, int64_t S2, int64_t A, double sigma);
+void merge_segments(std::vector<Seg> &k);
+int segment_template(const uint8_t *t, int W, int H, int stride, double sigma,
+                     int K_max, std::vector<Seg> &out, int *k_before_merge,
+                     double *sigma_used, double *rho_max);
+
+void set_error(const char *fmt, ...);
+
+// ------------------------------------------------- device-visible records
+// Per template constants (Section 5, steps 3-4).
+struct DevTmpl {
+  int W, H, K, n;      // n = W * H
+  double q_k;          // sum_i A_i c_i^2 (area-weighted Eq. (17))
+  double r64;          // sum_i A_i c_i in FP64 (zero up to rounding)
+  int seg_off;         // first segment in the generic arrays
+  int lp_class;        // LDS pitch class of the tile kernel
+  int pass_begin;      // tile plan: passes of this template
+  int pass_end;
+};
+
+// One segment for the tile kernel: LDS dword offsets of its top-left and
+// bottom-left corners relative to the lane's base, width | area << 12, c_i.
+struct TileRec {
+  int off_tl;
+  int off_bl;
+  int w_area;
+  float c;
+};
+
+// Rows [rel_row, rel_row + n_rows) of the window (template-relative,
+// zero-padded table coordinates) staged to LDS rows starting at lds_row.
+struct Interval {
+  int rel_row, n_rows, lds_row, pad;
+};
+
+struct PassDesc {
+  int seg_begin, seg_end;  // TileRec range
+  int iv_begin, iv_end;    // Interval range
+};
+
+struct PairDesc {
+  int frame, tmpl;
+  int nu, nv;              // offsets along u and v
+  int ntu, ntv;            // tiles along u and v
+  int item_begin, item_end;
+};
+
+struct WorkItem {
+  int pair;
+  int tile_begin, tile_end;
+  int pad;
+};
+
+// Kernel arguments of the persistent tile kernel.
+struct TileArgs {
+  const uint32_t *s;
+  const uint32_t *s2;
+  long long frame_stride;  // elements between frames of the sum tables
+  int sat_pitch;
+  int M, N;
+  const DevTmpl *tmpls;
+  const PassDesc *passes;
+  const Interval *ivs;
+  const TileRec *recs;
+  const PairDesc *pairs;
+  const WorkItem *items;
+  const int *order;        // execution order of items
+  int n_items;
+  int *queue;              // work counter, zero at launch
+  int k;                   // top-k (TOPK sink)
+  unsigned long long *partial;  // n_items x k keys (TOPK sink)
+  void *rho;               // MAP sink: float map
+  int rho_pitch;
+  uint8_t *degen;          // MAP sink: nullable
+};
+
+// Kernel arguments of the plain FP64 per-pair kernel.
+struct PlainArgs {
+  const uint32_t *s;
+  const uint32_t *s2;
+  int sat_pitch;
+  int nu, nv;
+  int W, H, K;
+  double q_k, r64;
+  const int4 *geom;        // x, y, w, h
+  const double *c64;
+  const int *area;
+  double *rho;
+  int rho_pitch;
+  uint8_t *degen;
+};
+
+// Tile kernel configuration: offsets per lane RU (u, stride 64) x RV (v),
+// NW waves per workgroup, each wave owning RV offset rows.
+struct TileCfg {
+  int ru, rv, nw;
+  int bu() const { return 64 * ru; }
+  int bv() const { return nw * rv; }
+  int threads() const { return 64 * nw; }
+};
+
+constexpr int kNumLpClasses = 6;
+constexpr int kLpClasses[kNumLpClasses] = {192, 256, 320, 384, 448, 576};
+
+// Launch wrappers (kernels.hip).
+int launch_sat(const uint8_t *f, int B, int M, int N, int f_pitch, uint32_t *s,
+               uint32_t *s2, int sat_pitch, uint32_t *scratch, hipStream_t st);
+size_t sat_scratch_words(int B, int M, int N);
+
+int tile_cfg_count();
+TileCfg tile_cfg(int i);
+int launch_tile(int cfg, bool map_sink, const TileArgs &a, int grid,
+                int lds_bytes, hipStream_t st);
+int tile_max_lds();
+int tile_occupancy(int cfg, bool map_sink, int lds_bytes);
+int launch_plain(const PlainArgs &a, hipStream_t st);
+int launch_zero(int *p, int n, hipStream_t st);
+int launch_merge(const PairDesc *pairs, int n_pairs,
+                 const unsigned long long *partial, int k,
+                 sncc_match *out, hipStream_t st);
+int launch_map_topk(const double *map, int pitch, int nu, int nv, int chunk,
+                    int k, unsigned long long *partial, hipStream_t st);
+int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride,
+                  int sat_pitch, const DevTmpl *tmpls, const int4 *geom,
+                  const double *c64, const int *area, const PairDesc *pairs,
+                  int n_pairs, const sncc_match *cand, int n_cand, int radius,
+                  sncc_match64 *out, int *count, hipStream_t st);
+
+}  // namespace sncc

@@ -1,0 +1,335 @@
+"""HIP path against the oracle, element by element (MI355X).
+
+Tolerances: sum tables, window sums and window energies are bit-exact
+(integer work); FP32-compensated rho within 1e-5 (the bound the matching
+method is held to); FP64 rho within 1e-9 (FP64 rounding of a sum of at most
+a few thousand terms, each bounded by the NCC denominator, stays orders of
+magnitude below this).  Argmax positions must match wherever the oracle's
+top-2 margin exceeds 1e-4.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import synth
+
+from gpu_util import build_sats, lib_templates, oracle_templates, topk_ok
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL64 = 1e-9
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_2502_01286_amd as S
+    return S
+
+
+@pytest.fixture(scope="module")
+def ctx(S):
+    import torch
+    torch.cuda.init()
+    c = S.sncc_ctx_create(0)
+    yield c
+    S.sncc_ctx_destroy(c)
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+# ------------------------------------------------------------------ tables
+@pytest.mark.parametrize("shape", [(3, 37, 29), (2, 130, 301), (1, 64, 256), (1, 1, 1),
+                                   (2, 300, 517)])
+def test_sat_bit_exact(S, ctx, shape):
+    B, N, M = shape
+    rng = np.random.default_rng(B * 1000 + N + M)
+    frames = [rng.integers(0, 256, (N, M)).astype(np.uint8) for _ in range(B)]
+    print("case", shape, flush=True)
+    _, s, s2 = build_sats(S, ctx, frames)
+    S.sncc_sync(ctx)
+    P = s.shape[-1]
+    gs, gs2 = _u32(s), _u32(s2)
+    for b in range(B):
+        os_, os2 = O.sum_tables(frames[b])
+        want = np.zeros((N + 1, P), np.uint64)
+        want[:, :M + 1] = os_ % (1 << 32)
+        assert (gs[b].astype(np.uint64) == want).all()
+        want[:, :M + 1] = os2 % (1 << 32)
+        assert (gs2[b].astype(np.uint64) == want).all()
+
+
+def test_sat_wraps_modulo_2_32_and_windows_stay_exact(S, ctx):
+    # all-255 frame: s^2 exceeds 2^32 many times over; 256x256 windows of f^2
+    # (the largest template of the workloads) are still exact
+    N, M = 700, 900
+    f = np.full((N, M), 255, np.uint8)
+    f[::7, ::5] = 3
+    _, s, s2 = build_sats(S, ctx, [f])
+    S.sncc_sync(ctx)
+    gs, gs2 = _u32(s)[0].astype(np.int64), _u32(s2)[0].astype(np.int64)
+    os_, os2 = O.sum_tables(f)
+    assert (gs[:, :M + 1] == os_ % (1 << 32)).all()
+    assert (gs2[:, :M + 1] == os2 % (1 << 32)).all()
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        u, v = int(rng.integers(0, M - 256 + 1)), int(rng.integers(0, N - 256 + 1))
+        box = lambda t: (t[v + 256, u + 256] - t[v + 256, u] - t[v, u + 256] + t[v, u]) % (1 << 32)
+        sf, sf2, V = O.window_sums(os_, os2, 256, 256, u, v)
+        assert box(gs) == sf and box(gs2) == sf2
+        assert sf2 < (1 << 32)
+
+
+# ------------------------------------------------------------------- maps
+def _case(seed, M, N, W, H, sigma, flat_region=False):
+    f = synth.scene(seed, M, N)
+    if flat_region:
+        f[10:10 + H + 20, 20:20 + W + 30] = 77          # uniform windows
+    rng = np.random.default_rng(seed + 1)
+    t, x, y = synth.crop_template(rng, f, W, H, sigma_max=sigma)
+    return f, t
+
+
+MAP_CASES = [
+    # seed, M, N, W, H, sigma
+    (1, 200, 150, 17, 13, 8),
+    (2, 203, 131, 32, 32, 4),
+    (3, 260, 170, 64, 40, 16),
+    (4, 96, 80, 96, 80, 8),      # template = image: one offset
+    (5, 300, 90, 7, 60, 4),
+    (6, 400, 300, 150, 150, 4),  # several LDS passes
+    (7, 333, 222, 200, 31, 12),
+]
+
+
+@pytest.mark.parametrize("case", MAP_CASES)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_map_parity(S, ctx, case, precision):
+    import torch
+    seed, M, N, W, H, sigma = case
+    print("case", case, precision, flush=True)
+    f, t = _case(seed, M, N, W, H, sigma, flat_region=(seed == 1))
+    _, s, s2 = build_sats(S, ctx, [f])
+    tm = lib_templates(S, ctx, [t], [sigma])
+    nu, nv = M - W + 1, N - H + 1
+    prec = S.SNCC_FP64 if precision == "fp64" else S.SNCC_FP32_KAHAN
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    pitch = nu + 3
+    rho = torch.full((nv, pitch), float("nan"), dtype=dt, device="cuda")
+    deg = torch.full((nv, pitch), 7, dtype=torch.uint8, device="cuda")
+    S.sncc_score(ctx, tm, 0, s, s2, M, N, prec, rho, deg)
+    S.sncc_sync(ctx)
+    got = rho.cpu().numpy()[:, :nu].astype(np.float64)
+    gdeg = deg.cpu().numpy()[:, :nu]
+    ta = oracle_templates([t], [sigma])[0]
+    want, flat = O.rho_map(f, ta, return_flag=True)
+    tol = TOL64 if precision == "fp64" else TOL32
+    err = np.abs(got - want)
+    assert np.isfinite(got).all()
+    assert err.max() <= tol, (err.max(), np.unravel_index(err.argmax(), err.shape))
+    assert (gdeg == flat.astype(np.uint8)).all()
+    assert (rho.cpu().numpy()[:, nu:] != rho.cpu().numpy()[:, nu:]).all()  # pad untouched
+    if O.top2_margin(want) > 1e-4:
+        gi = np.unravel_index(np.argmax(got), got.shape)
+        assert O.argmax(want)[:2] == (gi[1], gi[0])
+    S.sncc_tmpl_destroy(tm)
+
+
+def test_fp32_map_deterministic(S, ctx):
+    import torch
+    f, t = _case(11, 300, 200, 48, 40, 4)
+    _, s, s2 = build_sats(S, ctx, [f])
+    tm = lib_templates(S, ctx, [t], [4])
+    nu, nv = 300 - 48 + 1, 200 - 40 + 1
+    a = torch.empty((nv, nu), dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    S.sncc_score(ctx, tm, 0, s, s2, 300, 200, S.SNCC_FP32_KAHAN, a)
+    S.sncc_score(ctx, tm, 0, s, s2, 300, 200, S.SNCC_FP32_KAHAN, b)
+    S.sncc_sync(ctx)
+    assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+# ------------------------------------------------------------------- top-k
+def _multi(seed, B=3, M=240, N=180, sides=((24, 30), (40, 33), (17, 64), (64, 20)),
+           sigmas=(16, 8, 4, 12)):
+    frames = [synth.scene(seed + i, M, N) for i in range(B)]
+    rng = np.random.default_rng(seed)
+    temps = []
+    for (W, H), sg in zip(sides, sigmas):
+        fi = int(rng.integers(0, B))
+        t, _, _ = synth.crop_template(rng, frames[fi], W, H, sigma_max=sg)
+        temps.append(t)
+    pairs = [(b, t) for b in range(B) for t in range(len(temps))]
+    return frames, temps, list(sigmas), pairs
+
+
+@pytest.mark.parametrize("k", [1, 5, 32, 64])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_topk_parity(S, ctx, k, precision):
+    import torch
+    frames, temps, sigmas, pairs = _multi(50 + k)
+    B, N, M = len(frames), frames[0].shape[0], frames[0].shape[1]
+    print("case k", k, precision, flush=True)
+    _, s, s2 = build_sats(S, ctx, frames)
+    tm = lib_templates(S, ctx, temps, sigmas)
+    out = torch.zeros((len(pairs), k, 3), dtype=torch.int32, device="cuda")
+    prec = S.SNCC_FP64 if precision == "fp64" else S.SNCC_FP32_KAHAN
+    S.sncc_topk(ctx, tm, s, s2, B, M, N, pairs, k, prec, out)
+    S.sncc_sync(ctx)
+    got = S.decode_matches(out)
+    tas = oracle_templates(temps, sigmas)
+    tables = [O.sum_tables(f) for f in frames]
+    for p, (b, ti) in enumerate(pairs):
+        want_map = O.rho_map(frames[b], tas[ti], tables=tables[b])
+        errs = topk_ok(want_map, got[p], k, TOL32)
+        assert not errs, (p, errs[:5])
+
+
+def test_topk_more_slots_than_offsets(S, ctx):
+    import torch
+    f = synth.scene(9, 40, 30)
+    rng = np.random.default_rng(2)
+    t, _, _ = synth.crop_template(rng, f, 36, 27, sigma_max=4)
+    _, s, s2 = build_sats(S, ctx, [f])
+    tm = lib_templates(S, ctx, [t], [4])
+    out = torch.zeros((1, 32, 3), dtype=torch.int32, device="cuda")
+    S.sncc_topk(ctx, tm, s, s2, 1, 40, 30, [(0, 0)], 32, S.SNCC_FP32_KAHAN, out)
+    S.sncc_sync(ctx)
+    got = S.decode_matches(out)[0]
+    n_off = (40 - 36 + 1) * (30 - 27 + 1)
+    assert (got["u"][:n_off] >= 0).all()
+    assert (got["u"][n_off:] == -1).all() and np.isneginf(got["rho"][n_off:]).all()
+    want = O.rho_map(f, oracle_templates([t], [4])[0])
+    assert not topk_ok(want, got, n_off, TOL32)
+
+
+# ------------------------------------------------------------------ refine
+def test_refine_parity(S, ctx):
+    import torch
+    frames, temps, _, pairs = _multi(70, sigmas=(16, 16, 16, 16))
+    B, N, M = len(frames), frames[0].shape[0], frames[0].shape[1]
+    coarse_s, fine_s = [16] * len(temps), [4] * len(temps)
+    _, s, s2 = build_sats(S, ctx, frames)
+    fine = lib_templates(S, ctx, temps, fine_s)
+    tas_c = oracle_templates(temps, coarse_s)
+    tas_f = oracle_templates(temps, fine_s)
+    tables = [O.sum_tables(f) for f in frames]
+    k, radius = 8, 2
+    # candidates from the oracle's coarse pass, given to both sides as input
+    cand = np.zeros((len(pairs), k, 3), np.int32)
+    expected = []
+    for p, (b, ti) in enumerate(pairs):
+        res = O.coarse_fine(*tables[b], tas_c[ti], tas_f[ti], M, N, k=k, radius=radius)
+        for j, (u, v, r) in enumerate(res["coarse"]):
+            cand[p, j] = (u, v, np.float32(r).view(np.int32))
+        expected.append(res)
+    cand[0, k - 1] = (-1, -1, 0)          # an empty slot is ignored
+    expected[0] = O.coarse_fine(*tables[pairs[0][0]], tas_c[pairs[0][1]], tas_f[pairs[0][1]],
+                                M, N, k=k - 1, radius=radius)
+    dcand = torch.from_numpy(cand).cuda()
+    out = torch.zeros((len(pairs), 4), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(len(pairs), dtype=torch.int32, device="cuda")
+    S.sncc_refine(ctx, fine, s, s2, B, M, N, pairs, dcand, radius, out, cnt)
+    S.sncc_sync(ctx)
+    got = S.decode_matches64(out)
+    counts = cnt.cpu().numpy()
+    for p in range(len(pairs)):
+        res = expected[p]
+        assert counts[p] == len(res["fine_u"])
+        assert (int(got[p]["u"]), int(got[p]["v"])) == res["best"][:2], p
+        assert abs(float(got[p]["rho"]) - res["best"][2]) <= TOL64
+
+
+# ------------------------------------------------------------------ batches
+def test_batch_graph_parity_and_replays(S, ctx):
+    import torch
+    frames, temps, _, pairs = _multi(90, B=4, M=320, N=200,
+                                     sides=((24, 24), (40, 30), (64, 48), (33, 70), (90, 41)),
+                                     sigmas=(16, 16, 16, 16, 16))
+    B, N, M = len(frames), frames[0].shape[0], frames[0].shape[1]
+    k, radius = 16, 2
+    f = torch.from_numpy(np.stack(frames)).cuda()
+    P = S.sncc_sat_pitch(M)
+    s = torch.zeros((B, N + 1, P), dtype=torch.int32, device="cuda")
+    s2 = torch.zeros_like(s)
+    coarse = lib_templates(S, ctx, temps, [16] * len(temps))
+    fine = lib_templates(S, ctx, temps, [4] * len(temps))
+    topk = torch.zeros((len(pairs), k, 3), dtype=torch.int32, device="cuda")
+    best = torch.zeros((len(pairs), 4), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(len(pairs), dtype=torch.int32, device="cuda")
+    batch = S.sncc_batch_create(ctx, coarse, s, s2, B, M, N, pairs, k, topk, fine=fine,
+                                radius=radius, best_out=best, count_out=cnt, frames=f)
+    tas_c = oracle_templates(temps, [16] * len(temps))
+    tas_f = oracle_templates(temps, [4] * len(temps))
+    tables = [O.sum_tables(fr) for fr in frames]
+    results = []
+    for rep in range(3):
+        topk.zero_()
+        best.zero_()
+        S.sncc_batch_run(batch)
+        S.sncc_sync(ctx)
+        results.append((topk.clone(), best.clone()))
+        _ = torch.randn(1000, device="cuda").sum().item()   # eager work between replays
+    for a, b in results[1:]:
+        assert torch.equal(a, results[0][0]) and torch.equal(b, results[0][1])
+    st = batch.stats()
+    assert st["coarse_evals"] > 0 and st["ms_total"] != 0
+    got = S.decode_matches(results[0][0])
+    gbest = S.decode_matches64(results[0][1])
+    for p, (b, ti) in enumerate(pairs):
+        cmap = O.rho_map(frames[b], tas_c[ti], tables=tables[b])
+        errs = topk_ok(cmap, got[p], k, TOL32)
+        assert not errs, (p, errs[:4])
+        want = O.topk(cmap, k + 1)
+        res = O.coarse_fine(*tables[b], tas_c[ti], tas_f[ti], M, N, k=k, radius=radius,
+                            coarse_map=cmap)
+        gu, gv, gr = int(gbest[p]["u"]), int(gbest[p]["v"]), float(gbest[p]["rho"])
+        # the fine score the GPU reports is the oracle's fine score there
+        assert abs(O.rho_at(*tables[b], tas_f[ti], gu, gv) - gr) <= TOL64
+        if want[k - 1][2] - want[k][2] > 2e-5:   # coarse candidate sets are unique
+            assert (gu, gv) == res["best"][:2], p
+    batch.destroy()
+    assert _u32(s)[0, 0, 0] == 0
+
+
+# ------------------------------------------------------------- edge cases
+def test_errors(S, ctx):
+    import torch
+    f = synth.scene(3, 50, 40)
+    _, s, s2 = build_sats(S, ctx, [f])
+    rng = np.random.default_rng(0)
+    t = rng.integers(0, 256, (10, 60)).astype(np.uint8)      # wider than the image
+    tm = lib_templates(S, ctx, [t], [8])
+    out = torch.zeros((1, 1, 3), dtype=torch.int32, device="cuda")
+    with pytest.raises(S.SnccError) as e:
+        S.sncc_topk(ctx, tm, s, s2, 1, 50, 40, [(0, 0)], 1, S.SNCC_FP32_KAHAN, out)
+    assert e.value.code == S.SNCC_EINVAL
+    with pytest.raises(S.SnccError) as e:
+        S.sncc_topk(ctx, tm, s, s2, 1, 50, 40, [(1, 0)], 1, S.SNCC_FP32_KAHAN, out)
+    assert e.value.code == S.SNCC_EINVAL
+    big = rng.integers(0, 256, (260, 260)).astype(np.uint8)   # area above the exact bound
+    segs, _, _ = S.sncc_segment_template(big, 40)
+    with pytest.raises(S.SnccError) as e:
+        S.sncc_upload_templates(ctx, [segs], [260], [260])
+    assert e.value.code == S.SNCC_ERANGE
+    bad = segs.copy()
+    bad[0]["w"] += 1                                          # overlapping segments
+    with pytest.raises(S.SnccError) as e:
+        S.sncc_upload_templates(ctx, [bad[:5]], [260], [260])
+    assert e.value.code in (S.SNCC_EINVAL, S.SNCC_ERANGE)
+    small = rng.integers(0, 256, (12, 12)).astype(np.uint8)
+    segs, _, _ = S.sncc_segment_template(small, 30)
+    with pytest.raises(S.SnccError) as e:
+        S.sncc_upload_templates(ctx, [segs[:-1]], [12], [12])  # hole
+    assert e.value.code == S.SNCC_EINVAL
+    flat = np.zeros(1, S.SEGMENT_DTYPE)
+    flat[0] = (0, 0, 12, 12, 144 * 9, 144, 0)
+    with pytest.raises(S.SnccError) as e:
+        S.sncc_upload_templates(ctx, [flat], [12], [12])
+    assert e.value.code == S.SNCC_EDEGENERATE
+    with pytest.raises(S.SnccError):
+        S.sncc_score(ctx, tm, 5, s, s2, 50, 40, S.SNCC_FP64,
+                     torch.zeros((1, 1), dtype=torch.float64, device="cuda"))
