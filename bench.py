@@ -142,6 +142,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first copy a buffer of this size (a known-size kernel for "
+                         "scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("this build measures one GPU only: run with --gpus 1", file=sys.stderr)
@@ -151,6 +154,15 @@ def main():
     import torch
     import paper_2502_01286_amd as S
 
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.copy_calibration_mib} MiB")
+        del a, b
     log(f"[bench] generating workload {args.workload}")
     t0 = time.perf_counter()
     wl = make_workload(args.workload)

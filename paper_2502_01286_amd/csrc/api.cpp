@@ -217,6 +217,16 @@ int plan_template(const sncc_tmpl *tm, int t, const TileCfg &tc, int LP, int row
       rc.c = (float)tm->c64[t][q];
       ph.recs.push_back(rc);
     }
+    if ((ph.recs.size() - ps.seg_begin) % 2) {
+      // the kernel adds segments in pairs: a zero-weight entry (width 0,
+      // area 0, c 0) completes the last pair
+      TileRec z;
+      z.off_tl = ph.recs.back().off_tl;
+      z.off_bl = ph.recs.back().off_bl;
+      z.w_area = 0;
+      z.c = 0.f;
+      ph.recs.push_back(z);
+    }
     ps.seg_end = (int)ph.recs.size();
     ph.passes.push_back(ps);
     max_rows = std::max(max_rows, lds_row);

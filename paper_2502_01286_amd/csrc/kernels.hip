@@ -342,25 +342,46 @@ int launch_sat(const uint8_t *f, int B, int M, int N, int f_pitch, uint32_t *s,
 }
 
 // ------------------------------------------------------------ tile scoring
+// Buffer resource over `bytes` bytes at `p` (GFX9 raw buffer: loads at or
+// beyond `bytes` return zero).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+
+// Four-corner box sum of a window (Eqs. (13), (15)) through a buffer
+// resource: corners at byte offsets 0, cW, cH, cH + cW from voff + so.
+__device__ __forceinline__ uint32_t window_box(__amdgpu_buffer_rsrc_t r, int voff, int so, int cW,
+                                               int cH) {
+  const uint32_t a00 = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so, 0);
+  const uint32_t a01 = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so + cW, 0);
+  const uint32_t a10 = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so + cH, 0);
+  const uint32_t a11 = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so + cH + cW, 0);
+  return (a11 - a10) - (a01 - a00);
+}
+
+// Stages the pass's row intervals of one frame's sum table into LDS with
+// LDS-direct buffer loads: lane c4 of a wave moves 16 bytes of a row.
 template <int LP, int NW>
-__device__ __forceinline__ void stage_pass(const uint32_t *__restrict__ sat, int P, int N,
+__device__ __forceinline__ void stage_pass(__amdgpu_buffer_rsrc_t rs, int P,
                                            const Interval *__restrict__ ivs, int iv_begin,
                                            int iv_end, int u0, int v0, int stage_w4,
                                            uint32_t *lds, int wave, int lane) {
   for (int iv = iv_begin; iv < iv_end; ++iv) {
     const Interval I = ivs[iv];
     for (int j = wave; j < I.n_rows; j += NW) {
-      const int sr = v0 + I.rel_row + j;
-      uint4 *dst = reinterpret_cast<uint4 *>(lds + (I.lds_row + j) * LP);
-      if (sr <= N) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(sat + (long long)sr * P + u0);
-        for (int c4 = lane; c4 < stage_w4; c4 += 64)
-          dst[c4] = (u0 + 4 * c4 + 3 < P) ? src[c4] : make_uint4(0, 0, 0, 0);
-      } else {
-        for (int c4 = lane; c4 < stage_w4; c4 += 64) dst[c4] = make_uint4(0, 0, 0, 0);
+      const int src = ((v0 + I.rel_row + j) * P + u0) * 4;
+      uint32_t *dst = lds + (I.lds_row + j) * LP;
+#pragma unroll
+      for (int c = 0; c < (LP / 4 + 63) / 64; ++c) {
+        if (c * 64 + lane < stage_w4)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(
+              rs, (__attribute__((address_space(3))) void *)(dst + c * 256), 16,
+              lane * 16 + c * 1024, src, 0, 0);
       }
     }
   }
+  __builtin_amdgcn_s_waitcnt(0);
 }
 
 template <int RU, int RV, int NW, int LP, bool MAP>
@@ -371,20 +392,23 @@ __device__ __forceinline__ void run_item(
     const DevTmpl &td, u64 &lkey, int k, float *__restrict__ rho_out, int rho_pitch,
     uint8_t *__restrict__ degen, uint32_t *lds, int wave, int lane) {
   constexpr int BU = 64 * RU, BV = NW * RV, R = RU * RV;
-  const uint32_t *S = s + (long long)pd.frame * frame_stride;
-  const uint32_t *S2 = s2 + (long long)pd.frame * frame_stride;
+  const uint32_t bytes = (uint32_t)(N + 1) * (uint32_t)P * 4u;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(s + (long long)pd.frame * frame_stride, bytes);
+  const __amdgpu_buffer_rsrc_t rs2 = make_rsrc(s2 + (long long)pd.frame * frame_stride, bytes);
   const int W = td.W, H = td.H, n = td.n;
   const float inv_n = 1.0f / (float)n;
-  const double q_k = td.q_k;
+  const double qn = td.q_k / (double)n;  // energy * q_k = V * q_k / n
   const int stage_w4 = (BU + W + 1 + 3) >> 2;
   const int lbase = wave * RV * LP + lane;
+  const int cW = W * 4, cH = H * P * 4;  // byte offsets of the window corners
 
   for (int tile = it.tile_begin; tile < it.tile_end; ++tile) {
     const int tv = tile / pd.ntu, tu = tile - tv * pd.ntu;
     const int u0 = tu * BU, v0 = tv * BV;
+    const int voff = ((v0 + wave * RV) * P + u0 + lane) * 4;
 
-    // window sums (Eqs. (13), (15)) and the integer bias per offset
-    uint32_t sf[R], sf2[R];
+    // window sum (Eq. (13)) and the integer bias per offset; offsets outside
+    // the valid range read in-buffer garbage or zeros and are masked later
     int nb[R];
     float acc[R], cmp[R];
 #pragma unroll
@@ -392,51 +416,44 @@ __device__ __forceinline__ void run_item(
 #pragma unroll
       for (int du = 0; du < RU; ++du) {
         const int r = dv * RU + du;
-        const int u = u0 + lane + 64 * du, v = v0 + wave * RV + dv;
-        sf[r] = 0;
-        sf2[r] = 0;
-        if (u < pd.nu && v < pd.nv) {
-          const uint32_t *a0 = S + (long long)v * P + u;
-          const uint32_t *a1 = a0 + (long long)H * P;
-          sf[r] = (a1[W] - a1[0]) - (a0[W] - a0[0]);
-          const uint32_t *b0 = S2 + (long long)v * P + u;
-          const uint32_t *b1 = b0 + (long long)H * P;
-          sf2[r] = (b1[W] - b1[0]) - (b0[W] - b0[0]);
-        }
-        nb[r] = -(int)__builtin_rintf((float)sf[r] * inv_n);
+        const uint32_t sf = window_box(rs, voff + du * 256, dv * P * 4, cW, cH);
+        nb[r] = -(int)__builtin_rintf((float)sf * inv_n);
         acc[r] = 0.f;
         cmp[r] = 0.f;
       }
 
-    // per-segment terms (Eqs. (11), (12)), pass by pass
+    // per-segment terms (Eqs. (11), (12)), pass by pass; the products of two
+    // segments are added before one compensated (Kahan) step
     for (int p = td.pass_begin; p < td.pass_end; ++p) {
       const PassDesc ps = passes[p];
       __syncthreads();
-      stage_pass<LP, NW>(S, P, N, ivs, ps.iv_begin, ps.iv_end, u0, v0, stage_w4, lds, wave,
+      stage_pass<LP, NW>(rs, P, ivs, ps.iv_begin, ps.iv_end, u0, v0, stage_w4, lds, wave,
                          lane);
       __syncthreads();
       const TileRec *rp = recs + ps.seg_begin;
-      const int nseg = ps.seg_end - ps.seg_begin;
+      const int nseg = ps.seg_end - ps.seg_begin;  // even (padded)
 #pragma unroll 2
-      for (int i = 0; i < nseg; ++i) {
-        const TileRec rec = rp[i];
-        const uint32_t wa = (uint32_t)rec.w_area;
-        const int w = (int)(wa & 0xfffu);
-        const int A = (int)(wa >> 12);
-        const float c = rec.c;
-        const uint32_t *tl = lds + lbase + rec.off_tl;
-        const uint32_t *bl = lds + lbase + rec.off_bl;
-        const uint32_t *tr = tl + w;
-        const uint32_t *br = bl + w;
+      for (int i = 0; i < nseg; i += 2) {
+        const TileRec e0 = rp[i], e1 = rp[i + 1];
+        const uint32_t wa0 = (uint32_t)e0.w_area, wa1 = (uint32_t)e1.w_area;
+        const int w0 = (int)(wa0 & 0xfffu), A0 = (int)(wa0 >> 12);
+        const int w1 = (int)(wa1 & 0xfffu), A1 = (int)(wa1 >> 12);
+        const uint32_t *tl0 = lds + lbase + e0.off_tl, *bl0 = lds + lbase + e0.off_bl;
+        const uint32_t *tl1 = lds + lbase + e1.off_tl, *bl1 = lds + lbase + e1.off_bl;
+        const uint32_t *tr0 = tl0 + w0, *br0 = bl0 + w0;
+        const uint32_t *tr1 = tl1 + w1, *br1 = bl1 + w1;
 #pragma unroll
         for (int dv = 0; dv < RV; ++dv)
 #pragma unroll
           for (int du = 0; du < RU; ++du) {
             const int o = dv * LP + du * 64;
             const int r = dv * RU + du;
-            const uint32_t F = (br[o] - bl[o]) - (tr[o] - tl[o]);
-            const int G = (int)F + __mul24(A, nb[r]);
-            const float y = __builtin_fmaf((float)G, c, -cmp[r]);
+            const uint32_t F0 = (br0[o] - bl0[o]) - (tr0[o] - tl0[o]);
+            const uint32_t F1 = (br1[o] - bl1[o]) - (tr1[o] - tl1[o]);
+            const int G0 = (int)F0 + __mul24(A0, nb[r]);
+            const int G1 = (int)F1 + __mul24(A1, nb[r]);
+            float y = __builtin_fmaf((float)G0, e0.c, -cmp[r]);
+            y = __builtin_fmaf((float)G1, e1.c, y);
             const float t = acc[r] + y;
             cmp[r] = (t - acc[r]) - y;
             acc[r] = t;
@@ -454,14 +471,20 @@ __device__ __forceinline__ void run_item(
         const int u = u0 + lane + 64 * du, v = v0 + wave * RV + dv;
         cand[r] = 0;
         if (u < pd.nu && v < pd.nv) {
-          const long long V = (long long)((u64)(uint32_t)n * sf2[r] - (u64)sf[r] * sf[r]);
+          // window sums again (Eqs. (13), (15)): cheaper than keeping them live
+          const uint32_t sf = window_box(rs, voff + du * 256, dv * P * 4, cW, cH);
+          const uint32_t sf2 = window_box(rs2, voff + du * 256, dv * P * 4, cW, cH);
+          const u64 V = (u64)(uint32_t)n * sf2 - (u64)sf * sf;
+          const double x = (double)V * qn;
+          double rq = __builtin_amdgcn_rsq(x);
+          rq = __builtin_fma(0.5 * rq, __builtin_fma(-x * rq, rq, 1.0), rq);
           const double num = (double)acc[r] - (double)cmp[r];
-          const double rho = V == 0 ? 0.0 : num / sqrt((double)V / (double)n * q_k);
+          const float rho = V == 0 ? 0.f : (float)(num * rq);
           if (MAP) {
-            rho_out[(long long)v * rho_pitch + u] = (float)rho;
+            rho_out[(long long)v * rho_pitch + u] = rho;
             if (degen) degen[(long long)v * rho_pitch + u] = V == 0 ? 1 : 0;
           } else {
-            cand[r] = make_key((float)rho, v * pd.nu + u);
+            cand[r] = make_key(rho, v * pd.nu + u);
           }
         }
       }
