@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <memory>
@@ -124,7 +125,7 @@ namespace {
 // ------------------------------------------------------------- tile plans
 struct PlanHost {
   int cfg = 0;
-  TileCfg tc{2, 4, 8};
+  TileCfg tc{2, 4, 8, 2, 1};
   int lds_bytes = 0;
   int grid = 0;
   bool map_sink = false;
@@ -217,9 +218,9 @@ int plan_template(const sncc_tmpl *tm, int t, const TileCfg &tc, int LP, int row
       rc.c = (float)tm->c64[t][q];
       ph.recs.push_back(rc);
     }
-    if ((ph.recs.size() - ps.seg_begin) % 2) {
-      // the kernel adds segments in pairs: a zero-weight entry (width 0,
-      // area 0, c 0) completes the last pair
+    while ((ph.recs.size() - ps.seg_begin) % 4) {
+      // the kernel adds segments in blocks of four: zero-weight entries
+      // (width 0, area 0, c 0) complete the last block
       TileRec z;
       z.off_tl = ph.recs.back().off_tl;
       z.off_bl = ph.recs.back().off_bl;
@@ -249,9 +250,10 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
   std::vector<char> used(tm->T, 0);
   for (int p = 0; p < n_pairs; ++p) used[pairs[2 * p + 1]] = 1;
 
-  // LDS budget: two workgroups per CU when every template allows it
+  // LDS budget: tc.wgs workgroups per CU when every template allows it,
+  // otherwise one workgroup per CU
   const int topk_bytes = map_sink ? 0 : tc.nw * std::max(k, 1) * 8;
-  int budget = 80 * 1024 - 256;
+  int budget = tile_max_lds() / tc.wgs - 512;
   for (int pass = 0; pass < 2; ++pass) {
     ph.tmpls.assign(tm->T, DevTmpl{});
     ph.passes.clear();
@@ -325,8 +327,15 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
   }
   ph.order.resize(ph.items.size());
   for (size_t i = 0; i < ph.order.size(); ++i) ph.order[i] = (int)i;
-  std::stable_sort(ph.order.begin(), ph.order.end(),
-                   [&](int a, int b) { return item_cost[a] > item_cost[b]; });
+  if (tc.frame_major) {
+    std::stable_sort(ph.order.begin(), ph.order.end(), [&](int a, int b) {
+      const int fa = ph.pairs[ph.items[a].pair].frame, fb = ph.pairs[ph.items[b].pair].frame;
+      return fa != fb ? fa < fb : item_cost[a] > item_cost[b];
+    });
+  } else {
+    std::stable_sort(ph.order.begin(), ph.order.end(),
+                     [&](int a, int b) { return item_cost[a] > item_cost[b]; });
+  }
   ph.grid = (int)std::min<size_t>(ph.items.size(), (size_t)slots);
   if (ph.grid < 1) ph.grid = 1;
   return SNCC_OK;
@@ -1033,6 +1042,12 @@ int autotune(sncc_batch *b, int *best_cfg) {
       HIPCHK(hipEventRecord(e1, b->ctx->stream));
       HIPCHK(hipEventSynchronize(e1));
       HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    }
+    if (getenv("SNCC_TUNE_LOG")) {
+      const TileCfg tc = tile_cfg(c);
+      fprintf(stderr, "[sncc tune] cfg %d: tile %dx%d, %d threads, %d WG/CU budget, %s order, "
+              "LDS %d B, %zu items: %.3f ms\n", c, tc.bu(), tc.bv(), tc.threads(), tc.wgs,
+              tc.frame_major ? "frame-major" : "cost", pd.h.lds_bytes, pd.h.items.size(), ms);
     }
     if (ms < best) {
       best = ms;

@@ -422,7 +422,7 @@ __device__ __forceinline__ void run_item(
         cmp[r] = 0.f;
       }
 
-    // per-segment terms (Eqs. (11), (12)), pass by pass; the products of two
+    // per-segment terms (Eqs. (11), (12)), pass by pass; the products of four
     // segments are added before one compensated (Kahan) step
     for (int p = td.pass_begin; p < td.pass_end; ++p) {
       const PassDesc ps = passes[p];
@@ -431,29 +431,42 @@ __device__ __forceinline__ void run_item(
                          lane);
       __syncthreads();
       const TileRec *rp = recs + ps.seg_begin;
-      const int nseg = ps.seg_end - ps.seg_begin;  // even (padded)
+      const int nseg = ps.seg_end - ps.seg_begin;  // multiple of 4 (padded)
+      // the next block's records are loaded one iteration ahead so that the
+      // scalar-load wait never stalls the first LDS reads of a block
+      TileRec nx[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) nx[q] = rp[q];
 #pragma unroll 2
-      for (int i = 0; i < nseg; i += 2) {
-        const TileRec e0 = rp[i], e1 = rp[i + 1];
-        const uint32_t wa0 = (uint32_t)e0.w_area, wa1 = (uint32_t)e1.w_area;
-        const int w0 = (int)(wa0 & 0xfffu), A0 = (int)(wa0 >> 12);
-        const int w1 = (int)(wa1 & 0xfffu), A1 = (int)(wa1 >> 12);
-        const uint32_t *tl0 = lds + lbase + e0.off_tl, *bl0 = lds + lbase + e0.off_bl;
-        const uint32_t *tl1 = lds + lbase + e1.off_tl, *bl1 = lds + lbase + e1.off_bl;
-        const uint32_t *tr0 = tl0 + w0, *br0 = bl0 + w0;
-        const uint32_t *tr1 = tl1 + w1, *br1 = bl1 + w1;
+      for (int i = 0; i < nseg; i += 4) {
+        TileRec e[4];
+        const uint32_t *tl[4], *bl[4], *tr[4], *br[4];
+        int A[4];
+        const int inext = min(i + 4, nseg - 4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          e[q] = nx[q];
+          nx[q] = rp[inext + q];
+          const uint32_t wa = (uint32_t)e[q].w_area;
+          A[q] = (int)(wa >> 12);
+          tl[q] = lds + lbase + e[q].off_tl;
+          bl[q] = lds + lbase + e[q].off_bl;
+          tr[q] = tl[q] + (int)(wa & 0xfffu);
+          br[q] = bl[q] + (int)(wa & 0xfffu);
+        }
 #pragma unroll
         for (int dv = 0; dv < RV; ++dv)
 #pragma unroll
           for (int du = 0; du < RU; ++du) {
             const int o = dv * LP + du * 64;
             const int r = dv * RU + du;
-            const uint32_t F0 = (br0[o] - bl0[o]) - (tr0[o] - tl0[o]);
-            const uint32_t F1 = (br1[o] - bl1[o]) - (tr1[o] - tl1[o]);
-            const int G0 = (int)F0 + __mul24(A0, nb[r]);
-            const int G1 = (int)F1 + __mul24(A1, nb[r]);
-            float y = __builtin_fmaf((float)G0, e0.c, -cmp[r]);
-            y = __builtin_fmaf((float)G1, e1.c, y);
+            float y = -cmp[r];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const uint32_t F = (br[q][o] - bl[q][o]) - (tr[q][o] - tl[q][o]);
+              const int G = (int)F + __mul24(A[q], nb[r]);
+              y = __builtin_fmaf((float)G, e[q].c, y);
+            }
             const float t = acc[r] + y;
             cmp[r] = (t - acc[r]) - y;
             acc[r] = t;
@@ -519,11 +532,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   run_item<RU, RV, NW, LPV, MAP>(s, s2, frame_stride, P, N, passes, ivs, recs, it, pd, td, \
                                  lkey, k, rho_out, rho_pitch, degen, lds, wave, lane)
     switch (td.lp_class) {
-      case 0: SNCC_RUN(192); break;
-      case 1: SNCC_RUN(256); break;
-      case 2: SNCC_RUN(320); break;
-      case 3: SNCC_RUN(384); break;
-      case 4: SNCC_RUN(448); break;
+      case 0: SNCC_RUN(128); break;
+      case 1: SNCC_RUN(192); break;
+      case 2: SNCC_RUN(256); break;
+      case 3: SNCC_RUN(320); break;
+      case 4: SNCC_RUN(384); break;
+      case 5: SNCC_RUN(448); break;
       default: SNCC_RUN(576); break;
     }
 #undef SNCC_RUN
@@ -550,52 +564,71 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
 }
 
 struct TileEntry {
-  TileCfg cfg;
+  int ru, rv, nw;
   const void *fn_map;
   const void *fn_topk;
 };
 
-#define SNCC_TILE_ENTRY(RU, RV, NW)                                                   \
-  TileEntry {                                                                         \
-    TileCfg{RU, RV, NW}, reinterpret_cast<const void *>(&tile_kernel<RU, RV, NW, true>), \
-        reinterpret_cast<const void *>(&tile_kernel<RU, RV, NW, false>)                 \
+#define SNCC_TILE_ENTRY(RU, RV, NW)                                                 \
+  TileEntry {                                                                       \
+    RU, RV, NW, reinterpret_cast<const void *>(&tile_kernel<RU, RV, NW, true>),     \
+        reinterpret_cast<const void *>(&tile_kernel<RU, RV, NW, false>)             \
   }
 
 static const TileEntry kTileEntries[] = {
-    SNCC_TILE_ENTRY(2, 4, 8),
-    SNCC_TILE_ENTRY(2, 4, 4),
-    SNCC_TILE_ENTRY(1, 8, 8),
-    SNCC_TILE_ENTRY(2, 2, 8),
+    SNCC_TILE_ENTRY(2, 4, 8),  // 0: 128 x 32 offsets
+    SNCC_TILE_ENTRY(2, 4, 4),  // 1: 128 x 16
+    SNCC_TILE_ENTRY(1, 8, 8),  // 2:  64 x 64
+    SNCC_TILE_ENTRY(2, 2, 8),  // 3: 128 x 16
+    SNCC_TILE_ENTRY(1, 4, 8),  // 4:  64 x 32
+    SNCC_TILE_ENTRY(1, 4, 4),  // 5:  64 x 16
 };
 static const int kNumTileEntries = sizeof(kTileEntries) / sizeof(kTileEntries[0]);
 
-int tile_cfg_count() { return kNumTileEntries; }
+// Tile configurations the planner and the tuner choose from: kernel entry
+// and workgroups per CU the LDS budget is sized for.
+struct CfgEntry {
+  int entry, wgs, frame_major;
+};
+static const CfgEntry kCfgs[] = {
+    {0, 2, 1}, {0, 2, 0}, {1, 4, 1}, {3, 2, 1}, {3, 3, 1}, {4, 2, 1}, {5, 4, 1}, {2, 2, 1},
+};
+static const int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
+
+int tile_cfg_count() { return kNumCfgs; }
+TileCfg tile_cfg(int i) {
+  const TileEntry &e = kTileEntries[kCfgs[i].entry];
+  return TileCfg{e.ru, e.rv, e.nw, kCfgs[i].wgs, kCfgs[i].frame_major};
+}
+int tile_max_lds() { return 160 * 1024; }
+
+static const void *tile_fn(int cfg, bool map_sink) {
+  const TileEntry &e = kTileEntries[kCfgs[cfg].entry];
+  return map_sink ? e.fn_map : e.fn_topk;
+}
 
 int tile_occupancy(int cfg, bool map_sink, int lds_bytes) {
-  if (cfg < 0 || cfg >= kNumTileEntries) return 0;
-  const TileEntry &e = kTileEntries[cfg];
-  const void *fn = map_sink ? e.fn_map : e.fn_topk;
+  if (cfg < 0 || cfg >= kNumCfgs) return 0;
+  const void *fn = tile_fn(cfg, map_sink);
   (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, tile_max_lds() - 64);
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, e.cfg.threads(),
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, tile_cfg(cfg).threads(),
                                                    (size_t)lds_bytes) != hipSuccess)
     return 0;
   return blocks;
 }
-TileCfg tile_cfg(int i) { return kTileEntries[i].cfg; }
-int tile_max_lds() { return 160 * 1024; }
 
 int launch_tile(int cfg, bool map_sink, const TileArgs &a, int grid, int lds_bytes,
                 hipStream_t st) {
-  if (cfg < 0 || cfg >= kNumTileEntries) return -1;
-  const TileEntry &e = kTileEntries[cfg];
-  const void *fn = map_sink ? e.fn_map : e.fn_topk;
-  static bool attr_done[2][16] = {};
-  if (!attr_done[map_sink][cfg]) {
+  if (cfg < 0 || cfg >= kNumCfgs) return -1;
+  const void *fn = tile_fn(cfg, map_sink);
+  static bool attr_done[2][kNumTileEntries] = {};
+  const int ent = kCfgs[cfg].entry;
+  if (!attr_done[map_sink][ent]) {
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             tile_max_lds() - 64) != hipSuccess)
       return -1;
-    attr_done[map_sink][cfg] = true;
+    attr_done[map_sink][ent] = true;
   }
   long long fs = a.frame_stride;
   int P = a.sat_pitch, N = a.N, n_items = a.n_items, k = a.k, rp = a.rho_pitch;
@@ -613,7 +646,7 @@ int launch_tile(int cfg, bool map_sink, const TileArgs &a, int grid, int lds_byt
   uint8_t *dg = a.degen;
   void *args[] = {&s,  &s2, &fs, &P,  &N,     &tm,      &ps,  &iv,  &rc,  &pr,
                   &it, &ord, &n_items, &queue, &k, &partial, &rho, &rp, &dg};
-  hipError_t err = hipLaunchKernel(fn, dim3(grid), dim3(e.cfg.threads()), args,
+  hipError_t err = hipLaunchKernel(fn, dim3(grid), dim3(tile_cfg(cfg).threads()), args,
                                    (size_t)lds_bytes, st);
   return err == hipSuccess ? 0 : -1;
 }

@@ -111,16 +111,20 @@ struct PlainArgs {
 };
 
 // Tile kernel configuration: offsets per lane RU (u, stride 64) x RV (v),
-// NW waves per workgroup, each wave owning RV offset rows.
+// NW waves per workgroup, each wave owning RV offset rows; `wgs` is the
+// number of workgroups per CU the LDS budget is sized for; with
+// `frame_major`, work items run frame by frame (largest first within a
+// frame) so that concurrent workgroups share a frame's sum tables in cache,
+// otherwise largest first overall.
 struct TileCfg {
-  int ru, rv, nw;
+  int ru, rv, nw, wgs, frame_major;
   int bu() const { return 64 * ru; }
   int bv() const { return nw * rv; }
   int threads() const { return 64 * nw; }
 };
 
-constexpr int kNumLpClasses = 6;
-constexpr int kLpClasses[kNumLpClasses] = {192, 256, 320, 384, 448, 576};
+constexpr int kNumLpClasses = 7;
+constexpr int kLpClasses[kNumLpClasses] = {128, 192, 256, 320, 384, 448, 576};
 
 // Launch wrappers (kernels.hip).
 int launch_sat(const uint8_t *f, int B, int M, int N, int f_pitch, uint32_t *s,

@@ -1,0 +1,209 @@
+"""Parity at the workloads' full sizes, in the launch configurations the
+benchmark uses (MI355X).
+
+Where the oracle can produce a whole map in seconds the comparison is
+element by element; elsewhere the oracle scores sampled offsets one by one,
+and every match the GPU reports is re-scored by the oracle at its position.
+Inputs come from workloads.synth; no oracle input comes from the GPU.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import synth
+
+from gpu_util import build_sats, lib_templates, oracle_templates, topk_ok
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL64 = 1e-9
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_2502_01286_amd as S
+    return S
+
+
+@pytest.fixture(scope="module")
+def ctx(S):
+    import torch
+    torch.cuda.init()
+    c = S.sncc_ctx_create(0)
+    yield c
+    S.sncc_ctx_destroy(c)
+
+
+def _maps(S, ctx, f, t, sigma, k_max=5000):
+    import torch
+    N, M = f.shape
+    H, W = t.shape
+    _, s, s2 = build_sats(S, ctx, [f])
+    tm = lib_templates(S, ctx, [t], [sigma], k_max)
+    nu, nv = M - W + 1, N - H + 1
+    r32 = torch.empty((nv, nu), dtype=torch.float32, device="cuda")
+    r64 = torch.empty((nv, nu), dtype=torch.float64, device="cuda")
+    S.sncc_score(ctx, tm, 0, s, s2, M, N, S.SNCC_FP32_KAHAN, r32)
+    S.sncc_score(ctx, tm, 0, s, s2, M, N, S.SNCC_FP64, r64)
+    S.sncc_sync(ctx)
+    S.sncc_tmpl_destroy(tm)
+    return r32.cpu().numpy().astype(np.float64), r64.cpu().numpy(), s, s2
+
+
+def test_cfg0_full_map(S, ctx):
+    wl = synth.cfg0()
+    f, t = wl.frames[0], wl.templates[0]
+    print("cfg0 640x480, 32x32, sigma 8", flush=True)
+    g32, g64, _, _ = _maps(S, ctx, f, t, 8)
+    ta = O.precompute_template_approximation(t, 8)
+    want = O.rho_map(f, ta)
+    assert np.abs(g64 - want).max() <= TOL64
+    assert np.abs(g32 - want).max() <= TOL32
+    if O.top2_margin(want) > 1e-4:
+        u, v, _ = O.argmax(want)
+        assert np.unravel_index(np.argmax(g32), g32.shape) == (v, u)
+        assert np.unravel_index(np.argmax(g64), g64.shape) == (v, u)
+
+
+@pytest.mark.parametrize("sigma", [16, 8, 4])
+def test_cfg1_full_map(S, ctx, sigma):
+    wl = synth.cfg1(sigma)
+    f, t = wl.frames[0], wl.templates[0]
+    print(f"cfg1 1920x1080, 64x64, sigma {sigma}", flush=True)
+    g32, g64, _, _ = _maps(S, ctx, f, t, sigma)
+    ta = O.precompute_template_approximation(t, sigma)
+    want = O.rho_map(f, ta)
+    e32, e64 = np.abs(g32 - want).max(), np.abs(g64 - want).max()
+    print(f"  K {ta.K}: max|drho| fp32 {e32:.2e} fp64 {e64:.2e}", flush=True)
+    assert e64 <= TOL64 and e32 <= TOL32
+    if O.top2_margin(want) > 1e-4:
+        u, v, _ = O.argmax(want)
+        assert np.unravel_index(np.argmax(g32), g32.shape) == (v, u)
+
+
+@pytest.mark.parametrize("size,k_max", [(128, 5000), (256, 5000), (128, 10 ** 9)])
+def test_cfg2_sampled(S, ctx, size, k_max):
+    wl = synth.cfg2(size, k_max=k_max)
+    f, t = wl.frames[0], wl.templates[0]
+    N, M = f.shape
+    print(f"cfg2 3840x2160, {size}x{size}, sigma 4, K_max {k_max}", flush=True)
+    g32, g64, _, _ = _maps(S, ctx, f, t, 4, k_max)
+    ta = O.precompute_template_approximation(t, 4, k_max)
+    print(f"  K {ta.K} (sigma used {ta.sigma_used})", flush=True)
+    s_o, s2_o = O.sum_tables(f)
+    rng = np.random.default_rng(size + (k_max % 1000))
+    nv, nu = g32.shape
+    us = rng.integers(0, nu, 4000)
+    vs = rng.integers(0, nv, 4000)
+    # plus the neighbourhood of the GPU's best offset and of the crop origin
+    gv, gu = np.unravel_index(np.argmax(g32), g32.shape)
+    _, ox, oy = wl.origin[0]
+    for cu, cv in [(gu, gv), (ox, oy)]:
+        for dv in range(-2, 3):
+            for du in range(-2, 3):
+                if 0 <= cu + du < nu and 0 <= cv + dv < nv:
+                    us = np.append(us, cu + du)
+                    vs = np.append(vs, cv + dv)
+    want = O.rho_at(s_o, s2_o, ta, us, vs)
+    e32 = np.abs(g32[vs, us] - want).max()
+    e64 = np.abs(g64[vs, us] - want).max()
+    print(f"  sampled max|drho| fp32 {e32:.2e} fp64 {e64:.2e}", flush=True)
+    assert e32 <= TOL32 and e64 <= TOL64
+    # the best offset found by the GPU is at least as good as every sample
+    assert g32.max() >= want.max() - TOL32
+
+
+def _batch(S, ctx, wl, fine=False, k=None):
+    import torch
+    B, N, M = len(wl.frames), wl.N, wl.M
+    k = k or wl.k
+    f = torch.from_numpy(np.stack(wl.frames)).cuda()
+    P = S.sncc_sat_pitch(M)
+    s = torch.empty((B, N + 1, P), dtype=torch.int32, device="cuda")
+    s2 = torch.empty_like(s)
+    coarse = lib_templates(S, ctx, wl.templates, wl.sigmas, wl.k_max)
+    fn = lib_templates(S, ctx, wl.templates, [wl.fine_sigma] * len(wl.templates)) if fine else None
+    topk = torch.zeros((len(wl.pairs), k, 3), dtype=torch.int32, device="cuda")
+    best = torch.zeros((len(wl.pairs), 4), dtype=torch.int32, device="cuda") if fine else None
+    batch = S.sncc_batch_create(ctx, coarse, s, s2, B, M, N, wl.pairs, k, topk, fine=fn,
+                                radius=2, best_out=best, frames=f, tune=1)
+    batch.run()
+    S.sncc_sync(ctx)
+    out = (S.decode_matches(topk), S.decode_matches64(best) if fine else None)
+    batch.destroy()
+    S.sncc_tmpl_destroy(coarse)
+    if fn:
+        S.sncc_tmpl_destroy(fn)
+    return out
+
+
+def test_cfg3_batched_top5(S, ctx):
+    wl = synth.cfg3()
+    print("cfg3 16 frames 1920x1080 x 64 templates, top-5", flush=True)
+    got, _ = _batch(S, ctx, wl)
+    tas = oracle_templates(wl.templates, wl.sigmas)
+    tables = {}
+    rng = np.random.default_rng(33)
+    # every reported match re-scored by the oracle at its position
+    worst = 0.0
+    for p in rng.permutation(len(wl.pairs))[:256]:
+        b, ti = wl.pairs[p]
+        if b not in tables:
+            tables[b] = O.sum_tables(wl.frames[b])
+        g = got[p]
+        want = O.rho_at(*tables[b], tas[ti], g["u"].astype(np.int64), g["v"].astype(np.int64))
+        worst = max(worst, float(np.abs(want - g["rho"]).max()))
+        assert (np.diff(g["rho"]) <= 0).all()
+    print(f"  256 pairs re-scored: max|drho| {worst:.2e}", flush=True)
+    assert worst <= TOL32
+    # full oracle maps for the cheapest pairs: the top-5 must be the oracle's
+    cost = [(wl.M - tas[ti].W + 1) * (wl.N - tas[ti].H + 1) * tas[ti].K for b, ti in wl.pairs]
+    for p in np.argsort(cost)[:6]:
+        b, ti = wl.pairs[p]
+        if b not in tables:
+            tables[b] = O.sum_tables(wl.frames[b])
+        m = O.rho_map(wl.frames[b], tas[ti], tables=tables[b])
+        errs = topk_ok(m, got[p], 5, TOL32)
+        assert not errs, (p, errs[:3])
+
+
+def test_cfg4_batched_coarse_fine(S, ctx):
+    wl = synth.cfg4()
+    print("cfg4 256 frames 1280x720 x 32 templates, top-32 + FP64 refine", flush=True)
+    got, best = _batch(S, ctx, wl, fine=True)
+    tas_c = oracle_templates(wl.templates, wl.sigmas)
+    tas_f = oracle_templates(wl.templates, [wl.fine_sigma] * len(wl.templates))
+    rng = np.random.default_rng(44)
+    tables = {}
+    worst_c = worst_f = 0.0
+    for p in rng.permutation(len(wl.pairs))[:192]:
+        b, ti = wl.pairs[p]
+        if b not in tables:
+            tables[b] = O.sum_tables(wl.frames[b])
+        g = got[p]
+        want = O.rho_at(*tables[b], tas_c[ti], g["u"].astype(np.int64), g["v"].astype(np.int64))
+        worst_c = max(worst_c, float(np.abs(want - g["rho"]).max()))
+        bf = best[p]
+        wf = O.rho_at(*tables[b], tas_f[ti], int(bf["u"]), int(bf["v"]))
+        worst_f = max(worst_f, abs(float(wf) - float(bf["rho"])))
+    print(f"  192 pairs: coarse max|drho| {worst_c:.2e}, fine max|drho| {worst_f:.2e}", flush=True)
+    assert worst_c <= TOL32 and worst_f <= TOL64
+    # whole coarse maps for a few pairs: top-32 and the final argmax
+    checked = 0
+    for p in rng.permutation(len(wl.pairs))[:4]:
+        b, ti = wl.pairs[p]
+        if b not in tables:
+            tables[b] = O.sum_tables(wl.frames[b])
+        cmap = O.rho_map(wl.frames[b], tas_c[ti], tables=tables[b])
+        errs = topk_ok(cmap, got[p], 32, TOL32)
+        assert not errs, (p, errs[:3])
+        ref = O.topk(cmap, 33)
+        if ref[31][2] - ref[32][2] > 2e-5:
+            res = O.coarse_fine(*tables[b], tas_c[ti], tas_f[ti], wl.M, wl.N, k=32, radius=2,
+                                coarse_map=cmap)
+            assert (int(best[p]["u"]), int(best[p]["v"])) == res["best"][:2]
+            assert abs(float(best[p]["rho"]) - res["best"][2]) <= TOL64
+            checked += 1
+    print(f"  {checked} pairs with unique candidate sets: final argmax matches", flush=True)
