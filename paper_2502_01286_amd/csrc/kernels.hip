@@ -47,9 +47,21 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), 63);
 }
 
-__device__ __forceinline__ u64 shfl_u64(u64 x, int src) {
-  unsigned lo = (unsigned)__shfl((int)(unsigned)x, src);
-  unsigned hi = (unsigned)__shfl((int)(unsigned)(x >> 32), src);
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
+  // running maximum over lanes (same DPP pattern as the scan)
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+  return v;
+}
+
+// Value of lane `src` (wave-uniform) of a 64-bit register.
+__device__ __forceinline__ u64 lane_u64(u64 x, int src) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src);
   return ((u64)hi << 32) | lo;
 }
 
@@ -59,15 +71,14 @@ __device__ __forceinline__ u64 shfl_up_u64(u64 x, int d) {
   return ((u64)hi << 32) | lo;
 }
 
+// Maximum of a 64-bit key over the wave: the high words first, then the
+// low words among the lanes holding the highest high word.
 __device__ __forceinline__ u64 wave_max_u64(u64 x) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    unsigned lo = (unsigned)__shfl_xor((int)(unsigned)x, m);
-    unsigned hi = (unsigned)__shfl_xor((int)(unsigned)(x >> 32), m);
-    u64 y = ((u64)hi << 32) | lo;
-    x = y > x ? y : x;
-  }
-  return x;
+  const uint32_t hi = (uint32_t)(x >> 32);
+  const uint32_t mh = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(hi), 63);
+  const uint32_t lo = hi == mh ? (uint32_t)x : 0u;
+  const uint32_t ml = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(lo), 63);
+  return ((u64)mh << 32) | ml;
 }
 
 // Order-preserving map of a float to uint32 (larger float -> larger code).
@@ -97,10 +108,13 @@ __device__ __forceinline__ void topk_insert(u64 &lkey, u64 key, int k, int lane)
     lkey = up;
 }
 
-// Offers R candidate keys per lane (0 = none) to the wave's list.
+// Offers R candidate keys per lane (0 = none) to the wave's list.  Keys not
+// above `floor` (a key known to have k better keys elsewhere) are dropped.
 template <int R>
-__device__ __forceinline__ void topk_offer(u64 &lkey, u64 (&cand)[R], int k, int lane) {
-  u64 thr = shfl_u64(lkey, k - 1);
+__device__ __forceinline__ void topk_offer(u64 &lkey, u64 (&cand)[R], int k, int lane,
+                                           u64 floor = 0) {
+  u64 thr = lane_u64(lkey, k - 1);
+  thr = thr > floor ? thr : floor;
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if (cand[r] <= thr) cand[r] = 0;
@@ -111,7 +125,8 @@ __device__ __forceinline__ void topk_offer(u64 &lkey, u64 (&cand)[R], int k, int
     if (__ballot(best != 0) == 0) break;
     best = wave_max_u64(best);
     topk_insert(lkey, best, k, lane);
-    thr = shfl_u64(lkey, k - 1);
+    thr = lane_u64(lkey, k - 1);
+    thr = thr > floor ? thr : floor;
 #pragma unroll
     for (int r = 0; r < R; ++r)
       if (cand[r] == best || cand[r] <= thr) cand[r] = 0;
@@ -390,14 +405,14 @@ __device__ __forceinline__ void run_item(
     int P, int N, const PassDesc *__restrict__ passes, const Interval *__restrict__ ivs,
     const TileRec *__restrict__ recs, const WorkItem &it, const PairDesc &pd,
     const DevTmpl &td, u64 &lkey, int k, float *__restrict__ rho_out, int rho_pitch,
-    uint8_t *__restrict__ degen, uint32_t *lds, int wave, int lane) {
+    uint8_t *__restrict__ degen, uint32_t *lds, uint32_t *thr_sh, int wave, int lane) {
   constexpr int BU = 64 * RU, BV = NW * RV, R = RU * RV;
   const uint32_t bytes = (uint32_t)(N + 1) * (uint32_t)P * 4u;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(s + (long long)pd.frame * frame_stride, bytes);
   const __amdgpu_buffer_rsrc_t rs2 = make_rsrc(s2 + (long long)pd.frame * frame_stride, bytes);
   const int W = td.W, H = td.H, n = td.n;
   const float inv_n = 1.0f / (float)n;
-  const double qn = td.q_k / (double)n;  // energy * q_k = V * q_k / n
+  const float qnf = (float)(td.q_k / (double)n);  // energy * q_k = V * q_k / n
   const int stage_w4 = (BU + W + 1 + 3) >> 2;
   const int lbase = wave * RV * LP + lane;
   const int cW = W * 4, cH = H * P * 4;  // byte offsets of the window corners
@@ -474,7 +489,9 @@ __device__ __forceinline__ void run_item(
       }
     }
 
-    // epilogue: exact window energy (Eq. (16) x n), rho (Eqs. (17), (18))
+    // epilogue: exact window energy V = n * Eq. (16) in 64-bit integers, then
+    // rho = num / sqrt(V q_k / n) (Eqs. (17), (18)) in FP32; every lane
+    // computes (out-of-range reads are harmless) and invalid offsets are masked
     u64 cand[R];
 #pragma unroll
     for (int dv = 0; dv < RV; ++dv)
@@ -482,26 +499,32 @@ __device__ __forceinline__ void run_item(
       for (int du = 0; du < RU; ++du) {
         const int r = dv * RU + du;
         const int u = u0 + lane + 64 * du, v = v0 + wave * RV + dv;
-        cand[r] = 0;
-        if (u < pd.nu && v < pd.nv) {
-          // window sums again (Eqs. (13), (15)): cheaper than keeping them live
-          const uint32_t sf = window_box(rs, voff + du * 256, dv * P * 4, cW, cH);
-          const uint32_t sf2 = window_box(rs2, voff + du * 256, dv * P * 4, cW, cH);
-          const u64 V = (u64)(uint32_t)n * sf2 - (u64)sf * sf;
-          const double x = (double)V * qn;
-          double rq = __builtin_amdgcn_rsq(x);
-          rq = __builtin_fma(0.5 * rq, __builtin_fma(-x * rq, rq, 1.0), rq);
-          const double num = (double)acc[r] - (double)cmp[r];
-          const float rho = V == 0 ? 0.f : (float)(num * rq);
-          if (MAP) {
+        const uint32_t sf = window_box(rs, voff + du * 256, dv * P * 4, cW, cH);
+        const uint32_t sf2 = window_box(rs2, voff + du * 256, dv * P * 4, cW, cH);
+        const u64 V = (u64)(uint32_t)n * sf2 - (u64)sf * sf;
+        const float x =
+            __builtin_fmaf((float)(uint32_t)(V >> 32), 4294967296.0f, (float)(uint32_t)V) * qnf;
+        const float rho = V == 0 ? 0.f : (acc[r] - cmp[r]) * __builtin_amdgcn_rsqf(x);
+        const bool ok = u < pd.nu && v < pd.nv;
+        if (MAP) {
+          if (ok) {
             rho_out[(long long)v * rho_pitch + u] = rho;
             if (degen) degen[(long long)v * rho_pitch + u] = V == 0 ? 1 : 0;
-          } else {
-            cand[r] = make_key(rho, v * pd.nu + u);
           }
+        } else {
+          cand[r] = ok ? make_key(rho, v * pd.nu + u) : 0;
         }
       }
-    if (!MAP) topk_offer<R>(lkey, cand, k, lane);
+    if (!MAP) {
+      // waves publish the high word of their k-th key (a 32-bit store, so
+      // readers see an old or a new value, never a mix); (largest, 0) is at
+      // most some wave's k-th key and filters every wave
+      uint32_t fh = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) fh = max(fh, thr_sh[w]);
+      topk_offer<R>(lkey, cand, k, lane, (u64)fh << 32);
+      if (lane == 0) thr_sh[wave] = (uint32_t)(lane_u64(lkey, k - 1) >> 32);
+    }
   }
 }
 
@@ -516,6 +539,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     uint8_t *__restrict__ degen) {
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ int item_sh;
+  __shared__ uint32_t thr_sh[NW];  // high words of the waves' k-th keys (current item)
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (;;) {
     if (threadIdx.x == 0) item_sh = atomicAdd(queue, 1);
@@ -528,9 +552,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     const PairDesc pd = pairs[it.pair];
     const DevTmpl td = tmpls[pd.tmpl];
     u64 lkey = 0;
+    if (lane == 0) thr_sh[wave] = 0;  // ordered before use by the first pass barrier
 #define SNCC_RUN(LPV)                                                                    \
   run_item<RU, RV, NW, LPV, MAP>(s, s2, frame_stride, P, N, passes, ivs, recs, it, pd, td, \
-                                 lkey, k, rho_out, rho_pitch, degen, lds, wave, lane)
+                                 lkey, k, rho_out, rho_pitch, degen, lds, thr_sh, wave, lane)
     switch (td.lp_class) {
       case 0: SNCC_RUN(128); break;
       case 1: SNCC_RUN(192); break;
@@ -548,13 +573,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
       if (lane < k) buf[wave * k + lane] = lkey;
       __syncthreads();
       if (wave == 0) {
-        u64 thr = shfl_u64(lkey, k - 1);
+        u64 thr = lane_u64(lkey, k - 1);
         for (int w = 1; w < NW; ++w) {
           for (int j = 0; j < k; ++j) {
             const u64 key = buf[w * k + j];
             if (key <= thr) break;
             topk_insert(lkey, key, k, lane);
-            thr = shfl_u64(lkey, k - 1);
+            thr = lane_u64(lkey, k - 1);
           }
         }
         if (lane < k) partial[(long long)item * k + lane] = lkey;
@@ -727,10 +752,10 @@ __global__ __launch_bounds__(256) void merge_kernel(const PairDesc *__restrict__
   for (int item = pd.item_begin; item < pd.item_end; ++item) {
     const u64 mine = lane < k ? partial[(long long)item * k + lane] : 0;
     for (int j = 0; j < k; ++j) {
-      const u64 key = shfl_u64(mine, j);
+      const u64 key = lane_u64(mine, j);
       if (key <= thr) break;
       topk_insert(lkey, key, k, lane);
-      thr = shfl_u64(lkey, k - 1);
+      thr = lane_u64(lkey, k - 1);
     }
   }
   if (lane < k) {
@@ -782,13 +807,13 @@ __global__ __launch_bounds__(256) void map_topk_kernel(const double *__restrict_
   if (lane < k) buf[wave * k + lane] = lkey;
   __syncthreads();
   if (wave == 0) {
-    u64 thr = shfl_u64(lkey, k - 1);
+    u64 thr = lane_u64(lkey, k - 1);
     for (int w = 1; w < 4; ++w)
       for (int j = 0; j < k; ++j) {
         const u64 key = buf[w * k + j];
         if (key <= thr) break;
         topk_insert(lkey, key, k, lane);
-        thr = shfl_u64(lkey, k - 1);
+        thr = lane_u64(lkey, k - 1);
       }
     if (lane < k) partial[(long long)blockIdx.x * k + lane] = lkey;
   }
