@@ -142,6 +142,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--k", type=int, default=0, help="top-k per pair (default: the workload's)")
+    ap.add_argument("--coarse-sigma", type=float, default=0,
+                    help="override the coarse threshold of every template")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a buffer of this size (a known-size kernel for "
                          "scaling HBM counters)")
@@ -166,6 +169,10 @@ def main():
     log(f"[bench] generating workload {args.workload}")
     t0 = time.perf_counter()
     wl = make_workload(args.workload)
+    if args.k:
+        wl.k = args.k
+    if args.coarse_sigma:
+        wl.sigmas = [args.coarse_sigma] * len(wl.templates)
     B, N, M = len(wl.frames), wl.N, wl.M
     log(f"[bench] {B} frames {M}x{N}, {len(wl.templates)} templates, {len(wl.pairs)} pairs "
         f"({time.perf_counter() - t0:.1f} s)")
@@ -203,7 +210,9 @@ def main():
                                 tune=args.tune)
     st = batch.stats()
     log(f"[bench] batch planned in {time.perf_counter() - t0:.2f} s: {st['work_items']} items, "
-        f"tile {st['tile_u']}x{st['tile_v']}, {st['wg_threads']} threads, LDS {st['lds_bytes']} B")
+        f"tile {st['tile_u']}x{st['tile_v']}, {st['wg_threads']} threads, LDS {st['lds_bytes']} B, "
+        f"{st['n_passes']} LDS passes over {len(wl.templates)} templates, computed/valid evals "
+        f"{st['computed_evals'] / max(1, st['coarse_evals']):.3f}")
 
     for i in range(args.warmup):
         batch.run()

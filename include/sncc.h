@@ -261,6 +261,8 @@ typedef struct sncc_batch_stats {
   int64_t coarse_evals;      /* sum over pairs of offsets x K (coarse)     */
   int64_t n_offsets;         /* sum over pairs of offsets                  */
   int64_t work_items;
+  int64_t computed_evals;    /* evals incl. offsets of partial edge tiles  */
+  int64_t n_passes;          /* LDS passes summed over the used templates  */
   int n_launch_classes;      /* persistent scoring launches per run        */
   int tile_u, tile_v;        /* offsets per tile (u, v)                    */
   int wg_threads;

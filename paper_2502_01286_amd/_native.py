@@ -61,7 +61,8 @@ class sncc_batch_desc(C.Structure):
 
 class sncc_batch_stats(C.Structure):
     _fields_ = [("coarse_evals", C.c_int64), ("n_offsets", C.c_int64),
-                ("work_items", C.c_int64), ("n_launch_classes", C.c_int),
+                ("work_items", C.c_int64), ("computed_evals", C.c_int64),
+                ("n_passes", C.c_int64), ("n_launch_classes", C.c_int),
                 ("tile_u", C.c_int), ("tile_v", C.c_int), ("wg_threads", C.c_int),
                 ("lds_bytes", C.c_int), ("timed", C.c_int),
                 ("ms_sat", C.c_float), ("ms_score", C.c_float), ("ms_select", C.c_float),

@@ -138,6 +138,8 @@ struct PlanHost {
   std::vector<WorkItem> items;
   std::vector<int> order;
   int64_t coarse_evals = 0, n_offsets = 0;
+  int64_t computed_evals = 0;  // including offsets of partial edge tiles
+  int64_t n_passes = 0;        // LDS passes summed over used templates
 };
 
 int lp_class_for(int width) {
@@ -218,16 +220,6 @@ int plan_template(const sncc_tmpl *tm, int t, const TileCfg &tc, int LP, int row
       rc.c = (float)tm->c64[t][q];
       ph.recs.push_back(rc);
     }
-    while ((ph.recs.size() - ps.seg_begin) % 4) {
-      // the kernel adds segments in blocks of four: zero-weight entries
-      // (width 0, area 0, c 0) complete the last block
-      TileRec z;
-      z.off_tl = ph.recs.back().off_tl;
-      z.off_bl = ph.recs.back().off_bl;
-      z.w_area = 0;
-      z.c = 0.f;
-      ph.recs.push_back(z);
-    }
     ps.seg_end = (int)ph.recs.size();
     ph.passes.push_back(ps);
     max_rows = std::max(max_rows, lds_row);
@@ -259,6 +251,7 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
     ph.passes.clear();
     ph.ivs.clear();
     ph.recs.clear();
+    ph.n_passes = 0;
     bool ok = true;
     int max_bytes = topk_bytes;
     for (int t = 0; t < tm->T; ++t) {
@@ -278,6 +271,7 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
         max_bytes = std::max(max_bytes, rows * LP * 4);
       }
       ph.tmpls[t] = d;
+      ph.n_passes += d.pass_end - d.pass_begin;
     }
     if (ok) {
       ph.lds_bytes = (max_bytes + 255) & ~255;
@@ -306,6 +300,7 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
     tile_cost[p] = (double)bu * bv * (tm->K[t] + 8.0) + 0.5 * staged;
     total += tile_cost[p] * pd.ntu * pd.ntv;
     ph.coarse_evals += (int64_t)pd.nu * pd.nv * tm->K[t];
+    ph.computed_evals += (int64_t)pd.ntu * bu * pd.ntv * bv * tm->K[t];
     ph.n_offsets += (int64_t)pd.nu * pd.nv;
   }
   const double target = total / (slots * 6.0);
@@ -1135,6 +1130,8 @@ int sncc_batch_stats_get(sncc_batch *b, sncc_batch_stats *st) {
   const PlanHost &h = b->plan->h;
   memset(st, 0, sizeof *st);
   st->coarse_evals = h.coarse_evals;
+  st->computed_evals = h.computed_evals;
+  st->n_passes = h.n_passes;
   st->n_offsets = h.n_offsets;
   st->work_items = (int64_t)h.items.size();
   st->n_launch_classes = 1;
