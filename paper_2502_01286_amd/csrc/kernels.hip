@@ -446,18 +446,20 @@ __device__ __forceinline__ void run_item(
                          lane);
       __syncthreads();
       const TileRec *rp = recs + ps.seg_begin;
-      const int nseg = ps.seg_end - ps.seg_begin;  // multiple of 4 (padded)
-      // the next block's records are loaded one iteration ahead so that the
-      // scalar-load wait never stalls the first LDS reads of a block
+      const int nseg = ps.seg_end - ps.seg_begin;
+      const int nseg4 = nseg & ~3;
+      // blocks of four segments; the next block's records are loaded one
+      // iteration ahead so that the scalar-load wait never stalls the first
+      // LDS reads of a block
       TileRec nx[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) nx[q] = rp[q];
+      for (int q = 0; q < 4; ++q) nx[q] = rp[min(q, nseg - 1)];
 #pragma unroll 2
-      for (int i = 0; i < nseg; i += 4) {
+      for (int i = 0; i < nseg4; i += 4) {
         TileRec e[4];
         const uint32_t *tl[4], *bl[4], *tr[4], *br[4];
         int A[4];
-        const int inext = min(i + 4, nseg - 4);
+        const int inext = min(i + 4, nseg4 - 4);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           e[q] = nx[q];
@@ -482,6 +484,27 @@ __device__ __forceinline__ void run_item(
               const int G = (int)F + __mul24(A[q], nb[r]);
               y = __builtin_fmaf((float)G, e[q].c, y);
             }
+            const float t = acc[r] + y;
+            cmp[r] = (t - acc[r]) - y;
+            acc[r] = t;
+          }
+      }
+      // the last one to three segments, one compensated step each
+      for (int i = nseg4; i < nseg; ++i) {
+        const TileRec e = rp[i];
+        const uint32_t wa = (uint32_t)e.w_area;
+        const int A = (int)(wa >> 12);
+        const uint32_t *tl = lds + lbase + e.off_tl, *bl = lds + lbase + e.off_bl;
+        const uint32_t *tr = tl + (int)(wa & 0xfffu), *br = bl + (int)(wa & 0xfffu);
+#pragma unroll
+        for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+          for (int du = 0; du < RU; ++du) {
+            const int o = dv * LP + du * 64;
+            const int r = dv * RU + du;
+            const uint32_t F = (br[o] - bl[o]) - (tr[o] - tl[o]);
+            const int G = (int)F + __mul24(A, nb[r]);
+            const float y = __builtin_fmaf((float)G, e.c, -cmp[r]);
             const float t = acc[r] + y;
             cmp[r] = (t - acc[r]) - y;
             acc[r] = t;
