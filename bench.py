@@ -69,11 +69,11 @@ def load_traffic(workload):
 def make_workload(name):
     from workloads import synth
     if name == "coarse-fine":
-        return synth.cfg4()
+        return synth.coarse_fine_256x32()
     if name == "batched":
-        return synth.cfg3()
+        return synth.batch_16x64()
     if name == "coarse-fine-small":
-        return synth.cfg4(n_frames=16, n_templates=8)
+        return synth.coarse_fine_256x32(n_frames=16, n_templates=8)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -150,7 +150,7 @@ def main():
                          "scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("this build measures one GPU only: run with --gpus 1", file=sys.stderr)
+        print("this benchmark measures one GPU only: run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -52,10 +52,10 @@ def _maps(S, ctx, f, t, sigma, k_max=5000):
     return r32.cpu().numpy().astype(np.float64), r64.cpu().numpy(), s, s2
 
 
-def test_cfg0_full_map(S, ctx):
-    wl = synth.cfg0()
+def test_scene_640x480_full_map(S, ctx):
+    wl = synth.scene_640x480()
     f, t = wl.frames[0], wl.templates[0]
-    print("cfg0 640x480, 32x32, sigma 8", flush=True)
+    print("single scene 640x480, 32x32 template, sigma 8", flush=True)
     g32, g64, _, _ = _maps(S, ctx, f, t, 8)
     ta = O.precompute_template_approximation(t, 8)
     want = O.rho_map(f, ta)
@@ -68,10 +68,10 @@ def test_cfg0_full_map(S, ctx):
 
 
 @pytest.mark.parametrize("sigma", [16, 8, 4])
-def test_cfg1_full_map(S, ctx, sigma):
-    wl = synth.cfg1(sigma)
+def test_scene_1920x1080_full_map(S, ctx, sigma):
+    wl = synth.scene_1920x1080(sigma)
     f, t = wl.frames[0], wl.templates[0]
-    print(f"cfg1 1920x1080, 64x64, sigma {sigma}", flush=True)
+    print(f"single scene 1920x1080, 64x64 template, sigma {sigma}", flush=True)
     g32, g64, _, _ = _maps(S, ctx, f, t, sigma)
     ta = O.precompute_template_approximation(t, sigma)
     want = O.rho_map(f, ta)
@@ -84,11 +84,11 @@ def test_cfg1_full_map(S, ctx, sigma):
 
 
 @pytest.mark.parametrize("size,k_max", [(128, 5000), (256, 5000), (128, 10 ** 9)])
-def test_cfg2_sampled(S, ctx, size, k_max):
-    wl = synth.cfg2(size, k_max=k_max)
+def test_texture_3840x2160_sampled(S, ctx, size, k_max):
+    wl = synth.texture_3840x2160(size, k_max=k_max)
     f, t = wl.frames[0], wl.templates[0]
     N, M = f.shape
-    print(f"cfg2 3840x2160, {size}x{size}, sigma 4, K_max {k_max}", flush=True)
+    print(f"texture 3840x2160, {size}x{size} template, sigma 4, K_max {k_max}", flush=True)
     g32, g64, _, _ = _maps(S, ctx, f, t, 4, k_max)
     ta = O.precompute_template_approximation(t, 4, k_max)
     print(f"  K {ta.K} (sigma used {ta.sigma_used})", flush=True)
@@ -139,9 +139,9 @@ def _batch(S, ctx, wl, fine=False, k=None):
     return out
 
 
-def test_cfg3_batched_top5(S, ctx):
-    wl = synth.cfg3()
-    print("cfg3 16 frames 1920x1080 x 64 templates, top-5", flush=True)
+def test_batch_16x64_top5(S, ctx):
+    wl = synth.batch_16x64()
+    print("16 frames 1920x1080 x 64 templates, top-5", flush=True)
     got, _ = _batch(S, ctx, wl)
     tas = oracle_templates(wl.templates, wl.sigmas)
     tables = {}
@@ -169,9 +169,9 @@ def test_cfg3_batched_top5(S, ctx):
         assert not errs, (p, errs[:3])
 
 
-def test_cfg4_batched_coarse_fine(S, ctx):
-    wl = synth.cfg4()
-    print("cfg4 256 frames 1280x720 x 32 templates, top-32 + FP64 refine", flush=True)
+def test_coarse_fine_256x32(S, ctx):
+    wl = synth.coarse_fine_256x32()
+    print("256 frames 1280x720 x 32 templates, top-32 + FP64 refine", flush=True)
     got, best = _batch(S, ctx, wl, fine=True)
     tas_c = oracle_templates(wl.templates, wl.sigmas)
     tas_f = oracle_templates(wl.templates, [wl.fine_sigma] * len(wl.templates))

@@ -45,16 +45,29 @@ def _random_template(rng):
 N_TEMPLATES = int(os.environ.get("SNCC_P11_COUNT", "10000"))
 
 
+def _oracle_case(args):
+    t, sigma, k_max = args
+    try:
+        return _oracle_list(t, sigma, k_max)
+    except ValueError:
+        return None
+
+
 def test_p11_host_segmentation_equals_oracle():
+    from concurrent.futures import ProcessPoolExecutor
     rng = np.random.default_rng(11)
-    compared = 0
-    for i in range(N_TEMPLATES):
+    cases = []
+    for _ in range(N_TEMPLATES):
         t = _random_template(rng)
         sigma = float(rng.choice([0.5, 1, 2, 3, 4, 8, 12, 16, 2.75, 7.3]))
         k_max = int(rng.choice([5000, 5000, 20, 6]))
-        try:
-            want = _oracle_list(t, sigma, k_max)
-        except ValueError:
+        cases.append((t, sigma, k_max))
+    workers = max(1, min(8, len(os.sched_getaffinity(0))))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        wants = list(ex.map(_oracle_case, cases, chunksize=64))
+    compared = 0
+    for i, ((t, sigma, k_max), want) in enumerate(zip(cases, wants)):
+        if want is None:
             with pytest.raises(S.SnccError) as ei:
                 S.sncc_segment_template(t, sigma, k_max)
             assert ei.value.code == S.SNCC_EDEGENERATE

@@ -3,8 +3,7 @@
 This module only draws inputs: it holds none of the matching method's
 arithmetic and imports neither the oracle nor the GPU package, so both sides
 can take their inputs from it.  Every draw goes through
-``numpy.random.default_rng(seed)`` (PCG64); the seed of workload ``c``,
-item ``i`` is ``1000 * c + i``.
+``numpy.random.default_rng(seed)`` (PCG64) with fixed seeds per workload.
 
 Generators (uint8 grayscale, rows = y):
 
@@ -129,26 +128,26 @@ class Workload:
         return self.frames[0].shape[0]
 
 
-def cfg0(scale: float = 1.0) -> Workload:
+def scene_640x480(scale: float = 1.0) -> Workload:
     """One 640x480 scene, one 32x32 template, sigma_max 8, full map + argmax."""
     M, N = int(640 * scale), int(480 * scale)
     f = scene(0, M, N)
     rng = np.random.default_rng(1)
     t, x, y = crop_template(rng, f, 32, 32, sigma_max=8)
-    return Workload("cfg0", [f], [t], [8.0], [(0, 0)], k=1, origin=[(0, x, y)])
+    return Workload("scene_640x480", [f], [t], [8.0], [(0, 0)], k=1, origin=[(0, x, y)])
 
 
-def cfg1(sigma: float = 4.0, scale: float = 1.0) -> Workload:
+def scene_1920x1080(sigma: float = 4.0, scale: float = 1.0) -> Workload:
     """One 1920x1080 scene, one 64x64 template, sigma_max in {4, 8, 16}."""
     M, N = int(1920 * scale), int(1080 * scale)
     f = scene(1000, M, N)
     rng = np.random.default_rng(1001)
     t, x, y = crop_template(rng, f, 64, 64, sigma_max=16)
-    return Workload(f"cfg1_s{int(sigma)}", [f], [t], [float(sigma)], [(0, 0)], k=1,
+    return Workload(f"scene_1920x1080_s{int(sigma)}", [f], [t], [float(sigma)], [(0, 0)], k=1,
                     origin=[(0, x, y)])
 
 
-def cfg2(size: int = 128, scale: float = 1.0, k_max: int = 5000) -> Workload:
+def texture_3840x2160(size: int = 128, scale: float = 1.0, k_max: int = 5000) -> Workload:
     """One 3840x2160 texture, a 128x128 or 256x256 template taken at the
     highest gradient-energy position among 16 seeded candidates, sigma_max 4."""
     M, N = int(3840 * scale), int(2160 * scale)
@@ -165,12 +164,12 @@ def cfg2(size: int = 128, scale: float = 1.0, k_max: int = 5000) -> Workload:
             best = (e, x, y)
     _, x, y = best
     t, _, _ = crop_template(rng, f, size, size, sigma_max=4, pos=(x, y))
-    return Workload(f"cfg2_{size}", [f], [t], [4.0], [(0, 0)], k=1, k_max=k_max,
+    return Workload(f"texture_3840x2160_t{size}", [f], [t], [4.0], [(0, 0)], k=1, k_max=k_max,
                     origin=[(0, x, y)])
 
 
-def cfg3(n_frames: int = 16, n_templates: int = 64, M: int = 1920, N: int = 1080,
-         side_lo: int = 16, side_hi: int = 192, k: int = 5) -> Workload:
+def batch_16x64(n_frames: int = 16, n_templates: int = 64, M: int = 1920, N: int = 1080,
+                side_lo: int = 16, side_hi: int = 192, k: int = 5) -> Workload:
     """Batched: frames x templates of sides U{side_lo..side_hi}, sigma_max in
     {4, 8, 12, 16}, every pair scored, top-k per pair."""
     frames = [scene(3000 + i, M, N) for i in range(n_frames)]
@@ -186,10 +185,10 @@ def cfg3(n_frames: int = 16, n_templates: int = 64, M: int = 1920, N: int = 1080
         sig.append(s)
         origin.append((fi, x, y))
     pairs = [(fi, ti) for fi in range(n_frames) for ti in range(n_templates)]
-    return Workload("cfg3", frames, temps, sig, pairs, k=k, origin=origin)
+    return Workload("batch_16x64", frames, temps, sig, pairs, k=k, origin=origin)
 
 
-def cfg4(n_frames: int = 256, n_templates: int = 32, M: int = 1280, N: int = 720,
+def coarse_fine_256x32(n_frames: int = 256, n_templates: int = 32, M: int = 1280, N: int = 720,
          side_lo: int = 24, side_hi: int = 96, k: int = 32) -> Workload:
     """Batched coarse-fine: coarse sigma_max 16 (top-k), fine sigma_max 4."""
     frames = [scene(4000 + i, M, N) for i in range(n_frames)]
@@ -203,5 +202,5 @@ def cfg4(n_frames: int = 256, n_templates: int = 32, M: int = 1280, N: int = 720
         temps.append(t)
         origin.append((fi, x, y))
     pairs = [(fi, ti) for fi in range(n_frames) for ti in range(n_templates)]
-    return Workload("cfg4", frames, temps, [16.0] * n_templates, pairs, k=k,
+    return Workload("coarse_fine_256x32", frames, temps, [16.0] * n_templates, pairs, k=k,
                     fine_sigma=4.0, origin=origin)
