@@ -89,7 +89,7 @@ def cpu_baseline(wl, coarse_segs_k, budget_s=15.0, max_pairs=1024):
     est = lambda p: (wl.M - wl.templates[wl.pairs[p][1]].shape[1] + 1) * \
         (wl.N - wl.templates[wl.pairs[p][1]].shape[0] + 1) * coarse_segs_k[wl.pairs[p][1]]
     chosen, work = [], 0.0
-    rate_guess = 4e7 * cores          # evals/s of the NumPy oracle (rough, for sizing only)
+    rate_guess = 1.4e8 * cores         # evals/s of the NumPy oracle (rough, for sizing only)
     for p in order:
         if len(chosen) >= max_pairs or work / rate_guess > budget_s:
             break

@@ -24,6 +24,14 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it with `python -m paper_2502_01286_amd.build` "
         "(the HIP library is required; there is no fallback)")
 
+# PyTorch bundles its own HIP runtime (same soname as ROCm's).  Loading torch
+# first makes this library bind to that already-loaded runtime, so the process
+# holds a single HIP runtime whichever module the caller imports first.
+try:
+    import torch  # noqa: F401
+except ImportError:  # the C-ABI itself does not need torch
+    pass
+
 lib = C.CDLL(LIB_PATH)
 
 SNCC_OK = 0
