@@ -22,7 +22,13 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsncc.so")
 ARCH = os.environ.get("SNCC_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["segment.cpp", "api.cpp", "kernels.hip"]
+# (source, extra flags, object name): the scoring kernel's tile shapes are
+# separate objects built from one source so that they compile in parallel.
+N_TILE_SHAPES = 6
+SOURCES = [("segment.cpp", [], "segment.o"), ("api.cpp", [], "api.o"),
+           ("kernels.hip", [], "kernels.o")] + [
+    ("tile_entry.hip", [f"-DSNCC_TILE_ENTRY_ID={i}"], f"tile_entry_{i}.o")
+    for i in range(N_TILE_SHAPES)]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-x", "hip", f"--offload-arch={ARCH}",
@@ -43,16 +49,17 @@ def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
     tmp = tempfile.mkdtemp(prefix="sncc_build_")
     try:
-        def compile_one(src):
-            obj = os.path.join(tmp, os.path.basename(src) + ".o")
-            cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        def compile_one(job):
+            src, extra, name = job
+            obj = os.path.join(tmp, name)
+            cmd = [hipcc, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             r = subprocess.run(cmd, capture_output=True, text=True)
             if r.returncode != 0:
                 raise RuntimeError(f"compiling {src} failed:\n{r.stdout}\n{r.stderr}")
             return obj
-        with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4, 16)) as ex:
             objs = list(ex.map(compile_one, SOURCES))
         out_tmp = LIB + ".tmp"
         cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out_tmp]

@@ -136,7 +136,8 @@ struct PlanHost {
   std::vector<TileRec> recs;
   std::vector<PairDesc> pairs;
   std::vector<WorkItem> items;
-  std::vector<int> order;
+  std::vector<int> order;       // item indices, queue by queue
+  std::vector<int> qbeg;        // nq + 1 offsets into order
   int64_t coarse_evals = 0, n_offsets = 0;
   int64_t computed_evals = 0;  // including offsets of partial edge tiles
   int64_t n_passes = 0;        // LDS passes summed over used templates
@@ -245,7 +246,9 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
   // LDS budget: tc.wgs workgroups per CU when every template allows it,
   // otherwise one workgroup per CU
   const int topk_bytes = map_sink ? 0 : tc.nw * std::max(k, 1) * 8;
-  int budget = tile_max_lds() / tc.wgs - 512;
+  // the kernel keeps one FP32 scale per offset in LDS ahead of the staged rows
+  const int scale_bytes = 64 * tc.nw * tc.ru * tc.rv * 4;
+  int budget = tile_max_lds() / tc.wgs - 512 - scale_bytes;
   for (int pass = 0; pass < 2; ++pass) {
     ph.tmpls.assign(tm->T, DevTmpl{});
     ph.passes.clear();
@@ -268,7 +271,7 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
           ok = false;
           break;
         }
-        max_bytes = std::max(max_bytes, rows * LP * 4);
+        max_bytes = std::max(max_bytes, scale_bytes + rows * LP * 4);
       }
       ph.tmpls[t] = d;
       ph.n_passes += d.pass_end - d.pass_begin;
@@ -278,7 +281,7 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
       break;
     }
     if (pass == 1) SNCC_FAIL(SNCC_ERANGE, "a template needs more LDS rows than available");
-    budget = tile_max_lds() - 1024;
+    budget = tile_max_lds() - 1024 - scale_bytes;
   }
 
   // pairs and work items
@@ -305,31 +308,83 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
   }
   const double target = total / (slots * 6.0);
   std::vector<double> item_cost;
-  for (int p = 0; p < n_pairs; ++p) {
-    PairDesc &pd = ph.pairs[p];
-    const int ntiles = pd.ntu * pd.ntv;
-    int per = (int)std::max(1.0, std::floor(target / tile_cost[p]));
-    per = std::min(per, ntiles);
-    const int nitems = (ntiles + per - 1) / per;
-    per = (ntiles + nitems - 1) / nitems;  // even out
-    pd.item_begin = (int)ph.items.size();
-    for (int a = 0; a < ntiles; a += per) {
-      WorkItem it{p, a, std::min(ntiles, a + per), 0};
-      ph.items.push_back(it);
-      item_cost.push_back(tile_cost[p] * (it.tile_end - it.tile_begin));
-    }
-    pd.item_end = (int)ph.items.size();
-  }
-  ph.order.resize(ph.items.size());
-  for (size_t i = 0; i < ph.order.size(); ++i) ph.order[i] = (int)i;
+  ph.order.clear();
   if (tc.frame_major) {
-    std::stable_sort(ph.order.begin(), ph.order.end(), [&](int a, int b) {
-      const int fa = ph.pairs[ph.items[a].pair].frame, fb = ph.pairs[ph.items[b].pair].frame;
-      return fa != fb ? fa < fb : item_cost[a] > item_cost[b];
+    // Items are bands of kBandRows offset rows of one pair (split further
+    // only when a band alone exceeds the target cost).  A group is one band
+    // of one frame over all of that frame's templates.  Queues, one per XCD,
+    // take whole frames (frame mod kMaxQueues) when there are enough frames,
+    // else groups round-robin; each queue runs its groups in frame and band
+    // order, so the workgroups of one XCD read the same frame rows from
+    // their shared L2, and a pair's later bands start with the floor its
+    // earlier bands published.  Within a group the costliest items go first.
+    constexpr int kBandRows = 64;
+    const int band_tiles = std::max(1, kBandRows / bv);
+    std::vector<int64_t> group_of;
+    for (int p = 0; p < n_pairs; ++p) {
+      PairDesc &pd = ph.pairs[p];
+      pd.item_begin = (int)ph.items.size();
+      for (int b = 0; b * band_tiles < pd.ntv; ++b) {
+        const int t0 = b * band_tiles * pd.ntu;
+        const int t1 = std::min(pd.ntv, (b + 1) * band_tiles) * pd.ntu;
+        const int ntiles = t1 - t0;
+        int per = (int)std::max(1.0, std::floor(target / tile_cost[p]));
+        per = std::min(per, ntiles);
+        const int nitems = (ntiles + per - 1) / per;
+        per = (ntiles + nitems - 1) / nitems;
+        for (int a = t0; a < t1; a += per) {
+          WorkItem it{p, a, std::min(t1, a + per), 0};
+          ph.items.push_back(it);
+          item_cost.push_back(tile_cost[p] * (it.tile_end - it.tile_begin));
+          group_of.push_back((int64_t)pd.frame * 65536 + b);
+        }
+      }
+      pd.item_end = (int)ph.items.size();
+    }
+    std::vector<int> idx(ph.items.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+      return group_of[a] != group_of[b] ? group_of[a] < group_of[b] : item_cost[a] > item_cost[b];
     });
+    int n_groups = 0, n_frames = 0;
+    std::vector<int> gid(idx.size()), fid(idx.size());
+    for (size_t i = 0; i < idx.size(); ++i) {
+      if (i > 0 && group_of[idx[i]] != group_of[idx[i - 1]]) ++n_groups;
+      if (i > 0 && group_of[idx[i]] >> 16 != group_of[idx[i - 1]] >> 16) ++n_frames;
+      gid[i] = n_groups;
+      fid[i] = n_frames;
+    }
+    if (!idx.empty()) ++n_groups, ++n_frames;
+    const int nq = std::max(1, std::min(kMaxQueues, n_groups));
+    const bool by_frame = n_frames >= nq;
+    ph.qbeg.assign(1, 0);
+    for (int q = 0; q < nq; ++q) {
+      for (size_t i = 0; i < idx.size(); ++i)
+        if ((by_frame ? fid[i] : gid[i]) % nq == q) ph.order.push_back(idx[i]);
+      ph.qbeg.push_back((int)ph.order.size());
+    }
   } else {
+    for (int p = 0; p < n_pairs; ++p) {
+      PairDesc &pd = ph.pairs[p];
+      const int ntiles = pd.ntu * pd.ntv;
+      int per = (int)std::max(1.0, std::floor(target / tile_cost[p]));
+      per = std::min(per, ntiles);
+      const int nitems = (ntiles + per - 1) / per;
+      per = (ntiles + nitems - 1) / nitems;  // even out
+      pd.item_begin = (int)ph.items.size();
+      for (int a = 0; a < ntiles; a += per) {
+        WorkItem it{p, a, std::min(ntiles, a + per), 0};
+        ph.items.push_back(it);
+        item_cost.push_back(tile_cost[p] * (it.tile_end - it.tile_begin));
+      }
+      pd.item_end = (int)ph.items.size();
+    }
+    // one queue, costliest items first
+    ph.order.resize(ph.items.size());
+    for (size_t i = 0; i < ph.order.size(); ++i) ph.order[i] = (int)i;
     std::stable_sort(ph.order.begin(), ph.order.end(),
                      [&](int a, int b) { return item_cost[a] > item_cost[b]; });
+    ph.qbeg = {0, (int)ph.order.size()};
   }
   ph.grid = (int)std::min<size_t>(ph.items.size(), (size_t)slots);
   if (ph.grid < 1) ph.grid = 1;
@@ -341,7 +396,8 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
 // Device copy of a plan plus its completion event.
 struct PlanDev {
   PlanHost h;
-  DevBuf d_tmpls, d_passes, d_ivs, d_recs, d_pairs, d_items, d_order, d_queue, d_partial;
+  DevBuf d_tmpls, d_passes, d_ivs, d_recs, d_pairs, d_items, d_order, d_qbeg, d_queue,
+      d_partial;
   hipEvent_t done = nullptr;
   ~PlanDev() {
     if (done) (void)hipEventDestroy(done);
@@ -354,10 +410,13 @@ struct PlanDev {
     CHK(d_pairs.upload(h.pairs, st));
     CHK(d_items.upload(h.items, st));
     CHK(d_order.upload(h.order, st));
-    CHK(d_queue.reserve(256));
+    CHK(d_qbeg.upload(h.qbeg, st));
+    CHK(d_queue.reserve(zero_ints() * sizeof(int)));
     if (!h.map_sink) CHK(d_partial.reserve(std::max<size_t>(16, h.items.size() * h.k * 8)));
     return SNCC_OK;
   }
+  // work counters, then one floor key per pair (top-k sink), zeroed per launch
+  int zero_ints() const { return kQueueInts + (h.map_sink ? 0 : 2 * (int)h.pairs.size()); }
   TileArgs args(const uint32_t *s, const uint32_t *s2, long long fs, int P, int M, int N) {
     TileArgs a;
     a.s = s;
@@ -373,10 +432,15 @@ struct PlanDev {
     a.pairs = d_pairs.as<PairDesc>();
     a.items = d_items.as<WorkItem>();
     a.order = d_order.as<int>();
+    a.qbeg = d_qbeg.as<int>();
+    a.nq = (int)h.qbeg.size() - 1;
     a.n_items = (int)h.items.size();
     a.queue = d_queue.as<int>();
     a.k = h.k;
     a.partial = d_partial.as<unsigned long long>();
+    a.pair_floor =
+        h.map_sink ? nullptr : reinterpret_cast<unsigned long long *>(a.queue + kQueueInts);
+    a.n_zero = zero_ints();
     a.rho = nullptr;
     a.rho_pitch = 0;
     a.degen = nullptr;
@@ -703,7 +767,7 @@ int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint32_t *d_
   a.rho = d_rho;
   a.rho_pitch = rho_pitch;
   a.degen = d_degenerate;
-  if (launch_zero(a.queue, 1, ctx->stream) != 0 ||
+  if (launch_zero(a.queue, a.n_zero, ctx->stream) != 0 ||
       launch_tile(pd->h.cfg, true, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0)
     SNCC_FAIL(SNCC_EDEVICE, "tile launch: %s", hipGetErrorString(hipGetLastError()));
   return retire(ctx, std::move(pd));
@@ -725,7 +789,7 @@ int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uin
     CHK(build_plan(tm, 0, M, N, n_pairs, pairs, k, false, ctx->num_cu, pd->h));
     CHK(pd->upload(ctx->stream));
     TileArgs a = pd->args(d_s, d_s2, fs, sat_pitch, M, N);
-    if (launch_zero(a.queue, 1, ctx->stream) != 0 ||
+    if (launch_zero(a.queue, a.n_zero, ctx->stream) != 0 ||
         launch_tile(pd->h.cfg, false, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0 ||
         launch_merge(pd->d_pairs.as<PairDesc>(), n_pairs, a.partial, k, d_out, ctx->stream) != 0)
       SNCC_FAIL(SNCC_EDEVICE, "top-k launch: %s", hipGetErrorString(hipGetLastError()));
@@ -874,7 +938,7 @@ int enqueue_stage(sncc_batch *b, int stage, hipStream_t st) {
         SNCC_FAIL(SNCC_EDEVICE, "sum-table launch");
       return SNCC_OK;
     case 1:
-      if (launch_zero(a.queue, 1, st) != 0 ||
+      if (launch_zero(a.queue, a.n_zero, st) != 0 ||
           launch_tile(pd.h.cfg, false, a, pd.h.grid, pd.h.lds_bytes, st) != 0)
         SNCC_FAIL(SNCC_EDEVICE, "scoring launch");
       return SNCC_OK;
@@ -1031,7 +1095,7 @@ int autotune(sncc_batch *b, int *best_cfg) {
     TileArgs a = pd.args(d.d_s, d.d_s2, fs, d.sat_pitch, d.M, d.N);
     float ms = 0;
     for (int rep = 0; rep < 2; ++rep) {
-      launch_zero(a.queue, 1, b->ctx->stream);
+      launch_zero(a.queue, a.n_zero, b->ctx->stream);
       HIPCHK(hipEventRecord(e0, b->ctx->stream));
       launch_tile(c, false, a, pd.h.grid, pd.h.lds_bytes, b->ctx->stream);
       HIPCHK(hipEventRecord(e1, b->ctx->stream));

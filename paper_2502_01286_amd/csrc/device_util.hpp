@@ -1,0 +1,135 @@
+// Device helpers shared by the HIP kernels: wavefront scans and maxima over
+// DPP, 64-bit lane reads, the order-preserving float code and selection key,
+// the register-resident per-wave top-k list, and raw buffer access.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sncc_internal.hpp"
+
+namespace sncc {
+
+typedef unsigned long long u64;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  // Hillis-Steele within rows of 16 lanes, then row broadcasts (GFX9 DPP).
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), 63);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
+  // running maximum over lanes (same DPP pattern as the scan)
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+  return v;
+}
+
+// Value of lane `src` (wave-uniform) of a 64-bit register.
+__device__ __forceinline__ u64 lane_u64(u64 x, int src) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src);
+  return ((u64)hi << 32) | lo;
+}
+
+__device__ __forceinline__ u64 shfl_up_u64(u64 x, int d) {
+  unsigned lo = (unsigned)__shfl_up((int)(unsigned)x, d);
+  unsigned hi = (unsigned)__shfl_up((int)(unsigned)(x >> 32), d);
+  return ((u64)hi << 32) | lo;
+}
+
+// Maximum of a 64-bit key over the wave: the high words first, then the
+// low words among the lanes holding the highest high word.
+__device__ __forceinline__ u64 wave_max_u64(u64 x) {
+  const uint32_t hi = (uint32_t)(x >> 32);
+  const uint32_t mh = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(hi), 63);
+  const uint32_t lo = hi == mh ? (uint32_t)x : 0u;
+  const uint32_t ml = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(lo), 63);
+  return ((u64)mh << 32) | ml;
+}
+
+// Order-preserving map of a float to uint32 (larger float -> larger code).
+__device__ __forceinline__ uint32_t float_order(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float float_unorder(uint32_t o) {
+  uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+  return __uint_as_float(u);
+}
+
+// Selection key: higher rho first, then smaller row-major offset index.
+__device__ __forceinline__ u64 make_key(float rho, int idx) {
+  return ((u64)float_order(rho) << 32) | (u64)(0xffffffffu - (uint32_t)idx);
+}
+
+// Per-wave top-k list: lane j < k holds the j-th best key (0 = empty).
+// Inserts a wave-uniform key that beats the current k-th entry.
+__device__ __forceinline__ void topk_insert(u64 &lkey, u64 key, int k, int lane) {
+  const bool better = lane < k && lkey > key;
+  const int pos = __popcll(__ballot(better));
+  const u64 up = shfl_up_u64(lkey, 1);
+  if (lane == pos)
+    lkey = key;
+  else if (lane > pos && lane < k)
+    lkey = up;
+}
+
+// Offers R candidate keys per lane (0 = none) to the wave's list.  Keys not
+// above `floor` (a key known to have k better keys elsewhere) are dropped.
+template <int R>
+__device__ __forceinline__ void topk_offer(u64 &lkey, u64 (&cand)[R], int k, int lane,
+                                           u64 floor = 0) {
+  u64 thr = lane_u64(lkey, k - 1);
+  thr = thr > floor ? thr : floor;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (cand[r] <= thr) cand[r] = 0;
+  for (;;) {
+    u64 best = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) best = cand[r] > best ? cand[r] : best;
+    if (__ballot(best != 0) == 0) break;
+    best = wave_max_u64(best);
+    topk_insert(lkey, best, k, lane);
+    thr = lane_u64(lkey, k - 1);
+    thr = thr > floor ? thr : floor;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (cand[r] == best || cand[r] <= thr) cand[r] = 0;
+  }
+}
+
+// Buffer resource over `bytes` bytes at `p` (GFX9 raw buffer: loads at or
+// beyond `bytes` return zero).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+
+// Four-corner box sum of a window (Eqs. (13), (15)) through a buffer
+// resource: corners at byte offsets 0, cW, cH, cH + cW from voff + so.
+__device__ __forceinline__ uint32_t window_box(__amdgpu_buffer_rsrc_t r, int voff, int so, int cW,
+                                               int cH) {
+  const uint32_t a00 = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so, 0);
+  const uint32_t a01 = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so + cW, 0);
+  const uint32_t a10 = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so + cH, 0);
+  const uint32_t a11 = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so + cH + cW, 0);
+  return (a11 - a10) - (a01 - a00);
+}
+
+}  // namespace sncc

@@ -14,8 +14,8 @@
 //    (wave-uniform scalar loads) and forms each box sum from four LDS reads in
 //    32-bit modular arithmetic (exact), subtracts area x (window mean rounded
 //    to an integer) in integers and accumulates the product with c_i in FP32
-//    with Kahan compensation.  The epilogue takes the window energy in 64-bit
-//    integers and rho in FP64.  Results go either to a map or to a per-wave
+//    with Kahan compensation.  The window energy is exact in 64-bit integers;
+//    rho is formed in FP32.  Results go either to a map or to a per-wave
 //    register-resident top-k list.
 //  * Plain FP64 kernel: one thread per offset, segments from global memory,
 //    FP64 accumulation; used for the FP64 map, the per-pair baseline and the
@@ -25,113 +25,9 @@
 
 #include <cstdint>
 
-#include "sncc_internal.hpp"
+#include "device_util.hpp"
 
 namespace sncc {
-
-typedef unsigned long long u64;
-
-// ------------------------------------------------------------ wave helpers
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-  // Hillis-Steele within rows of 16 lanes, then row broadcasts (GFX9 DPP).
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
-  return v;
-}
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), 63);
-}
-
-__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
-  // running maximum over lanes (same DPP pattern as the scan)
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
-  return v;
-}
-
-// Value of lane `src` (wave-uniform) of a 64-bit register.
-__device__ __forceinline__ u64 lane_u64(u64 x, int src) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src);
-  return ((u64)hi << 32) | lo;
-}
-
-__device__ __forceinline__ u64 shfl_up_u64(u64 x, int d) {
-  unsigned lo = (unsigned)__shfl_up((int)(unsigned)x, d);
-  unsigned hi = (unsigned)__shfl_up((int)(unsigned)(x >> 32), d);
-  return ((u64)hi << 32) | lo;
-}
-
-// Maximum of a 64-bit key over the wave: the high words first, then the
-// low words among the lanes holding the highest high word.
-__device__ __forceinline__ u64 wave_max_u64(u64 x) {
-  const uint32_t hi = (uint32_t)(x >> 32);
-  const uint32_t mh = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(hi), 63);
-  const uint32_t lo = hi == mh ? (uint32_t)x : 0u;
-  const uint32_t ml = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(lo), 63);
-  return ((u64)mh << 32) | ml;
-}
-
-// Order-preserving map of a float to uint32 (larger float -> larger code).
-__device__ __forceinline__ uint32_t float_order(float f) {
-  uint32_t u = __float_as_uint(f);
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float float_unorder(uint32_t o) {
-  uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
-  return __uint_as_float(u);
-}
-
-// Selection key: higher rho first, then smaller row-major offset index.
-__device__ __forceinline__ u64 make_key(float rho, int idx) {
-  return ((u64)float_order(rho) << 32) | (u64)(0xffffffffu - (uint32_t)idx);
-}
-
-// Per-wave top-k list: lane j < k holds the j-th best key (0 = empty).
-// Inserts a wave-uniform key that beats the current k-th entry.
-__device__ __forceinline__ void topk_insert(u64 &lkey, u64 key, int k, int lane) {
-  const bool better = lane < k && lkey > key;
-  const int pos = __popcll(__ballot(better));
-  const u64 up = shfl_up_u64(lkey, 1);
-  if (lane == pos)
-    lkey = key;
-  else if (lane > pos && lane < k)
-    lkey = up;
-}
-
-// Offers R candidate keys per lane (0 = none) to the wave's list.  Keys not
-// above `floor` (a key known to have k better keys elsewhere) are dropped.
-template <int R>
-__device__ __forceinline__ void topk_offer(u64 &lkey, u64 (&cand)[R], int k, int lane,
-                                           u64 floor = 0) {
-  u64 thr = lane_u64(lkey, k - 1);
-  thr = thr > floor ? thr : floor;
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (cand[r] <= thr) cand[r] = 0;
-  for (;;) {
-    u64 best = 0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) best = cand[r] > best ? cand[r] : best;
-    if (__ballot(best != 0) == 0) break;
-    best = wave_max_u64(best);
-    topk_insert(lkey, best, k, lane);
-    thr = lane_u64(lkey, k - 1);
-    thr = thr > floor ? thr : floor;
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (cand[r] == best || cand[r] <= thr) cand[r] = 0;
-  }
-}
 
 // ---------------------------------------------------------------- sum tables
 constexpr int SAT_TY = 64;
@@ -357,281 +253,25 @@ int launch_sat(const uint8_t *f, int B, int M, int N, int f_pitch, uint32_t *s,
 }
 
 // ------------------------------------------------------------ tile scoring
-// Buffer resource over `bytes` bytes at `p` (GFX9 raw buffer: loads at or
-// beyond `bytes` return zero).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
-                                           0x00020000);
-}
-
-// Four-corner box sum of a window (Eqs. (13), (15)) through a buffer
-// resource: corners at byte offsets 0, cW, cH, cH + cW from voff + so.
-__device__ __forceinline__ uint32_t window_box(__amdgpu_buffer_rsrc_t r, int voff, int so, int cW,
-                                               int cH) {
-  const uint32_t a00 = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so, 0);
-  const uint32_t a01 = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so + cW, 0);
-  const uint32_t a10 = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so + cH, 0);
-  const uint32_t a11 = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so + cH + cW, 0);
-  return (a11 - a10) - (a01 - a00);
-}
-
-// Stages the pass's row intervals of one frame's sum table into LDS with
-// LDS-direct buffer loads: lane c4 of a wave moves 16 bytes of a row.
-template <int LP, int NW>
-__device__ __forceinline__ void stage_pass(__amdgpu_buffer_rsrc_t rs, int P,
-                                           const Interval *__restrict__ ivs, int iv_begin,
-                                           int iv_end, int u0, int v0, int stage_w4,
-                                           uint32_t *lds, int wave, int lane) {
-  for (int iv = iv_begin; iv < iv_end; ++iv) {
-    const Interval I = ivs[iv];
-    for (int j = wave; j < I.n_rows; j += NW) {
-      const int src = ((v0 + I.rel_row + j) * P + u0) * 4;
-      uint32_t *dst = lds + (I.lds_row + j) * LP;
-#pragma unroll
-      for (int c = 0; c < (LP / 4 + 63) / 64; ++c) {
-        if (c * 64 + lane < stage_w4)
-          __builtin_amdgcn_raw_ptr_buffer_load_lds(
-              rs, (__attribute__((address_space(3))) void *)(dst + c * 256), 16,
-              lane * 16 + c * 1024, src, 0, 0);
-      }
-    }
-  }
-  __builtin_amdgcn_s_waitcnt(0);
-}
-
-template <int RU, int RV, int NW, int LP, bool MAP>
-__device__ __forceinline__ void run_item(
-    const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
-    int P, int N, const PassDesc *__restrict__ passes, const Interval *__restrict__ ivs,
-    const TileRec *__restrict__ recs, const WorkItem &it, const PairDesc &pd,
-    const DevTmpl &td, u64 &lkey, int k, float *__restrict__ rho_out, int rho_pitch,
-    uint8_t *__restrict__ degen, uint32_t *lds, uint32_t *thr_sh, int wave, int lane) {
-  constexpr int BU = 64 * RU, BV = NW * RV, R = RU * RV;
-  const uint32_t bytes = (uint32_t)(N + 1) * (uint32_t)P * 4u;
-  const __amdgpu_buffer_rsrc_t rs = make_rsrc(s + (long long)pd.frame * frame_stride, bytes);
-  const __amdgpu_buffer_rsrc_t rs2 = make_rsrc(s2 + (long long)pd.frame * frame_stride, bytes);
-  const int W = td.W, H = td.H, n = td.n;
-  const float inv_n = 1.0f / (float)n;
-  const float qnf = (float)(td.q_k / (double)n);  // energy * q_k = V * q_k / n
-  const int stage_w4 = (BU + W + 1 + 3) >> 2;
-  const int lbase = wave * RV * LP + lane;
-  const int cW = W * 4, cH = H * P * 4;  // byte offsets of the window corners
-
-  for (int tile = it.tile_begin; tile < it.tile_end; ++tile) {
-    const int tv = tile / pd.ntu, tu = tile - tv * pd.ntu;
-    const int u0 = tu * BU, v0 = tv * BV;
-    const int voff = ((v0 + wave * RV) * P + u0 + lane) * 4;
-
-    // window sum (Eq. (13)) and the integer bias per offset; offsets outside
-    // the valid range read in-buffer garbage or zeros and are masked later
-    int nb[R];
-    float acc[R], cmp[R];
-#pragma unroll
-    for (int dv = 0; dv < RV; ++dv)
-#pragma unroll
-      for (int du = 0; du < RU; ++du) {
-        const int r = dv * RU + du;
-        const uint32_t sf = window_box(rs, voff + du * 256, dv * P * 4, cW, cH);
-        nb[r] = -(int)__builtin_rintf((float)sf * inv_n);
-        acc[r] = 0.f;
-        cmp[r] = 0.f;
-      }
-
-    // per-segment terms (Eqs. (11), (12)), pass by pass; the products of four
-    // segments are added before one compensated (Kahan) step
-    for (int p = td.pass_begin; p < td.pass_end; ++p) {
-      const PassDesc ps = passes[p];
-      __syncthreads();
-      stage_pass<LP, NW>(rs, P, ivs, ps.iv_begin, ps.iv_end, u0, v0, stage_w4, lds, wave,
-                         lane);
-      __syncthreads();
-      const TileRec *rp = recs + ps.seg_begin;
-      const int nseg = ps.seg_end - ps.seg_begin;
-      const int nseg4 = nseg & ~3;
-      // blocks of four segments; the next block's records are loaded one
-      // iteration ahead so that the scalar-load wait never stalls the first
-      // LDS reads of a block
-      TileRec nx[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) nx[q] = rp[min(q, nseg - 1)];
-#pragma unroll 2
-      for (int i = 0; i < nseg4; i += 4) {
-        TileRec e[4];
-        const uint32_t *tl[4], *bl[4], *tr[4], *br[4];
-        int A[4];
-        const int inext = min(i + 4, nseg4 - 4);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          e[q] = nx[q];
-          nx[q] = rp[inext + q];
-          const uint32_t wa = (uint32_t)e[q].w_area;
-          A[q] = (int)(wa >> 12);
-          tl[q] = lds + lbase + e[q].off_tl;
-          bl[q] = lds + lbase + e[q].off_bl;
-          tr[q] = tl[q] + (int)(wa & 0xfffu);
-          br[q] = bl[q] + (int)(wa & 0xfffu);
-        }
-#pragma unroll
-        for (int dv = 0; dv < RV; ++dv)
-#pragma unroll
-          for (int du = 0; du < RU; ++du) {
-            const int o = dv * LP + du * 64;
-            const int r = dv * RU + du;
-            float y = -cmp[r];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const uint32_t F = (br[q][o] - bl[q][o]) - (tr[q][o] - tl[q][o]);
-              const int G = (int)F + __mul24(A[q], nb[r]);
-              y = __builtin_fmaf((float)G, e[q].c, y);
-            }
-            const float t = acc[r] + y;
-            cmp[r] = (t - acc[r]) - y;
-            acc[r] = t;
-          }
-      }
-      // the last one to three segments, one compensated step each
-      for (int i = nseg4; i < nseg; ++i) {
-        const TileRec e = rp[i];
-        const uint32_t wa = (uint32_t)e.w_area;
-        const int A = (int)(wa >> 12);
-        const uint32_t *tl = lds + lbase + e.off_tl, *bl = lds + lbase + e.off_bl;
-        const uint32_t *tr = tl + (int)(wa & 0xfffu), *br = bl + (int)(wa & 0xfffu);
-#pragma unroll
-        for (int dv = 0; dv < RV; ++dv)
-#pragma unroll
-          for (int du = 0; du < RU; ++du) {
-            const int o = dv * LP + du * 64;
-            const int r = dv * RU + du;
-            const uint32_t F = (br[o] - bl[o]) - (tr[o] - tl[o]);
-            const int G = (int)F + __mul24(A, nb[r]);
-            const float y = __builtin_fmaf((float)G, e.c, -cmp[r]);
-            const float t = acc[r] + y;
-            cmp[r] = (t - acc[r]) - y;
-            acc[r] = t;
-          }
-      }
-    }
-
-    // epilogue: exact window energy V = n * Eq. (16) in 64-bit integers, then
-    // rho = num / sqrt(V q_k / n) (Eqs. (17), (18)) in FP32; every lane
-    // computes (out-of-range reads are harmless) and invalid offsets are masked
-    u64 cand[R];
-#pragma unroll
-    for (int dv = 0; dv < RV; ++dv)
-#pragma unroll
-      for (int du = 0; du < RU; ++du) {
-        const int r = dv * RU + du;
-        const int u = u0 + lane + 64 * du, v = v0 + wave * RV + dv;
-        const uint32_t sf = window_box(rs, voff + du * 256, dv * P * 4, cW, cH);
-        const uint32_t sf2 = window_box(rs2, voff + du * 256, dv * P * 4, cW, cH);
-        const u64 V = (u64)(uint32_t)n * sf2 - (u64)sf * sf;
-        const float x =
-            __builtin_fmaf((float)(uint32_t)(V >> 32), 4294967296.0f, (float)(uint32_t)V) * qnf;
-        const float rho = V == 0 ? 0.f : (acc[r] - cmp[r]) * __builtin_amdgcn_rsqf(x);
-        const bool ok = u < pd.nu && v < pd.nv;
-        if (MAP) {
-          if (ok) {
-            rho_out[(long long)v * rho_pitch + u] = rho;
-            if (degen) degen[(long long)v * rho_pitch + u] = V == 0 ? 1 : 0;
-          }
-        } else {
-          cand[r] = ok ? make_key(rho, v * pd.nu + u) : 0;
-        }
-      }
-    if (!MAP) {
-      // waves publish the high word of their k-th key (a 32-bit store, so
-      // readers see an old or a new value, never a mix); (largest, 0) is at
-      // most some wave's k-th key and filters every wave
-      uint32_t fh = 0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) fh = max(fh, thr_sh[w]);
-      topk_offer<R>(lkey, cand, k, lane, (u64)fh << 32);
-      if (lane == 0) thr_sh[wave] = (uint32_t)(lane_u64(lkey, k - 1) >> 32);
-    }
-  }
-}
-
-template <int RU, int RV, int NW, bool MAP>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void tile_kernel(
-    const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
-    int P, int N, const DevTmpl *__restrict__ tmpls, const PassDesc *__restrict__ passes,
-    const Interval *__restrict__ ivs, const TileRec *__restrict__ recs,
-    const PairDesc *__restrict__ pairs, const WorkItem *__restrict__ items,
-    const int *__restrict__ order, int n_items, int *__restrict__ queue, int k,
-    u64 *__restrict__ partial, float *__restrict__ rho_out, int rho_pitch,
-    uint8_t *__restrict__ degen) {
-  extern __shared__ __align__(16) uint32_t lds[];
-  __shared__ int item_sh;
-  __shared__ uint32_t thr_sh[NW];  // high words of the waves' k-th keys (current item)
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (;;) {
-    if (threadIdx.x == 0) item_sh = atomicAdd(queue, 1);
-    __syncthreads();
-    const int q = item_sh;
-    __syncthreads();
-    if (q >= n_items) break;
-    const int item = order[q];
-    const WorkItem it = items[item];
-    const PairDesc pd = pairs[it.pair];
-    const DevTmpl td = tmpls[pd.tmpl];
-    u64 lkey = 0;
-    if (lane == 0) thr_sh[wave] = 0;  // ordered before use by the first pass barrier
-#define SNCC_RUN(LPV)                                                                    \
-  run_item<RU, RV, NW, LPV, MAP>(s, s2, frame_stride, P, N, passes, ivs, recs, it, pd, td, \
-                                 lkey, k, rho_out, rho_pitch, degen, lds, thr_sh, wave, lane)
-    switch (td.lp_class) {
-      case 0: SNCC_RUN(128); break;
-      case 1: SNCC_RUN(192); break;
-      case 2: SNCC_RUN(256); break;
-      case 3: SNCC_RUN(320); break;
-      case 4: SNCC_RUN(384); break;
-      case 5: SNCC_RUN(448); break;
-      default: SNCC_RUN(576); break;
-    }
-#undef SNCC_RUN
-    if (!MAP) {
-      // merge the waves' lists into wave 0's and write the item's partial
-      u64 *buf = reinterpret_cast<u64 *>(lds);
-      __syncthreads();
-      if (lane < k) buf[wave * k + lane] = lkey;
-      __syncthreads();
-      if (wave == 0) {
-        u64 thr = lane_u64(lkey, k - 1);
-        for (int w = 1; w < NW; ++w) {
-          for (int j = 0; j < k; ++j) {
-            const u64 key = buf[w * k + j];
-            if (key <= thr) break;
-            topk_insert(lkey, key, k, lane);
-            thr = lane_u64(lkey, k - 1);
-          }
-        }
-        if (lane < k) partial[(long long)item * k + lane] = lkey;
-      }
-    }
-  }
-}
-
 struct TileEntry {
   int ru, rv, nw;
   const void *fn_map;
   const void *fn_topk;
 };
 
-#define SNCC_TILE_ENTRY(RU, RV, NW)                                                 \
-  TileEntry {                                                                       \
-    RU, RV, NW, reinterpret_cast<const void *>(&tile_kernel<RU, RV, NW, true>),     \
-        reinterpret_cast<const void *>(&tile_kernel<RU, RV, NW, false>)             \
-  }
-
+// One entry per tile shape (kTileShapes); the kernels live in the
+// translation units built from tile_entry.hip.
 static const TileEntry kTileEntries[] = {
-    SNCC_TILE_ENTRY(2, 4, 8),  // 0: 128 x 32 offsets
-    SNCC_TILE_ENTRY(2, 4, 4),  // 1: 128 x 16
-    SNCC_TILE_ENTRY(1, 8, 8),  // 2:  64 x 64
-    SNCC_TILE_ENTRY(2, 2, 8),  // 3: 128 x 16
-    SNCC_TILE_ENTRY(1, 4, 8),  // 4:  64 x 32
-    SNCC_TILE_ENTRY(1, 4, 4),  // 5:  64 x 16
+    {kTileShapes[0][0], kTileShapes[0][1], kTileShapes[0][2], tile_fn_0(true), tile_fn_0(false)},
+    {kTileShapes[1][0], kTileShapes[1][1], kTileShapes[1][2], tile_fn_1(true), tile_fn_1(false)},
+    {kTileShapes[2][0], kTileShapes[2][1], kTileShapes[2][2], tile_fn_2(true), tile_fn_2(false)},
+    {kTileShapes[3][0], kTileShapes[3][1], kTileShapes[3][2], tile_fn_3(true), tile_fn_3(false)},
+    {kTileShapes[4][0], kTileShapes[4][1], kTileShapes[4][2], tile_fn_4(true), tile_fn_4(false)},
+    {kTileShapes[5][0], kTileShapes[5][1], kTileShapes[5][2], tile_fn_5(true), tile_fn_5(false)},
 };
-static const int kNumTileEntries = sizeof(kTileEntries) / sizeof(kTileEntries[0]);
+static_assert(sizeof(kTileEntries) / sizeof(kTileEntries[0]) == kNumTileShapes,
+              "one table entry per tile shape");
+static const int kNumTileEntries = kNumTileShapes;
 
 // Tile configurations the planner and the tuner choose from: kernel entry
 // and workgroups per CU the LDS budget is sized for.
@@ -679,7 +319,7 @@ int launch_tile(int cfg, bool map_sink, const TileArgs &a, int grid, int lds_byt
     attr_done[map_sink][ent] = true;
   }
   long long fs = a.frame_stride;
-  int P = a.sat_pitch, N = a.N, n_items = a.n_items, k = a.k, rp = a.rho_pitch;
+  int P = a.sat_pitch, N = a.N, nq = a.nq, k = a.k, rp = a.rho_pitch;
   const uint32_t *s = a.s, *s2 = a.s2;
   const DevTmpl *tm = a.tmpls;
   const PassDesc *ps = a.passes;
@@ -687,13 +327,14 @@ int launch_tile(int cfg, bool map_sink, const TileArgs &a, int grid, int lds_byt
   const TileRec *rc = a.recs;
   const PairDesc *pr = a.pairs;
   const WorkItem *it = a.items;
-  const int *ord = a.order;
+  const int *ord = a.order, *qbeg = a.qbeg;
   int *queue = a.queue;
-  u64 *partial = a.partial;
+  u64 *partial = a.partial, *pfloor = a.pair_floor;
   float *rho = static_cast<float *>(a.rho);
   uint8_t *dg = a.degen;
   void *args[] = {&s,  &s2, &fs, &P,  &N,     &tm,      &ps,  &iv,  &rc,  &pr,
-                  &it, &ord, &n_items, &queue, &k, &partial, &rho, &rp, &dg};
+                  &it, &ord, &qbeg, &nq, &queue, &k, &partial, &pfloor, &rho, &rp,
+                  &dg};
   hipError_t err = hipLaunchKernel(fn, dim3(grid), dim3(tile_cfg(cfg).threads()), args,
                                    (size_t)lds_bytes, st);
   return err == hipSuccess ? 0 : -1;

@@ -84,14 +84,20 @@ struct TileArgs {
   const TileRec *recs;
   const PairDesc *pairs;
   const WorkItem *items;
-  const int *order;        // execution order of items
+  const int *order;        // execution order of items, queue by queue
+  const int *qbeg;         // nq + 1 offsets into order
+  int nq;                  // work queues (1..kMaxQueues)
   int n_items;
-  int *queue;              // work counter, zero at launch
+  int *queue;              // counters at queue[16 j], then (TOPK sink) the
+                           // pair floors; kQueueInts + 2 n_pairs ints zeroed
+                           // at launch
   int k;                   // top-k (TOPK sink)
   unsigned long long *partial;  // n_items x k keys (TOPK sink)
+  unsigned long long *pair_floor;  // n_pairs keys, zero at launch (TOPK sink)
   void *rho;               // MAP sink: float map
   int rho_pitch;
   uint8_t *degen;          // MAP sink: nullable
+  int n_zero;              // ints of `queue` to zero before a launch (host side)
 };
 
 // Kernel arguments of the plain FP64 per-pair kernel.
@@ -123,8 +129,33 @@ struct TileCfg {
   int threads() const { return 64 * nw; }
 };
 
-constexpr int kNumLpClasses = 7;
-constexpr int kLpClasses[kNumLpClasses] = {128, 192, 256, 320, 384, 448, 576};
+constexpr int kMaxQueues = 8;  // one per XCD of an MI355X
+constexpr int kQueueInts = 16 * kMaxQueues;
+
+// LDS row pitches (words) the scoring kernel is compiled for; a template
+// uses the smallest one that holds a tile's staged row (tile width + W + 1,
+// rounded up to 16 bytes).
+constexpr int kNumLpClasses = 11;
+constexpr int kLpClasses[kNumLpClasses] = {128, 160, 192, 224, 256, 288, 320, 384, 448, 512, 576};
+
+// Tile shapes of the scoring kernel: offsets per lane along u (RU) and v
+// (RV) and waves per workgroup (NW); a tile is 64 RU x NW RV offsets.
+constexpr int kNumTileShapes = 6;
+constexpr int kTileShapes[kNumTileShapes][3] = {
+    {2, 4, 8},  // 128 x 32
+    {2, 4, 4},  // 128 x 16
+    {1, 8, 8},  //  64 x 64
+    {2, 2, 8},  // 128 x 16
+    {1, 4, 8},  //  64 x 32
+    {1, 4, 4},  //  64 x 16
+};
+// Host stubs of tile shape i's kernels (tile_entry.hip): rho-map or top-k sink.
+const void *tile_fn_0(bool map_sink);
+const void *tile_fn_1(bool map_sink);
+const void *tile_fn_2(bool map_sink);
+const void *tile_fn_3(bool map_sink);
+const void *tile_fn_4(bool map_sink);
+const void *tile_fn_5(bool map_sink);
 
 // Launch wrappers (kernels.hip).
 int launch_sat(const uint8_t *f, int B, int M, int N, int f_pitch, uint32_t *s,

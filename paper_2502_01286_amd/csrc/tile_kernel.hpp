@@ -1,0 +1,321 @@
+// The persistent scoring kernel (Eqs. (11)-(18)), templated on the tile
+// shape: RU x RV offsets per lane, NW waves, LDS row pitch LP (words) and the
+// sink (rho map or per-item top-k partials).  Each tile shape is compiled in
+// its own translation unit (tile_entry.hip).
+#pragma once
+
+#include "device_util.hpp"
+
+namespace sncc {
+
+static_assert(kNumLpClasses == 11, "the LP-class switch in tile_kernel lists 11 cases");
+
+// Stages the pass's row intervals of one frame's sum table into LDS with
+// LDS-direct buffer loads: lane c4 of a wave moves 16 bytes of a row.
+template <int LP, int NW>
+__device__ __forceinline__ void stage_pass(__amdgpu_buffer_rsrc_t rs, int P,
+                                           const Interval *__restrict__ ivs, int iv_begin,
+                                           int iv_end, int u0, int v0, int stage_w4,
+                                           uint32_t *lds, int wave, int lane) {
+  for (int iv = iv_begin; iv < iv_end; ++iv) {
+    const Interval I = ivs[iv];
+    for (int j = wave; j < I.n_rows; j += NW) {
+      const int src = ((v0 + I.rel_row + j) * P + u0) * 4;
+      uint32_t *dst = lds + (I.lds_row + j) * LP;
+#pragma unroll
+      for (int c = 0; c < (LP / 4 + 63) / 64; ++c) {
+        if (c * 64 + lane < stage_w4)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(
+              rs, (__attribute__((address_space(3))) void *)(dst + c * 256), 16,
+              lane * 16 + c * 1024, src, 0, 0);
+      }
+    }
+  }
+}
+
+template <int RU, int RV, int NW, int LP, bool MAP>
+__device__ __forceinline__ void run_item(
+    const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
+    int P, int N, const PassDesc *__restrict__ passes, const Interval *__restrict__ ivs,
+    const TileRec *__restrict__ recs, const WorkItem &it, const PairDesc &pd,
+    const DevTmpl &td, u64 &lkey, int k, float *__restrict__ rho_out, int rho_pitch,
+    uint8_t *__restrict__ degen, uint32_t *lds, float *scl, uint32_t *thr_sh, int wave,
+    int lane) {
+  constexpr int BU = 64 * RU, BV = NW * RV, R = RU * RV;
+  // per-offset scales live in LDS (thread-private slots) from the prologue to
+  // the epilogue, which keeps them out of registers during the segment loop
+  float *const my_sc = scl + wave * 64 + lane;
+  const uint32_t bytes = (uint32_t)(N + 1) * (uint32_t)P * 4u;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(s + (long long)pd.frame * frame_stride, bytes);
+  const __amdgpu_buffer_rsrc_t rs2 = make_rsrc(s2 + (long long)pd.frame * frame_stride, bytes);
+  const int W = td.W, H = td.H, n = td.n;
+  const float inv_n = 1.0f / (float)n;
+  const float qnf = (float)(td.q_k / (double)n);  // energy * q_k = V * q_k / n
+  const int stage_w4 = (BU + W + 1 + 3) >> 2;
+  const int lbase = wave * RV * LP + lane;
+  const int cW = W * 4, cH = H * P * 4;  // byte offsets of the window corners
+
+  for (int tile = it.tile_begin; tile < it.tile_end; ++tile) {
+    const int tv = tile / pd.ntu, tu = tile - tv * pd.ntu;
+    const int u0 = tu * BU, v0 = tv * BV;
+    const int voff = ((v0 + wave * RV) * P + u0 + lane) * 4;
+
+    // the first pass's rows are requested before the prologue's loads so
+    // that both latencies overlap
+    __syncthreads();
+    {
+      const PassDesc ps = passes[td.pass_begin];
+      stage_pass<LP, NW>(rs, P, ivs, ps.iv_begin, ps.iv_end, u0, v0, stage_w4, lds, wave,
+                         lane);
+    }
+
+    // per offset: window sums of f and f^2 (Eqs. (13), (15)), the integer
+    // bias, and the scale 1 / sqrt(V q_k / n) from the exact window energy
+    // V = n * Eq. (16) in 64-bit integers (0 when V = 0).  The loads are
+    // issued before the first staging wait so that their latency overlaps
+    // it; offsets outside the valid range read in-buffer values and are
+    // masked in the epilogue
+    int nb[R];
+    float acc[R], cmp[R];
+#pragma unroll
+    for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+      for (int du = 0; du < RU; ++du) {
+        const int r = dv * RU + du;
+        const uint32_t sf = window_box(rs, voff + du * 256, dv * P * 4, cW, cH);
+        const uint32_t sf2 = window_box(rs2, voff + du * 256, dv * P * 4, cW, cH);
+        nb[r] = -(int)__builtin_rintf((float)sf * inv_n);
+        const u64 V = (u64)(uint32_t)n * sf2 - (u64)sf * sf;
+        const float x =
+            __builtin_fmaf((float)(uint32_t)(V >> 32), 4294967296.0f, (float)(uint32_t)V) * qnf;
+        my_sc[r * NW * 64] = V == 0 ? 0.f : __builtin_amdgcn_rsqf(x);
+        acc[r] = 0.f;
+        cmp[r] = 0.f;
+      }
+
+    // per-segment terms (Eqs. (11), (12)), pass by pass; the products of four
+    // segments are added before one compensated (Kahan) step
+    for (int p = td.pass_begin; p < td.pass_end; ++p) {
+      const PassDesc ps = passes[p];
+      if (p != td.pass_begin) {
+        __syncthreads();
+        stage_pass<LP, NW>(rs, P, ivs, ps.iv_begin, ps.iv_end, u0, v0, stage_w4, lds, wave,
+                           lane);
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      const TileRec *rp = recs + ps.seg_begin;
+      const int nseg = ps.seg_end - ps.seg_begin;
+      const int nseg4 = nseg & ~3;
+      // blocks of four segments; the next block's records are loaded one
+      // iteration ahead so that the scalar-load wait never stalls the first
+      // LDS reads of a block
+      TileRec nx[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) nx[q] = rp[min(q, nseg - 1)];
+#pragma unroll 2
+      for (int i = 0; i < nseg4; i += 4) {
+        TileRec e[4];
+        const uint32_t *tl[4], *bl[4], *tr[4], *br[4];
+        int A[4];
+        const int inext = min(i + 4, nseg4 - 4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          e[q] = nx[q];
+          nx[q] = rp[inext + q];
+          const uint32_t wa = (uint32_t)e[q].w_area;
+          A[q] = (int)(wa >> 12);
+          tl[q] = lds + lbase + e[q].off_tl;
+          bl[q] = lds + lbase + e[q].off_bl;
+          tr[q] = tl[q] + (int)(wa & 0xfffu);
+          br[q] = bl[q] + (int)(wa & 0xfffu);
+        }
+#pragma unroll
+        for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+          for (int du = 0; du < RU; ++du) {
+            const int o = dv * LP + du * 64;
+            const int r = dv * RU + du;
+            float y = -cmp[r];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const uint32_t F = (br[q][o] - bl[q][o]) - (tr[q][o] - tl[q][o]);
+              const int G = (int)F + __mul24(A[q], nb[r]);
+              y = __builtin_fmaf((float)G, e[q].c, y);
+            }
+            const float t = acc[r] + y;
+            cmp[r] = (t - acc[r]) - y;
+            acc[r] = t;
+          }
+      }
+      // the last one to three segments, one compensated step each
+      for (int i = nseg4; i < nseg; ++i) {
+        const TileRec e = rp[i];
+        const uint32_t wa = (uint32_t)e.w_area;
+        const int A = (int)(wa >> 12);
+        const uint32_t *tl = lds + lbase + e.off_tl, *bl = lds + lbase + e.off_bl;
+        const uint32_t *tr = tl + (int)(wa & 0xfffu), *br = bl + (int)(wa & 0xfffu);
+#pragma unroll
+        for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+          for (int du = 0; du < RU; ++du) {
+            const int o = dv * LP + du * 64;
+            const int r = dv * RU + du;
+            const uint32_t F = (br[o] - bl[o]) - (tr[o] - tl[o]);
+            const int G = (int)F + __mul24(A, nb[r]);
+            const float y = __builtin_fmaf((float)G, e.c, -cmp[r]);
+            const float t = acc[r] + y;
+            cmp[r] = (t - acc[r]) - y;
+            acc[r] = t;
+          }
+      }
+    }
+
+    // epilogue: rho = num / sqrt(V q_k / n) (Eqs. (17), (18)) in FP32
+    if (MAP) {
+#pragma unroll
+      for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+        for (int du = 0; du < RU; ++du) {
+          const int r = dv * RU + du;
+          const int u = u0 + lane + 64 * du, v = v0 + wave * RV + dv;
+          const float sc = my_sc[r * NW * 64];
+          if (u < pd.nu && v < pd.nv) {
+            rho_out[(long long)v * rho_pitch + u] = (acc[r] - cmp[r]) * sc;
+            if (degen) degen[(long long)v * rho_pitch + u] = sc == 0.f ? 1 : 0;
+          }
+        }
+    } else {
+      // waves publish the high word of their k-th key (a 32-bit store, so
+      // readers see an old or a new value, never a mix); (largest, 0) is at
+      // most some wave's k-th key and filters every wave.  A float test
+      // against that high word (never stricter than the key test) skips key
+      // building for tiles with no candidate
+      uint32_t fh = (uint32_t)(lane_u64(lkey, k - 1) >> 32);
+#pragma unroll
+      for (int w = 0; w < NW; ++w) fh = max(fh, thr_sh[w]);
+      const float fth = fh <= 0x007fffffu ? -__builtin_inff() : float_unorder(fh);
+      float rho[R];
+      bool any = false;
+#pragma unroll
+      for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+        for (int du = 0; du < RU; ++du) {
+          const int r = dv * RU + du;
+          const int u = u0 + lane + 64 * du, v = v0 + wave * RV + dv;
+          rho[r] = (u < pd.nu && v < pd.nv) ? (acc[r] - cmp[r]) * my_sc[r * NW * 64]
+                                            : -__builtin_inff();
+          any |= rho[r] >= fth;
+        }
+      if (__ballot(any) != 0) {
+        u64 cand[R];
+#pragma unroll
+        for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+          for (int du = 0; du < RU; ++du) {
+            const int r = dv * RU + du;
+            const int u = u0 + lane + 64 * du, v = v0 + wave * RV + dv;
+            cand[r] = rho[r] >= fth && rho[r] != -__builtin_inff()
+                          ? make_key(rho[r], v * pd.nu + u) : 0;
+          }
+        topk_offer<R>(lkey, cand, k, lane, (u64)fh << 32);
+        if (lane == 0) thr_sh[wave] = (uint32_t)(lane_u64(lkey, k - 1) >> 32);
+      }
+    }
+  }
+}
+
+template <int RU, int RV, int NW, bool MAP>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void tile_kernel(
+    const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
+    int P, int N, const DevTmpl *__restrict__ tmpls, const PassDesc *__restrict__ passes,
+    const Interval *__restrict__ ivs, const TileRec *__restrict__ recs,
+    const PairDesc *__restrict__ pairs, const WorkItem *__restrict__ items,
+    const int *__restrict__ order, const int *__restrict__ qbeg, int nq,
+    int *__restrict__ queue, int k, u64 *__restrict__ partial, u64 *__restrict__ pair_floor,
+    float *__restrict__ rho_out, int rho_pitch, uint8_t *__restrict__ degen) {
+  // dynamic LDS: per-offset scales (R words per thread), then the staged rows
+  extern __shared__ __align__(16) uint32_t lds[];
+  constexpr int kScaleWords = 64 * NW * RU * RV;
+  __shared__ int item_sh;
+  __shared__ uint32_t floor_sh;     // high word of the pair's published floor
+  __shared__ uint32_t thr_sh[NW];  // high words of the waves' k-th keys (current item)
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // Work queues: queue j holds order[qbeg[j] .. qbeg[j + 1]) and its counter
+  // sits at queue[16 j].  A workgroup drains the queue of the chiplet (XCD)
+  // it runs on, whose L2 then holds the frame rows that queue's items share,
+  // and then the others in turn; every workgroup leaves once it has found
+  // all queues empty.
+  const int home = (int)(__builtin_amdgcn_s_getreg(20 | (3 << 11)) & 15) % nq;
+  int tried = 0;  // queues found empty (thread 0)
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int got = -1;
+      while (tried < nq) {
+        const int qq = (home + tried) % nq;
+        const int i = atomicAdd(queue + 16 * qq, 1);
+        if (i < qbeg[qq + 1] - qbeg[qq]) {
+          got = order[qbeg[qq] + i];
+          break;
+        }
+        ++tried;
+      }
+      item_sh = got;
+      // a key below the k-th key of another item of the same pair cannot be
+      // in the pair's top k; items publish theirs when they finish
+      if (!MAP && got >= 0)
+        floor_sh = (uint32_t)(__hip_atomic_load(pair_floor + items[got].pair, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT) >> 32);
+    }
+    __syncthreads();
+    const int item = item_sh;
+    __syncthreads();
+    if (item < 0) break;
+    const WorkItem it = items[item];
+    const PairDesc pd = pairs[it.pair];
+    const DevTmpl td = tmpls[pd.tmpl];
+    u64 lkey = 0;
+    if (lane == 0) thr_sh[wave] = MAP ? 0u : floor_sh;  // ordered by the first pass barrier
+#define SNCC_RUN(LPV)                                                                    \
+  run_item<RU, RV, NW, LPV, MAP>(s, s2, frame_stride, P, N, passes, ivs, recs, it, pd, td, \
+                                 lkey, k, rho_out, rho_pitch, degen, lds + kScaleWords,      \
+                                 reinterpret_cast<float *>(lds), thr_sh, wave, lane)
+    switch (td.lp_class) {
+      case 0: SNCC_RUN(kLpClasses[0]); break;
+      case 1: SNCC_RUN(kLpClasses[1]); break;
+      case 2: SNCC_RUN(kLpClasses[2]); break;
+      case 3: SNCC_RUN(kLpClasses[3]); break;
+      case 4: SNCC_RUN(kLpClasses[4]); break;
+      case 5: SNCC_RUN(kLpClasses[5]); break;
+      case 6: SNCC_RUN(kLpClasses[6]); break;
+      case 7: SNCC_RUN(kLpClasses[7]); break;
+      case 8: SNCC_RUN(kLpClasses[8]); break;
+      case 9: SNCC_RUN(kLpClasses[9]); break;
+      default: SNCC_RUN(kLpClasses[10]); break;
+    }
+#undef SNCC_RUN
+    if (!MAP) {
+      // merge the waves' lists into wave 0's and write the item's partial
+      u64 *buf = reinterpret_cast<u64 *>(lds);
+      __syncthreads();
+      if (lane < k) buf[wave * k + lane] = lkey;
+      __syncthreads();
+      if (wave == 0) {
+        u64 thr = lane_u64(lkey, k - 1);
+        for (int w = 1; w < NW; ++w) {
+          for (int j = 0; j < k; ++j) {
+            const u64 key = buf[w * k + j];
+            if (key <= thr) break;
+            topk_insert(lkey, key, k, lane);
+            thr = lane_u64(lkey, k - 1);
+          }
+        }
+        if (lane < k) partial[(long long)item * k + lane] = lkey;
+        const u64 kth = lane_u64(lkey, k - 1);
+        if (lane == 0 && kth != 0) atomicMax(pair_floor + it.pair, kth);
+      }
+    }
+  }
+}
+
+}  // namespace sncc
