@@ -45,25 +45,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("tile_kernel.hpp", "device_util.hpp", "tile_entry.hip", "sncc_internal.hpp")
+
+
 def kernel_source_hash():
+    """First 16 hex digits of the SHA-256 over the scoring kernel's sources."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2502_01286_amd", "csrc", "kernels.hip"), "rb") as fh:
-        h.update(fh.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2502_01286_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def load_traffic(workload):
-    """HBM bytes per scoring launch from committed rocprofv3 --pmc summaries
-    (FETCH_SIZE, WRITE_SIZE, scaled by a copy kernel of known size), or None
-    when they were taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"tile_kernel_{workload}_traffic.json")
+    """HBM bytes per scoring launch from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
+    copy kernel of known size), or None when it was taken on another kernel
+    source.  The summary is text: `key: value` lines, `#` comments."""
+    path = os.path.join(ROOT, "profiles", f"tile_kernel_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
+    d = {}
     with open(path) as fh:
-        d = json.load(fh)
-    if d.get("kernels_hip_sha256_16") != kernel_source_hash():
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#") and ":" in line:
+                key, val = line.split(":", 1)
+                d[key.strip()] = val.strip()
+    if d.get("kernel_sources_sha256_16") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch")
+    try:
+        return int(d["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def make_workload(name):
@@ -295,7 +309,8 @@ def main():
                    "coarse_sigma": sorted(set(wl.sigmas)), "fine_sigma": wl.fine_sigma,
                    "K_coarse": [min(Kc), max(Kc)], "coarse_evals": evals,
                    "fine_offsets_scored": fine_offsets,
-                   "arith": "u32 box sums, f32 compensated accumulation, f64 epilogue/refine"},
+                   "arith": "u32 box sums, i64 window energy, f32 compensated accumulation "
+                            "and f32 rho (coarse), f64 refine"},
         "frames_per_s": B / (ms_per_step / 1e3),
         "stage_ms": avg, "prep_ms_host": prep_ms,
         "roofline": roof, "plain_fp64": plain, "cpu_baseline": cpu,

@@ -29,7 +29,9 @@ Readings taken where the paper is silent or inconsistent:
 
 Parity status per function: every public function is pinned by the CPU tests
 under ``tests/`` (brute-force Eq. (1), closed forms, invariants, hand-derived
-golden fixtures).  ``coarse_fine`` is pinned only through its parts; the quality
+golden fixtures).  ``threshold_match`` is pinned against brute-force Eq. (1)
+maps of both approximation images and a planted copy.  ``coarse_fine`` is
+pinned only through its parts; the quality
 of the coarse-to-fine heuristic itself (whether it finds the global maximum) has
 no reference value: parity unpinned for that property.
 """
@@ -50,7 +52,7 @@ from .ncc import (
     rho_map,
     brute_ncc_map,
 )
-from .select import topk, argmax, top2_margin, coarse_fine
+from .select import topk, argmax, top2_margin, coarse_fine, paper_sigmas, threshold_match
 
 __all__ = [
     "Segment",
@@ -69,4 +71,6 @@ __all__ = [
     "argmax",
     "top2_margin",
     "coarse_fine",
+    "paper_sigmas",
+    "threshold_match",
 ]

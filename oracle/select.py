@@ -1,4 +1,5 @@
-"""Selection of matches: top-K, argmax and the coarse-to-fine refinement.
+"""Selection of matches: top-K, argmax, the coarse-to-fine refinement and the
+paper's own two-threshold search.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -86,3 +87,47 @@ def coarse_fine(s, s2, coarse: TemplateApprox, fine: TemplateApprox,
         "fine_rho": fr,
         "best": (int(cu[best]), int(cv[best]), float(fr[best])),
     }
+
+
+def paper_sigmas(t: np.ndarray, fast: float = 0.99, slow: float = 0.1):
+    """Section 5's experimental thresholds relative to the template:
+    sigma_max,fast = 0.99 sigma_t and sigma_max,slow = 0.1 sigma_t, with
+    sigma_t the population standard deviation of t (as in Eq. (2))."""
+    tf = np.asarray(t, dtype=np.float64)
+    sigma_t = float(np.sqrt(((tf - tf.mean()) ** 2).mean()))
+    return fast * sigma_t, slow * sigma_t
+
+
+def threshold_match(s, s2, fast: TemplateApprox, slow: TemplateApprox, M: int, N: int,
+                    precision: float = 0.9, thr_fast=None, thr_slow=None, fast_map=None):
+    """The matching algorithm of Section 5, steps 5 and 7a-j.
+
+    threshold_fast = precision * rho_fast and threshold_slow = precision *
+    rho_slow, where rho_fast and rho_slow are the NCCs of the two
+    approximations with the template (the second output of
+    precompute_template_approximation), unless given explicitly.  At every
+    offset rho is computed with the fast approximation; offsets with
+    rho < threshold_fast are skipped; the others are scored again with the
+    slow approximation and appended to the matches when that rho is at least
+    threshold_slow.
+
+    Returns a dict: thresholds, the fast survivors (arrays u, v, rho_fast) and
+    the matches as (u, v, rho_slow) triplets in row-major offset order.
+    """
+    if (fast.W, fast.H) != (slow.W, slow.H):
+        raise ValueError("fast and slow approximations differ in size")
+    tf = precision * fast.rho_max if thr_fast is None else float(thr_fast)
+    ts = precision * slow.rho_max if thr_slow is None else float(thr_slow)
+    nu, nv = M - fast.W + 1, N - fast.H + 1
+    if fast_map is None:
+        vv, uu = np.meshgrid(np.arange(nv), np.arange(nu), indexing="ij")
+        fast_map = rho_at(s, s2, fast, uu, vv)
+    keep = np.asarray(fast_map) >= tf          # step 7f: skip rho < threshold_fast
+    cv, cu = np.nonzero(keep)                  # row-major order
+    rf = np.asarray(fast_map)[cv, cu]
+    rs = rho_at(s, s2, slow, cu, cv) if len(cu) else np.zeros(0)
+    hit = rs >= ts                             # step 7j
+    matches = [(int(u), int(v), float(r)) for u, v, r in zip(cu[hit], cv[hit], rs[hit])]
+    return {"thr_fast": tf, "thr_slow": ts, "cand_u": cu.astype(np.int64),
+            "cand_v": cv.astype(np.int64), "cand_rho": rf, "cand_rho_slow": rs,
+            "matches": matches}

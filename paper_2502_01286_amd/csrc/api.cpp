@@ -1206,11 +1206,11 @@ int sncc_batch_stats_get(sncc_batch *b, sncc_batch_stats *st) {
   st->timed = b->timed ? 1 : 0;
   st->ms_sat = st->ms_score = st->ms_select = st->ms_refine = st->ms_total = -1.f;
   if (b->timed && hipEventQuery(b->ev[4]) == hipSuccess) {
-    hipEventElapsedTime(&st->ms_sat, b->ev[0], b->ev[1]);
-    hipEventElapsedTime(&st->ms_score, b->ev[1], b->ev[2]);
-    hipEventElapsedTime(&st->ms_select, b->ev[2], b->ev[3]);
-    hipEventElapsedTime(&st->ms_refine, b->ev[3], b->ev[4]);
-    hipEventElapsedTime(&st->ms_total, b->ev[0], b->ev[4]);
+    (void)hipEventElapsedTime(&st->ms_sat, b->ev[0], b->ev[1]);
+    (void)hipEventElapsedTime(&st->ms_score, b->ev[1], b->ev[2]);
+    (void)hipEventElapsedTime(&st->ms_select, b->ev[2], b->ev[3]);
+    (void)hipEventElapsedTime(&st->ms_refine, b->ev[3], b->ev[4]);
+    (void)hipEventElapsedTime(&st->ms_total, b->ev[0], b->ev[4]);
     (void)hipGetLastError();
   }
   return SNCC_OK;

@@ -20,6 +20,7 @@ import pytest
 import oracle as O
 from oracle import ncc as ONCC
 from oracle import segmentation as OSEG
+from oracle import select as OSEL
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -339,6 +340,66 @@ def test_z1_unweighted_denominator_breaks_the_ncc_bound():
     assert rho_w == pytest.approx(1.0, abs=1e-12) and rho_unw > 1.0
 
 
+# ------------------------------------ the paper's two-threshold search (Sec. 5)
+def test_paper_sigmas_population_std():
+    t = (np.indices((6, 8)).sum(0) % 2 * 2).astype(np.uint8)   # 0/2 checker: std 1
+    sf, ss = O.paper_sigmas(t)
+    assert sf == pytest.approx(0.99, abs=1e-15) and ss == pytest.approx(0.1, abs=1e-15)
+
+
+def _threshold_case(seed):
+    rng = np.random.default_rng(500 + seed)
+    f, t, x, y = _rand_case(500 + seed, M=34, N=26, W=7, H=6, smooth=seed % 2 == 1)
+    f[y:y + 6, x:x + 7] = t                    # an exact copy of t at (x, y)
+    sf, ss = O.paper_sigmas(t)
+    fast = O.precompute_template_approximation(t, sf)
+    slow = O.precompute_template_approximation(t, ss)
+    return f, t, x, y, fast, slow
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_threshold_match_equals_brute_force(seed):
+    """Survivors and matches equal the offsets where brute-force Eq. (1) with
+    the fast and slow approximation images clears both thresholds."""
+    f, t, x, y, fast, slow = _threshold_case(seed)
+    N, M = f.shape
+    s, s2 = O.sum_tables(f)
+    for precision in (0.9, 0.5):
+        res = O.threshold_match(s, s2, fast, slow, M, N, precision=precision)
+        bf = O.brute_ncc_map(f, O.approximation_image(fast.W, fast.H, fast.segments))
+        bs = O.brute_ncc_map(f, O.approximation_image(slow.W, slow.H, slow.segments))
+        bf, bs = np.nan_to_num(bf, nan=0.0), np.nan_to_num(bs, nan=0.0)
+        tf, ts = precision * fast.rho_max, precision * slow.rho_max
+        assert res["thr_fast"] == tf and res["thr_slow"] == ts
+        clear = (np.abs(bf - tf) > 1e-9) & (np.abs(bs - ts) > 1e-9)
+        want_c = {(u, v) for v, u in zip(*np.nonzero((bf >= tf) & clear))}
+        got_c = {(int(u), int(v)) for u, v in zip(res["cand_u"], res["cand_v"])
+                 if clear[v, u]}
+        assert got_c == want_c
+        want_m = {(u, v) for v, u in zip(*np.nonzero((bf >= tf) & (bs >= ts) & clear))}
+        got = {(u, v): r for u, v, r in res["matches"]}
+        assert {k for k in got if clear[k[1], k[0]]} == want_m
+        for (u, v), r in got.items():
+            assert r == pytest.approx(bs[v, u], abs=1e-12)
+        assert (x, y) in got                   # the copy is always found
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_threshold_match_planted_copy(seed):
+    f, t, x, y, fast, slow = _threshold_case(10 + seed)
+    N, M = f.shape
+    s, s2 = O.sum_tables(f)
+    res = O.threshold_match(s, s2, fast, slow, M, N)
+    i = [k for k, (u, v) in enumerate(zip(res["cand_u"], res["cand_v"])) if (u, v) == (x, y)]
+    assert len(i) == 1
+    assert res["cand_rho"][i[0]] == pytest.approx(math.sqrt(fast.q_k / fast.q_t), abs=1e-12)
+    got = {(u, v): r for u, v, r in res["matches"]}
+    assert got[(x, y)] == pytest.approx(math.sqrt(slow.q_k / slow.q_t), abs=1e-12)
+    # matches are a subset of the survivors, in row-major order
+    keys = [(v, u) for u, v, _ in res["matches"]]
+    assert keys == sorted(keys)
+
+
 # ----------------------------------------------- planted mistakes are caught
 def _pins_pass():
     """A compact run of the pins above; returns False on the first failure."""
@@ -353,7 +414,9 @@ def _pins_pass():
         test_p4_piecewise_constant_template_scores_one()
         for seed in range(6):
             test_p7_partition_invariants(seed)
-    except (AssertionError, ValueError, IndexError):
+        test_threshold_match_equals_brute_force(0)
+        test_threshold_match_planted_copy(0)
+    except (AssertionError, ValueError, IndexError, KeyError):
         return False
     return True
 
@@ -388,6 +451,14 @@ MUTANTS = {
                             "k[i].x == k[j].x"),
     "mean_term_uses_wrong_area": (ONCC, "_rho",
                                   "b -= fbar * seg.area", "b -= fbar * seg.w"),
+    "fast_test_inverted": (OSEL, "threshold_match",
+                           "keep = np.asarray(fast_map) >= tf",
+                           "keep = np.asarray(fast_map) > -tf"),
+    "slow_rescored_with_fast": (OSEL, "threshold_match",
+                                "rs = rho_at(s, s2, slow, cu, cv)",
+                                "rs = rho_at(s, s2, fast, cu, cv)"),
+    "thresholds_swapped": (OSEL, "threshold_match",
+                           "tf = precision * fast.rho_max", "tf = precision * slow.rho_max"),
 }
 
 
