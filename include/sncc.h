@@ -74,6 +74,15 @@ typedef struct sncc_match64 {
   double rho;
 } sncc_match64;
 
+/* An entry of the two-threshold search's output (Section 5, step 7j): the
+ * index of the (frame, template) pair, the offset and rho. */
+typedef struct sncc_hit {
+  int32_t pair;
+  int32_t u, v;
+  int32_t reserved;  /* zero */
+  double rho;
+} sncc_hit;
+
 typedef struct sncc_ctx sncc_ctx;
 typedef struct sncc_tmpl sncc_tmpl;
 typedef struct sncc_batch sncc_batch;
@@ -236,6 +245,38 @@ int sncc_refine(sncc_ctx *ctx, const sncc_tmpl *fine, const uint32_t *d_s,
                 const uint32_t *d_s2, int B, int M, int N, int sat_pitch,
                 int n_pairs, const int32_t *pairs, const sncc_match *d_cand,
                 int n_cand, int radius, sncc_match64 *d_out, int32_t *d_count);
+
+/*
+ * The matching algorithm of Section 5 as printed (steps 5 and 7a-j), over
+ * pairs: rho with the fast approximation at every offset (FP32 compensated,
+ * one persistent launch); offsets with rho >= thr_fast[template] survive and
+ * are compacted into d_cand; each survivor is scored again with the slow
+ * approximation in FP64 and appended to d_out when that rho is at least
+ * thr_slow[template].  The paper sets the thresholds to precision (0.9)
+ * times the NCC of each approximation with its template (rho_max of
+ * sncc_segment_template) and builds the approximations with sigma_max of
+ * 0.99 and 0.1 times the template's standard deviation.  The fast test is
+ * taken on the FP32 rho against the threshold rounded to FP32.
+ *
+ *   fast, slow   template sets of equal sizes (same indices)
+ *   thr_fast, thr_slow  host, one finite threshold per template
+ *   pairs        host, n_pairs x {frame, template}
+ *   d_cand       device, cand_cap entries: survivors of the fast test with
+ *                rho = the FP32 fast rho (scratch the caller owns)
+ *   d_out        device, out_cap entries: matches with rho = the slow rho
+ *   d_counts     device, 2 int32: survivors and matches found; either may
+ *                exceed its capacity, and entries beyond it are not written
+ *                (the slow pass then sees only the first cand_cap survivors)
+ * Entries come in no particular order.
+ * Errors: SNCC_EINVAL (NULL, sizes, thresholds, capacities < 1, alignment),
+ *         SNCC_EDEVICE, SNCC_ENOMEM.
+ */
+int sncc_threshold_match(sncc_ctx *ctx, const sncc_tmpl *fast, const sncc_tmpl *slow,
+                         const double *thr_fast, const double *thr_slow,
+                         const uint32_t *d_s, const uint32_t *d_s2, int B, int M, int N,
+                         int sat_pitch, int n_pairs, const int32_t *pairs,
+                         sncc_hit *d_cand, int cand_cap, sncc_hit *d_out, int out_cap,
+                         int32_t *d_counts);
 
 /* ------------------------------------------------------------ batches */
 typedef struct sncc_batch_desc {

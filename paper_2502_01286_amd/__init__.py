@@ -13,6 +13,7 @@ from ._native import (  # noqa: F401
     SnccError,
     decode_matches,
     decode_matches64,
+    decode_hits,
     header_functions,
     lib,
 )

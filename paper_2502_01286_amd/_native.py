@@ -98,6 +98,8 @@ _SIGS = {
     "sncc_topk": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _i, _i, _vp]),
     "sncc_argmax": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _i, _vp]),
     "sncc_refine": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _vp, _i, _i, _vp, _vp]),
+    "sncc_threshold_match": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp,
+                                  _vp, _i, _vp, _i, _vp]),
     "sncc_batch_create": (_i, [_vp, _vp, _vp]),
     "sncc_batch_run": (_i, [_vp]),
     "sncc_batch_stats_get": (_i, [_vp, _vp]),
@@ -271,6 +273,25 @@ def sncc_refine(ctx, fine, s, s2, B, M, N, pairs, cand, radius, out, count=None)
                            _ptr(out, torch.int32, "out"), _ptr(count, torch.int32, "count")))
 
 
+def sncc_threshold_match(ctx, fast, slow, thr_fast, thr_slow, s, s2, B, M, N, pairs, cand,
+                         out, counts):
+    """Section 5's two-threshold search.  thr_fast, thr_slow: one float per
+    template (host); cand, out: int32 (cap, 6) hit buffers (pair, u, v, 0,
+    rho f64); counts: int32 (2,) device."""
+    import torch
+    p = _pairs_array(pairs)
+    tf = np.ascontiguousarray(thr_fast, dtype=np.float64)
+    ts = np.ascontiguousarray(thr_slow, dtype=np.float64)
+    if cand.dim() != 2 or cand.shape[1] != 6 or out.dim() != 2 or out.shape[1] != 6:
+        raise ValueError("cand and out must be int32 (cap, 6) tensors")
+    _check(lib.sncc_threshold_match(ctx, fast, slow, tf.ctypes.data, ts.ctypes.data,
+                                    _ptr(s, torch.int32, "s"), _ptr(s2, torch.int32, "s2"),
+                                    int(B), int(M), int(N), s.shape[-1], len(p), p.ctypes.data,
+                                    _ptr(cand, torch.int32, "cand"), cand.shape[0],
+                                    _ptr(out, torch.int32, "out"), out.shape[0],
+                                    _ptr(counts, torch.int32, "counts")))
+
+
 class Batch:
     """Owns a sncc_batch handle and the host copies its descriptor points to."""
 
@@ -351,4 +372,18 @@ def decode_matches64(out) -> np.ndarray:
     res["u"] = a[:, 0]
     res["v"] = a[:, 1]
     res["rho"] = a[:, 2:4].copy().view(np.float64)[:, 0]
+    return res
+
+
+def decode_hits(buf, count=None) -> np.ndarray:
+    """(cap, 6) int32 hit buffer -> structured numpy (pair, u, v, rho float64),
+    the first min(count, cap) entries (all when count is None)."""
+    a = np.ascontiguousarray(buf.detach().cpu().numpy().astype(np.int32, copy=False))
+    n = a.shape[0] if count is None else min(int(count), a.shape[0])
+    a = a[:n]
+    res = np.zeros(n, dtype=[("pair", "<i4"), ("u", "<i4"), ("v", "<i4"), ("rho", "<f8")])
+    res["pair"] = a[:, 0]
+    res["u"] = a[:, 1]
+    res["v"] = a[:, 2]
+    res["rho"] = a[:, 4:6].copy().view(np.float64)[:, 0]
     return res

@@ -128,7 +128,7 @@ struct PlanHost {
   TileCfg tc{2, 4, 8, 2, 1};
   int lds_bytes = 0;
   int grid = 0;
-  bool map_sink = false;
+  int sink = kSinkTopk;
   int k = 0;
   std::vector<DevTmpl> tmpls;
   std::vector<PassDesc> passes;
@@ -231,12 +231,13 @@ int plan_template(const sncc_tmpl *tm, int t, const TileCfg &tc, int LP, int row
 }
 
 int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
-               const int32_t *pairs, int k, bool map_sink, int num_cu, PlanHost &ph) {
+               const int32_t *pairs, int k, int sink, int num_cu, PlanHost &ph,
+               const double *thr = nullptr) {
   if (cfg < 0 || cfg >= tile_cfg_count()) SNCC_FAIL(SNCC_EINVAL, "bad tile config %d", cfg);
   ph = PlanHost();
   ph.cfg = cfg;
   ph.tc = tile_cfg(cfg);
-  ph.map_sink = map_sink;
+  ph.sink = sink;
   ph.k = k;
   const TileCfg tc = ph.tc;
   const int bu = tc.bu(), bv = tc.bv();
@@ -245,7 +246,7 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
 
   // LDS budget: tc.wgs workgroups per CU when every template allows it,
   // otherwise one workgroup per CU
-  const int topk_bytes = map_sink ? 0 : tc.nw * std::max(k, 1) * 8;
+  const int topk_bytes = sink == kSinkTopk ? tc.nw * std::max(k, 1) * 8 : 0;
   // the kernel keeps one FP32 scale per offset in LDS ahead of the staged rows
   const int scale_bytes = 64 * tc.nw * tc.ru * tc.rv * 4;
   int budget = tile_max_lds() / tc.wgs - 512 - scale_bytes;
@@ -260,6 +261,7 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
     for (int t = 0; t < tm->T; ++t) {
       DevTmpl d = tm->dev[t];
       d.pass_begin = d.pass_end = 0;
+      d.thr = thr ? (float)thr[t] : 0.f;
       if (used[t]) {
         const int cls = lp_class_for(bu + tm->W[t] + 1);
         if (cls < 0) SNCC_FAIL(SNCC_ERANGE, "template %d too wide (W=%d) for the tile kernel", t, tm->W[t]);
@@ -285,7 +287,7 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
   }
 
   // pairs and work items
-  const int occ = std::max(1, tile_occupancy(cfg, map_sink, ph.lds_bytes));
+  const int occ = std::max(1, tile_occupancy(cfg, sink, ph.lds_bytes));
   const int slots = std::max(1, num_cu) * occ;
   std::vector<double> tile_cost(n_pairs);
   double total = 0;
@@ -397,7 +399,7 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
 struct PlanDev {
   PlanHost h;
   DevBuf d_tmpls, d_passes, d_ivs, d_recs, d_pairs, d_items, d_order, d_qbeg, d_queue,
-      d_partial;
+      d_partial, d_thr;
   hipEvent_t done = nullptr;
   ~PlanDev() {
     if (done) (void)hipEventDestroy(done);
@@ -412,11 +414,14 @@ struct PlanDev {
     CHK(d_order.upload(h.order, st));
     CHK(d_qbeg.upload(h.qbeg, st));
     CHK(d_queue.reserve(zero_ints() * sizeof(int)));
-    if (!h.map_sink) CHK(d_partial.reserve(std::max<size_t>(16, h.items.size() * h.k * 8)));
+    if (h.sink == kSinkTopk)
+      CHK(d_partial.reserve(std::max<size_t>(16, h.items.size() * h.k * 8)));
     return SNCC_OK;
   }
   // work counters, then one floor key per pair (top-k sink), zeroed per launch
-  int zero_ints() const { return kQueueInts + (h.map_sink ? 0 : 2 * (int)h.pairs.size()); }
+  int zero_ints() const {
+    return kQueueInts + (h.sink == kSinkTopk ? 2 * (int)h.pairs.size() : 0);
+  }
   TileArgs args(const uint32_t *s, const uint32_t *s2, long long fs, int P, int M, int N) {
     TileArgs a;
     a.s = s;
@@ -439,7 +444,9 @@ struct PlanDev {
     a.k = h.k;
     a.partial = d_partial.as<unsigned long long>();
     a.pair_floor =
-        h.map_sink ? nullptr : reinterpret_cast<unsigned long long *>(a.queue + kQueueInts);
+        h.sink == kSinkTopk ? reinterpret_cast<unsigned long long *>(a.queue + kQueueInts)
+                            : nullptr;
+    a.co = CompactOut{nullptr, 0, nullptr};
     a.n_zero = zero_ints();
     a.rho = nullptr;
     a.rho_pitch = 0;
@@ -761,14 +768,14 @@ int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint32_t *d_
   if (precision != SNCC_FP32_KAHAN) SNCC_FAIL(SNCC_EINVAL, "unknown precision %d", precision);
   std::unique_ptr<PlanDev> pd(new PlanDev());
   const int32_t pair[2] = {0, index};
-  CHK(build_plan(tm, 0, M, N, 1, pair, 0, true, ctx->num_cu, pd->h));
+  CHK(build_plan(tm, 0, M, N, 1, pair, 0, kSinkMap, ctx->num_cu, pd->h));
   CHK(pd->upload(ctx->stream));
   TileArgs a = pd->args(d_s, d_s2, (long long)(N + 1) * sat_pitch, sat_pitch, M, N);
   a.rho = d_rho;
   a.rho_pitch = rho_pitch;
   a.degen = d_degenerate;
   if (launch_zero(a.queue, a.n_zero, ctx->stream) != 0 ||
-      launch_tile(pd->h.cfg, true, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0)
+      launch_tile(pd->h.cfg, kSinkMap, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0)
     SNCC_FAIL(SNCC_EDEVICE, "tile launch: %s", hipGetErrorString(hipGetLastError()));
   return retire(ctx, std::move(pd));
 }
@@ -786,11 +793,11 @@ int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uin
   const long long fs = (long long)(N + 1) * sat_pitch;
   std::unique_ptr<PlanDev> pd(new PlanDev());
   if (precision == SNCC_FP32_KAHAN) {
-    CHK(build_plan(tm, 0, M, N, n_pairs, pairs, k, false, ctx->num_cu, pd->h));
+    CHK(build_plan(tm, 0, M, N, n_pairs, pairs, k, kSinkTopk, ctx->num_cu, pd->h));
     CHK(pd->upload(ctx->stream));
     TileArgs a = pd->args(d_s, d_s2, fs, sat_pitch, M, N);
     if (launch_zero(a.queue, a.n_zero, ctx->stream) != 0 ||
-        launch_tile(pd->h.cfg, false, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0 ||
+        launch_tile(pd->h.cfg, kSinkTopk, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0 ||
         launch_merge(pd->d_pairs.as<PairDesc>(), n_pairs, a.partial, k, d_out, ctx->stream) != 0)
       SNCC_FAIL(SNCC_EDEVICE, "top-k launch: %s", hipGetErrorString(hipGetLastError()));
     return retire(ctx, std::move(pd));
@@ -898,6 +905,47 @@ int sncc_refine(sncc_ctx *ctx, const sncc_tmpl *fine, const uint32_t *d_s, const
   return retire(ctx, std::move(pd));
 }
 
+int sncc_threshold_match(sncc_ctx *ctx, const sncc_tmpl *fast, const sncc_tmpl *slow,
+                         const double *thr_fast, const double *thr_slow, const uint32_t *d_s,
+                         const uint32_t *d_s2, int B, int M, int N, int sat_pitch, int n_pairs,
+                         const int32_t *pairs, sncc_hit *d_cand, int cand_cap, sncc_hit *d_out,
+                         int out_cap, int32_t *d_counts) {
+  g_err.clear();
+  CHK(check_ctx(ctx));
+  CHK(check_sats(d_s, d_s2, M, N, sat_pitch));
+  if (B < 1) SNCC_FAIL(SNCC_EINVAL, "B must be >= 1");
+  if (!fast || !slow) SNCC_FAIL(SNCC_EINVAL, "NULL template set");
+  if (fast->T != slow->T) SNCC_FAIL(SNCC_EINVAL, "fast and slow sets differ in size");
+  for (int t = 0; t < fast->T; ++t)
+    if (fast->W[t] != slow->W[t] || fast->H[t] != slow->H[t])
+      SNCC_FAIL(SNCC_EINVAL, "slow template %d differs in size from the fast one", t);
+  CHK(check_pairs(fast, B, M, N, n_pairs, pairs));
+  if (!thr_fast || !thr_slow) SNCC_FAIL(SNCC_EINVAL, "NULL thresholds");
+  for (int t = 0; t < fast->T; ++t)
+    if (!std::isfinite(thr_fast[t]) || !std::isfinite(thr_slow[t]))
+      SNCC_FAIL(SNCC_EINVAL, "threshold of template %d is not finite", t);
+  if (cand_cap < 1 || out_cap < 1) SNCC_FAIL(SNCC_EINVAL, "capacities must be >= 1");
+  if (!d_cand || !d_out || !d_counts || !aligned16(d_cand) || !aligned16(d_out) ||
+      !aligned16(d_counts))
+    SNCC_FAIL(SNCC_EINVAL, "NULL or misaligned buffers");
+  const long long fs = (long long)(N + 1) * sat_pitch;
+  std::unique_ptr<PlanDev> pd(new PlanDev());
+  CHK(build_plan(fast, 0, M, N, n_pairs, pairs, 1, kSinkCompact, ctx->num_cu, pd->h, thr_fast));
+  CHK(pd->upload(ctx->stream));
+  std::vector<double> ts(thr_slow, thr_slow + slow->T);
+  CHK(pd->d_thr.upload(ts, ctx->stream));
+  TileArgs a = pd->args(d_s, d_s2, fs, sat_pitch, M, N);
+  a.co = CompactOut{d_cand, cand_cap, d_counts};
+  if (launch_zero(a.queue, a.n_zero, ctx->stream) != 0 ||
+      launch_zero(d_counts, 2, ctx->stream) != 0 ||
+      launch_tile(pd->h.cfg, kSinkCompact, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0 ||
+      launch_slow(d_s, d_s2, fs, sat_pitch, slow->d_dev.as<DevTmpl>(), slow->d_geom.as<int4>(),
+                  slow->d_c64.as<double>(), pd->d_pairs.as<PairDesc>(), pd->d_thr.as<double>(),
+                  d_cand, d_counts, cand_cap, d_out, out_cap, d_counts + 1, ctx->stream) != 0)
+    SNCC_FAIL(SNCC_EDEVICE, "threshold search launch: %s", hipGetErrorString(hipGetLastError()));
+  return retire(ctx, std::move(pd));
+}
+
 }  // extern "C"
 
 // ================================================================= batches
@@ -939,7 +987,7 @@ int enqueue_stage(sncc_batch *b, int stage, hipStream_t st) {
       return SNCC_OK;
     case 1:
       if (launch_zero(a.queue, a.n_zero, st) != 0 ||
-          launch_tile(pd.h.cfg, false, a, pd.h.grid, pd.h.lds_bytes, st) != 0)
+          launch_tile(pd.h.cfg, kSinkTopk, a, pd.h.grid, pd.h.lds_bytes, st) != 0)
         SNCC_FAIL(SNCC_EDEVICE, "scoring launch");
       return SNCC_OK;
     case 2:
@@ -1088,7 +1136,7 @@ int autotune(sncc_batch *b, int *best_cfg) {
   *best_cfg = 0;
   for (int c = 0; c < tile_cfg_count(); ++c) {
     PlanDev pd;
-    if (build_plan(d.coarse, c, d.M, d.N, d.n_pairs, b->pairs.data(), d.k, false,
+    if (build_plan(d.coarse, c, d.M, d.N, d.n_pairs, b->pairs.data(), d.k, kSinkTopk,
                    b->ctx->num_cu, pd.h) != SNCC_OK)
       continue;
     if (pd.upload(b->ctx->stream) != SNCC_OK) continue;
@@ -1097,7 +1145,7 @@ int autotune(sncc_batch *b, int *best_cfg) {
     for (int rep = 0; rep < 2; ++rep) {
       launch_zero(a.queue, a.n_zero, b->ctx->stream);
       HIPCHK(hipEventRecord(e0, b->ctx->stream));
-      launch_tile(c, false, a, pd.h.grid, pd.h.lds_bytes, b->ctx->stream);
+      launch_tile(c, kSinkTopk, a, pd.h.grid, pd.h.lds_bytes, b->ctx->stream);
       HIPCHK(hipEventRecord(e1, b->ctx->stream));
       HIPCHK(hipEventSynchronize(e1));
       HIPCHK(hipEventElapsedTime(&ms, e0, e1));
@@ -1165,7 +1213,7 @@ int sncc_batch_create(sncc_ctx *ctx, const sncc_batch_desc *desc, sncc_batch **o
     }
   }
   b->plan.reset(new PlanDev());
-  CHK(build_plan(d.coarse, cfg, d.M, d.N, d.n_pairs, b->pairs.data(), d.k, false, ctx->num_cu,
+  CHK(build_plan(d.coarse, cfg, d.M, d.N, d.n_pairs, b->pairs.data(), d.k, kSinkTopk, ctx->num_cu,
                  b->plan->h));
   CHK(b->plan->upload(ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));

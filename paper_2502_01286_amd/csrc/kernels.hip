@@ -23,6 +23,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "device_util.hpp"
@@ -253,21 +254,19 @@ int launch_sat(const uint8_t *f, int B, int M, int N, int f_pitch, uint32_t *s,
 }
 
 // ------------------------------------------------------------ tile scoring
-struct TileEntry {
-  int ru, rv, nw;
-  const void *fn_map;
-  const void *fn_topk;
-};
-
 // One entry per tile shape (kTileShapes); the kernels live in the
 // translation units built from tile_entry.hip.
+struct TileEntry {
+  int ru, rv, nw;
+  const void *(*fn)(int sink);
+};
 static const TileEntry kTileEntries[] = {
-    {kTileShapes[0][0], kTileShapes[0][1], kTileShapes[0][2], tile_fn_0(true), tile_fn_0(false)},
-    {kTileShapes[1][0], kTileShapes[1][1], kTileShapes[1][2], tile_fn_1(true), tile_fn_1(false)},
-    {kTileShapes[2][0], kTileShapes[2][1], kTileShapes[2][2], tile_fn_2(true), tile_fn_2(false)},
-    {kTileShapes[3][0], kTileShapes[3][1], kTileShapes[3][2], tile_fn_3(true), tile_fn_3(false)},
-    {kTileShapes[4][0], kTileShapes[4][1], kTileShapes[4][2], tile_fn_4(true), tile_fn_4(false)},
-    {kTileShapes[5][0], kTileShapes[5][1], kTileShapes[5][2], tile_fn_5(true), tile_fn_5(false)},
+    {kTileShapes[0][0], kTileShapes[0][1], kTileShapes[0][2], tile_fn_0},
+    {kTileShapes[1][0], kTileShapes[1][1], kTileShapes[1][2], tile_fn_1},
+    {kTileShapes[2][0], kTileShapes[2][1], kTileShapes[2][2], tile_fn_2},
+    {kTileShapes[3][0], kTileShapes[3][1], kTileShapes[3][2], tile_fn_3},
+    {kTileShapes[4][0], kTileShapes[4][1], kTileShapes[4][2], tile_fn_4},
+    {kTileShapes[5][0], kTileShapes[5][1], kTileShapes[5][2], tile_fn_5},
 };
 static_assert(sizeof(kTileEntries) / sizeof(kTileEntries[0]) == kNumTileShapes,
               "one table entry per tile shape");
@@ -290,14 +289,13 @@ TileCfg tile_cfg(int i) {
 }
 int tile_max_lds() { return 160 * 1024; }
 
-static const void *tile_fn(int cfg, bool map_sink) {
-  const TileEntry &e = kTileEntries[kCfgs[cfg].entry];
-  return map_sink ? e.fn_map : e.fn_topk;
+static const void *tile_fn(int cfg, int sink) {
+  return kTileEntries[kCfgs[cfg].entry].fn(sink);
 }
 
-int tile_occupancy(int cfg, bool map_sink, int lds_bytes) {
+int tile_occupancy(int cfg, int sink, int lds_bytes) {
   if (cfg < 0 || cfg >= kNumCfgs) return 0;
-  const void *fn = tile_fn(cfg, map_sink);
+  const void *fn = tile_fn(cfg, sink);
   (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, tile_max_lds() - 64);
   int blocks = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, tile_cfg(cfg).threads(),
@@ -306,17 +304,17 @@ int tile_occupancy(int cfg, bool map_sink, int lds_bytes) {
   return blocks;
 }
 
-int launch_tile(int cfg, bool map_sink, const TileArgs &a, int grid, int lds_bytes,
+int launch_tile(int cfg, int sink, const TileArgs &a, int grid, int lds_bytes,
                 hipStream_t st) {
-  if (cfg < 0 || cfg >= kNumCfgs) return -1;
-  const void *fn = tile_fn(cfg, map_sink);
-  static bool attr_done[2][kNumTileEntries] = {};
+  if (cfg < 0 || cfg >= kNumCfgs || sink < kSinkTopk || sink > kSinkCompact) return -1;
+  const void *fn = tile_fn(cfg, sink);
+  static bool attr_done[3][kNumTileEntries] = {};
   const int ent = kCfgs[cfg].entry;
-  if (!attr_done[map_sink][ent]) {
+  if (!attr_done[sink][ent]) {
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             tile_max_lds() - 64) != hipSuccess)
       return -1;
-    attr_done[map_sink][ent] = true;
+    attr_done[sink][ent] = true;
   }
   long long fs = a.frame_stride;
   int P = a.sat_pitch, N = a.N, nq = a.nq, k = a.k, rp = a.rho_pitch;
@@ -332,9 +330,10 @@ int launch_tile(int cfg, bool map_sink, const TileArgs &a, int grid, int lds_byt
   u64 *partial = a.partial, *pfloor = a.pair_floor;
   float *rho = static_cast<float *>(a.rho);
   uint8_t *dg = a.degen;
+  CompactOut co = a.co;
   void *args[] = {&s,  &s2, &fs, &P,  &N,     &tm,      &ps,  &iv,  &rc,  &pr,
                   &it, &ord, &qbeg, &nq, &queue, &k, &partial, &pfloor, &rho, &rp,
-                  &dg};
+                  &dg, &co};
   hipError_t err = hipLaunchKernel(fn, dim3(grid), dim3(tile_cfg(cfg).threads()), args,
                                    (size_t)lds_bytes, st);
   return err == hipSuccess ? 0 : -1;
@@ -619,6 +618,74 @@ int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride,
   if (n_cand * (2 * radius + 1) * (2 * radius + 1) > REFINE_CAP) return -1;
   hipLaunchKernelGGL(refine_kernel, dim3(n_pairs), dim3(256), 0, st, s, s2, frame_stride,
                      P, tmpls, geom, c64, pairs, cand, n_cand, radius, out, count);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// --------------------------------------------------- two-threshold search
+// Section 5, steps 7g-j for the offsets that passed the fast test: rho with
+// the slow approximation in FP64 (one wave per offset, lanes striding over
+// the segments, then a butterfly sum), appended to the output when it
+// reaches the template's slow threshold.
+__global__ __launch_bounds__(256) void slow_kernel(
+    const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
+    int P, const DevTmpl *__restrict__ tmpls, const int4 *__restrict__ geom,
+    const double *__restrict__ c64, const PairDesc *__restrict__ pairs,
+    const double *__restrict__ thr, const sncc_hit *__restrict__ cand,
+    const int *__restrict__ cand_count, int cand_cap, sncc_hit *__restrict__ out, int out_cap,
+    int *__restrict__ out_count) {
+  const int lane = threadIdx.x & 63;
+  const int n_cand = min(*cand_count, cand_cap);
+  for (int c = blockIdx.x * 4 + (threadIdx.x >> 6); c < n_cand; c += gridDim.x * 4) {
+    const sncc_hit h = cand[c];
+    const PairDesc pd = pairs[h.pair];
+    const DevTmpl td = tmpls[pd.tmpl];
+    const uint32_t *S = s + (long long)pd.frame * frame_stride;
+    const uint32_t *S2 = s2 + (long long)pd.frame * frame_stride;
+    const uint32_t *a0 = S + (long long)h.v * P + h.u;
+    double acc = 0.0;
+    for (int i = lane; i < td.K; i += 64) {
+      const int4 g = geom[td.seg_off + i];  // x, y, width, height
+      const uint32_t *q0 = a0 + (long long)g.y * P + g.x;
+      const uint32_t *q2 = q0 + (long long)g.w * P;
+      const uint32_t F = (q2[g.z] - q2[0]) - (q0[g.z] - q0[0]);  // Eq. (11)
+      acc = __builtin_fma((double)F, c64[td.seg_off + i], acc);
+    }
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
+    if (lane == 0) {
+      const uint32_t *a1 = a0 + (long long)td.H * P;
+      const uint32_t sf = (a1[td.W] - a1[0]) - (a0[td.W] - a0[0]);  // Eq. (13)
+      const uint32_t *b0 = S2 + (long long)h.v * P + h.u;
+      const uint32_t *b1 = b0 + (long long)td.H * P;
+      const uint32_t sf2 = (b1[td.W] - b1[0]) - (b0[td.W] - b0[0]);  // Eq. (15)
+      const long long V = (long long)((u64)(uint32_t)td.n * sf2 - (u64)sf * sf);
+      const double num = acc - (double)sf / (double)td.n * td.r64;  // Eq. (12)
+      const double rho =
+          V == 0 ? 0.0 : num / sqrt((double)V / (double)td.n * td.q_k);  // Eqs. (17), (18)
+      if (rho >= thr[pd.tmpl]) {
+        const int pos = atomicAdd(out_count, 1);
+        if (pos < out_cap) {
+          sncc_hit o;
+          o.pair = h.pair;
+          o.u = h.u;
+          o.v = h.v;
+          o.reserved = 0;
+          o.rho = rho;
+          out[pos] = o;
+        }
+      }
+    }
+  }
+}
+
+int launch_slow(const uint32_t *s, const uint32_t *s2, long long frame_stride, int P,
+                const DevTmpl *tmpls, const int4 *geom, const double *c64,
+                const PairDesc *pairs, const double *thr, const sncc_hit *cand,
+                const int *cand_count, int cand_cap, sncc_hit *out, int out_cap,
+                int *out_count, hipStream_t st) {
+  const int blocks = std::max(1, std::min((cand_cap + 3) / 4, 8192));
+  hipLaunchKernelGGL(slow_kernel, dim3(blocks), dim3(256), 0, st, s, s2, frame_stride, P,
+                     tmpls, geom, c64, pairs, thr, cand, cand_count, cand_cap, out, out_cap,
+                     out_count);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -36,6 +36,8 @@ struct DevTmpl {
   int lp_class;        // LDS pitch class of the tile kernel
   int pass_begin;      // tile plan: passes of this template
   int pass_end;
+  float thr;           // survivor threshold of the compacting sink
+  int pad;
 };
 
 // One segment for the tile kernel: LDS dword offsets of its top-left and
@@ -71,6 +73,18 @@ struct WorkItem {
   int pad;
 };
 
+// Sinks of the persistent tile kernel: per-item top-k partials, a rho map,
+// or a compacted list of the offsets whose rho reaches a threshold.
+constexpr int kSinkTopk = 0;
+constexpr int kSinkMap = 1;
+constexpr int kSinkCompact = 2;
+
+struct CompactOut {
+  sncc_hit *hits;  // cap entries
+  int cap;
+  int *count;      // entries wanted (may exceed cap; zero at launch)
+};
+
 // Kernel arguments of the persistent tile kernel.
 struct TileArgs {
   const uint32_t *s;
@@ -97,6 +111,7 @@ struct TileArgs {
   void *rho;               // MAP sink: float map
   int rho_pitch;
   uint8_t *degen;          // MAP sink: nullable
+  CompactOut co;           // compacting sink
   int n_zero;              // ints of `queue` to zero before a launch (host side)
 };
 
@@ -149,13 +164,13 @@ constexpr int kTileShapes[kNumTileShapes][3] = {
     {1, 4, 8},  //  64 x 32
     {1, 4, 4},  //  64 x 16
 };
-// Host stubs of tile shape i's kernels (tile_entry.hip): rho-map or top-k sink.
-const void *tile_fn_0(bool map_sink);
-const void *tile_fn_1(bool map_sink);
-const void *tile_fn_2(bool map_sink);
-const void *tile_fn_3(bool map_sink);
-const void *tile_fn_4(bool map_sink);
-const void *tile_fn_5(bool map_sink);
+// Host stubs of tile shape i's kernels (tile_entry.hip), one per sink.
+const void *tile_fn_0(int sink);
+const void *tile_fn_1(int sink);
+const void *tile_fn_2(int sink);
+const void *tile_fn_3(int sink);
+const void *tile_fn_4(int sink);
+const void *tile_fn_5(int sink);
 
 // Launch wrappers (kernels.hip).
 int launch_sat(const uint8_t *f, int B, int M, int N, int f_pitch, uint32_t *s,
@@ -164,10 +179,15 @@ size_t sat_scratch_words(int B, int M, int N);
 
 int tile_cfg_count();
 TileCfg tile_cfg(int i);
-int launch_tile(int cfg, bool map_sink, const TileArgs &a, int grid,
+int launch_slow(const uint32_t *s, const uint32_t *s2, long long frame_stride, int P,
+                const DevTmpl *tmpls, const int4 *geom, const double *c64,
+                const PairDesc *pairs, const double *thr, const sncc_hit *cand,
+                const int *cand_count, int cand_cap, sncc_hit *out, int out_cap,
+                int *out_count, hipStream_t st);
+int launch_tile(int cfg, int sink, const TileArgs &a, int grid,
                 int lds_bytes, hipStream_t st);
 int tile_max_lds();
-int tile_occupancy(int cfg, bool map_sink, int lds_bytes);
+int tile_occupancy(int cfg, int sink, int lds_bytes);
 int launch_plain(const PlainArgs &a, hipStream_t st);
 int launch_zero(int *p, int n, hipStream_t st);
 int launch_merge(const PairDesc *pairs, int n_pairs,

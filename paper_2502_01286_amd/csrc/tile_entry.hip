@@ -1,4 +1,4 @@
-// One tile shape of the persistent scoring kernel, both sinks.  Compiled
+// One tile shape of the persistent scoring kernel, every sink.  Compiled
 // once per row of kTileShapes with -DSNCC_TILE_ENTRY_ID=<row>, so that the
 // shapes build in parallel.
 #include "tile_kernel.hpp"
@@ -18,9 +18,12 @@ constexpr int kNW = kTileShapes[SNCC_TILE_ENTRY_ID][2];
 #define SNCC_TILE_FN_(i) tile_fn_##i
 #define SNCC_TILE_FN(i) SNCC_TILE_FN_(i)
 
-const void *SNCC_TILE_FN(SNCC_TILE_ENTRY_ID)(bool map_sink) {
-  return map_sink ? reinterpret_cast<const void *>(&tile_kernel<kRU, kRV, kNW, true>)
-                  : reinterpret_cast<const void *>(&tile_kernel<kRU, kRV, kNW, false>);
+const void *SNCC_TILE_FN(SNCC_TILE_ENTRY_ID)(int sink) {
+  switch (sink) {
+    case kSinkTopk: return reinterpret_cast<const void *>(&tile_kernel<kRU, kRV, kNW, kSinkTopk>);
+    case kSinkMap: return reinterpret_cast<const void *>(&tile_kernel<kRU, kRV, kNW, kSinkMap>);
+    default: return reinterpret_cast<const void *>(&tile_kernel<kRU, kRV, kNW, kSinkCompact>);
+  }
 }
 
 }  // namespace sncc

@@ -33,14 +33,14 @@ __device__ __forceinline__ void stage_pass(__amdgpu_buffer_rsrc_t rs, int P,
   }
 }
 
-template <int RU, int RV, int NW, int LP, bool MAP>
+template <int RU, int RV, int NW, int LP, int SINK>
 __device__ __forceinline__ void run_item(
     const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
     int P, int N, const PassDesc *__restrict__ passes, const Interval *__restrict__ ivs,
     const TileRec *__restrict__ recs, const WorkItem &it, const PairDesc &pd,
     const DevTmpl &td, u64 &lkey, int k, float *__restrict__ rho_out, int rho_pitch,
-    uint8_t *__restrict__ degen, uint32_t *lds, float *scl, uint32_t *thr_sh, int wave,
-    int lane) {
+    uint8_t *__restrict__ degen, uint32_t *lds, float *scl, uint32_t *thr_sh,
+    const CompactOut &co, int wave, int lane) {
   constexpr int BU = 64 * RU, BV = NW * RV, R = RU * RV;
   // per-offset scales live in LDS (thread-private slots) from the prologue to
   // the epilogue, which keeps them out of registers during the segment loop
@@ -172,7 +172,7 @@ __device__ __forceinline__ void run_item(
     }
 
     // epilogue: rho = num / sqrt(V q_k / n) (Eqs. (17), (18)) in FP32
-    if (MAP) {
+    if (SINK == kSinkMap) {
 #pragma unroll
       for (int dv = 0; dv < RV; ++dv)
 #pragma unroll
@@ -185,6 +185,46 @@ __device__ __forceinline__ void run_item(
             if (degen) degen[(long long)v * rho_pitch + u] = sc == 0.f ? 1 : 0;
           }
         }
+    } else if (SINK == kSinkCompact) {
+      // offsets whose rho reaches the template's threshold are appended to
+      // the survivor list: one atomic per wave, lanes write in lane order
+      int cnt = 0;
+      bool pass[R];
+#pragma unroll
+      for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+        for (int du = 0; du < RU; ++du) {
+          const int r = dv * RU + du;
+          const int u = u0 + lane + 64 * du, v = v0 + wave * RV + dv;
+          acc[r] = (acc[r] - cmp[r]) * my_sc[r * NW * 64];  // acc now holds rho
+          pass[r] = u < pd.nu && v < pd.nv && acc[r] >= td.thr;
+          cnt += pass[r] ? 1 : 0;
+        }
+      const uint32_t incl = wave_incl_scan((uint32_t)cnt);
+      const int total = (int)__builtin_amdgcn_readlane((int)incl, 63);
+      if (total > 0) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(co.count, total);
+        int pos = __builtin_amdgcn_readlane(base, 0) + (int)incl - cnt;
+#pragma unroll
+        for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+          for (int du = 0; du < RU; ++du) {
+            const int r = dv * RU + du;
+            if (pass[r]) {
+              if (pos < co.cap) {
+                sncc_hit h;
+                h.pair = it.pair;
+                h.u = u0 + lane + 64 * du;
+                h.v = v0 + wave * RV + dv;
+                h.reserved = 0;
+                h.rho = (double)acc[r];
+                co.hits[pos] = h;
+              }
+              ++pos;
+            }
+          }
+      }
     } else {
       // waves publish the high word of their k-th key (a 32-bit store, so
       // readers see an old or a new value, never a mix); (largest, 0) is at
@@ -225,7 +265,7 @@ __device__ __forceinline__ void run_item(
   }
 }
 
-template <int RU, int RV, int NW, bool MAP>
+template <int RU, int RV, int NW, int SINK>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void tile_kernel(
     const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
     int P, int N, const DevTmpl *__restrict__ tmpls, const PassDesc *__restrict__ passes,
@@ -233,7 +273,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     const PairDesc *__restrict__ pairs, const WorkItem *__restrict__ items,
     const int *__restrict__ order, const int *__restrict__ qbeg, int nq,
     int *__restrict__ queue, int k, u64 *__restrict__ partial, u64 *__restrict__ pair_floor,
-    float *__restrict__ rho_out, int rho_pitch, uint8_t *__restrict__ degen) {
+    float *__restrict__ rho_out, int rho_pitch, uint8_t *__restrict__ degen, CompactOut co) {
   // dynamic LDS: per-offset scales (R words per thread), then the staged rows
   extern __shared__ __align__(16) uint32_t lds[];
   constexpr int kScaleWords = 64 * NW * RU * RV;
@@ -263,7 +303,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
       item_sh = got;
       // a key below the k-th key of another item of the same pair cannot be
       // in the pair's top k; items publish theirs when they finish
-      if (!MAP && got >= 0)
+      if (SINK == kSinkTopk && got >= 0)
         floor_sh = (uint32_t)(__hip_atomic_load(pair_floor + items[got].pair, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT) >> 32);
     }
@@ -275,11 +315,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     const PairDesc pd = pairs[it.pair];
     const DevTmpl td = tmpls[pd.tmpl];
     u64 lkey = 0;
-    if (lane == 0) thr_sh[wave] = MAP ? 0u : floor_sh;  // ordered by the first pass barrier
+    if (lane == 0) thr_sh[wave] = SINK == kSinkTopk ? floor_sh : 0u;  // ordered by a barrier
 #define SNCC_RUN(LPV)                                                                    \
-  run_item<RU, RV, NW, LPV, MAP>(s, s2, frame_stride, P, N, passes, ivs, recs, it, pd, td, \
+  run_item<RU, RV, NW, LPV, SINK>(s, s2, frame_stride, P, N, passes, ivs, recs, it, pd, td, \
                                  lkey, k, rho_out, rho_pitch, degen, lds + kScaleWords,      \
-                                 reinterpret_cast<float *>(lds), thr_sh, wave, lane)
+                                 reinterpret_cast<float *>(lds), thr_sh, co, wave, lane)
     switch (td.lp_class) {
       case 0: SNCC_RUN(kLpClasses[0]); break;
       case 1: SNCC_RUN(kLpClasses[1]); break;
@@ -294,7 +334,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
       default: SNCC_RUN(kLpClasses[10]); break;
     }
 #undef SNCC_RUN
-    if (!MAP) {
+    if (SINK == kSinkTopk) {
       // merge the waves' lists into wave 0's and write the item's partial
       u64 *buf = reinterpret_cast<u64 *>(lds);
       __syncthreads();
