@@ -9,7 +9,10 @@ candidates' neighbourhoods with the fine approximation (one graph launch).
 Default workload ("coarse-fine"): 256 frames 1280x720 x 32 templates with
 sides U{24..96}, coarse sigma_max 16 (top-32 per pair), fine sigma_max 4 on
 +-2 px neighbourhoods.  `--workload batched` runs 16 frames 1920x1080 x 64
-templates (sides U{16..192}, sigma_max U{4,8,12,16}, top-5) instead.
+templates (sides U{16..192}, sigma_max U{4,8,12,16}, top-5) instead;
+`--workload threshold` runs the paper's own two-threshold search (Section 5)
+on 4 frames 1920x1080 x 4 templates 64x64 with relative thresholds (value =
+fast plus slow evaluations per second).
 
 Prints one JSON line.  value = coarse offset x segment evaluations per
 second of the whole step.
@@ -146,6 +149,167 @@ def _cpu_pair(job, prep):
     return cmap.size * c.K
 
 
+# ------------------------------------------------ the two-threshold search
+PRECISION = 0.9           # Section 5's precision
+OPS_PER_SLOW_EVAL = 5     # 3 integer add/sub (Eq. (11)), 1 int->FP64 convert, 1 FP64 FMA
+FP64_VALU_PEAK_TOPS = VALU_PEAK_TOPS   # FP64 vector FMA issues at the FP32 lane rate
+
+
+def _cpu_threshold_prep(job):
+    import oracle as O
+    f, t = job
+    sf, ss = O.paper_sigmas(t)
+    return O.precompute_template_approximation(t, sf), O.precompute_template_approximation(t, ss)
+
+
+def _cpu_threshold_pair(job, prep, max_slow):
+    import numpy as np
+    import oracle as O
+    f, t = job
+    fa, sl = prep
+    N, M = f.shape
+    s, s2 = O.sum_tables(f)
+    fmap = O.rho_map(f, fa, tables=(s, s2))
+    thr_f = PRECISION * fa.rho_max
+    cv, cu = np.nonzero(fmap >= thr_f)
+    cu, cv = cu[:max_slow], cv[:max_slow]
+    r = O.rho_at(s, s2, sl, cu, cv)
+    int((r >= PRECISION * sl.rho_max).sum())
+    return fmap.size * fa.K + len(cu) * sl.K
+
+
+def cpu_threshold_baseline(wl, budget_s=15.0):
+    """The oracle's threshold_match steps on one pair per process: the whole
+    fast map, then the slow rho at the first survivors (bounded)."""
+    from concurrent.futures import ProcessPoolExecutor
+    cores = max(1, min(16, len(os.sched_getaffinity(0)), len(wl.pairs)))
+    jobs = [(wl.frames[b], wl.templates[t]) for b, t in wl.pairs[:cores]]
+    max_slow = int(2e6 * budget_s / 15.0)
+    with ProcessPoolExecutor(max_workers=cores) as ex:
+        preps = list(ex.map(_cpu_threshold_prep, jobs))
+        t0 = time.perf_counter()
+        evals = sum(ex.map(_cpu_threshold_pair, jobs, preps, [max_slow] * len(jobs)))
+        dt = time.perf_counter() - t0
+    return {"value": evals / dt, "unit": UNIT, "cores": cores, "kind": "oracle",
+            "sample": f"{len(jobs)} (frame, template) pairs of the same workload, one per "
+                      f"process: whole fast rho map (FP64) + slow rho at up to {max_slow} "
+                      f"survivors each, {dt:.1f} s wall"}
+
+
+def run_threshold(args):
+    import numpy as np
+    import torch
+    import paper_2502_01286_amd as S
+    from workloads import synth
+
+    wl = synth.threshold_4x4()
+    B, N, M = len(wl.frames), wl.N, wl.M
+    log(f"[bench] threshold search: {B} frames {M}x{N}, {len(wl.templates)} templates "
+        f"{wl.templates[0].shape[1]}x{wl.templates[0].shape[0]}, {len(wl.pairs)} pairs")
+    t0 = time.perf_counter()
+    fast_l, slow_l, tf, ts, Kf, Ks = [], [], [], [], [], []
+    for t in wl.templates:
+        sigma_t = float(np.asarray(t, np.float64).std())     # population deviation
+        a, _, rf = S.sncc_segment_template(t, 0.99 * sigma_t)
+        b, _, rs = S.sncc_segment_template(t, 0.1 * sigma_t)
+        fast_l.append(a)
+        slow_l.append(b)
+        tf.append(PRECISION * rf)
+        ts.append(PRECISION * rs)
+        Kf.append(len(a))
+        Ks.append(len(b))
+    prep_ms = (time.perf_counter() - t0) * 1e3
+    log(f"[bench] prep {prep_ms:.1f} ms, K fast {Kf}, K slow {Ks}")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = S.sncc_ctx_create(0)
+    Ws = [t.shape[1] for t in wl.templates]
+    Hs = [t.shape[0] for t in wl.templates]
+    fast = S.sncc_upload_templates(ctx, fast_l, Ws, Hs)
+    slow = S.sncc_upload_templates(ctx, slow_l, Ws, Hs)
+    f = torch.from_numpy(np.stack(wl.frames)).to(dev)
+    P = S.sncc_sat_pitch(M)
+    s = torch.empty((B, N + 1, P), dtype=torch.int32, device=dev)
+    s2 = torch.empty_like(s)
+    offs = [(M - Ws[t] + 1) * (N - Hs[t] + 1) for _, t in wl.pairs]
+    cap = sum(offs)
+    cand = torch.empty((cap, 6), dtype=torch.int32, device=dev)
+    out = torch.empty((cap, 6), dtype=torch.int32, device=dev)
+    counts = torch.zeros(4, dtype=torch.int32, device=dev)
+
+    def step():
+        S.sncc_build_sats(ctx, f, s, s2)
+        S.sncc_threshold_match(ctx, fast, slow, tf, ts, s, s2, B, M, N, wl.pairs, cand, out,
+                               counts)
+
+    S.sncc_ctx_set_timing(ctx, True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stage = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+        stage.append(S.sncc_ctx_stage_ms(ctx))   # waits for this step's slow pass
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    n_cand, n_out = (int(x) for x in counts[:2].cpu())
+    hits = S.decode_hits(cand, n_cand)
+    per_pair = np.bincount(hits["pair"], minlength=len(wl.pairs))
+    fast_evals = int(sum(o * Kf[t] for o, (_, t) in zip(offs, wl.pairs)))
+    slow_evals = int(sum(int(c) * Ks[t] for c, (_, t) in zip(per_pair, wl.pairs)))
+    ms_fast = float(np.median([x[0] for x in stage]))
+    ms_slow = float(np.median([x[1] for x in stage]))
+    value = (fast_evals + slow_evals) / (ms_per_step / 1e3)
+    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (fast {ms_fast:.3f} ms, slow "
+        f"{ms_slow:.3f} ms); {n_cand} survivors, {n_out} matches")
+    fast_tops = OPS_PER_EVAL * fast_evals / (ms_fast / 1e3) / 1e12
+    slow_tops = OPS_PER_SLOW_EVAL * slow_evals / (ms_slow / 1e3) / 1e12
+    if ms_slow >= ms_fast:
+        roof = {"bound": "alu", "achieved": round(slow_tops, 3),
+                "peak": round(FP64_VALU_PEAK_TOPS, 2), "unit": "TOP/s (FP64 VALU lane ops)",
+                "frac": round(slow_tops / FP64_VALU_PEAK_TOPS, 4), "traffic": None,
+                "kernel": "slow_kernel (FP64 slow pass)", "kernel_ms": round(ms_slow, 4),
+                "ops_per_eval": OPS_PER_SLOW_EVAL, "evals_per_launch": slow_evals}
+    else:
+        roof = {"bound": "alu", "achieved": round(fast_tops, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "TOP/s (VALU lane ops)", "frac": round(fast_tops / VALU_PEAK_TOPS, 4),
+                "traffic": None, "kernel": "tile_kernel (compacting sink)",
+                "kernel_ms": round(ms_fast, 4), "ops_per_eval": OPS_PER_EVAL,
+                "evals_per_launch": fast_evals}
+    roof["stages"] = {"fast_ms": round(ms_fast, 4), "fast_tops": round(fast_tops, 3),
+                      "slow_ms": round(ms_slow, 4), "slow_tops": round(slow_tops, 3)}
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_threshold_baseline(wl, budget_s=args.cpu_budget)
+        log(f"[bench] cpu {cpu}")
+    S.sncc_tmpl_destroy(fast)
+    S.sncc_tmpl_destroy(slow)
+    S.sncc_ctx_destroy(ctx)
+    line = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "threshold", "frames": B, "width": M, "height": N,
+                   "templates": len(wl.templates), "pairs": len(wl.pairs),
+                   "precision": PRECISION, "sigma_fast": "0.99 sigma_t",
+                   "sigma_slow": "0.1 sigma_t", "K_fast": Kf, "K_slow": Ks,
+                   "fast_evals": fast_evals, "slow_evals": slow_evals,
+                   "survivors": n_cand, "matches": n_out,
+                   "arith": "u32 box sums, f32 compensated fast rho, f64 slow rho"},
+        "frames_per_s": B / (ms_per_step / 1e3), "prep_ms_host": prep_ms,
+        "roofline": roof, "plain_fp64": None, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +330,9 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("this benchmark measures one GPU only: run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "threshold":
+        run_threshold(args)
+        return
 
     import numpy as np
     import torch

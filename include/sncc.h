@@ -133,6 +133,18 @@ int sncc_ctx_create(int device, uintptr_t hip_stream, sncc_ctx **out);
 int sncc_ctx_destroy(sncc_ctx *ctx);
 /* Waits for the context's stream; reports pending HIP errors. */
 int sncc_sync(sncc_ctx *ctx);
+/*
+ * Stage timing.  With timing enabled, calls that launch several kernels
+ * record HIP events on the context's stream between their stages, and
+ * sncc_ctx_stage_ms returns the device time of each stage of the last such
+ * call (waiting for it): sncc_topk with SNCC_FP32_KAHAN gives {scoring,
+ * selection}; sncc_threshold_match gives {fast scoring and compaction, slow
+ * FP64 pass}.  *n receives the number of stages (0 when the last call
+ * recorded none); at most cap values are written to ms.
+ * Errors: SNCC_EINVAL, SNCC_EDEVICE.
+ */
+int sncc_ctx_set_timing(sncc_ctx *ctx, int enable);
+int sncc_ctx_stage_ms(sncc_ctx *ctx, float *ms, int cap, int *n);
 
 /* ------------------------------------------------------------- sum tables */
 /* Minimum pitch (elements) of a sum table for images M pixels wide:

@@ -3,7 +3,7 @@
 The work is done by ``libsncc.so`` (HIP kernels behind the C-ABI declared in
 ``include/sncc.h``); this package is its thin Python binding.  Importing it
 raises ImportError when the library has not been built
-(``python -m paper_2502_01286_amd.build``).
+(``python paper_2502_01286_amd/build.py``).
 """
 
 from ._native import *  # noqa: F401,F403

@@ -21,7 +21,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "sncc.h")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is missing: build it with `python -m paper_2502_01286_amd.build` "
+        f"{LIB_PATH} is missing: build it with `python paper_2502_01286_amd/build.py` "
         "(the HIP library is required; there is no fallback)")
 
 # PyTorch bundles its own HIP runtime (same soname as ROCm's).  Loading torch
@@ -89,6 +89,8 @@ _SIGS = {
     "sncc_ctx_create": (_i, [_i, C.c_size_t, _vp]),
     "sncc_ctx_destroy": (_i, [_vp]),
     "sncc_sync": (_i, [_vp]),
+    "sncc_ctx_set_timing": (_i, [_vp, _i]),
+    "sncc_ctx_stage_ms": (_i, [_vp, _vp, _i, _vp]),
     "sncc_sat_pitch": (_i, [_i, _vp]),
     "sncc_build_sats": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _i]),
     "sncc_upload_templates": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
@@ -106,7 +108,11 @@ _SIGS = {
     "sncc_batch_destroy": (_i, [_vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
-    _f = getattr(lib, _name)
+    try:
+        _f = getattr(lib, _name)
+    except AttributeError as _e:
+        raise ImportError(f"{LIB_PATH} does not export {_name}: it is older than the sources; "
+                          "rebuild it with `python paper_2502_01286_amd/build.py`") from _e
     _f.restype = _res
     _f.argtypes = _args
 
@@ -271,6 +277,18 @@ def sncc_refine(ctx, fine, s, s2, B, M, N, pairs, cand, radius, out, count=None)
                            int(B), int(M), int(N), s.shape[-1], len(p), p.ctypes.data,
                            _ptr(cand, torch.int32, "cand"), cand.shape[1], int(radius),
                            _ptr(out, torch.int32, "out"), _ptr(count, torch.int32, "count")))
+
+
+def sncc_ctx_set_timing(ctx, enable: bool):
+    _check(lib.sncc_ctx_set_timing(ctx, 1 if enable else 0))
+
+
+def sncc_ctx_stage_ms(ctx):
+    """Device times (ms) of the stages of the last timed call."""
+    ms = (C.c_float * 4)()
+    n = C.c_int(0)
+    _check(lib.sncc_ctx_stage_ms(ctx, ms, 4, C.byref(n)))
+    return [float(ms[i]) for i in range(n.value)]
 
 
 def sncc_threshold_match(ctx, fast, slow, thr_fast, thr_slow, s, s2, B, M, N, pairs, cand,

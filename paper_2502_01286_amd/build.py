@@ -1,6 +1,6 @@
 """Builds libsncc.so (HIP for gfx950) in place, next to this file.
 
-    python -m paper_2502_01286_amd.build
+    python paper_2502_01286_amd/build.py
 
 Each translation unit is compiled to an object with hipcc, then linked into
 one shared library.  Floating point is compiled without contraction so the

@@ -107,6 +107,17 @@ struct sncc_ctx {
   DevBuf sat_scratch;
   DevBuf map_scratch;
   std::vector<std::unique_ptr<PlanDev>> retired;  // awaiting completion
+  bool timing = false;                             // record stage events
+  hipEvent_t tev[4] = {};
+  int n_stages = 0;                                // stages of the last timed call
+  ~sncc_ctx() {
+    for (auto &e : tev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  // Records the boundary before stage i (or after the last, i = n) of a call.
+  void mark(int i) {
+    if (timing && i < 4) (void)hipEventRecord(tev[i], stream);
+  }
 };
 
 struct sncc_tmpl {
@@ -596,6 +607,29 @@ int sncc_ctx_destroy(sncc_ctx *ctx) {
   return SNCC_OK;
 }
 
+int sncc_ctx_set_timing(sncc_ctx *ctx, int enable) {
+  g_err.clear();
+  CHK(check_ctx(ctx));
+  if (enable)
+    for (auto &e : ctx->tev)
+      if (!e) HIPCHK(hipEventCreate(&e));
+  ctx->timing = enable != 0;
+  ctx->n_stages = 0;
+  return SNCC_OK;
+}
+
+int sncc_ctx_stage_ms(sncc_ctx *ctx, float *ms, int cap, int *n) {
+  g_err.clear();
+  CHK(check_ctx(ctx));
+  if (!n || (cap > 0 && !ms)) SNCC_FAIL(SNCC_EINVAL, "NULL output");
+  *n = ctx->n_stages;
+  if (ctx->n_stages == 0) return SNCC_OK;
+  HIPCHK(hipEventSynchronize(ctx->tev[ctx->n_stages]));
+  for (int i = 0; i < ctx->n_stages && i < cap; ++i)
+    HIPCHK(hipEventElapsedTime(&ms[i], ctx->tev[i], ctx->tev[i + 1]));
+  return SNCC_OK;
+}
+
 int sncc_sync(sncc_ctx *ctx) {
   g_err.clear();
   CHK(check_ctx(ctx));
@@ -796,10 +830,17 @@ int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uin
     CHK(build_plan(tm, 0, M, N, n_pairs, pairs, k, kSinkTopk, ctx->num_cu, pd->h));
     CHK(pd->upload(ctx->stream));
     TileArgs a = pd->args(d_s, d_s2, fs, sat_pitch, M, N);
-    if (launch_zero(a.queue, a.n_zero, ctx->stream) != 0 ||
-        launch_tile(pd->h.cfg, kSinkTopk, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0 ||
-        launch_merge(pd->d_pairs.as<PairDesc>(), n_pairs, a.partial, k, d_out, ctx->stream) != 0)
+    ctx->n_stages = 0;
+    if (launch_zero(a.queue, a.n_zero, ctx->stream) != 0)
       SNCC_FAIL(SNCC_EDEVICE, "top-k launch: %s", hipGetErrorString(hipGetLastError()));
+    ctx->mark(0);
+    if (launch_tile(pd->h.cfg, kSinkTopk, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0)
+      SNCC_FAIL(SNCC_EDEVICE, "top-k launch: %s", hipGetErrorString(hipGetLastError()));
+    ctx->mark(1);
+    if (launch_merge(pd->d_pairs.as<PairDesc>(), n_pairs, a.partial, k, d_out, ctx->stream) != 0)
+      SNCC_FAIL(SNCC_EDEVICE, "top-k launch: %s", hipGetErrorString(hipGetLastError()));
+    ctx->mark(2);
+    if (ctx->timing) ctx->n_stages = 2;
     return retire(ctx, std::move(pd));
   }
   if (precision != SNCC_FP64) SNCC_FAIL(SNCC_EINVAL, "unknown precision %d", precision);
@@ -936,13 +977,20 @@ int sncc_threshold_match(sncc_ctx *ctx, const sncc_tmpl *fast, const sncc_tmpl *
   CHK(pd->d_thr.upload(ts, ctx->stream));
   TileArgs a = pd->args(d_s, d_s2, fs, sat_pitch, M, N);
   a.co = CompactOut{d_cand, cand_cap, d_counts};
+  ctx->n_stages = 0;
   if (launch_zero(a.queue, a.n_zero, ctx->stream) != 0 ||
-      launch_zero(d_counts, 2, ctx->stream) != 0 ||
-      launch_tile(pd->h.cfg, kSinkCompact, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0 ||
-      launch_slow(d_s, d_s2, fs, sat_pitch, slow->d_dev.as<DevTmpl>(), slow->d_geom.as<int4>(),
+      launch_zero(d_counts, 2, ctx->stream) != 0)
+    SNCC_FAIL(SNCC_EDEVICE, "threshold search launch: %s", hipGetErrorString(hipGetLastError()));
+  ctx->mark(0);
+  if (launch_tile(pd->h.cfg, kSinkCompact, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0)
+    SNCC_FAIL(SNCC_EDEVICE, "threshold search launch: %s", hipGetErrorString(hipGetLastError()));
+  ctx->mark(1);
+  if (launch_slow(d_s, d_s2, fs, sat_pitch, slow->d_dev.as<DevTmpl>(), slow->d_geom.as<int4>(),
                   slow->d_c64.as<double>(), pd->d_pairs.as<PairDesc>(), pd->d_thr.as<double>(),
                   d_cand, d_counts, cand_cap, d_out, out_cap, d_counts + 1, ctx->stream) != 0)
     SNCC_FAIL(SNCC_EDEVICE, "threshold search launch: %s", hipGetErrorString(hipGetLastError()));
+  ctx->mark(2);
+  if (ctx->timing) ctx->n_stages = 2;
   return retire(ctx, std::move(pd));
 }
 

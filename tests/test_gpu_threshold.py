@@ -226,3 +226,26 @@ def test_errors(S, ctx):
                                counts)
     for h in (fast, slow, other):
         S.sncc_tmpl_destroy(h)
+
+
+def test_stage_timing(S, ctx):
+    import torch
+    frames = [synth.scene(7400, 256, 192)]
+    rng = np.random.default_rng(9)
+    t, _, _ = synth.crop_template(rng, frames[0], 30, 26, sigma_max=10)
+    _, s, s2 = build_sats(S, ctx, frames)
+    fast, slow, tf, ts = _prepare(S, ctx, [t])
+    cand = torch.zeros((1 << 15, 6), dtype=torch.int32, device="cuda")
+    out = torch.zeros((1 << 15, 6), dtype=torch.int32, device="cuda")
+    counts = torch.zeros(4, dtype=torch.int32, device="cuda")
+    S.sncc_ctx_set_timing(ctx, True)
+    try:
+        S.sncc_threshold_match(ctx, fast, slow, tf, ts, s, s2, 1, 256, 192, [(0, 0)], cand, out,
+                               counts)
+        ms = S.sncc_ctx_stage_ms(ctx)
+        assert len(ms) == 2 and all(m > 0 for m in ms)
+    finally:
+        S.sncc_ctx_set_timing(ctx, False)
+    assert S.sncc_ctx_stage_ms(ctx) == []
+    S.sncc_tmpl_destroy(fast)
+    S.sncc_tmpl_destroy(slow)

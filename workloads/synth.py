@@ -204,3 +204,22 @@ def coarse_fine_256x32(n_frames: int = 256, n_templates: int = 32, M: int = 1280
     pairs = [(fi, ti) for fi in range(n_frames) for ti in range(n_templates)]
     return Workload("coarse_fine_256x32", frames, temps, [16.0] * n_templates, pairs, k=k,
                     fine_sigma=4.0, origin=origin)
+
+
+def threshold_4x4(n_frames: int = 4, n_templates: int = 4, M: int = 1920, N: int = 1080,
+                  side: int = 64) -> Workload:
+    """The paper's two-threshold search over a small batch: scenes 1920x1080,
+    side x side templates cropped from random frames (re-drawn until their
+    deviation exceeds 16 / 0.99), every pair scored; the thresholds are taken
+    relative to each template (0.99 and 0.1 of its deviation)."""
+    frames = [scene(6000 + i, M, N) for i in range(n_frames)]
+    rng = np.random.default_rng(6999)
+    temps, origin = [], []
+    for _ in range(n_templates):
+        fi = int(rng.integers(0, n_frames))
+        t, x, y = crop_template(rng, frames[fi], side, side, sigma_max=16)
+        temps.append(t)
+        origin.append((fi, x, y))
+    pairs = [(fi, ti) for fi in range(n_frames) for ti in range(n_templates)]
+    return Workload("threshold_4x4", frames, temps, [0.0] * n_templates, pairs, k=0,
+                    origin=origin, note="relative thresholds")
