@@ -12,7 +12,8 @@ sides U{24..96}, coarse sigma_max 16 (top-32 per pair), fine sigma_max 4 on
 templates (sides U{16..192}, sigma_max U{4,8,12,16}, top-5) instead;
 `--workload threshold` runs the paper's own two-threshold search (Section 5)
 on 4 frames 1920x1080 x 4 templates 64x64 with relative thresholds (value =
-fast plus slow evaluations per second).
+fast plus slow evaluations per second); `--workload prep` times the host
+template preparation alone (1024 templates, both approximations).
 
 Prints one JSON line.  value = coarse offset x segment evaluations per
 second of the whole step.
@@ -310,6 +311,79 @@ def run_threshold(args):
     print(json.dumps(line), flush=True)
 
 
+# --------------------------------------------- batched template preparation
+def _cpu_prep_sample(job):
+    import oracle as O
+    t, sf, ss = job
+    O.precompute_template_approximation(t, sf)
+    O.precompute_template_approximation(t, ss)
+    return 1
+
+
+def run_prep(args):
+    """Template preparation (Section 5, lines 1-5 of the algorithm, the part the
+    paper times separately): both approximations of many templates on host
+    threads.  Host only; no device work."""
+    import numpy as np
+    import paper_2502_01286_amd as S
+    from workloads import synth
+
+    wl = synth.prep_1024()
+    ts = wl.templates
+    sd = [float(np.asarray(t, np.float64).std()) for t in ts]
+    sig = [0.99 * x for x in sd] + [0.1 * x for x in sd]
+    both = ts + ts
+    log(f"[bench] preparation: {len(ts)} templates (sides {min(t.shape[0] for t in ts)}.."
+        f"{max(t.shape[0] for t in ts)}), fast and slow approximations")
+    for _ in range(args.warmup):
+        S.sncc_segment_templates(both, sig, 5000, 0)
+    times = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        lists, su, rm, st = S.sncc_segment_templates(both, sig, 5000, 0)
+        times.append(time.perf_counter() - t0)
+    t_all = float(np.median(times))
+    t0 = time.perf_counter()
+    S.sncc_segment_templates(both, sig, 5000, 1)
+    t_one = time.perf_counter() - t0
+    threads = os.cpu_count() or 1
+    K = [len(a) for a in lists]
+    log(f"[bench] {t_all * 1e3:.1f} ms on all threads, {t_one * 1e3:.1f} ms on one; K fast "
+        f"{min(K[:len(ts)])}..{max(K[:len(ts)])}, K slow {min(K[len(ts):])}..{max(K[len(ts):])}")
+    cpu = None
+    if not args.no_cpu:
+        from concurrent.futures import ProcessPoolExecutor
+        cores = max(1, min(16, len(os.sched_getaffinity(0))))
+        rng = np.random.default_rng(4242)
+        pick = rng.permutation(len(ts))
+        jobs = [(ts[i], 0.99 * sd[i], 0.1 * sd[i]) for i in pick]
+        done, t0 = 0, time.perf_counter()
+        with ProcessPoolExecutor(max_workers=cores) as ex:
+            for chunk in range(0, len(jobs), cores * 4):
+                done += sum(ex.map(_cpu_prep_sample, jobs[chunk:chunk + cores * 4]))
+                if time.perf_counter() - t0 > args.cpu_budget:
+                    break
+        dt = time.perf_counter() - t0
+        cpu = {"value": done / dt, "unit": "templates/s", "cores": cores, "kind": "oracle",
+               "sample": f"{done} seeded templates of the same set, both approximations, "
+                         f"{dt:.1f} s wall on {cores} processes"}
+        log(f"[bench] cpu {cpu}")
+    line = {
+        "metric": "template preparation (both approximations per template)",
+        "value": len(ts) / t_all, "unit": "templates/s", "n_gpus": 0,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_all * 1e3,
+        "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "prep", "templates": len(ts), "host_threads": threads,
+                   "sigma_fast": "0.99 sigma_t", "sigma_slow": "0.1 sigma_t", "K_max": 5000,
+                   "K_fast": [min(K[:len(ts)]), max(K[:len(ts)])],
+                   "K_slow": [min(K[len(ts):]), max(K[len(ts):])],
+                   "one_thread_templates_per_s": len(ts) / t_one},
+        "roofline": None, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,6 +406,9 @@ def main():
         sys.exit(2)
     if args.workload == "threshold":
         run_threshold(args)
+        return
+    if args.workload == "prep":
+        run_prep(args)
         return
 
     import numpy as np

@@ -122,6 +122,31 @@ int sncc_segment_template(const uint8_t *t, int W, int H, int t_stride,
                           int cap, int *K_out, double *sigma_used,
                           double *rho_max);
 
+/*
+ * Batched template preparation: sncc_segment_template for T templates at
+ * once on n_threads host threads (0: one per hardware thread).  Template i
+ * is t[i], W[i] x H[i] bytes with row stride t_stride[i], split with
+ * sigma_max[i]; K_max is shared.  The lists are identical to the single
+ * calls' and are written back to back: template i's K_i segments start at
+ * out[seg_off[i]], and seg_off[T] is the total.
+ *
+ *   out, out_cap  host array; when the total exceeds out_cap nothing is
+ *                 written to out (seg_off is still filled) and SNCC_ENOSPC
+ *                 is returned
+ *   seg_off       host, T + 1 entries
+ *   sigma_used, rho_max, status  host, T entries each, nullable: per
+ *                 template the accepted threshold, the NCC with the
+ *                 approximation (NaN when uniform) and the status
+ * A uniform approximation does not stop the others: every list is written
+ * and the call returns SNCC_EDEGENERATE naming the first such template.
+ * Errors: SNCC_EINVAL, SNCC_ENOSPC, SNCC_EDEGENERATE.
+ */
+int sncc_segment_templates(int T, const uint8_t *const *t, const int *W, const int *H,
+                           const int *t_stride, const double *sigma_max, int K_max,
+                           int n_threads, sncc_segment *out, int64_t out_cap,
+                           int64_t *seg_off, double *sigma_used, double *rho_max,
+                           int *status);
+
 /* ---------------------------------------------------------------- context */
 /*
  * Binds a device and a HIP stream (hipStream_t passed as an integer, e.g.

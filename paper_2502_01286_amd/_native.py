@@ -86,6 +86,8 @@ _SIGS = {
     "sncc_last_error": (C.c_char_p, []),
     "sncc_version": (_i, []),
     "sncc_segment_template": (_i, [_vp, _i, _i, _i, _d, _i, _vp, _i, _vp, _vp, _vp]),
+    "sncc_segment_templates": (_i, [_i, _vp, _vp, _vp, _vp, _vp, _i, _i, _vp, C.c_int64, _vp,
+                                    _vp, _vp, _vp]),
     "sncc_ctx_create": (_i, [_i, C.c_size_t, _vp]),
     "sncc_ctx_destroy": (_i, [_vp]),
     "sncc_sync": (_i, [_vp]),
@@ -162,6 +164,35 @@ def sncc_segment_template(t, sigma_max: float, K_max: int = 5000):
     _check(lib.sncc_segment_template(t.ctypes.data, W, H, W, float(sigma_max), int(K_max),
                                      out.ctypes.data, cap, C.byref(K), C.byref(su), C.byref(rm)))
     return out[:K.value].copy(), su.value, rm.value
+
+
+def sncc_segment_templates(templates, sigmas, K_max: int = 5000, n_threads: int = 0,
+                           check: bool = True):
+    """Batched sncc_segment_template on host threads.  Returns (list of
+    segment arrays, sigma_used array, rho_max array, status array); with
+    check, a non-OK status raises SnccError."""
+    ts = [np.ascontiguousarray(t, dtype=np.uint8) for t in templates]
+    T = len(ts)
+    if T < 1 or len(sigmas) != T:
+        raise ValueError("need one sigma per template and at least one template")
+    ptrs = (C.c_void_p * T)(*[t.ctypes.data for t in ts])
+    W = np.array([t.shape[1] for t in ts], dtype=np.int32)
+    H = np.array([t.shape[0] for t in ts], dtype=np.int32)
+    sg = np.ascontiguousarray(sigmas, dtype=np.float64)
+    cap = int((W.astype(np.int64) * H).sum())
+    out = np.zeros(cap, dtype=SEGMENT_DTYPE)
+    off = np.zeros(T + 1, dtype=np.int64)
+    su = np.zeros(T)
+    rm = np.zeros(T)
+    st = np.zeros(T, dtype=np.int32)
+    rc = lib.sncc_segment_templates(T, ptrs, W.ctypes.data, H.ctypes.data, W.ctypes.data,
+                                    sg.ctypes.data, int(K_max), int(n_threads), out.ctypes.data,
+                                    cap, off.ctypes.data, su.ctypes.data, rm.ctypes.data,
+                                    st.ctypes.data)
+    if check:
+        _check(rc)
+    lists = [out[off[i]:off[i + 1]].copy() for i in range(T)]
+    return lists, su, rm, st
 
 
 def sncc_sat_pitch(M: int) -> int:

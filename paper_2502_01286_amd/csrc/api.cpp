@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -13,6 +14,7 @@
 #include <memory>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "sncc_internal.hpp"
@@ -575,6 +577,77 @@ int sncc_segment_template(const uint8_t *t, int W, int H, int t_stride, double s
     out[i].area = (int32_t)segs[i].area;
     out[i].reserved = 0;
   }
+  return SNCC_OK;
+}
+
+int sncc_segment_templates(int T, const uint8_t *const *t, const int *W, const int *H,
+                           const int *t_stride, const double *sigma_max, int K_max,
+                           int n_threads, sncc_segment *out, int64_t out_cap, int64_t *seg_off,
+                           double *sigma_used, double *rho_max, int *status) {
+  g_err.clear();
+  if (T < 1 || !t || !W || !H || !t_stride || !sigma_max || !seg_off)
+    SNCC_FAIL(SNCC_EINVAL, "NULL argument or T < 1");
+  if (K_max < 1) SNCC_FAIL(SNCC_EINVAL, "K_max must be >= 1");
+  for (int i = 0; i < T; ++i) {
+    if (!t[i] || W[i] < 1 || H[i] < 1 || t_stride[i] < W[i])
+      SNCC_FAIL(SNCC_EINVAL, "template %d: bad pointer, size %dx%d or stride %d", i,
+                W[i], H[i], t_stride[i]);
+    if (std::isnan(sigma_max[i])) SNCC_FAIL(SNCC_EINVAL, "template %d: sigma_max is NaN", i);
+  }
+  std::vector<std::vector<Seg>> lists(T);
+  std::vector<int> st(T, SNCC_OK);
+  std::vector<double> su(T, 0.0), rm(T, 0.0);
+  std::atomic<int> next{0};
+  auto worker = [&]() {
+    for (int i = next.fetch_add(1); i < T; i = next.fetch_add(1)) {
+      int kbm = 0;
+      st[i] = segment_template(t[i], W[i], H[i], t_stride[i], sigma_max[i], K_max, lists[i],
+                               &kbm, &su[i], &rm[i]);
+    }
+  };
+  int nt = n_threads > 0 ? n_threads : (int)std::thread::hardware_concurrency();
+  nt = std::max(1, std::min(nt, T));
+  if (nt == 1) {
+    worker();
+  } else {
+    std::vector<std::thread> pool;
+    try {
+      for (int k = 1; k < nt; ++k) pool.emplace_back(worker);
+    } catch (...) {
+      // fewer threads than asked for: the ones running (and this one) finish the work
+    }
+    worker();
+    for (auto &th : pool) th.join();
+  }
+  int64_t total = 0;
+  int first_bad = SNCC_OK, bad_index = -1;
+  for (int i = 0; i < T; ++i) {
+    seg_off[i] = total;
+    total += (int64_t)lists[i].size();
+    if (sigma_used) sigma_used[i] = su[i];
+    if (rho_max) rho_max[i] = st[i] == SNCC_OK ? rm[i] : std::nan("");
+    if (status) status[i] = st[i];
+    if (st[i] != SNCC_OK && first_bad == SNCC_OK) first_bad = st[i], bad_index = i;
+  }
+  seg_off[T] = total;
+  if (total > out_cap || (!out && total > 0))
+    SNCC_FAIL(SNCC_ENOSPC, "need %lld segments, capacity %lld", (long long)total,
+              (long long)out_cap);
+  for (int i = 0; i < T; ++i) {
+    sncc_segment *o = out + seg_off[i];
+    for (const Seg &g : lists[i]) {
+      o->x = g.x;
+      o->y = g.y;
+      o->w = g.w;
+      o->h = g.h;
+      o->sum = g.sum;
+      o->area = (int32_t)g.area;
+      o->reserved = 0;
+      ++o;
+    }
+  }
+  if (first_bad != SNCC_OK)
+    SNCC_FAIL(first_bad, "template %d: uniform template approximation", bad_index);
   return SNCC_OK;
 }
 

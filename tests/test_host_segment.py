@@ -136,3 +136,73 @@ def test_kmax_loop_matches_oracle_sigma_used():
         got = _lib_list(t, 4, k_max)
         want = _oracle_list(t, 4, k_max)
         assert got[0] == want[0] and got[1] == want[1]
+
+
+# ------------------------------------------------ batched preparation (host)
+def _batch_cases(seed, n):
+    rng = np.random.default_rng(seed)
+    ts, sg = [], []
+    for i in range(n):
+        t = _random_template(rng) if i % 3 else \
+            rng.integers(0, 256, (int(rng.integers(8, 65)), int(rng.integers(8, 65)))).astype(np.uint8)
+        ts.append(t)
+        sd = float(t.astype(np.float64).std())
+        sg.append([0.99 * sd, 0.1 * sd, float(rng.choice([0, 4, 16, 60]))][i % 3])
+    return ts, sg
+
+
+@pytest.mark.parametrize("n_threads", [1, 4, 0])
+def test_batched_preparation_equals_single_calls(n_threads):
+    ts, sg = _batch_cases(21, 300)
+    lists, su, rm, st = S.sncc_segment_templates(ts, sg, 5000, n_threads, check=False)
+    for i, (t, s) in enumerate(zip(ts, sg)):
+        try:
+            one, su1, rm1 = S.sncc_segment_template(t, s, 5000)
+        except S.SnccError as e:
+            assert e.code == S.SNCC_EDEGENERATE and st[i] == S.SNCC_EDEGENERATE
+            continue
+        assert st[i] == S.SNCC_OK
+        assert (lists[i] == one).all() and len(lists[i]) == len(one)
+        assert su[i] == su1 and rm[i] == rm1
+
+
+def test_batched_preparation_equals_oracle():
+    ts, sg = _batch_cases(22, 120)
+    lists, su, rm, st = S.sncc_segment_templates(ts, sg, 200, 0, check=False)
+    for i, (t, s) in enumerate(zip(ts, sg)):
+        try:
+            want, wsu, wrm = _oracle_list(t, s, 200)
+        except ValueError:
+            assert st[i] == S.SNCC_EDEGENERATE
+            continue
+        got = [(int(g["x"]), int(g["y"]), int(g["w"]), int(g["h"]), int(g["sum"]),
+                int(g["area"])) for g in lists[i]]
+        assert got == want and su[i] == wsu
+        assert rm[i] == pytest.approx(wrm, abs=1e-12)
+
+
+def test_batched_preparation_degenerate_and_capacity():
+    rng = np.random.default_rng(23)
+    ts = [rng.integers(0, 256, (9, 7)).astype(np.uint8), np.full((5, 6), 17, np.uint8),
+          rng.integers(0, 256, (4, 12)).astype(np.uint8)]
+    sg = [10.0, 3.0, 10.0]
+    with pytest.raises(S.SnccError) as e:
+        S.sncc_segment_templates(ts, sg)
+    assert e.value.code == S.SNCC_EDEGENERATE and "template 1" in str(e.value)
+    lists, su, rm, st = S.sncc_segment_templates(ts, sg, check=False)
+    assert list(st) == [S.SNCC_OK, S.SNCC_EDEGENERATE, S.SNCC_OK]
+    assert np.isnan(rm[1]) and len(lists[1]) == 1
+    for i in (0, 2):
+        one, _, _ = S.sncc_segment_template(ts[i], sg[i])
+        assert (lists[i] == one).all()
+    # capacity: offsets are filled, nothing is written
+    W = np.array([t.shape[1] for t in ts], np.int32)
+    H = np.array([t.shape[0] for t in ts], np.int32)
+    ptrs = (C.c_void_p * 3)(*[t.ctypes.data for t in ts])
+    sgs = np.array(sg)
+    out = np.zeros(2, dtype=S.SEGMENT_DTYPE)
+    off = np.zeros(4, np.int64)
+    rc = S.lib.sncc_segment_templates(3, ptrs, W.ctypes.data, H.ctypes.data, W.ctypes.data,
+                                      sgs.ctypes.data, 5000, 2, out.ctypes.data, 2,
+                                      off.ctypes.data, None, None, None)
+    assert rc == S.SNCC_ENOSPC and off[3] > 2 and (out["area"] == 0).all()

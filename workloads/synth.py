@@ -223,3 +223,21 @@ def threshold_4x4(n_frames: int = 4, n_templates: int = 4, M: int = 1920, N: int
     pairs = [(fi, ti) for fi in range(n_frames) for ti in range(n_templates)]
     return Workload("threshold_4x4", frames, temps, [0.0] * n_templates, pairs, k=0,
                     origin=origin, note="relative thresholds")
+
+
+def prep_1024(n_templates: int = 1024, n_frames: int = 8, M: int = 1920, N: int = 1080,
+              side_lo: int = 16, side_hi: int = 192) -> Workload:
+    """Templates only, for timing their preparation: crops of sides
+    U{side_lo..side_hi} (independently) from seeded scenes, each re-drawn
+    until its deviation exceeds 4 / 0.99."""
+    frames = [scene(8000 + i, M, N) for i in range(n_frames)]
+    rng = np.random.default_rng(8999)
+    temps = []
+    for _ in range(n_templates):
+        W = int(rng.integers(side_lo, side_hi + 1))
+        H = int(rng.integers(side_lo, side_hi + 1))
+        fi = int(rng.integers(0, n_frames))
+        t, _, _ = crop_template(rng, frames[fi], W, H, sigma_max=4)
+        temps.append(t)
+    return Workload("prep_1024", [], temps, [0.0] * n_templates, [], k=0,
+                    note="templates only")
