@@ -13,7 +13,10 @@ templates (sides U{16..192}, sigma_max U{4,8,12,16}, top-5) instead;
 `--workload threshold` runs the paper's own two-threshold search (Section 5)
 on 4 frames 1920x1080 x 4 templates 64x64 with relative thresholds (value =
 fast plus slow evaluations per second); `--workload prep` times the host
-template preparation alone (1024 templates, both approximations).
+template preparation alone (1024 templates, both approximations);
+`--workload large` runs one 3840x2160 frame with a 640x480 and a 384x384
+template (areas beyond one exact f^2 box; the first in the direct form),
+top-5 per pair.
 
 Prints one JSON line.  value = coarse offset x segment evaluations per
 second of the whole step.
@@ -88,6 +91,8 @@ def make_workload(name):
     from workloads import synth
     if name == "coarse-fine":
         return synth.coarse_fine_256x32()
+    if name == "large":
+        return synth.large_3840x2160()
     if name == "batched":
         return synth.batch_16x64()
     if name == "coarse-fine-small":

@@ -48,10 +48,15 @@ extern "C" {
 #define SNCC_FP32_KAHAN 0     /* integer box sums, FP32 compensated sum        */
 #define SNCC_FP64 1           /* integer box sums, FP64 sum                    */
 
-/* Largest template area n = W*H for which every window sum of f^2 is below
- * 2^32 (255^2 * n < 2^32), so that differences of the modulo-2^32 sum
- * tables are exact. */
-#define SNCC_MAX_TEMPLATE_AREA 66051
+/* Largest template area n = W*H (2^23 - 1).  Within it every window and
+ * segment sum of f is below 2^31 and exact as a difference of four entries of
+ * the modulo-2^32 table, the integer terms of the FP32 path fit their 24-bit
+ * multiplies, and n * (sum of f^2) fits 64 bits.  Sums of f^2 are exact for
+ * boxes of up to SNCC_MAX_SQ_BOX_AREA pixels (255^2 * 66051 < 2^32); larger
+ * windows are summed in bands of rows, so the template width may not exceed
+ * that area. */
+#define SNCC_MAX_TEMPLATE_AREA 8388607
+#define SNCC_MAX_SQ_BOX_AREA 66051
 
 /* One rectangle of the approximation: the 5-tuple of Eq. (6) with the mean
  * k_i = sum / area kept as an exact integer ratio (Eq. (4)). */
@@ -182,7 +187,8 @@ int sncc_sat_pitch(int M, int *pitch_elems);
  * 0..x and rows 0..y; row 0 and column 0 are zero (the values at index -1
  * in Eqs. (11), (13), (15)).  Values are stored modulo 2^32; any box sum
  * taken as a difference of four entries is exact while its true value is
- * below 2^32 (so for f^2 windows of area <= SNCC_MAX_TEMPLATE_AREA).
+ * below 2^32 (so for f^2 boxes of area <= SNCC_MAX_SQ_BOX_AREA; larger
+ * windows are taken as several such boxes).
  *
  *   d_f        device, B frames of N rows x f_pitch bytes, frames contiguous
  *   d_s, d_s2  device, B frames of (N + 1) rows x sat_pitch uint32, frames
@@ -204,7 +210,8 @@ int sncc_build_sats(sncc_ctx *ctx, const uint8_t *d_f, int B, int M, int N,
  *   segs[i]    host array of K[i] segments of template i
  * Errors: SNCC_EINVAL (NULL, sizes, segments outside the template or not
  *         covering it exactly once), SNCC_ERANGE (W*H above
- *         SNCC_MAX_TEMPLATE_AREA), SNCC_EDEGENERATE (q_k == 0),
+ *         SNCC_MAX_TEMPLATE_AREA or W above SNCC_MAX_SQ_BOX_AREA),
+ *         SNCC_EDEGENERATE (q_k == 0),
  *         SNCC_ENOMEM, SNCC_EDEVICE.
  */
 int sncc_upload_templates(sncc_ctx *ctx, int T, const sncc_segment *const *segs,

@@ -227,6 +227,7 @@ int plan_template(const sncc_tmpl *tm, int t, const TileCfg &tc, int LP, int row
     ps.seg_begin = (int)ph.recs.size();
     for (size_t q = i; q < j; ++q) {
       const Seg &g = segs[q];
+      if (g.w >= (1 << 12) || g.area >= (1 << 20)) return -2;  // w | area << 12 overflows
       TileRec rc;
       rc.off_tl = slot[g.y] * LP + g.x;
       rc.off_bl = slot[g.y + g.h] * LP + g.x;
@@ -243,7 +244,38 @@ int plan_template(const sncc_tmpl *tm, int t, const TileCfg &tc, int LP, int row
   return max_rows;
 }
 
-int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
+// Direct form of a template for the tile kernel (no LDS staging): one pass
+// whose records are pairs of TileRec slots holding a DirectRec (byte offsets
+// of the corners in a table of pitch P, 4 w, A_i, c_i).
+void plan_direct(const sncc_tmpl *tm, int t, int P, PlanHost &ph, DevTmpl &d) {
+  if (ph.recs.size() & 1) ph.recs.push_back(TileRec{0, 0, 0, 0.f});
+  d.lp_class = kLpDirect;
+  d.pass_begin = (int)ph.passes.size();
+  PassDesc ps;
+  ps.iv_begin = ps.iv_end = (int)ph.ivs.size();
+  ps.seg_begin = (int)ph.recs.size();
+  const std::vector<Seg> &segs = tm->segs[t];
+  for (size_t q = 0; q < segs.size(); ++q) {
+    const Seg &g = segs[q];
+    DirectRec dr;
+    dr.tl = (g.y * P + g.x) * 4;
+    dr.bl = ((g.y + g.h) * P + g.x) * 4;
+    dr.w4 = g.w * 4;
+    dr.area = (int)g.area;
+    dr.c = (float)tm->c64[t][q];
+    dr.pad[0] = dr.pad[1] = dr.pad[2] = 0;
+    TileRec two[2];
+    static_assert(sizeof(two) == sizeof(DirectRec), "a direct record spans two slots");
+    memcpy(two, &dr, sizeof dr);
+    ph.recs.push_back(two[0]);
+    ph.recs.push_back(two[1]);
+  }
+  ps.seg_end = (int)ph.recs.size();
+  ph.passes.push_back(ps);
+  d.pass_end = (int)ph.passes.size();
+}
+
+int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int P, int n_pairs,
                const int32_t *pairs, int k, int sink, int num_cu, PlanHost &ph,
                const double *thr = nullptr) {
   if (cfg < 0 || cfg >= tile_cfg_count()) SNCC_FAIL(SNCC_EINVAL, "bad tile config %d", cfg);
@@ -276,17 +308,29 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
       d.pass_begin = d.pass_end = 0;
       d.thr = thr ? (float)thr[t] : 0.f;
       if (used[t]) {
+        // LDS staging when a row class holds the staged width and every
+        // segment fits the packed record; the direct form otherwise
         const int cls = lp_class_for(bu + tm->W[t] + 1);
-        if (cls < 0) SNCC_FAIL(SNCC_ERANGE, "template %d too wide (W=%d) for the tile kernel", t, tm->W[t]);
-        const int LP = kLpClasses[cls];
-        d.lp_class = cls;
-        const int rows_budget = budget / (LP * 4);
-        const int rows = plan_template(tm, t, tc, LP, rows_budget, ph, d);
-        if (rows < 0) {
+        const size_t mark_recs = ph.recs.size(), mark_ivs = ph.ivs.size();
+        const size_t mark_passes = ph.passes.size();
+        int rows = -2;
+        if (cls >= 0) {
+          const int LP = kLpClasses[cls];
+          d.lp_class = cls;
+          rows = plan_template(tm, t, tc, LP, budget / (LP * 4), ph, d);
+          if (rows >= 0) max_bytes = std::max(max_bytes, scale_bytes + rows * LP * 4);
+        }
+        if (rows == -1 && pass == 0) {  // rows do not fit: retry with one workgroup per CU
           ok = false;
           break;
         }
-        max_bytes = std::max(max_bytes, scale_bytes + rows * LP * 4);
+        if (rows < 0) {
+          ph.recs.resize(mark_recs);
+          ph.ivs.resize(mark_ivs);
+          ph.passes.resize(mark_passes);
+          plan_direct(tm, t, P, ph, d);
+          max_bytes = std::max(max_bytes, scale_bytes);
+        }
       }
       ph.tmpls[t] = d;
       ph.n_passes += d.pass_end - d.pass_begin;
@@ -295,7 +339,6 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int n_pairs,
       ph.lds_bytes = (max_bytes + 255) & ~255;
       break;
     }
-    if (pass == 1) SNCC_FAIL(SNCC_ERANGE, "a template needs more LDS rows than available");
     budget = tile_max_lds() - 1024 - scale_bytes;
   }
 
@@ -750,9 +793,9 @@ int sncc_upload_templates(sncc_ctx *ctx, int T, const sncc_segment *const *segs,
     const int w = W[t], h = H[t], k = K[t];
     if (w < 1 || h < 1 || k < 1 || !segs[t]) SNCC_FAIL(SNCC_EINVAL, "template %d: bad size or list", t);
     const long long n = (long long)w * h;
-    if (n > SNCC_MAX_TEMPLATE_AREA)
-      SNCC_FAIL(SNCC_ERANGE, "template %d: area %lld above %d (f^2 window sums would exceed 2^32)",
-                t, n, SNCC_MAX_TEMPLATE_AREA);
+    if (n > SNCC_MAX_TEMPLATE_AREA || w > kMaxSqBoxArea)
+      SNCC_FAIL(SNCC_ERANGE, "template %d: %dx%d outside the exact range (area <= %d, width <= %d)",
+                t, w, h, SNCC_MAX_TEMPLATE_AREA, kMaxSqBoxArea);
     std::vector<char> cover((size_t)n, 0);
     std::vector<Seg> list;
     int64_t total = 0;
@@ -793,6 +836,7 @@ int sncc_upload_templates(sncc_ctx *ctx, int T, const sncc_segment *const *segs,
     d.n = (int)n;
     d.q_k = qk;
     d.r64 = r;
+    d.sq_rows = n <= kMaxSqBoxArea ? h : kMaxSqBoxArea / w;
     d.seg_off = (int)geom.size();
     tm->W.push_back(w);
     tm->H.push_back(h);
@@ -860,6 +904,7 @@ int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint32_t *d_
     a.W = tm->W[index];
     a.H = tm->H[index];
     a.K = tm->K[index];
+    a.sq_rows = tm->dev[index].sq_rows;
     a.q_k = tm->q_k[index];
     a.r64 = tm->r64[index];
     a.geom = tm->d_geom.as<int4>() + tm->seg_off[index];
@@ -875,7 +920,7 @@ int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint32_t *d_
   if (precision != SNCC_FP32_KAHAN) SNCC_FAIL(SNCC_EINVAL, "unknown precision %d", precision);
   std::unique_ptr<PlanDev> pd(new PlanDev());
   const int32_t pair[2] = {0, index};
-  CHK(build_plan(tm, 0, M, N, 1, pair, 0, kSinkMap, ctx->num_cu, pd->h));
+  CHK(build_plan(tm, 0, M, N, sat_pitch, 1, pair, 0, kSinkMap, ctx->num_cu, pd->h));
   CHK(pd->upload(ctx->stream));
   TileArgs a = pd->args(d_s, d_s2, (long long)(N + 1) * sat_pitch, sat_pitch, M, N);
   a.rho = d_rho;
@@ -900,7 +945,7 @@ int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uin
   const long long fs = (long long)(N + 1) * sat_pitch;
   std::unique_ptr<PlanDev> pd(new PlanDev());
   if (precision == SNCC_FP32_KAHAN) {
-    CHK(build_plan(tm, 0, M, N, n_pairs, pairs, k, kSinkTopk, ctx->num_cu, pd->h));
+    CHK(build_plan(tm, 0, M, N, sat_pitch, n_pairs, pairs, k, kSinkTopk, ctx->num_cu, pd->h));
     CHK(pd->upload(ctx->stream));
     TileArgs a = pd->args(d_s, d_s2, fs, sat_pitch, M, N);
     ctx->n_stages = 0;
@@ -954,6 +999,7 @@ int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uin
     a.W = tm->W[t];
     a.H = tm->H[t];
     a.K = tm->K[t];
+    a.sq_rows = tm->dev[t].sq_rows;
     a.q_k = tm->q_k[t];
     a.r64 = tm->r64[t];
     a.geom = tm->d_geom.as<int4>() + tm->seg_off[t];
@@ -1044,7 +1090,8 @@ int sncc_threshold_match(sncc_ctx *ctx, const sncc_tmpl *fast, const sncc_tmpl *
     SNCC_FAIL(SNCC_EINVAL, "NULL or misaligned buffers");
   const long long fs = (long long)(N + 1) * sat_pitch;
   std::unique_ptr<PlanDev> pd(new PlanDev());
-  CHK(build_plan(fast, 0, M, N, n_pairs, pairs, 1, kSinkCompact, ctx->num_cu, pd->h, thr_fast));
+  CHK(build_plan(fast, 0, M, N, sat_pitch, n_pairs, pairs, 1, kSinkCompact, ctx->num_cu, pd->h,
+                 thr_fast));
   CHK(pd->upload(ctx->stream));
   std::vector<double> ts(thr_slow, thr_slow + slow->T);
   CHK(pd->d_thr.upload(ts, ctx->stream));
@@ -1257,7 +1304,7 @@ int autotune(sncc_batch *b, int *best_cfg) {
   *best_cfg = 0;
   for (int c = 0; c < tile_cfg_count(); ++c) {
     PlanDev pd;
-    if (build_plan(d.coarse, c, d.M, d.N, d.n_pairs, b->pairs.data(), d.k, kSinkTopk,
+    if (build_plan(d.coarse, c, d.M, d.N, d.sat_pitch, d.n_pairs, b->pairs.data(), d.k, kSinkTopk,
                    b->ctx->num_cu, pd.h) != SNCC_OK)
       continue;
     if (pd.upload(b->ctx->stream) != SNCC_OK) continue;
@@ -1334,8 +1381,8 @@ int sncc_batch_create(sncc_ctx *ctx, const sncc_batch_desc *desc, sncc_batch **o
     }
   }
   b->plan.reset(new PlanDev());
-  CHK(build_plan(d.coarse, cfg, d.M, d.N, d.n_pairs, b->pairs.data(), d.k, kSinkTopk, ctx->num_cu,
-                 b->plan->h));
+  CHK(build_plan(d.coarse, cfg, d.M, d.N, d.sat_pitch, d.n_pairs, b->pairs.data(), d.k, kSinkTopk,
+                 ctx->num_cu, b->plan->h));
   CHK(b->plan->upload(ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
 

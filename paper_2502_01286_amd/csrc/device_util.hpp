@@ -132,4 +132,33 @@ __device__ __forceinline__ uint32_t window_box(__amdgpu_buffer_rsrc_t r, int vof
   return (a11 - a10) - (a01 - a00);
 }
 
+// Sum of f^2 over a W x H window (Eq. (15)) as an exact 64-bit value.  Each
+// box of at most kMaxSqBoxArea pixels is exact as a difference of four
+// entries of the modulo-2^32 table, so the window is taken in bands of
+// `band` rows (band * W <= kMaxSqBoxArea) and the band sums are added in
+// 64 bits.  Buffer form: corners at voff + so (+ cW for the right column),
+// `rowb` bytes per table row.
+__device__ __forceinline__ u64 window_sq(__amdgpu_buffer_rsrc_t r, int voff, int so, int cW,
+                                         int rowb, int H, int band) {
+  if (band >= H) return window_box(r, voff, so, cW, H * rowb);
+  u64 acc = 0;
+  for (int y = 0; y < H; y += band) {
+    const int h = min(band, H - y);
+    acc += window_box(r, voff, so + y * rowb, cW, h * rowb);
+  }
+  return acc;
+}
+
+// Pointer form: a0 is the window's top-left table entry, P the row pitch.
+__device__ __forceinline__ u64 window_sq(const uint32_t *__restrict__ a0, int W, int H, int P,
+                                         int band) {
+  u64 acc = 0;
+  for (int y = 0; y < H; y += band) {
+    const int h = min(band, H - y);
+    const uint32_t *t0 = a0 + (long long)y * P, *t1 = t0 + (long long)h * P;
+    acc += (uint32_t)((t1[W] - t1[0]) - (t0[W] - t0[0]));
+  }
+  return acc;
+}
+
 }  // namespace sncc

@@ -344,15 +344,14 @@ int launch_tile(int cfg, int sink, const TileArgs &a, int grid, int lds_bytes,
 // box_i * c_i; Eq. (12)'s mean term is fbar * sum_i A_i c_i.
 __device__ __forceinline__ double rho_plain(const uint32_t *__restrict__ S,
                                             const uint32_t *__restrict__ S2, int P, int u,
-                                            int v, int W, int H, int K, double q_k,
-                                            double r64, const int4 *__restrict__ geom,
+                                            int v, int W, int H, int K, int sq_rows,
+                                            double q_k, double r64,
+                                            const int4 *__restrict__ geom,
                                             const double *__restrict__ c64, bool &flat) {
   const uint32_t *a0 = S + (long long)v * P + u;
   const uint32_t *a1 = a0 + (long long)H * P;
   const uint32_t sf = (a1[W] - a1[0]) - (a0[W] - a0[0]);
-  const uint32_t *b0 = S2 + (long long)v * P + u;
-  const uint32_t *b1 = b0 + (long long)H * P;
-  const uint32_t sf2 = (b1[W] - b1[0]) - (b0[W] - b0[0]);
+  const u64 sf2 = window_sq(S2 + (long long)v * P + u, W, H, P, sq_rows);  // Eq. (15)
   const int n = W * H;
   const long long V = (long long)((u64)(uint32_t)n * sf2 - (u64)sf * sf);
   double acc = 0.0;
@@ -371,14 +370,14 @@ __device__ __forceinline__ double rho_plain(const uint32_t *__restrict__ S,
 
 __global__ __launch_bounds__(256) void plain_kernel(
     const uint32_t *__restrict__ S, const uint32_t *__restrict__ S2, int P, int nu, int nv,
-    int W, int H, int K, double q_k, double r64, const int4 *__restrict__ geom,
+    int W, int H, int K, int sq_rows, double q_k, double r64, const int4 *__restrict__ geom,
     const double *__restrict__ c64, double *__restrict__ rho, int rho_pitch,
     uint8_t *__restrict__ degen) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int u = blockIdx.x * 64 + lane, v = blockIdx.y * 4 + wave;
   if (u >= nu || v >= nv) return;
   bool flat;
-  const double r = rho_plain(S, S2, P, u, v, W, H, K, q_k, r64, geom, c64, flat);
+  const double r = rho_plain(S, S2, P, u, v, W, H, K, sq_rows, q_k, r64, geom, c64, flat);
   rho[(long long)v * rho_pitch + u] = r;
   if (degen) degen[(long long)v * rho_pitch + u] = flat ? 1 : 0;
 }
@@ -386,7 +385,8 @@ __global__ __launch_bounds__(256) void plain_kernel(
 int launch_plain(const PlainArgs &a, hipStream_t st) {
   dim3 grid((a.nu + 63) / 64, (a.nv + 3) / 4);
   hipLaunchKernelGGL(plain_kernel, grid, dim3(256), 0, st, a.s, a.s2, a.sat_pitch, a.nu,
-                     a.nv, a.W, a.H, a.K, a.q_k, a.r64, a.geom, a.c64, a.rho, a.rho_pitch,
+                     a.nv, a.W, a.H, a.K, a.sq_rows, a.q_k, a.r64, a.geom, a.c64, a.rho,
+                     a.rho_pitch,
                      a.degen);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -569,7 +569,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
     const int idx = list[i];
     const int v = idx / pd.nu, u = idx - v * pd.nu;
     bool flat;
-    const double r = rho_plain(S, S2, P, u, v, td.W, td.H, td.K, td.q_k, td.r64,
+    const double r = rho_plain(S, S2, P, u, v, td.W, td.H, td.K, td.sq_rows, td.q_k, td.r64,
                                geom + td.seg_off, c64 + td.seg_off, flat);
     if (r > br || (r == br && idx < bi)) {
       br = r;
@@ -654,9 +654,7 @@ __global__ __launch_bounds__(256) void slow_kernel(
     if (lane == 0) {
       const uint32_t *a1 = a0 + (long long)td.H * P;
       const uint32_t sf = (a1[td.W] - a1[0]) - (a0[td.W] - a0[0]);  // Eq. (13)
-      const uint32_t *b0 = S2 + (long long)h.v * P + h.u;
-      const uint32_t *b1 = b0 + (long long)td.H * P;
-      const uint32_t sf2 = (b1[td.W] - b1[0]) - (b0[td.W] - b0[0]);  // Eq. (15)
+      const u64 sf2 = window_sq(S2 + (long long)h.v * P + h.u, td.W, td.H, P, td.sq_rows);
       const long long V = (long long)((u64)(uint32_t)td.n * sf2 - (u64)sf * sf);
       const double num = acc - (double)sf / (double)td.n * td.r64;  // Eq. (12)
       const double rho =

@@ -37,8 +37,12 @@ struct DevTmpl {
   int pass_begin;      // tile plan: passes of this template
   int pass_end;
   float thr;           // survivor threshold of the compacting sink
-  int pad;
+  int sq_rows;         // rows per band of the f^2 window sum (>= H: one box)
 };
+
+// Largest box whose sum of f^2 stays below 2^32 (255^2 * 66051 < 2^32): larger
+// windows take their f^2 sum band by band (sq_rows rows of W pixels each).
+constexpr int kMaxSqBoxArea = 66051;
 
 // One segment for the tile kernel: LDS dword offsets of its top-left and
 // bottom-left corners relative to the lane's base, width | area << 12, c_i.
@@ -47,6 +51,15 @@ struct TileRec {
   int off_bl;
   int w_area;
   float c;
+};
+
+// One segment for the tile kernel's direct form (corners read from the
+// global table, no LDS): byte offsets of the top-left and bottom-left
+// corners relative to the window's top-left entry, 4 W_i, A_i and c_i.
+struct DirectRec {
+  int tl, bl, w4, area;
+  float c;
+  int pad[3];
 };
 
 // Rows [rel_row, rel_row + n_rows) of the window (template-relative,
@@ -122,6 +135,7 @@ struct PlainArgs {
   int sat_pitch;
   int nu, nv;
   int W, H, K;
+  int sq_rows;             // rows per band of the f^2 window sum
   double q_k, r64;
   const int4 *geom;        // x, y, w, h
   const double *c64;
@@ -152,6 +166,8 @@ constexpr int kQueueInts = 16 * kMaxQueues;
 // rounded up to 16 bytes).
 constexpr int kNumLpClasses = 11;
 constexpr int kLpClasses[kNumLpClasses] = {128, 160, 192, 224, 256, 288, 320, 384, 448, 512, 576};
+// lp_class of a template scored in the direct form
+constexpr int kLpDirect = kNumLpClasses;
 
 // Tile shapes of the scoring kernel: offsets per lane along u (RU) and v
 // (RV) and waves per workgroup (NW); a tile is 64 RU x NW RV offsets.

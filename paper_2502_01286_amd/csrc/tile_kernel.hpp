@@ -1,6 +1,7 @@
 // The persistent scoring kernel (Eqs. (11)-(18)), templated on the tile
-// shape: RU x RV offsets per lane, NW waves, LDS row pitch LP (words) and the
-// sink (rho map or per-item top-k partials).  Each tile shape is compiled in
+// shape: RU x RV offsets per lane, NW waves, LDS row pitch LP (words; 0 for
+// the direct form that reads corners from the global table) and the sink
+// (rho map, per-item top-k partials, or a compacted survivor list).  Each tile shape is compiled in
 // its own translation unit (tile_entry.hip).
 #pragma once
 
@@ -11,20 +12,25 @@ namespace sncc {
 static_assert(kNumLpClasses == 11, "the LP-class switch in tile_kernel lists 11 cases");
 
 // Stages the pass's row intervals of one frame's sum table into LDS with
-// LDS-direct buffer loads: lane c4 of a wave moves 16 bytes of a row.
+// LDS-direct buffer loads: lane c4 of a wave moves 16 bytes of a row.  Rows
+// below the table's last row (N) and 16-byte chunks past its pitch are not
+// read: only offsets outside the valid range would use them, and those are
+// masked, so every load stays inside the frame's table.
 template <int LP, int NW>
-__device__ __forceinline__ void stage_pass(__amdgpu_buffer_rsrc_t rs, int P,
+__device__ __forceinline__ void stage_pass(__amdgpu_buffer_rsrc_t rs, int P, int N,
                                            const Interval *__restrict__ ivs, int iv_begin,
                                            int iv_end, int u0, int v0, int stage_w4,
                                            uint32_t *lds, int wave, int lane) {
+  const int w4 = min(stage_w4, (P - u0) >> 2);  // P and u0 are multiples of 64
   for (int iv = iv_begin; iv < iv_end; ++iv) {
     const Interval I = ivs[iv];
-    for (int j = wave; j < I.n_rows; j += NW) {
+    const int rows = min(I.n_rows, N + 1 - (v0 + I.rel_row));
+    for (int j = wave; j < rows; j += NW) {
       const int src = ((v0 + I.rel_row + j) * P + u0) * 4;
       uint32_t *dst = lds + (I.lds_row + j) * LP;
 #pragma unroll
       for (int c = 0; c < (LP / 4 + 63) / 64; ++c) {
-        if (c * 64 + lane < stage_w4)
+        if (c * 64 + lane < w4)
           __builtin_amdgcn_raw_ptr_buffer_load_lds(
               rs, (__attribute__((address_space(3))) void *)(dst + c * 256), 16,
               lane * 16 + c * 1024, src, 0, 0);
@@ -58,14 +64,13 @@ __device__ __forceinline__ void run_item(
   for (int tile = it.tile_begin; tile < it.tile_end; ++tile) {
     const int tv = tile / pd.ntu, tu = tile - tv * pd.ntu;
     const int u0 = tu * BU, v0 = tv * BV;
-    const int voff = ((v0 + wave * RV) * P + u0 + lane) * 4;
 
     // the first pass's rows are requested before the prologue's loads so
     // that both latencies overlap
-    __syncthreads();
-    {
+    if constexpr (LP != 0) {
+      __syncthreads();
       const PassDesc ps = passes[td.pass_begin];
-      stage_pass<LP, NW>(rs, P, ivs, ps.iv_begin, ps.iv_end, u0, v0, stage_w4, lds, wave,
+      stage_pass<LP, NW>(rs, P, N, ivs, ps.iv_begin, ps.iv_end, u0, v0, stage_w4, lds, wave,
                          lane);
     }
 
@@ -73,8 +78,8 @@ __device__ __forceinline__ void run_item(
     // bias, and the scale 1 / sqrt(V q_k / n) from the exact window energy
     // V = n * Eq. (16) in 64-bit integers (0 when V = 0).  The loads are
     // issued before the first staging wait so that their latency overlaps
-    // it; offsets outside the valid range read in-buffer values and are
-    // masked in the epilogue
+    // it; offsets outside the valid range read the window of the nearest
+    // valid offset (inside the table) and are masked in the epilogue
     int nb[R];
     float acc[R], cmp[R];
 #pragma unroll
@@ -82,8 +87,11 @@ __device__ __forceinline__ void run_item(
 #pragma unroll
       for (int du = 0; du < RU; ++du) {
         const int r = dv * RU + du;
-        const uint32_t sf = window_box(rs, voff + du * 256, dv * P * 4, cW, cH);
-        const uint32_t sf2 = window_box(rs2, voff + du * 256, dv * P * 4, cW, cH);
+        const int uc = min(u0 + lane + 64 * du, pd.nu - 1);
+        const int vc = min(v0 + wave * RV + dv, pd.nv - 1);
+        const int wo = (vc * P + uc) * 4;
+        const uint32_t sf = window_box(rs, wo, 0, cW, cH);
+        const u64 sf2 = window_sq(rs2, wo, 0, cW, P * 4, H, td.sq_rows);
         nb[r] = -(int)__builtin_rintf((float)sf * inv_n);
         const u64 V = (u64)(uint32_t)n * sf2 - (u64)sf * sf;
         const float x =
@@ -93,14 +101,59 @@ __device__ __forceinline__ void run_item(
         cmp[r] = 0.f;
       }
 
+    if constexpr (LP == 0) {
+      // direct form: corners from the global table through buffer loads with
+      // the segment's corner offsets as scalar offsets; same arithmetic as
+      // the staged form, four segments per compensated step
+      const PassDesc ps = passes[td.pass_begin];
+      const DirectRec *dp = reinterpret_cast<const DirectRec *>(recs + ps.seg_begin);
+      const int nseg = (ps.seg_end - ps.seg_begin) >> 1;
+      int vb[R];
+#pragma unroll
+      for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+        for (int du = 0; du < RU; ++du) {
+          const int uc = min(u0 + lane + 64 * du, pd.nu - 1);
+          const int vc = min(v0 + wave * RV + dv, pd.nv - 1);
+          vb[dv * RU + du] = (vc * P + uc) * 4;
+        }
+      for (int i = 0; i < nseg; i += 4) {
+        float y[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) y[r] = -cmp[r];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (i + q < nseg) {
+            const DirectRec e = dp[i + q];
+            const int tr = e.tl + e.w4, br = e.bl + e.w4;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const uint32_t a00 = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], e.tl, 0);
+              const uint32_t a01 = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], tr, 0);
+              const uint32_t a10 = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], e.bl, 0);
+              const uint32_t a11 = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], br, 0);
+              const uint32_t F = (a11 - a10) - (a01 - a00);  // Eq. (11)
+              const int G = (int)F + __mul24(e.area, nb[r]);
+              y[r] = __builtin_fmaf((float)G, e.c, y[r]);
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float t = acc[r] + y[r];
+          cmp[r] = (t - acc[r]) - y[r];
+          acc[r] = t;
+        }
+      }
+    } else {
     // per-segment terms (Eqs. (11), (12)), pass by pass; the products of four
     // segments are added before one compensated (Kahan) step
     for (int p = td.pass_begin; p < td.pass_end; ++p) {
       const PassDesc ps = passes[p];
       if (p != td.pass_begin) {
         __syncthreads();
-        stage_pass<LP, NW>(rs, P, ivs, ps.iv_begin, ps.iv_end, u0, v0, stage_w4, lds, wave,
-                           lane);
+        stage_pass<LP, NW>(rs, P, N, ivs, ps.iv_begin, ps.iv_end, u0, v0, stage_w4, lds,
+                           wave, lane);
       }
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
@@ -170,6 +223,8 @@ __device__ __forceinline__ void run_item(
           }
       }
     }
+
+    }  // staged form
 
     // epilogue: rho = num / sqrt(V q_k / n) (Eqs. (17), (18)) in FP32
     if (SINK == kSinkMap) {
@@ -278,7 +333,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   extern __shared__ __align__(16) uint32_t lds[];
   constexpr int kScaleWords = 64 * NW * RU * RV;
   __shared__ int item_sh;
-  __shared__ uint32_t floor_sh;     // high word of the pair's published floor
   __shared__ uint32_t thr_sh[NW];  // high words of the waves' k-th keys (current item)
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // Work queues: queue j holds order[qbeg[j] .. qbeg[j + 1]) and its counter
@@ -302,10 +356,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
       }
       item_sh = got;
       // a key below the k-th key of another item of the same pair cannot be
-      // in the pair's top k; items publish theirs when they finish
+      // in the pair's top k; items publish theirs when they finish.  Every
+      // wave's threshold word starts from that floor (no wave reads these
+      // words any more: the previous item's merge passed a barrier)
+      uint32_t fl = 0;
       if (SINK == kSinkTopk && got >= 0)
-        floor_sh = (uint32_t)(__hip_atomic_load(pair_floor + items[got].pair, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT) >> 32);
+        fl = (uint32_t)(__hip_atomic_load(pair_floor + items[got].pair, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) >> 32);
+      for (int w = 0; w < NW; ++w) thr_sh[w] = fl;
     }
     __syncthreads();
     const int item = item_sh;
@@ -315,7 +373,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     const PairDesc pd = pairs[it.pair];
     const DevTmpl td = tmpls[pd.tmpl];
     u64 lkey = 0;
-    if (lane == 0) thr_sh[wave] = SINK == kSinkTopk ? floor_sh : 0u;  // ordered by a barrier
 #define SNCC_RUN(LPV)                                                                    \
   run_item<RU, RV, NW, LPV, SINK>(s, s2, frame_stride, P, N, passes, ivs, recs, it, pd, td, \
                                  lkey, k, rho_out, rho_pitch, degen, lds + kScaleWords,      \
@@ -331,7 +388,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
       case 7: SNCC_RUN(kLpClasses[7]); break;
       case 8: SNCC_RUN(kLpClasses[8]); break;
       case 9: SNCC_RUN(kLpClasses[9]); break;
-      default: SNCC_RUN(kLpClasses[10]); break;
+      case 10: SNCC_RUN(kLpClasses[10]); break;
+      default: SNCC_RUN(0); break;  // direct form
     }
 #undef SNCC_RUN
     if (SINK == kSinkTopk) {

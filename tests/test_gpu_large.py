@@ -1,0 +1,120 @@
+"""Templates beyond the single-box range of the f^2 table (n > 66051) and
+templates too wide for the LDS-staged form (MI355X).
+
+Windows of more than 66051 pixels take their sum of f^2 in bands of rows
+(each band exact as a difference of four modulo-2^32 entries); templates whose
+staged row would not fit an LDS pitch class, or whose segments do not fit the
+packed record, are scored in the direct form (corners read from the global
+table).  The oracle computes with unbounded integers, so its maps are the
+reference at these sizes too; the frames are bright so that the windows'
+sums of f^2 exceed 2^32.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import synth
+
+from gpu_util import build_sats, lib_templates
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL64 = 1e-9
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_2502_01286_amd as S
+    return S
+
+
+@pytest.fixture(scope="module")
+def ctx(S):
+    import torch
+    torch.cuda.init()
+    c = S.sncc_ctx_create(0)
+    yield c
+    S.sncc_ctx_destroy(c)
+
+
+def _bright(seed, M, N):
+    """A scene compressed into 190..255: window sums of f^2 above 2^32."""
+    f = synth.scene(seed, M, N).astype(np.float64)
+    return np.clip(np.rint(190 + f * 65 / 255), 0, 255).astype(np.uint8)
+
+
+def _maps(S, ctx, f, t, sigma):
+    import torch
+    N, M = f.shape
+    H, W = t.shape
+    _, s, s2 = build_sats(S, ctx, [f])
+    tm = lib_templates(S, ctx, [t], [sigma])
+    nu, nv = M - W + 1, N - H + 1
+    r32 = torch.empty((nv, nu), dtype=torch.float32, device="cuda")
+    r64 = torch.empty((nv, nu), dtype=torch.float64, device="cuda")
+    S.sncc_score(ctx, tm, 0, s, s2, M, N, S.SNCC_FP32_KAHAN, r32)
+    S.sncc_score(ctx, tm, 0, s, s2, M, N, S.SNCC_FP64, r64)
+    top = torch.zeros((1, 5, 3), dtype=torch.int32, device="cuda")
+    S.sncc_topk(ctx, tm, s, s2, 1, M, N, [(0, 0)], 5, S.SNCC_FP32_KAHAN, top)
+    S.sncc_sync(ctx)
+    S.sncc_tmpl_destroy(tm)
+    return (r32.cpu().numpy().astype(np.float64), r64.cpu().numpy(),
+            S.decode_matches(top)[0])
+
+
+def _check(f, t, sigma, g32, g64, top):
+    ta = O.precompute_template_approximation(t, sigma)
+    s, s2 = O.sum_tables(f)
+    H, W = t.shape
+    vv, uu = np.meshgrid(np.arange(g32.shape[0]), np.arange(g32.shape[1]), indexing="ij")
+    _, sf2, _ = O.window_sums(s, s2, W, H, uu, vv)
+    print(f"  K {ta.K}, largest window sum of f^2 {int(sf2.max())} (2^32 = {2 ** 32})",
+          flush=True)
+    assert sf2.max() >= 2 ** 32
+    want = O.rho_map(f, ta, tables=(s, s2))
+    e32, e64 = np.abs(g32 - want).max(), np.abs(g64 - want).max()
+    print(f"  max|drho| fp32 {e32:.2e} fp64 {e64:.2e}", flush=True)
+    assert e32 <= TOL32 and e64 <= TOL64
+    ref = O.topk(want, 5)
+    for r in range(5):
+        assert abs(float(top[r]["rho"]) - want[top[r]["v"], top[r]["u"]]) <= TOL32
+        if r + 1 < len(ref) and ref[r][2] - ref[r + 1][2] > 1e-4 and \
+                (r == 0 or ref[r - 1][2] - ref[r][2] > 1e-4):
+            assert (int(top[r]["u"]), int(top[r]["v"])) == ref[r][:2]
+
+
+
+
+@pytest.mark.parametrize("shape,frame,sigma", [
+    ((400, 300), (1024, 768), 12),    # n = 120000, staged in LDS (row pitch 448)
+    ((150, 600), (1280, 720), 12),    # n = 90000, too wide to stage: direct form
+])
+def test_large_templates(S, ctx, shape, frame, sigma):
+    H, W = shape
+    M, N = frame
+    f = _bright(9100 + W, M, N)
+    rng = np.random.default_rng(W)
+    t, _, _ = synth.crop_template(rng, f, W, H, sigma_max=sigma)
+    print(f"template {W}x{H} on {M}x{N}, sigma {sigma}", flush=True)
+    g32, g64, top = _maps(S, ctx, f, t, sigma)
+    _check(f, t, sigma, g32, g64, top)
+
+
+def test_huge_flat_segment_direct(S, ctx):
+    """A 2048 x 1100 template whose flat left half (1024 x 1100, more than 2^20
+    pixels) is one segment, on a 2560 x 1440 frame: direct form."""
+    rng = np.random.default_rng(77)
+    W, H = 2048, 1100
+    t = np.full((H, W), 240, np.uint8)
+    t[:, 1024:] = 205
+    t[800:, 1024:] = 225
+    t[100:140, 1300:1360] = rng.integers(150, 255, (40, 60))
+    f = _bright(9300, 2560, 1440)
+    f[70:70 + H, 300:300 + W] = t
+    print("template 2048x1100 with a flat 1024x1100 half on 2560x1440", flush=True)
+    ta = O.precompute_template_approximation(t, 10)
+    assert max(g.area for g in ta.segments) >= 1 << 20
+    g32, g64, top = _maps(S, ctx, f, t, 10)
+    _check(f, t, 10, g32, g64, top)

@@ -310,11 +310,14 @@ def test_errors(S, ctx):
     with pytest.raises(S.SnccError) as e:
         S.sncc_topk(ctx, tm, s, s2, 1, 50, 40, [(1, 0)], 1, S.SNCC_FP32_KAHAN, out)
     assert e.value.code == S.SNCC_EINVAL
-    big = rng.integers(0, 256, (260, 260)).astype(np.uint8)   # area above the exact bound
-    segs, _, _ = S.sncc_segment_template(big, 40)
+    halves = np.zeros(2, S.SEGMENT_DTYPE)                     # area above the exact bound
+    halves[0] = (0, 0, 2048, 2049, 0, 2048 * 2049, 0)
+    halves[1] = (2048, 0, 2048, 2049, 2048 * 2049 * 9, 2048 * 2049, 0)
     with pytest.raises(S.SnccError) as e:
-        S.sncc_upload_templates(ctx, [segs], [260], [260])
+        S.sncc_upload_templates(ctx, [halves], [4096], [2049])
     assert e.value.code == S.SNCC_ERANGE
+    big = rng.integers(0, 256, (260, 260)).astype(np.uint8)
+    segs, _, _ = S.sncc_segment_template(big, 40)
     bad = segs.copy()
     bad[0]["w"] += 1                                          # overlapping segments
     with pytest.raises(S.SnccError) as e:

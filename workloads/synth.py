@@ -241,3 +241,18 @@ def prep_1024(n_templates: int = 1024, n_frames: int = 8, M: int = 1920, N: int 
         temps.append(t)
     return Workload("prep_1024", [], temps, [0.0] * n_templates, [], k=0,
                     note="templates only")
+
+
+def large_3840x2160(sizes=((640, 480), (384, 384)), sigma: float = 16.0) -> Workload:
+    """One 3840x2160 scene and templates beyond a single exact f^2 box
+    (n > 66051): a 640x480 crop (too wide for the staged form) and a 384x384
+    crop, each at a seeded position; sigma_max 16, top-5 per pair."""
+    f = scene(9500, 3840, 2160)
+    rng = np.random.default_rng(9501)
+    temps, origin = [], []
+    for W, H in sizes:
+        t, x, y = crop_template(rng, f, W, H, sigma_max=sigma)
+        temps.append(t)
+        origin.append((0, x, y))
+    return Workload("large_3840x2160", [f], temps, [sigma] * len(temps),
+                    [(0, i) for i in range(len(temps))], k=5, origin=origin)
