@@ -126,13 +126,19 @@ __device__ __forceinline__ void run_item(
           if (i + q < nseg) {
             const DirectRec e = dp[i + q];
             const int tr = e.tl + e.w4, br = e.bl + e.w4;
+            // all corners of the segment first, so that the loads of the
+            // lane's R offsets are in flight together
+            uint32_t a00[R], a01[R], a10[R], a11[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-              const uint32_t a00 = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], e.tl, 0);
-              const uint32_t a01 = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], tr, 0);
-              const uint32_t a10 = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], e.bl, 0);
-              const uint32_t a11 = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], br, 0);
-              const uint32_t F = (a11 - a10) - (a01 - a00);  // Eq. (11)
+              a00[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], e.tl, 0);
+              a01[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], tr, 0);
+              a10[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], e.bl, 0);
+              a11[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], br, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const uint32_t F = (a11[r] - a10[r]) - (a01[r] - a00[r]);  // Eq. (11)
               const int G = (int)F + __mul24(e.area, nb[r]);
               y[r] = __builtin_fmaf((float)G, e.c, y[r]);
             }
