@@ -11,10 +11,12 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <map>
 #include <memory>
 #include <sstream>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "sncc_internal.hpp"
@@ -178,33 +180,70 @@ int rows_needed(const std::vector<char> &cov, const Seg &g, int bv) {
   return add;
 }
 
-// Splits a template's segment list into passes whose staged rows fit
-// `rows_budget` LDS rows of pitch LP; appends passes, intervals, records.
-// Returns the largest number of rows any pass stages, or -1.
+// Horizontal chains of a segment list: maximal runs of segments with equal
+// y and h where each starts at the column the previous one ends, cut into
+// pieces of at most kMaxChain segments.  Returns the pieces as index lists,
+// in order of first segment.
+std::vector<std::vector<int>> horizontal_chains(const std::vector<Seg> &segs) {
+  std::map<std::tuple<int, int, int>, int> at;  // (y, h, x) -> index
+  for (size_t i = 0; i < segs.size(); ++i) at[{segs[i].y, segs[i].h, segs[i].x}] = (int)i;
+  std::vector<int> next(segs.size(), -1);
+  std::vector<char> has_prev(segs.size(), 0);
+  for (size_t i = 0; i < segs.size(); ++i) {
+    auto it = at.find({segs[i].y, segs[i].h, segs[i].x + segs[i].w});
+    if (it != at.end()) {
+      next[i] = it->second;
+      has_prev[it->second] = 1;
+    }
+  }
+  std::vector<std::vector<int>> pieces;
+  for (size_t i = 0; i < segs.size(); ++i) {
+    if (has_prev[i]) continue;
+    std::vector<int> piece;
+    for (int k = (int)i; k >= 0; k = next[k]) {
+      piece.push_back(k);
+      if ((int)piece.size() == kMaxChain) {
+        pieces.push_back(piece);
+        piece.clear();
+      }
+    }
+    if (!piece.empty()) pieces.push_back(piece);
+  }
+  return pieces;
+}
+
+// Splits a template's chains into passes whose staged rows fit `rows_budget`
+// LDS rows of pitch LP; appends passes, intervals and records.  Returns the
+// largest number of rows any pass stages, -1 when one chain alone does not
+// fit, -2 when a segment's area does not fit the 24-bit multiply.
 int plan_template(const sncc_tmpl *tm, int t, const TileCfg &tc, int LP, int rows_budget,
                   PlanHost &ph, DevTmpl &d) {
   const int H = tm->H[t], bv = tc.bv();
   const int span = H + bv;  // rows 0 .. H + bv - 1
   const std::vector<Seg> &segs = tm->segs[t];
+  for (const Seg &g : segs)
+    if (g.area >= (1 << 23)) return -2;
+  const std::vector<std::vector<int>> pieces = horizontal_chains(segs);
   d.pass_begin = (int)ph.passes.size();
   int max_rows = 0;
   size_t i = 0;
-  while (i < segs.size()) {
+  while (i < pieces.size()) {
     std::vector<char> cov(span, 0);
     int count = 0;
     size_t j = i;
     if (span <= rows_budget) {
       std::fill(cov.begin(), cov.end(), 1);
       count = span;
-      j = segs.size();
+      j = pieces.size();
     } else {
-      while (j < segs.size()) {
-        const int add = rows_needed(cov, segs[j], bv);
+      while (j < pieces.size()) {  // the pieces of a chain share their rows
+        const Seg &g = segs[pieces[j][0]];
+        const int add = rows_needed(cov, g, bv);
         if (count + add > rows_budget) break;
-        mark_rows(cov, segs[j], bv, count);
+        mark_rows(cov, g, bv, count);
         ++j;
       }
-      if (j == i) return -1;  // one segment does not fit
+      if (j == i) return -1;  // one chain does not fit
     }
     PassDesc ps;
     ps.iv_begin = (int)ph.ivs.size();
@@ -225,15 +264,21 @@ int plan_template(const sncc_tmpl *tm, int t, const TileCfg &tc, int LP, int row
     }
     ps.iv_end = (int)ph.ivs.size();
     ps.seg_begin = (int)ph.recs.size();
-    for (size_t q = i; q < j; ++q) {
-      const Seg &g = segs[q];
-      if (g.w >= (1 << 12) || g.area >= (1 << 20)) return -2;  // w | area << 12 overflows
-      TileRec rc;
-      rc.off_tl = slot[g.y] * LP + g.x;
-      rc.off_bl = slot[g.y + g.h] * LP + g.x;
-      rc.w_area = (int)((uint32_t)g.w | ((uint32_t)g.area << 12));
-      rc.c = (float)tm->c64[t][q];
-      ph.recs.push_back(rc);
+    for (int L = kMaxChain; L >= 1; --L) {
+      ps.n_chain[L - 1] = 0;
+      for (size_t q = i; q < j; ++q) {
+        const std::vector<int> &pc = pieces[q];
+        if ((int)pc.size() != L) continue;
+        ++ps.n_chain[L - 1];
+        const Seg &g0 = segs[pc[0]];
+        const int top = slot[g0.y] * LP, bot = slot[g0.y + g0.h] * LP;
+        ph.recs.push_back(TileRec{top + g0.x, bot + g0.x, 0, 0.f});  // left boundary
+        for (int k : pc) {
+          const Seg &g = segs[k];
+          ph.recs.push_back(TileRec{top + g.x + g.w, bot + g.x + g.w, (int)g.area,
+                                    (float)tm->c64[t][k]});
+        }
+      }
     }
     ps.seg_end = (int)ph.recs.size();
     ph.passes.push_back(ps);
@@ -251,7 +296,7 @@ void plan_direct(const sncc_tmpl *tm, int t, int P, PlanHost &ph, DevTmpl &d) {
   if (ph.recs.size() & 1) ph.recs.push_back(TileRec{0, 0, 0, 0.f});
   d.lp_class = kLpDirect;
   d.pass_begin = (int)ph.passes.size();
-  PassDesc ps;
+  PassDesc ps{};
   ps.iv_begin = ps.iv_end = (int)ph.ivs.size();
   ps.seg_begin = (int)ph.recs.size();
   const std::vector<Seg> &segs = tm->segs[t];

@@ -44,12 +44,16 @@ struct DevTmpl {
 // windows take their f^2 sum band by band (sq_rows rows of W pixels each).
 constexpr int kMaxSqBoxArea = 66051;
 
-// One segment for the tile kernel: LDS dword offsets of its top-left and
-// bottom-left corners relative to the lane's base, width | area << 12, c_i.
+// One boundary column of a horizontal chain for the staged tile kernel: LDS
+// dword offsets (relative to the lane's base) of the column's entries in the
+// chain's top row y and bottom row y + h, and A_i, c_i of the segment that
+// ends at this column (0, 0 for the chain's first column).  The segment's box
+// sum (Eq. (11)) is the difference of the column differences of its right
+// and left boundaries.
 struct TileRec {
   int off_tl;
   int off_bl;
-  int w_area;
+  int w_area;  // A_i (staged form); see DirectRec for the direct form
   float c;
 };
 
@@ -68,10 +72,19 @@ struct Interval {
   int rel_row, n_rows, lds_row, pad;
 };
 
+// A staged pass: its row intervals and its records.  The records form
+// horizontal chains (segments with equal y and h, each starting where the
+// previous one ends); a chain of L segments has L + 1 records, one per
+// boundary column.  Chains are grouped by length: n_chain[L - 1] chains of
+// length L = 4, 3, 2, 1 in that order.  (The direct form uses seg_begin,
+// seg_end only.)
 struct PassDesc {
   int seg_begin, seg_end;  // TileRec range
   int iv_begin, iv_end;    // Interval range
+  int n_chain[4];          // chains of length 1, 2, 3, 4
 };
+
+constexpr int kMaxChain = 4;  // longer chains are cut into pieces
 
 struct PairDesc {
   int frame, tmpl;

@@ -39,6 +39,56 @@ __device__ __forceinline__ void stage_pass(__amdgpu_buffer_rsrc_t rs, int P, int
   }
 }
 
+// NC horizontal chains of L segments each (records rp[c (L + 1) + j]) for
+// the lane's RU x RV offsets.  Per boundary column the difference of the
+// chain's bottom and top rows is read once (two LDS reads); a segment's box
+// sum (Eq. (11), exact modulo 2^32) is the difference of its right and left
+// columns' values, G_i = F_i - A_i b in integers, and the products G_i c_i of
+// the block are summed in FP32 before one compensated (Kahan) addition per
+// offset.  `base` is the lane's LDS origin.
+template <int RU, int RV, int LP, int L, int NC>
+__device__ __forceinline__ void chain_block(const TileRec *__restrict__ rp, const uint32_t *base,
+                                            const int (&nb)[RU * RV], float (&acc)[RU * RV],
+                                            float (&cmp)[RU * RV]) {
+  constexpr int NI = L + 1;
+  const uint32_t *tp[NC][NI], *bp[NC][NI];
+  int A[NC][NI];
+  float c[NC][NI];
+#pragma unroll
+  for (int ch = 0; ch < NC; ++ch)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const TileRec e = rp[ch * NI + j];
+      tp[ch][j] = base + e.off_tl;
+      bp[ch][j] = base + e.off_bl;
+      A[ch][j] = e.w_area;
+      c[ch][j] = e.c;
+    }
+#pragma unroll
+  for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+    for (int du = 0; du < RU; ++du) {
+      const int o = dv * LP + du * 64;
+      const int r = dv * RU + du;
+      float y = -cmp[r];
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch) {
+        uint32_t prev = bp[ch][0][o] - tp[ch][0][o];
+#pragma unroll
+        for (int j = 1; j < NI; ++j) {
+          const uint32_t cur = bp[ch][j][o] - tp[ch][j][o];
+          const uint32_t F = cur - prev;
+          const int G = (int)F + __mul24(A[ch][j], nb[r]);
+          y = __builtin_fmaf((float)G, c[ch][j], y);
+          prev = cur;
+        }
+      }
+      const float t = acc[r] + y;
+      cmp[r] = (t - acc[r]) - y;
+      acc[r] = t;
+    }
+}
+
 template <int RU, int RV, int NW, int LP, int SINK>
 __device__ __forceinline__ void run_item(
     const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
@@ -56,7 +106,8 @@ __device__ __forceinline__ void run_item(
   const __amdgpu_buffer_rsrc_t rs2 = make_rsrc(s2 + (long long)pd.frame * frame_stride, bytes);
   const int W = td.W, H = td.H, n = td.n;
   const float inv_n = 1.0f / (float)n;
-  const float qnf = (float)(td.q_k / (double)n);  // energy * q_k = V * q_k / n
+  const double qnd = td.q_k / (double)n;  // energy * q_k = V * q_k / n
+  const bool one_box = n <= kMaxSqBoxArea;
   const int stage_w4 = (BU + W + 1 + 3) >> 2;
   const int lbase = wave * RV * LP + lane;
   const int cW = W * 4, cH = H * P * 4;  // byte offsets of the window corners
@@ -82,24 +133,46 @@ __device__ __forceinline__ void run_item(
     // valid offset (inside the table) and are masked in the epilogue
     int nb[R];
     float acc[R], cmp[R];
+    if (one_box) {
+      // one exact box per window: V = n * sum f^2 - (sum f)^2 as one FP64 fma
+      // of integers below 2^53, hence exact
 #pragma unroll
-    for (int dv = 0; dv < RV; ++dv)
+      for (int dv = 0; dv < RV; ++dv)
 #pragma unroll
-      for (int du = 0; du < RU; ++du) {
-        const int r = dv * RU + du;
-        const int uc = min(u0 + lane + 64 * du, pd.nu - 1);
-        const int vc = min(v0 + wave * RV + dv, pd.nv - 1);
-        const int wo = (vc * P + uc) * 4;
-        const uint32_t sf = window_box(rs, wo, 0, cW, cH);
-        const u64 sf2 = window_sq(rs2, wo, 0, cW, P * 4, H, td.sq_rows);
-        nb[r] = -(int)__builtin_rintf((float)sf * inv_n);
-        const u64 V = (u64)(uint32_t)n * sf2 - (u64)sf * sf;
-        const float x =
-            __builtin_fmaf((float)(uint32_t)(V >> 32), 4294967296.0f, (float)(uint32_t)V) * qnf;
-        my_sc[r * NW * 64] = V == 0 ? 0.f : __builtin_amdgcn_rsqf(x);
-        acc[r] = 0.f;
-        cmp[r] = 0.f;
-      }
+        for (int du = 0; du < RU; ++du) {
+          const int r = dv * RU + du;
+          const int uc = min(u0 + lane + 64 * du, pd.nu - 1);
+          const int vc = min(v0 + wave * RV + dv, pd.nv - 1);
+          const int wo = (vc * P + uc) * 4;
+          const uint32_t sf = window_box(rs, wo, 0, cW, cH);
+          const uint32_t sf2 = window_box(rs2, wo, 0, cW, cH);
+          nb[r] = -(int)__builtin_rintf((float)sf * inv_n);
+          const double fs = (double)sf;
+          const double Vd = __builtin_fma((double)n, (double)sf2, -(fs * fs));
+          my_sc[r * NW * 64] = Vd == 0.0 ? 0.f : __builtin_amdgcn_rsqf((float)(Vd * qnd));
+          acc[r] = 0.f;
+          cmp[r] = 0.f;
+        }
+    } else {
+      // banded sum of f^2; V in 64-bit integers
+#pragma unroll
+      for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+        for (int du = 0; du < RU; ++du) {
+          const int r = dv * RU + du;
+          const int uc = min(u0 + lane + 64 * du, pd.nu - 1);
+          const int vc = min(v0 + wave * RV + dv, pd.nv - 1);
+          const int wo = (vc * P + uc) * 4;
+          const uint32_t sf = window_box(rs, wo, 0, cW, cH);
+          const u64 sf2 = window_sq(rs2, wo, 0, cW, P * 4, H, td.sq_rows);
+          nb[r] = -(int)__builtin_rintf((float)sf * inv_n);
+          const u64 V = (u64)(uint32_t)n * sf2 - (u64)sf * sf;
+          const float x = (float)((double)V * qnd);
+          my_sc[r * NW * 64] = V == 0 ? 0.f : __builtin_amdgcn_rsqf(x);
+          acc[r] = 0.f;
+          cmp[r] = 0.f;
+        }
+    }
 
     if constexpr (LP == 0) {
       // direct form: corners from the global table through buffer loads with
@@ -163,73 +236,22 @@ __device__ __forceinline__ void run_item(
       }
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
+      // chains grouped by length, about four segments per compensated step
       const TileRec *rp = recs + ps.seg_begin;
-      const int nseg = ps.seg_end - ps.seg_begin;
-      const int nseg4 = nseg & ~3;
-      // blocks of four segments; the next block's records are loaded one
-      // iteration ahead so that the scalar-load wait never stalls the first
-      // LDS reads of a block
-      TileRec nx[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) nx[q] = rp[min(q, nseg - 1)];
-#pragma unroll 2
-      for (int i = 0; i < nseg4; i += 4) {
-        TileRec e[4];
-        const uint32_t *tl[4], *bl[4], *tr[4], *br[4];
-        int A[4];
-        const int inext = min(i + 4, nseg4 - 4);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          e[q] = nx[q];
-          nx[q] = rp[inext + q];
-          const uint32_t wa = (uint32_t)e[q].w_area;
-          A[q] = (int)(wa >> 12);
-          tl[q] = lds + lbase + e[q].off_tl;
-          bl[q] = lds + lbase + e[q].off_bl;
-          tr[q] = tl[q] + (int)(wa & 0xfffu);
-          br[q] = bl[q] + (int)(wa & 0xfffu);
-        }
-#pragma unroll
-        for (int dv = 0; dv < RV; ++dv)
-#pragma unroll
-          for (int du = 0; du < RU; ++du) {
-            const int o = dv * LP + du * 64;
-            const int r = dv * RU + du;
-            float y = -cmp[r];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const uint32_t F = (br[q][o] - bl[q][o]) - (tr[q][o] - tl[q][o]);
-              const int G = (int)F + __mul24(A[q], nb[r]);
-              y = __builtin_fmaf((float)G, e[q].c, y);
-            }
-            const float t = acc[r] + y;
-            cmp[r] = (t - acc[r]) - y;
-            acc[r] = t;
-          }
+      for (int q = ps.n_chain[3]; q > 0; --q, rp += 5)
+        chain_block<RU, RV, LP, 4, 1>(rp, lds + lbase, nb, acc, cmp);
+      for (int q = ps.n_chain[2]; q > 0; --q, rp += 4)
+        chain_block<RU, RV, LP, 3, 1>(rp, lds + lbase, nb, acc, cmp);
+      int q2 = ps.n_chain[1];
+      for (; q2 >= 2; q2 -= 2, rp += 6) chain_block<RU, RV, LP, 2, 2>(rp, lds + lbase, nb, acc, cmp);
+      if (q2) {
+        chain_block<RU, RV, LP, 2, 1>(rp, lds + lbase, nb, acc, cmp);
+        rp += 3;
       }
-      // the last one to three segments, one compensated step each
-      for (int i = nseg4; i < nseg; ++i) {
-        const TileRec e = rp[i];
-        const uint32_t wa = (uint32_t)e.w_area;
-        const int A = (int)(wa >> 12);
-        const uint32_t *tl = lds + lbase + e.off_tl, *bl = lds + lbase + e.off_bl;
-        const uint32_t *tr = tl + (int)(wa & 0xfffu), *br = bl + (int)(wa & 0xfffu);
-#pragma unroll
-        for (int dv = 0; dv < RV; ++dv)
-#pragma unroll
-          for (int du = 0; du < RU; ++du) {
-            const int o = dv * LP + du * 64;
-            const int r = dv * RU + du;
-            const uint32_t F = (br[o] - bl[o]) - (tr[o] - tl[o]);
-            const int G = (int)F + __mul24(A, nb[r]);
-            const float y = __builtin_fmaf((float)G, e.c, -cmp[r]);
-            const float t = acc[r] + y;
-            cmp[r] = (t - acc[r]) - y;
-            acc[r] = t;
-          }
-      }
+      int q1 = ps.n_chain[0];
+      for (; q1 >= 4; q1 -= 4, rp += 8) chain_block<RU, RV, LP, 1, 4>(rp, lds + lbase, nb, acc, cmp);
+      for (; q1 > 0; --q1, rp += 2) chain_block<RU, RV, LP, 1, 1>(rp, lds + lbase, nb, acc, cmp);
     }
-
     }  // staged form
 
     // epilogue: rho = num / sqrt(V q_k / n) (Eqs. (17), (18)) in FP32
