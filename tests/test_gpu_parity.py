@@ -105,6 +105,53 @@ MAP_CASES = [
 ]
 
 
+def _special_template(kind, rng):
+    """Templates whose segmentations stress the record layout: long runs of
+    segments with equal rows (stripes), one-pixel-wide or one-row templates,
+    and a 2 x 2 template."""
+    if kind == "stripes":     # 40 x 24: 8 bands of rows, columns of width 3
+        t = (np.indices((24, 40))[1] // 3 % 2) * 90 + (np.indices((24, 40))[0] // 3) * 12 + 20
+        return np.clip(t + rng.integers(0, 2, (24, 40)), 0, 255).astype(np.uint8), 1.5
+    if kind == "column":      # W = 1
+        return rng.integers(0, 256, (20, 1)).astype(np.uint8), 30.0
+    if kind == "row":         # H = 1
+        return rng.integers(0, 256, (1, 25)).astype(np.uint8), 30.0
+    return np.array([[10, 200], [90, 30]], np.uint8), 0.5   # 2 x 2
+
+
+@pytest.mark.parametrize("kind", ["stripes", "column", "row", "tiny"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_map_parity_special_templates(S, ctx, kind, precision):
+    import torch
+    rng = np.random.default_rng(["stripes", "column", "row", "tiny"].index(kind) + 500)
+    t, sigma = _special_template(kind, rng)
+    H, W = t.shape
+    M, N = 170, 120
+    f = synth.scene(77, M, N)
+    f[30:30 + H, 40:40 + W] = t                     # an exact copy
+    print("template", kind, t.shape, precision, flush=True)
+    _, s, s2 = build_sats(S, ctx, [f])
+    tm = lib_templates(S, ctx, [t], [sigma])
+    ta = oracle_templates([t], [sigma])[0]
+    if kind == "stripes":
+        hz = {}
+        for g in ta.segments:
+            hz.setdefault((g.y, g.h), []).append(g.x)
+        assert max(len(v) for v in hz.values()) > 4    # chains longer than one piece
+    nu, nv = M - W + 1, N - H + 1
+    prec = S.SNCC_FP64 if precision == "fp64" else S.SNCC_FP32_KAHAN
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    rho = torch.empty((nv, nu), dtype=dt, device="cuda")
+    S.sncc_score(ctx, tm, 0, s, s2, M, N, prec, rho)
+    S.sncc_sync(ctx)
+    got = rho.cpu().numpy().astype(np.float64)
+    want = O.rho_map(f, ta)
+    tol = TOL64 if precision == "fp64" else TOL32
+    assert np.abs(got - want).max() <= tol
+    assert abs(got[30, 40] - ta.rho_max) <= tol       # the copy scores rho_max
+    S.sncc_tmpl_destroy(tm)
+
+
 @pytest.mark.parametrize("case", MAP_CASES)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_map_parity(S, ctx, case, precision):
