@@ -623,9 +623,25 @@ int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride,
 
 // --------------------------------------------------- two-threshold search
 // Section 5, steps 7g-j for the offsets that passed the fast test: rho with
-// the slow approximation in FP64 (one wave per offset, lanes striding over
-// the segments, then a butterfly sum), appended to the output when it
-// reaches the template's slow threshold.
+// the slow approximation in FP64, appended to the output when it reaches the
+// template's slow threshold.  A wave takes 64 consecutive survivors.  The
+// compaction writes each tile's survivors together, so such a group usually
+// belongs to one pair: then every lane scores its own offset over the shared
+// segment list (neighbouring lanes read neighbouring table entries).
+// Otherwise the wave scores the group's survivors one at a time, lanes
+// striding over the segments and a butterfly sum.
+__device__ __forceinline__ double slow_rho_finish(double acc, const uint32_t *__restrict__ S,
+                                                  const uint32_t *__restrict__ S2, int P,
+                                                  int u, int v, const DevTmpl &td) {
+  const uint32_t *a0 = S + (long long)v * P + u;
+  const uint32_t *a1 = a0 + (long long)td.H * P;
+  const uint32_t sf = (a1[td.W] - a1[0]) - (a0[td.W] - a0[0]);  // Eq. (13)
+  const u64 sf2 = window_sq(S2 + (long long)v * P + u, td.W, td.H, P, td.sq_rows);
+  const long long V = (long long)((u64)(uint32_t)td.n * sf2 - (u64)sf * sf);
+  const double num = acc - (double)sf / (double)td.n * td.r64;  // Eq. (12)
+  return V == 0 ? 0.0 : num / sqrt((double)V / (double)td.n * td.q_k);  // Eqs. (17), (18)
+}
+
 __global__ __launch_bounds__(256) void slow_kernel(
     const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
     int P, const DevTmpl *__restrict__ tmpls, const int4 *__restrict__ geom,
@@ -635,33 +651,38 @@ __global__ __launch_bounds__(256) void slow_kernel(
     int *__restrict__ out_count) {
   const int lane = threadIdx.x & 63;
   const int n_cand = min(*cand_count, cand_cap);
-  for (int c = blockIdx.x * 4 + (threadIdx.x >> 6); c < n_cand; c += gridDim.x * 4) {
-    const sncc_hit h = cand[c];
-    const PairDesc pd = pairs[h.pair];
-    const DevTmpl td = tmpls[pd.tmpl];
-    const uint32_t *S = s + (long long)pd.frame * frame_stride;
-    const uint32_t *S2 = s2 + (long long)pd.frame * frame_stride;
-    const uint32_t *a0 = S + (long long)h.v * P + h.u;
-    double acc = 0.0;
-    for (int i = lane; i < td.K; i += 64) {
-      const int4 g = geom[td.seg_off + i];  // x, y, width, height
-      const uint32_t *q0 = a0 + (long long)g.y * P + g.x;
-      const uint32_t *q2 = q0 + (long long)g.w * P;
-      const uint32_t F = (q2[g.z] - q2[0]) - (q0[g.z] - q0[0]);  // Eq. (11)
-      acc = __builtin_fma((double)F, c64[td.seg_off + i], acc);
-    }
-    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
-    if (lane == 0) {
-      const uint32_t *a1 = a0 + (long long)td.H * P;
-      const uint32_t sf = (a1[td.W] - a1[0]) - (a0[td.W] - a0[0]);  // Eq. (13)
-      const u64 sf2 = window_sq(S2 + (long long)h.v * P + h.u, td.W, td.H, P, td.sq_rows);
-      const long long V = (long long)((u64)(uint32_t)td.n * sf2 - (u64)sf * sf);
-      const double num = acc - (double)sf / (double)td.n * td.r64;  // Eq. (12)
-      const double rho =
-          V == 0 ? 0.0 : num / sqrt((double)V / (double)td.n * td.q_k);  // Eqs. (17), (18)
-      if (rho >= thr[pd.tmpl]) {
-        const int pos = atomicAdd(out_count, 1);
-        if (pos < out_cap) {
+  for (int base = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; base < n_cand;
+       base += gridDim.x * 4 * 64) {
+    const int c = base + lane;
+    const bool valid = c < n_cand;
+    const sncc_hit h = cand[valid ? c : base];
+    const int pair0 = __builtin_amdgcn_readfirstlane(h.pair);
+    if (__ballot(h.pair != pair0) == 0) {
+      // one pair: lanes over offsets, segments in order
+      const PairDesc pd = pairs[pair0];
+      const DevTmpl td = tmpls[pd.tmpl];
+      const uint32_t *S = s + (long long)pd.frame * frame_stride;
+      const uint32_t *S2 = s2 + (long long)pd.frame * frame_stride;
+      const uint32_t *a0 = S + (long long)h.v * P + h.u;
+      const int4 *gp = geom + td.seg_off;
+      const double *cp = c64 + td.seg_off;
+      double acc = 0.0;
+      for (int i = 0; i < td.K; ++i) {
+        const int4 g = gp[i];  // x, y, width, height
+        const uint32_t *q0 = a0 + (long long)g.y * P + g.x;
+        const uint32_t *q2 = q0 + (long long)g.w * P;
+        const uint32_t F = (q2[g.z] - q2[0]) - (q0[g.z] - q0[0]);  // Eq. (11)
+        acc = __builtin_fma((double)F, cp[i], acc);
+      }
+      const double rho = slow_rho_finish(acc, S, S2, P, h.u, h.v, td);
+      const bool hit = valid && rho >= thr[pd.tmpl];
+      const u64 m = __ballot(hit);
+      if (m != 0) {
+        int pos0 = 0;
+        if (lane == 0) pos0 = atomicAdd(out_count, __popcll(m));
+        const int pos = __builtin_amdgcn_readfirstlane(pos0) +
+                        __popcll(m & ((1ull << lane) - 1ull));
+        if (hit && pos < out_cap) {
           sncc_hit o;
           o.pair = h.pair;
           o.u = h.u;
@@ -669,6 +690,41 @@ __global__ __launch_bounds__(256) void slow_kernel(
           o.reserved = 0;
           o.rho = rho;
           out[pos] = o;
+        }
+      }
+    } else {
+      // mixed pairs: one survivor at a time
+      const int end = min(base + 64, n_cand);
+      for (int cc = base; cc < end; ++cc) {
+        const sncc_hit e = cand[cc];
+        const PairDesc pd = pairs[e.pair];
+        const DevTmpl td = tmpls[pd.tmpl];
+        const uint32_t *S = s + (long long)pd.frame * frame_stride;
+        const uint32_t *S2 = s2 + (long long)pd.frame * frame_stride;
+        const uint32_t *a0 = S + (long long)e.v * P + e.u;
+        double acc = 0.0;
+        for (int i = lane; i < td.K; i += 64) {
+          const int4 g = geom[td.seg_off + i];
+          const uint32_t *q0 = a0 + (long long)g.y * P + g.x;
+          const uint32_t *q2 = q0 + (long long)g.w * P;
+          const uint32_t F = (q2[g.z] - q2[0]) - (q0[g.z] - q0[0]);
+          acc = __builtin_fma((double)F, c64[td.seg_off + i], acc);
+        }
+        for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
+        if (lane == 0) {
+          const double rho = slow_rho_finish(acc, S, S2, P, e.u, e.v, td);
+          if (rho >= thr[pd.tmpl]) {
+            const int pos = atomicAdd(out_count, 1);
+            if (pos < out_cap) {
+              sncc_hit o;
+              o.pair = e.pair;
+              o.u = e.u;
+              o.v = e.v;
+              o.reserved = 0;
+              o.rho = rho;
+              out[pos] = o;
+            }
+          }
         }
       }
     }
@@ -680,7 +736,7 @@ int launch_slow(const uint32_t *s, const uint32_t *s2, long long frame_stride, i
                 const PairDesc *pairs, const double *thr, const sncc_hit *cand,
                 const int *cand_count, int cand_cap, sncc_hit *out, int out_cap,
                 int *out_count, hipStream_t st) {
-  const int blocks = std::max(1, std::min((cand_cap + 3) / 4, 8192));
+  const int blocks = std::max(1, std::min((cand_cap + 255) / 256, 8192));
   hipLaunchKernelGGL(slow_kernel, dim3(blocks), dim3(256), 0, st, s, s2, frame_stride, P,
                      tmpls, geom, c64, pairs, thr, cand, cand_count, cand_cap, out, out_cap,
                      out_count);

@@ -270,9 +270,11 @@ __device__ __forceinline__ void run_item(
         }
     } else if (SINK == kSinkCompact) {
       // offsets whose rho reaches the template's threshold are appended to
-      // the survivor list: one atomic per wave, lanes write in lane order
-      int cnt = 0;
-      bool pass[R];
+      // the survivor list with one atomic per wave, ordered by (du, dv) slot
+      // and then by lane, so that neighbouring entries are neighbouring
+      // offsets of one row
+      u64 m[R];
+      int total = 0;
 #pragma unroll
       for (int dv = 0; dv < RV; ++dv)
 #pragma unroll
@@ -280,32 +282,32 @@ __device__ __forceinline__ void run_item(
           const int r = dv * RU + du;
           const int u = u0 + lane + 64 * du, v = v0 + wave * RV + dv;
           acc[r] = (acc[r] - cmp[r]) * my_sc[r * NW * 64];  // acc now holds rho
-          pass[r] = u < pd.nu && v < pd.nv && acc[r] >= td.thr;
-          cnt += pass[r] ? 1 : 0;
+          m[r] = __ballot(u < pd.nu && v < pd.nv && acc[r] >= td.thr);
+          total += __popcll(m[r]);
         }
-      const uint32_t incl = wave_incl_scan((uint32_t)cnt);
-      const int total = (int)__builtin_amdgcn_readlane((int)incl, 63);
       if (total > 0) {
         int base = 0;
         if (lane == 0) base = atomicAdd(co.count, total);
-        int pos = __builtin_amdgcn_readlane(base, 0) + (int)incl - cnt;
+        int pos = __builtin_amdgcn_readfirstlane(base);
+        const u64 below = (1ull << lane) - 1ull;
 #pragma unroll
         for (int dv = 0; dv < RV; ++dv)
 #pragma unroll
           for (int du = 0; du < RU; ++du) {
             const int r = dv * RU + du;
-            if (pass[r]) {
-              if (pos < co.cap) {
+            if ((m[r] >> lane) & 1ull) {
+              const int at = pos + __popcll(m[r] & below);
+              if (at < co.cap) {
                 sncc_hit h;
                 h.pair = it.pair;
                 h.u = u0 + lane + 64 * du;
                 h.v = v0 + wave * RV + dv;
                 h.reserved = 0;
                 h.rho = (double)acc[r];
-                co.hits[pos] = h;
+                co.hits[at] = h;
               }
-              ++pos;
             }
+            pos += __popcll(m[r]);
           }
       }
     } else {
