@@ -248,22 +248,22 @@ def run_threshold(args):
         S.sncc_threshold_match(ctx, fast, slow, tf, ts, s, s2, B, M, N, wl.pairs, cand, out,
                                counts)
 
-    S.sncc_ctx_set_timing(ctx, True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    stage = []
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record()
     for _ in range(args.steps):
         step()
-        stage.append(S.sncc_ctx_stage_ms(ctx))   # waits for this step's slow pass
-    e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
+    # stage times from separate steps: reading them waits for each step
+    S.sncc_ctx_set_timing(ctx, True)
+    stage = []
+    for _ in range(max(3, min(args.steps, 10))):
+        step()
+        stage.append(S.sncc_ctx_stage_ms(ctx))
+    S.sncc_ctx_set_timing(ctx, False)
     n_cand, n_out = (int(x) for x in counts[:2].cpu())
     hits = S.decode_hits(cand, n_cand)
     per_pair = np.bincount(hits["pair"], minlength=len(wl.pairs))

@@ -104,6 +104,21 @@ bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 // ------------------------------------------------------------------ handles
 struct PlanDev;
 
+// Everything a one-call tile plan depends on: a repeated call with an equal
+// key reuses the plan already on the device instead of building and
+// uploading it again.
+struct PlanKey {
+  int sink = -1;
+  uint64_t tmpl = 0, tmpl2 = 0;  // serials of the template sets (0: none)
+  int M = 0, N = 0, P = 0, k = 0;
+  std::vector<int32_t> pairs;
+  std::vector<double> thr;       // thresholds the plan carries
+  bool operator==(const PlanKey &o) const {
+    return sink == o.sink && tmpl == o.tmpl && tmpl2 == o.tmpl2 && M == o.M && N == o.N &&
+           P == o.P && k == o.k && pairs == o.pairs && thr == o.thr;
+  }
+};
+
 struct sncc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -114,6 +129,8 @@ struct sncc_ctx {
   bool timing = false;                             // record stage events
   hipEvent_t tev[4] = {};
   int n_stages = 0;                                // stages of the last timed call
+  PlanKey cache_key[3];                            // last plan per sink
+  std::unique_ptr<PlanDev> cache[3];
   ~sncc_ctx() {
     for (auto &e : tev)
       if (e) (void)hipEventDestroy(e);
@@ -126,6 +143,7 @@ struct sncc_ctx {
 
 struct sncc_tmpl {
   sncc_ctx *ctx = nullptr;
+  uint64_t serial = 0;  // unique per uploaded set (plan cache key)
   int T = 0;
   std::vector<int> W, H, K, seg_off;
   std::vector<std::vector<Seg>> segs;
@@ -585,6 +603,28 @@ int retire(sncc_ctx *ctx, std::unique_ptr<PlanDev> pd) {
   return SNCC_OK;
 }
 
+// The context's plan for `key` (key.sink's slot), built and uploaded by
+// `make` on a miss; the plan it replaces is retired, since work queued with
+// it may still be running.  Calls on one context are ordered by its stream,
+// so reusing a plan while earlier work still reads it is safe.
+template <class Make>
+int cached_plan(sncc_ctx *ctx, PlanKey key, Make make, PlanDev **out) {
+  const int slot = key.sink;
+  if (ctx->cache[slot] && ctx->cache_key[slot] == key) {
+    *out = ctx->cache[slot].get();
+    return SNCC_OK;
+  }
+  if (ctx->cache[slot]) CHK(retire(ctx, std::move(ctx->cache[slot])));
+  ctx->cache_key[slot] = PlanKey{};
+  std::unique_ptr<PlanDev> pd(new PlanDev());
+  CHK(make(*pd));
+  CHK(pd->upload(ctx->stream));
+  ctx->cache[slot] = std::move(pd);
+  ctx->cache_key[slot] = std::move(key);
+  *out = ctx->cache[slot].get();
+  return SNCC_OK;
+}
+
 int check_ctx(sncc_ctx *ctx) {
   if (!ctx) SNCC_FAIL(SNCC_EINVAL, "NULL context");
   HIPCHK(hipSetDevice(ctx->device));
@@ -829,7 +869,9 @@ int sncc_upload_templates(sncc_ctx *ctx, int T, const sncc_segment *const *segs,
   *out = nullptr;
   std::unique_ptr<sncc_tmpl> tm(new (std::nothrow) sncc_tmpl());
   if (!tm) SNCC_FAIL(SNCC_ENOMEM, "template allocation");
+  static std::atomic<uint64_t> serials{0};
   tm->ctx = ctx;
+  tm->serial = ++serials;
   tm->T = T;
   std::vector<int4> geom;
   std::vector<double> c64all;
@@ -988,10 +1030,19 @@ int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uin
   if (k < 1 || k > 64) SNCC_FAIL(SNCC_EINVAL, "k must be in 1..64");
   if (!d_out || !aligned16(d_out)) SNCC_FAIL(SNCC_EINVAL, "NULL or misaligned output");
   const long long fs = (long long)(N + 1) * sat_pitch;
-  std::unique_ptr<PlanDev> pd(new PlanDev());
   if (precision == SNCC_FP32_KAHAN) {
-    CHK(build_plan(tm, 0, M, N, sat_pitch, n_pairs, pairs, k, kSinkTopk, ctx->num_cu, pd->h));
-    CHK(pd->upload(ctx->stream));
+    PlanKey key;
+    key.sink = kSinkTopk;
+    key.tmpl = tm->serial;
+    key.M = M;
+    key.N = N;
+    key.P = sat_pitch;
+    key.k = k;
+    key.pairs.assign(pairs, pairs + 2 * n_pairs);
+    PlanDev *pd = nullptr;
+    CHK(cached_plan(ctx, std::move(key), [&](PlanDev &d) {
+      return build_plan(tm, 0, M, N, sat_pitch, n_pairs, pairs, k, kSinkTopk, ctx->num_cu, d.h);
+    }, &pd));
     TileArgs a = pd->args(d_s, d_s2, fs, sat_pitch, M, N);
     ctx->n_stages = 0;
     if (launch_zero(a.queue, a.n_zero, ctx->stream) != 0)
@@ -1004,9 +1055,10 @@ int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uin
       SNCC_FAIL(SNCC_EDEVICE, "top-k launch: %s", hipGetErrorString(hipGetLastError()));
     ctx->mark(2);
     if (ctx->timing) ctx->n_stages = 2;
-    return retire(ctx, std::move(pd));
+    return SNCC_OK;
   }
   if (precision != SNCC_FP64) SNCC_FAIL(SNCC_EINVAL, "unknown precision %d", precision);
+  std::unique_ptr<PlanDev> pd(new PlanDev());
   // plain form: one FP64 map per pair, then chunked top-k and the merge
   const int chunk = 64 * 1024;
   PlanHost &h = pd->h;
@@ -1134,12 +1186,23 @@ int sncc_threshold_match(sncc_ctx *ctx, const sncc_tmpl *fast, const sncc_tmpl *
       !aligned16(d_counts))
     SNCC_FAIL(SNCC_EINVAL, "NULL or misaligned buffers");
   const long long fs = (long long)(N + 1) * sat_pitch;
-  std::unique_ptr<PlanDev> pd(new PlanDev());
-  CHK(build_plan(fast, 0, M, N, sat_pitch, n_pairs, pairs, 1, kSinkCompact, ctx->num_cu, pd->h,
-                 thr_fast));
-  CHK(pd->upload(ctx->stream));
-  std::vector<double> ts(thr_slow, thr_slow + slow->T);
-  CHK(pd->d_thr.upload(ts, ctx->stream));
+  PlanKey key;
+  key.sink = kSinkCompact;
+  key.tmpl = fast->serial;
+  key.tmpl2 = slow->serial;
+  key.M = M;
+  key.N = N;
+  key.P = sat_pitch;
+  key.pairs.assign(pairs, pairs + 2 * n_pairs);
+  key.thr.assign(thr_fast, thr_fast + fast->T);
+  key.thr.insert(key.thr.end(), thr_slow, thr_slow + slow->T);
+  PlanDev *pd = nullptr;
+  CHK(cached_plan(ctx, std::move(key), [&](PlanDev &d) {
+    CHK(build_plan(fast, 0, M, N, sat_pitch, n_pairs, pairs, 1, kSinkCompact, ctx->num_cu, d.h,
+                   thr_fast));
+    std::vector<double> ts(thr_slow, thr_slow + slow->T);
+    return d.d_thr.upload(ts, ctx->stream);
+  }, &pd));
   TileArgs a = pd->args(d_s, d_s2, fs, sat_pitch, M, N);
   a.co = CompactOut{d_cand, cand_cap, d_counts};
   ctx->n_stages = 0;
@@ -1156,7 +1219,7 @@ int sncc_threshold_match(sncc_ctx *ctx, const sncc_tmpl *fast, const sncc_tmpl *
     SNCC_FAIL(SNCC_EDEVICE, "threshold search launch: %s", hipGetErrorString(hipGetLastError()));
   ctx->mark(2);
   if (ctx->timing) ctx->n_stages = 2;
-  return retire(ctx, std::move(pd));
+  return SNCC_OK;
 }
 
 }  // extern "C"

@@ -253,6 +253,42 @@ def test_topk_more_slots_than_offsets(S, ctx):
     assert not topk_ok(want, got, n_off, TOL32)
 
 
+def test_topk_repeated_calls_match_fresh_contexts(S, ctx):
+    """A context keeps the plan of its last top-k call and reuses it when the
+    call repeats; each change of what the plan depends on (k, the pair list,
+    the template set) and each change of the tables (not part of the plan)
+    must give exactly what a fresh context gives."""
+    import torch
+    frames, temps, sigmas, pairs = _multi(90)
+    B, N, M = len(frames), frames[0].shape[0], frames[0].shape[1]
+    _, s, s2 = build_sats(S, ctx, frames)
+    _, r, r2 = build_sats(S, ctx, [synth.scene(990 + i, M, N) for i in range(B)])
+    tm = lib_templates(S, ctx, temps, sigmas)
+    tm2 = lib_templates(S, ctx, temps[::-1], sigmas[::-1])
+
+    def run(c, t, tabs, pr, k):
+        out = torch.zeros((len(pr), k, 3), dtype=torch.int32, device="cuda")
+        S.sncc_topk(c, t, tabs[0], tabs[1], B, M, N, pr, k, S.SNCC_FP32_KAHAN, out)
+        S.sncc_sync(c)
+        return out.cpu().numpy()
+
+    calls = [(tm, (s, s2), pairs, 8), (tm, (s, s2), pairs, 8), (tm, (r, r2), pairs, 8),
+             (tm, (r, r2), pairs, 3), (tm, (r, r2), pairs[::-1], 3), (tm2, (r, r2), pairs[::-1], 3),
+             (tm, (s, s2), pairs, 8)]
+    got = [run(ctx, *c) for c in calls]
+    for i, (c, g) in enumerate(zip(calls, got)):
+        fresh = S.sncc_ctx_create(0)
+        try:
+            want = run(fresh, *c)
+        finally:
+            S.sncc_ctx_destroy(fresh)
+        assert np.array_equal(g, want), i
+    assert np.array_equal(got[0], got[1]) and np.array_equal(got[0], got[-1])
+    assert not np.array_equal(got[1], got[2])
+    for h in (tm, tm2):
+        S.sncc_tmpl_destroy(h)
+
+
 # ------------------------------------------------------------------ refine
 def test_refine_parity(S, ctx):
     import torch

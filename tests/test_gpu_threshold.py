@@ -203,6 +203,55 @@ def test_scene_1920x1080_paper_thresholds(S, ctx):
             assert any(int(h["u"]) == x0 and int(h["v"]) == y0 for h in got["out"])
 
 
+def test_repeated_calls_match_fresh_contexts(S, ctx):
+    """A context keeps the plan of its last threshold search and reuses it
+    when the call repeats; a change of either threshold, of the pair list or
+    of the tables must give what a fresh context gives."""
+    import torch
+    rng = np.random.default_rng(31)
+    frames = [synth.scene(7400 + i, 180, 140) for i in range(2)]
+    templates = [synth.crop_template(rng, frames[j], w, h, sigma_max=10)[0]
+                 for j, (w, h) in enumerate([(21, 17), (30, 26)])]
+    _, s, s2 = build_sats(S, ctx, frames)
+    _, r, r2 = build_sats(S, ctx, [synth.scene(7500 + i, 180, 140) for i in range(2)])
+    fast, slow, tf, ts = _prepare(S, ctx, templates)
+    pairs = [(b, j) for b in range(2) for j in range(2)]
+    cap = 2 * 180 * 140
+
+    def run(c, tabs, pr, a, b):
+        cand = torch.zeros((cap, 6), dtype=torch.int32, device="cuda")
+        out = torch.zeros((cap, 6), dtype=torch.int32, device="cuda")
+        counts = torch.zeros(4, dtype=torch.int32, device="cuda")
+        S.sncc_threshold_match(c, fast, slow, a, b, tabs[0], tabs[1], 2, 180, 140, pr, cand, out,
+                               counts)
+        S.sncc_sync(c)
+        nc, nm = (int(x) for x in counts[:2].cpu())
+        key = lambda h: np.sort(h, order=["pair", "v", "u"])  # noqa: E731
+        return nc, nm, key(S.decode_hits(cand, nc)), key(S.decode_hits(out, nm))
+
+    lo = tf - 0.3
+    calls = [((s, s2), pairs, tf, ts), ((s, s2), pairs, tf, ts), ((r, r2), pairs, tf, ts),
+             ((r, r2), pairs, lo, ts), ((r, r2), pairs, lo, ts - 0.2),
+             ((r, r2), pairs[::-1], lo, ts - 0.2), ((s, s2), pairs, tf, ts)]
+    got = [run(ctx, *c) for c in calls]
+    for i, (c, g) in enumerate(zip(calls, got)):
+        fresh = S.sncc_ctx_create(0)
+        try:
+            want = run(fresh, *c)
+        finally:
+            S.sncc_ctx_destroy(fresh)
+        assert g[:2] == want[:2], (i, g[:2], want[:2])
+        for a, b in ((g[2], want[2]), (g[3], want[3])):
+            for f in ("pair", "u", "v"):
+                assert np.array_equal(a[f], b[f]), (i, f)
+            # the slow pass may sum a survivor in either of its two orders
+            assert np.abs(a["rho"] - b["rho"]).max(initial=0) <= 1e-12, i
+    assert got[0][:2] == got[1][:2] == got[-1][:2]
+    assert got[3][0] > got[2][0] and got[4][1] > got[3][1]
+    S.sncc_tmpl_destroy(fast)
+    S.sncc_tmpl_destroy(slow)
+
+
 def test_errors(S, ctx):
     import torch
     frames = [synth.scene(7300, 64, 48)]
