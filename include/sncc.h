@@ -58,6 +58,11 @@ extern "C" {
 #define SNCC_MAX_TEMPLATE_AREA 8388607
 #define SNCC_MAX_SQ_BOX_AREA 66051
 
+/* Largest sum table of one frame, (N + 1) * sat_pitch * 4 bytes, that the
+ * scoring entry points accept (2^31 - 1: they address a frame's table with
+ * 32-bit byte offsets); larger frames give SNCC_EINVAL. */
+#define SNCC_MAX_TABLE_BYTES 2147483647LL
+
 /* One rectangle of the approximation: the 5-tuple of Eq. (6) with the mean
  * k_i = sum / area kept as an exact integer ratio (Eq. (4)). */
 typedef struct sncc_segment {

@@ -45,6 +45,7 @@ SNCC_FP32_KAHAN = 0
 SNCC_FP64 = 1
 SNCC_MAX_TEMPLATE_AREA = 8388607
 SNCC_MAX_SQ_BOX_AREA = 66051
+SNCC_MAX_TABLE_BYTES = 2147483647
 
 
 class sncc_segment(C.Structure):

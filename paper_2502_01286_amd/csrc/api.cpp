@@ -639,6 +639,10 @@ int check_sats(const uint32_t *s, const uint32_t *s2, int M, int N, int P) {
   sncc_sat_pitch(M, &need);
   if (P < need || P % 64 != 0)
     SNCC_FAIL(SNCC_EINVAL, "sat_pitch %d: need a multiple of 64 >= %d", P, need);
+  // the scoring kernels address one frame's table with 32-bit byte offsets
+  if ((long long)(N + 1) * P * 4 > (long long)SNCC_MAX_TABLE_BYTES)
+    SNCC_FAIL(SNCC_EINVAL, "sum table of %lld bytes per frame exceeds %lld",
+              (long long)(N + 1) * P * 4, (long long)SNCC_MAX_TABLE_BYTES);
   return SNCC_OK;
 }
 

@@ -624,22 +624,39 @@ int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride,
 // --------------------------------------------------- two-threshold search
 // Section 5, steps 7g-j for the offsets that passed the fast test: rho with
 // the slow approximation in FP64, appended to the output when it reaches the
-// template's slow threshold.  A wave takes 64 consecutive survivors.  The
-// compaction writes each tile's survivors together, so such a group usually
-// belongs to one pair: then every lane scores its own offset over the shared
-// segment list (neighbouring lanes read neighbouring table entries).
-// Otherwise the wave scores the group's survivors one at a time, lanes
-// striding over the segments and a butterfly sum.
-__device__ __forceinline__ double slow_rho_finish(double acc, const uint32_t *__restrict__ S,
-                                                  const uint32_t *__restrict__ S2, int P,
-                                                  int u, int v, const DevTmpl &td) {
-  const uint32_t *a0 = S + (long long)v * P + u;
-  const uint32_t *a1 = a0 + (long long)td.H * P;
-  const uint32_t sf = (a1[td.W] - a1[0]) - (a0[td.W] - a0[0]);  // Eq. (13)
-  const u64 sf2 = window_sq(S2 + (long long)v * P + u, td.W, td.H, P, td.sq_rows);
-  const long long V = (long long)((u64)(uint32_t)td.n * sf2 - (u64)sf * sf);
-  const double num = acc - (double)sf / (double)td.n * td.r64;  // Eq. (12)
-  return V == 0 ? 0.0 : num / sqrt((double)V / (double)td.n * td.q_k);  // Eqs. (17), (18)
+// template's slow threshold.  A wave takes 64 consecutive survivors and
+// scores them pair by pair: the lanes of one pair each score their own offset
+// over the pair's shared segment list (uniform geometry, so every table read
+// is one buffer load whose lanes read neighbouring entries when the
+// survivors are neighbouring offsets, as the compaction mostly leaves them),
+// while the other lanes idle.  Segments are taken in blocks of kSlowBlock
+// with all their loads issued before the block is summed, in segment order:
+// a survivor's rho does not depend on how the survivors fall into groups.
+constexpr int kSlowBlock = 8;
+
+// Sum over the segments of c_i F_i (Eq. (12), first term) for the window at
+// voff (bytes from the frame table's base); uniform segment list.
+__device__ __forceinline__ double slow_sum(__amdgpu_buffer_rsrc_t rs, int voff, int P4,
+                                           const int4 *__restrict__ gp,
+                                           const double *__restrict__ cp, int K) {
+  double acc = 0.0;
+  int i = 0;
+  for (; i + kSlowBlock <= K; i += kSlowBlock) {
+    uint32_t F[kSlowBlock];
+#pragma unroll
+    for (int j = 0; j < kSlowBlock; ++j) {
+      const int4 g = gp[i + j];  // x, y, width, height
+      F[j] = window_box(rs, voff, g.y * P4 + g.x * 4, g.z * 4, g.w * P4);  // Eq. (11)
+    }
+#pragma unroll
+    for (int j = 0; j < kSlowBlock; ++j) acc = __builtin_fma((double)F[j], cp[i + j], acc);
+  }
+  for (; i < K; ++i) {
+    const int4 g = gp[i];
+    const uint32_t F = window_box(rs, voff, g.y * P4 + g.x * 4, g.z * 4, g.w * P4);
+    acc = __builtin_fma((double)F, cp[i], acc);
+  }
+  return acc;
 }
 
 __global__ __launch_bounds__(256) void slow_kernel(
@@ -651,80 +668,52 @@ __global__ __launch_bounds__(256) void slow_kernel(
     int *__restrict__ out_count) {
   const int lane = threadIdx.x & 63;
   const int n_cand = min(*cand_count, cand_cap);
+  const int P4 = P * 4;
+  const uint32_t bytes = (uint32_t)(frame_stride * 4);
   for (int base = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; base < n_cand;
        base += gridDim.x * 4 * 64) {
     const int c = base + lane;
-    const bool valid = c < n_cand;
-    const sncc_hit h = cand[valid ? c : base];
-    const int pair0 = __builtin_amdgcn_readfirstlane(h.pair);
-    if (__ballot(h.pair != pair0) == 0) {
-      // one pair: lanes over offsets, segments in order
+    const sncc_hit h = cand[c < n_cand ? c : base];
+    bool todo = c < n_cand;
+    for (;;) {
+      const u64 m = __ballot(todo);
+      if (m == 0) break;
+      const int first = __builtin_ctzll(m);
+      const int pair0 = __builtin_amdgcn_readlane(h.pair, first);
+      const bool mine = todo && h.pair == pair0;
+      todo = todo && !mine;
+      // lanes of other pairs score the first lane's offset (in range for
+      // this pair's template) and discard it
+      const int u = mine ? h.u : __builtin_amdgcn_readlane(h.u, first);
+      const int v = mine ? h.v : __builtin_amdgcn_readlane(h.v, first);
       const PairDesc pd = pairs[pair0];
       const DevTmpl td = tmpls[pd.tmpl];
-      const uint32_t *S = s + (long long)pd.frame * frame_stride;
-      const uint32_t *S2 = s2 + (long long)pd.frame * frame_stride;
-      const uint32_t *a0 = S + (long long)h.v * P + h.u;
-      const int4 *gp = geom + td.seg_off;
-      const double *cp = c64 + td.seg_off;
-      double acc = 0.0;
-      for (int i = 0; i < td.K; ++i) {
-        const int4 g = gp[i];  // x, y, width, height
-        const uint32_t *q0 = a0 + (long long)g.y * P + g.x;
-        const uint32_t *q2 = q0 + (long long)g.w * P;
-        const uint32_t F = (q2[g.z] - q2[0]) - (q0[g.z] - q0[0]);  // Eq. (11)
-        acc = __builtin_fma((double)F, cp[i], acc);
-      }
-      const double rho = slow_rho_finish(acc, S, S2, P, h.u, h.v, td);
-      const bool hit = valid && rho >= thr[pd.tmpl];
-      const u64 m = __ballot(hit);
-      if (m != 0) {
+      const __amdgpu_buffer_rsrc_t rs = make_rsrc(s + (long long)pd.frame * frame_stride, bytes);
+      const __amdgpu_buffer_rsrc_t rs2 =
+          make_rsrc(s2 + (long long)pd.frame * frame_stride, bytes);
+      const int voff = v * P4 + u * 4;
+      const double acc = slow_sum(rs, voff, P4, geom + td.seg_off, c64 + td.seg_off, td.K);
+      const uint32_t sf = window_box(rs, voff, 0, td.W * 4, td.H * P4);  // Eq. (13)
+      const u64 sf2 = window_sq(rs2, voff, 0, td.W * 4, P4, td.H, td.sq_rows);
+      const long long V = (long long)((u64)(uint32_t)td.n * sf2 - (u64)sf * sf);
+      const double num = acc - (double)sf / (double)td.n * td.r64;  // Eq. (12)
+      const double rho =
+          V == 0 ? 0.0 : num / sqrt((double)V / (double)td.n * td.q_k);  // Eqs. (17), (18)
+      const bool hit = mine && rho >= thr[pd.tmpl];
+      const u64 hm = __ballot(hit);
+      if (hm != 0) {
         int pos0 = 0;
-        if (lane == 0) pos0 = atomicAdd(out_count, __popcll(m));
+        if (lane == 0) pos0 = atomicAdd(out_count, __popcll(hm));
         const int pos = __builtin_amdgcn_readfirstlane(pos0) +
-                        __popcll(m & ((1ull << lane) - 1ull));
+                        __popcll(hm & ((1ull << lane) - 1ull));
         if (hit && pos < out_cap) {
           sncc_hit o;
-          o.pair = h.pair;
-          o.u = h.u;
-          o.v = h.v;
+          o.pair = pair0;
+          o.u = u;
+          o.v = v;
           o.reserved = 0;
           o.rho = rho;
           out[pos] = o;
-        }
-      }
-    } else {
-      // mixed pairs: one survivor at a time
-      const int end = min(base + 64, n_cand);
-      for (int cc = base; cc < end; ++cc) {
-        const sncc_hit e = cand[cc];
-        const PairDesc pd = pairs[e.pair];
-        const DevTmpl td = tmpls[pd.tmpl];
-        const uint32_t *S = s + (long long)pd.frame * frame_stride;
-        const uint32_t *S2 = s2 + (long long)pd.frame * frame_stride;
-        const uint32_t *a0 = S + (long long)e.v * P + e.u;
-        double acc = 0.0;
-        for (int i = lane; i < td.K; i += 64) {
-          const int4 g = geom[td.seg_off + i];
-          const uint32_t *q0 = a0 + (long long)g.y * P + g.x;
-          const uint32_t *q2 = q0 + (long long)g.w * P;
-          const uint32_t F = (q2[g.z] - q2[0]) - (q0[g.z] - q0[0]);
-          acc = __builtin_fma((double)F, c64[td.seg_off + i], acc);
-        }
-        for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
-        if (lane == 0) {
-          const double rho = slow_rho_finish(acc, S, S2, P, e.u, e.v, td);
-          if (rho >= thr[pd.tmpl]) {
-            const int pos = atomicAdd(out_count, 1);
-            if (pos < out_cap) {
-              sncc_hit o;
-              o.pair = e.pair;
-              o.u = e.u;
-              o.v = e.v;
-              o.reserved = 0;
-              o.rho = rho;
-              out[pos] = o;
-            }
-          }
         }
       }
     }

@@ -57,3 +57,17 @@ def test_segment_dtype_layout():
     assert S.SEGMENT_DTYPE.itemsize == 32
     a = np.zeros(2, S.SEGMENT_DTYPE)
     assert a.strides == (32,)
+
+
+def test_header_constants_match_binding():
+    """Every numeric macro of the header has the same value in the binding."""
+    import os
+    import re
+    import paper_2502_01286_amd._native as nat
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with open(os.path.join(root, "include", "sncc.h")) as fh:
+        text = fh.read()
+    macros = re.findall(r"^#define (SNCC_\w+) \(?(-?\d+)(?:LL)?\)?", text, re.M)
+    assert len(macros) >= 10
+    for name, val in macros:
+        assert getattr(nat, name) == int(val), name
