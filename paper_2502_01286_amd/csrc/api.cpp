@@ -171,6 +171,12 @@ struct PlanHost {
   std::vector<WorkItem> items;
   std::vector<int> order;       // item indices, queue by queue
   std::vector<int> qbeg;        // nq + 1 offsets into order
+  // slow pass of the two-threshold search
+  std::vector<SlowTmpl> slow;
+  std::vector<uint32_t> slot_off;
+  std::vector<double> slot_c;
+  int slow_lds = 0;             // bytes of the largest staged region
+  int run_cap = 0;              // (tile, wave) pairs of the plan
   int64_t coarse_evals = 0, n_offsets = 0;
   int64_t computed_evals = 0;  // including offsets of partial edge tiles
   int64_t n_passes = 0;        // LDS passes summed over used templates
@@ -200,9 +206,10 @@ int rows_needed(const std::vector<char> &cov, const Seg &g, int bv) {
 
 // Horizontal chains of a segment list: maximal runs of segments with equal
 // y and h where each starts at the column the previous one ends, cut into
-// pieces of at most kMaxChain segments.  Returns the pieces as index lists,
+// pieces of at most max_len segments.  Returns the pieces as index lists,
 // in order of first segment.
-std::vector<std::vector<int>> horizontal_chains(const std::vector<Seg> &segs) {
+std::vector<std::vector<int>> horizontal_chains(const std::vector<Seg> &segs,
+                                               int max_len = kMaxChain) {
   std::map<std::tuple<int, int, int>, int> at;  // (y, h, x) -> index
   for (size_t i = 0; i < segs.size(); ++i) at[{segs[i].y, segs[i].h, segs[i].x}] = (int)i;
   std::vector<int> next(segs.size(), -1);
@@ -220,7 +227,7 @@ std::vector<std::vector<int>> horizontal_chains(const std::vector<Seg> &segs) {
     std::vector<int> piece;
     for (int k = (int)i; k >= 0; k = next[k]) {
       piece.push_back(k);
-      if ((int)piece.size() == kMaxChain) {
+      if ((int)piece.size() == max_len) {
         pieces.push_back(piece);
         piece.clear();
       }
@@ -512,13 +519,72 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int P, int n_pairs,
   return SNCC_OK;
 }
 
+// Boundary-slot tables of the slow approximations for the staged slow pass
+// (see SlowTmpl), for runs of the tile shape `tc`; templates whose region
+// does not fit kSlowRegionWords are scored from the global tables.
+void plan_slow(const sncc_tmpl *slow, const TileCfg &tc, PlanHost &ph) {
+  ph.slow.assign(slow->T, SlowTmpl{-1, 0, 0, 0});
+  ph.slot_off.clear();
+  ph.slot_c.clear();
+  ph.slow_lds = 0;
+  for (int t = 0; t < slow->T; ++t) {
+    const int W = slow->W[t], H = slow->H[t];
+    const int pitch = tc.bu() + W + 1, rows = tc.rv + H;
+    if ((long long)pitch * rows > kSlowRegionWords) continue;
+    const std::vector<Seg> &segs = slow->segs[t];
+    std::vector<std::vector<int>> pieces = horizontal_chains(segs, kSlowChainMax);
+    // pieces in raster order of their first segment: a wave's slots then
+    // read nearby rows
+    std::stable_sort(pieces.begin(), pieces.end(),
+                     [&](const std::vector<int> &a, const std::vector<int> &b) {
+                       const Seg &x = segs[a[0]], &y = segs[b[0]];
+                       return x.y != y.y ? x.y < y.y : x.x < y.x;
+                     });
+    SlowTmpl st;
+    st.tbl = (int)ph.slot_off.size();
+    st.pitch = pitch;
+    st.rows = rows;
+    int fill = 0;  // slots used in the current 16-lane row
+    for (const std::vector<int> &pc : pieces) {
+      const int need = (int)pc.size() + 1;
+      if (fill + need > 16) {
+        for (; fill < 16; ++fill) {
+          ph.slot_off.push_back(0);
+          ph.slot_c.push_back(0.0);
+        }
+      }
+      fill %= 16;
+      const Seg &g0 = segs[pc[0]];
+      const uint32_t top = (uint32_t)(g0.y * pitch), bot = (uint32_t)((g0.y + g0.h) * pitch);
+      auto slot = [&](int x) { return ((top + x) * 4) | (((bot + x) * 4) << 16); };  // bytes
+      ph.slot_off.push_back(slot(g0.x));
+      ph.slot_c.push_back(0.0);
+      for (int i : pc) {
+        ph.slot_off.push_back(slot(segs[i].x + segs[i].w));
+        ph.slot_c.push_back(slow->c64[t][i]);
+      }
+      fill += need;
+    }
+    while (ph.slot_off.size() % 64 != 0) {
+      ph.slot_off.push_back(0);
+      ph.slot_c.push_back(0.0);
+    }
+    st.n_iter = ((int)ph.slot_off.size() - st.tbl) / 64;
+    ph.slow[t] = st;
+    ph.slow_lds = std::max(ph.slow_lds, pitch * rows * 4);
+  }
+  long long tiles = 0;
+  for (const WorkItem &it : ph.items) tiles += it.tile_end - it.tile_begin;
+  ph.run_cap = (int)std::min<long long>(tiles * tc.nw, 1 << 30);
+}
+
 }  // namespace
 
 // Device copy of a plan plus its completion event.
 struct PlanDev {
   PlanHost h;
   DevBuf d_tmpls, d_passes, d_ivs, d_recs, d_pairs, d_items, d_order, d_qbeg, d_queue,
-      d_partial, d_thr;
+      d_partial, d_thr, d_slow, d_slot_off, d_slot_c, d_runs;
   hipEvent_t done = nullptr;
   ~PlanDev() {
     if (done) (void)hipEventDestroy(done);
@@ -535,11 +601,19 @@ struct PlanDev {
     CHK(d_queue.reserve(zero_ints() * sizeof(int)));
     if (h.sink == kSinkTopk)
       CHK(d_partial.reserve(std::max<size_t>(16, h.items.size() * h.k * 8)));
+    if (h.sink == kSinkCompact) {
+      CHK(d_slow.upload(h.slow, st));
+      CHK(d_slot_off.upload(h.slot_off, st));
+      CHK(d_slot_c.upload(h.slot_c, st));
+      CHK(d_runs.reserve(std::max<size_t>(16, (size_t)h.run_cap * sizeof(RunDesc))));
+    }
     return SNCC_OK;
   }
-  // work counters, then one floor key per pair (top-k sink), zeroed per launch
+  // work counters, then one floor key per pair (top-k sink) or the run and
+  // slow-pass counters (compacting sink), zeroed per launch
   int zero_ints() const {
-    return kQueueInts + (h.sink == kSinkTopk ? 2 * (int)h.pairs.size() : 0);
+    return kQueueInts + (h.sink == kSinkTopk ? 2 * (int)h.pairs.size()
+                                             : h.sink == kSinkCompact ? 16 : 0);
   }
   TileArgs args(const uint32_t *s, const uint32_t *s2, long long fs, int P, int M, int N) {
     TileArgs a;
@@ -565,7 +639,12 @@ struct PlanDev {
     a.pair_floor =
         h.sink == kSinkTopk ? reinterpret_cast<unsigned long long *>(a.queue + kQueueInts)
                             : nullptr;
-    a.co = CompactOut{nullptr, 0, nullptr};
+    a.co = CompactOut{nullptr, 0, nullptr, nullptr, 0, nullptr};
+    if (h.sink == kSinkCompact) {
+      a.co.runs = d_runs.as<RunDesc>();
+      a.co.run_cap = h.run_cap;
+      a.co.run_count = a.queue + kQueueInts;
+    }
     a.n_zero = zero_ints();
     a.rho = nullptr;
     a.rho_pitch = 0;
@@ -1204,11 +1283,14 @@ int sncc_threshold_match(sncc_ctx *ctx, const sncc_tmpl *fast, const sncc_tmpl *
   CHK(cached_plan(ctx, std::move(key), [&](PlanDev &d) {
     CHK(build_plan(fast, 0, M, N, sat_pitch, n_pairs, pairs, 1, kSinkCompact, ctx->num_cu, d.h,
                    thr_fast));
+    plan_slow(slow, d.h.tc, d.h);
     std::vector<double> ts(thr_slow, thr_slow + slow->T);
     return d.d_thr.upload(ts, ctx->stream);
   }, &pd));
   TileArgs a = pd->args(d_s, d_s2, fs, sat_pitch, M, N);
-  a.co = CompactOut{d_cand, cand_cap, d_counts};
+  a.co.hits = d_cand;
+  a.co.cap = cand_cap;
+  a.co.count = d_counts;
   ctx->n_stages = 0;
   if (launch_zero(a.queue, a.n_zero, ctx->stream) != 0 ||
       launch_zero(d_counts, 2, ctx->stream) != 0)
@@ -1217,9 +1299,33 @@ int sncc_threshold_match(sncc_ctx *ctx, const sncc_tmpl *fast, const sncc_tmpl *
   if (launch_tile(pd->h.cfg, kSinkCompact, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0)
     SNCC_FAIL(SNCC_EDEVICE, "threshold search launch: %s", hipGetErrorString(hipGetLastError()));
   ctx->mark(1);
-  if (launch_slow(d_s, d_s2, fs, sat_pitch, slow->d_dev.as<DevTmpl>(), slow->d_geom.as<int4>(),
-                  slow->d_c64.as<double>(), pd->d_pairs.as<PairDesc>(), pd->d_thr.as<double>(),
-                  d_cand, d_counts, cand_cap, d_out, out_cap, d_counts + 1, ctx->stream) != 0)
+  SlowArgs sa;
+  sa.s = d_s;
+  sa.s2 = d_s2;
+  sa.frame_stride = fs;
+  sa.P = sat_pitch;
+  sa.N = N;
+  sa.tmpls = slow->d_dev.as<DevTmpl>();
+  sa.geom = slow->d_geom.as<int4>();
+  sa.c64 = slow->d_c64.as<double>();
+  sa.stmpl = pd->d_slow.as<SlowTmpl>();
+  sa.slot_off = pd->d_slot_off.as<uint32_t>();
+  sa.slot_c = pd->d_slot_c.as<double>();
+  sa.pairs = pd->d_pairs.as<PairDesc>();
+  sa.thr = pd->d_thr.as<double>();
+  sa.cand = d_cand;
+  sa.cand_count = d_counts;
+  sa.cand_cap = cand_cap;
+  sa.runs = a.co.runs;
+  sa.run_count = a.co.run_count;
+  sa.run_cap = a.co.run_cap;
+  sa.work = a.queue + kQueueInts + 8;
+  sa.out = d_out;
+  sa.out_cap = out_cap;
+  sa.out_count = d_counts + 1;
+  const int slow_lds = pd->h.slow_lds;
+  const int slow_grid = std::max(1, std::min(pd->h.run_cap, ctx->num_cu * slow_occupancy(slow_lds)));
+  if (launch_slow(sa, slow_grid, slow_lds, ctx->stream) != 0)
     SNCC_FAIL(SNCC_EDEVICE, "threshold search launch: %s", hipGetErrorString(hipGetLastError()));
   ctx->mark(2);
   if (ctx->timing) ctx->n_stages = 2;

@@ -624,15 +624,23 @@ int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride,
 // --------------------------------------------------- two-threshold search
 // Section 5, steps 7g-j for the offsets that passed the fast test: rho with
 // the slow approximation in FP64, appended to the output when it reaches the
-// template's slow threshold.  A wave takes 64 consecutive survivors and
-// scores them pair by pair: the lanes of one pair each score their own offset
-// over the pair's shared segment list (uniform geometry, so every table read
-// is one buffer load whose lanes read neighbouring entries when the
-// survivors are neighbouring offsets, as the compaction mostly leaves them),
-// while the other lanes idle.  Segments are taken in blocks of kSlowBlock
-// with all their loads issued before the block is summed, in segment order:
-// a survivor's rho does not depend on how the survivors fall into groups.
+// template's slow threshold.  Workgroups take runs of the survivor list (the
+// survivors one wave of the fast pass found in one tile: one pair, a few
+// offset rows, 64 RU columns) from a counter.
+//
+// Staged form: the workgroup copies the run's region of the frame's table
+// (every entry a window of the run reads) to LDS; each wave then scores four
+// survivors at a time, lanes over the template's boundary slots (see
+// SlowTmpl): per slot two LDS reads give the boundary column's difference
+// D = s(y + h) - s(y) (modulo 2^32), and the lane below in the same chain
+// holds the previous boundary, so F_i = D - D_prev is the segment's box sum
+// (Eq. (11)); c_i F_i is accumulated in FP64 per lane and summed over the
+// wave at the end.  Global form (regions too large for LDS): lanes over the
+// run's survivors, each scoring its own offset over the shared segment list
+// with buffer loads whose scalar offset is the segment's corner, blocks of
+// kSlowBlock segments loaded before they are summed in segment order.
 constexpr int kSlowBlock = 8;
+constexpr int kSlowBatch = 4;  // survivors per wave in the staged form
 
 // Sum over the segments of c_i F_i (Eq. (12), first term) for the window at
 // voff (bytes from the frame table's base); uniform segment list.
@@ -659,76 +667,177 @@ __device__ __forceinline__ double slow_sum(__amdgpu_buffer_rsrc_t rs, int voff, 
   return acc;
 }
 
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const u64 b = (u64)__double_as_longlong(x);
+  const uint32_t lo =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROW_MASK, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL,
+                                                            ROW_MASK, 0xf, false);
+  return __longlong_as_double((long long)(((u64)hi << 32) | lo));
+}
+
+// Sum of x over the wave, wave-uniform: an inclusive DPP scan (shifts
+// within rows of 16 lanes, then the row broadcasts) read at lane 63.
+__device__ __forceinline__ double wave_total_f64(double x) {
+  x += dpp_f64<0x111, 0xf>(x);
+  x += dpp_f64<0x112, 0xf>(x);
+  x += dpp_f64<0x114, 0xf>(x);
+  x += dpp_f64<0x118, 0xf>(x);
+  x += dpp_f64<0x142, 0xa>(x);
+  x += dpp_f64<0x143, 0xc>(x);
+  const u64 b = (u64)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+  return __longlong_as_double((long long)(((u64)hi << 32) | lo));
+}
+
+__device__ __forceinline__ uint32_t lds_at(const uint32_t *region, int byte_off) {
+  return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(region) + byte_off);
+}
+
+// rho from the numerator's segment sum and the window sums (Eqs. (12),
+// (16)-(18)), FP64.
+__device__ __forceinline__ double slow_rho(double acc, uint32_t sf, u64 sf2, const DevTmpl &td) {
+  const long long V = (long long)((u64)(uint32_t)td.n * sf2 - (u64)sf * sf);
+  const double num = acc - (double)sf / (double)td.n * td.r64;
+  return V == 0 ? 0.0 : num / sqrt((double)V / (double)td.n * td.q_k);
+}
+
+// Kernel arguments are restrict-qualified pointers (not an argument block)
+// so that wave-uniform descriptor and segment reads become scalar loads.
 __global__ __launch_bounds__(256) void slow_kernel(
     const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
-    int P, const DevTmpl *__restrict__ tmpls, const int4 *__restrict__ geom,
-    const double *__restrict__ c64, const PairDesc *__restrict__ pairs,
-    const double *__restrict__ thr, const sncc_hit *__restrict__ cand,
-    const int *__restrict__ cand_count, int cand_cap, sncc_hit *__restrict__ out, int out_cap,
+    int P, int N, const DevTmpl *__restrict__ tmpls, const int4 *__restrict__ geom,
+    const double *__restrict__ c64, const SlowTmpl *__restrict__ stmpl,
+    const uint32_t *__restrict__ slot_off, const double *__restrict__ slot_c,
+    const PairDesc *__restrict__ pairs, const double *__restrict__ thrs,
+    const sncc_hit *__restrict__ cand, const int *__restrict__ cand_count, int cand_cap,
+    const RunDesc *__restrict__ runs, const int *__restrict__ run_count, int run_cap,
+    int *__restrict__ work, sncc_hit *__restrict__ out, int out_cap,
     int *__restrict__ out_count) {
-  const int lane = threadIdx.x & 63;
+  extern __shared__ uint32_t region[];
+  __shared__ int run_sh;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n_cand = min(*cand_count, cand_cap);
+  const int n_runs = min(*run_count, run_cap);
   const int P4 = P * 4;
   const uint32_t bytes = (uint32_t)(frame_stride * 4);
-  for (int base = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; base < n_cand;
-       base += gridDim.x * 4 * 64) {
-    const int c = base + lane;
-    const sncc_hit h = cand[c < n_cand ? c : base];
-    bool todo = c < n_cand;
-    for (;;) {
-      const u64 m = __ballot(todo);
-      if (m == 0) break;
-      const int first = __builtin_ctzll(m);
-      const int pair0 = __builtin_amdgcn_readlane(h.pair, first);
-      const bool mine = todo && h.pair == pair0;
-      todo = todo && !mine;
-      // lanes of other pairs score the first lane's offset (in range for
-      // this pair's template) and discard it
-      const int u = mine ? h.u : __builtin_amdgcn_readlane(h.u, first);
-      const int v = mine ? h.v : __builtin_amdgcn_readlane(h.v, first);
-      const PairDesc pd = pairs[pair0];
-      const DevTmpl td = tmpls[pd.tmpl];
-      const __amdgpu_buffer_rsrc_t rs = make_rsrc(s + (long long)pd.frame * frame_stride, bytes);
-      const __amdgpu_buffer_rsrc_t rs2 =
-          make_rsrc(s2 + (long long)pd.frame * frame_stride, bytes);
-      const int voff = v * P4 + u * 4;
-      const double acc = slow_sum(rs, voff, P4, geom + td.seg_off, c64 + td.seg_off, td.K);
-      const uint32_t sf = window_box(rs, voff, 0, td.W * 4, td.H * P4);  // Eq. (13)
-      const u64 sf2 = window_sq(rs2, voff, 0, td.W * 4, P4, td.H, td.sq_rows);
-      const long long V = (long long)((u64)(uint32_t)td.n * sf2 - (u64)sf * sf);
-      const double num = acc - (double)sf / (double)td.n * td.r64;  // Eq. (12)
-      const double rho =
-          V == 0 ? 0.0 : num / sqrt((double)V / (double)td.n * td.q_k);  // Eqs. (17), (18)
-      const bool hit = mine && rho >= thr[pd.tmpl];
-      const u64 hm = __ballot(hit);
-      if (hm != 0) {
-        int pos0 = 0;
-        if (lane == 0) pos0 = atomicAdd(out_count, __popcll(hm));
-        const int pos = __builtin_amdgcn_readfirstlane(pos0) +
-                        __popcll(hm & ((1ull << lane) - 1ull));
-        if (hit && pos < out_cap) {
-          sncc_hit o;
-          o.pair = pair0;
-          o.u = u;
-          o.v = v;
-          o.reserved = 0;
-          o.rho = rho;
-          out[pos] = o;
+  auto emit = [&](int pair, int u, int v, double rho) {
+    const int pos = atomicAdd(out_count, 1);
+    if (pos < out_cap) {
+      sncc_hit o;
+      o.pair = pair;
+      o.u = u;
+      o.v = v;
+      o.reserved = 0;
+      o.rho = rho;
+      out[pos] = o;
+    }
+  };
+  for (;;) {
+    if (threadIdx.x == 0) run_sh = atomicAdd(work, 1);
+    __syncthreads();
+    const int r = __builtin_amdgcn_readfirstlane(run_sh);
+    if (r >= n_runs) break;
+    const RunDesc rd = runs[r];
+    const int start = rd.start, end = min(rd.start + rd.count, n_cand);
+    const PairDesc pd = pairs[rd.pair];
+    const DevTmpl td = tmpls[pd.tmpl];
+    const SlowTmpl st = stmpl[pd.tmpl];
+    const double thr = thrs[pd.tmpl];
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(s + (long long)pd.frame * frame_stride, bytes);
+    const __amdgpu_buffer_rsrc_t rs2 = make_rsrc(s2 + (long long)pd.frame * frame_stride, bytes);
+    if (start < end && st.tbl >= 0) {
+      // region rows [v0, v0 + rows), columns [u0, u0 + pitch), clamped to
+      // the table (clamped entries are never read by a window of the run)
+      for (int row = wave; row < st.rows; row += 4) {
+        const int gy = min(rd.v0 + row, N);
+        for (int c = lane; c < st.pitch; c += 64) {
+          const int gx = min(rd.u0 + c, P - 1);
+          region[row * st.pitch + c] =
+              __builtin_amdgcn_raw_buffer_load_b32(rs, (gy * P + gx) * 4, 0, 0);
         }
       }
+      __syncthreads();
+      const __amdgpu_buffer_rsrc_t rso = make_rsrc(slot_off + st.tbl, (uint32_t)st.n_iter * 256u);
+      const __amdgpu_buffer_rsrc_t rsc = make_rsrc(slot_c + st.tbl, (uint32_t)st.n_iter * 512u);
+      for (int b = start + wave * kSlowBatch; b < end; b += 4 * kSlowBatch) {
+        int su[kSlowBatch], sv[kSlowBatch], base[kSlowBatch];  // base: region bytes
+#pragma unroll
+        for (int j = 0; j < kSlowBatch; ++j) {
+          const sncc_hit h = cand[min(b + j, end - 1)];
+          su[j] = h.u;
+          sv[j] = h.v;
+          base[j] = ((h.v - rd.v0) * st.pitch + (h.u - rd.u0)) * 4;
+        }
+        double acc[kSlowBatch];
+#pragma unroll
+        for (int j = 0; j < kSlowBatch; ++j) acc[j] = 0.0;
+        // slot entries of the next block are requested before this one is used
+        uint32_t o = __builtin_amdgcn_raw_buffer_load_b32(rso, lane * 4, 0, 0);
+        double c = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rsc, lane * 8, 0, 0));
+        for (int it = 0; it < st.n_iter; ++it) {
+          const int nx = min(it + 1, st.n_iter - 1);
+          const uint32_t o_next = __builtin_amdgcn_raw_buffer_load_b32(rso, lane * 4, nx * 256, 0);
+          const double c_next = __builtin_bit_cast(
+              double, __builtin_amdgcn_raw_buffer_load_b64(rsc, lane * 8, nx * 512, 0));
+          const int top = (int)(o & 0xffffu), bot = (int)(o >> 16);
+#pragma unroll
+          for (int j = 0; j < kSlowBatch; ++j) {
+            const uint32_t D = lds_at(region, base[j] + bot) - lds_at(region, base[j] + top);
+            // previous boundary's difference (row_shr:1); kept a separate move:
+            // folded into the subtraction as v_subrev_u32_dpp it came out negated
+            uint32_t Dp = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)D, 0x111, 0xf, 0xf, false);
+            asm volatile("" : "+v"(Dp));
+            acc[j] = __builtin_fma((double)(D - Dp), c, acc[j]);
+          }
+          o = o_next;
+          c = c_next;
+        }
+#pragma unroll
+        for (int j = 0; j < kSlowBatch; ++j) {
+          const double sum = wave_total_f64(acc[j]);
+          if (b + j < end) {
+            const int q = base[j], qh = q + td.H * st.pitch * 4, w4 = td.W * 4;
+            const uint32_t sf = (lds_at(region, qh + w4) - lds_at(region, qh)) -
+                                (lds_at(region, q + w4) - lds_at(region, q));  // Eq. (13)
+            const u64 sf2 = window_sq(rs2, (sv[j] * P + su[j]) * 4, 0, w4, P4, td.H,
+                                      td.sq_rows);  // Eq. (15)
+            const double rho = slow_rho(sum, sf, sf2, td);
+            if (lane == 0 && rho >= thr) emit(rd.pair, su[j], sv[j], rho);
+          }
+        }
+      }
+    } else if (start < end) {
+      for (int b = start + wave * 64; b < end; b += 256) {
+        const int c = b + lane;
+        const sncc_hit h = cand[min(c, end - 1)];
+        const int voff = h.v * P4 + h.u * 4;
+        const double acc = slow_sum(rs, voff, P4, geom + td.seg_off, c64 + td.seg_off, td.K);
+        const uint32_t sf = window_box(rs, voff, 0, td.W * 4, td.H * P4);  // Eq. (13)
+        const u64 sf2 = window_sq(rs2, voff, 0, td.W * 4, P4, td.H, td.sq_rows);
+        const double rho = slow_rho(acc, sf, sf2, td);
+        if (c < end && rho >= thr) emit(rd.pair, h.u, h.v, rho);
+      }
     }
+    __syncthreads();  // region and run_sh are rewritten for the next run
   }
 }
 
-int launch_slow(const uint32_t *s, const uint32_t *s2, long long frame_stride, int P,
-                const DevTmpl *tmpls, const int4 *geom, const double *c64,
-                const PairDesc *pairs, const double *thr, const sncc_hit *cand,
-                const int *cand_count, int cand_cap, sncc_hit *out, int out_cap,
-                int *out_count, hipStream_t st) {
-  const int blocks = std::max(1, std::min((cand_cap + 255) / 256, 8192));
-  hipLaunchKernelGGL(slow_kernel, dim3(blocks), dim3(256), 0, st, s, s2, frame_stride, P,
-                     tmpls, geom, c64, pairs, thr, cand, cand_count, cand_cap, out, out_cap,
-                     out_count);
+int slow_occupancy(int lds_bytes) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, slow_kernel, 256, lds_bytes) !=
+      hipSuccess)
+    return 1;
+  return std::max(1, blocks);
+}
+
+int launch_slow(const SlowArgs &a, int grid, int lds_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(slow_kernel, dim3(grid), dim3(256), lds_bytes, st, a.s, a.s2,
+                     a.frame_stride, a.P, a.N, a.tmpls, a.geom, a.c64, a.stmpl, a.slot_off,
+                     a.slot_c, a.pairs, a.thr, a.cand, a.cand_count, a.cand_cap, a.runs,
+                     a.run_count, a.run_cap, a.work, a.out, a.out_cap, a.out_count);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -105,10 +105,70 @@ constexpr int kSinkTopk = 0;
 constexpr int kSinkMap = 1;
 constexpr int kSinkCompact = 2;
 
+// A run of the survivor list: the survivors one wave found in one tile,
+// written together at hits[start, start + count) (entries at or beyond the
+// list's capacity were not written).  They lie in offset rows
+// [v0, v0 + RV) and columns [u0, u0 + 64 RU) of pair `pair`.
+struct RunDesc {
+  int start, count, pair, u0, v0;
+  int pad[3];
+};
+
 struct CompactOut {
   sncc_hit *hits;  // cap entries
   int cap;
   int *count;      // entries wanted (may exceed cap; zero at launch)
+  RunDesc *runs;   // run_cap entries, one per (tile, wave) with survivors
+  int run_cap;
+  int *run_count;  // zero at launch
+};
+
+// Slow pass of the two-threshold search.  A template whose region (the
+// table rows and columns that the windows of one run's offsets cover) fits
+// the LDS budget is scored from LDS through a boundary-slot table: its
+// segments as horizontal chains, each chain of L segments taking L + 1
+// consecutive slots inside one 16-lane row (so that a lane finds the
+// previous boundary one lane down), padded to whole waves.  Slot j holds the
+// LDS byte offsets of the boundary column's entries in the chain's top row
+// y and bottom row y + h (relative to the window's top-left entry; bottom in
+// the high 16 bits) and c_i of the segment ending there (0 at a chain's
+// first boundary and in padding slots).
+struct SlowTmpl {
+  int tbl;     // first slot (-1: scored from the global tables)
+  int n_iter;  // slots / 64
+  int pitch;   // LDS row pitch (words) of the region
+  int rows;    // region rows
+};
+
+// Region of a run: rows [v0, v0 + RV + H), columns [u0, u0 + 64 RU + W] of
+// the frame's table; at most this many words.
+constexpr int kSlowRegionWords = 13312;  // 52 KB: three workgroups per CU
+static_assert(kSlowRegionWords * 4 <= 65536, "slot byte offsets are 16-bit");
+constexpr int kSlowChainMax = 15;        // segments per chain piece (16 slots)
+
+struct SlowArgs {
+  const uint32_t *s;
+  const uint32_t *s2;
+  long long frame_stride;
+  int P, N;
+  const DevTmpl *tmpls;     // slow approximations
+  const int4 *geom;
+  const double *c64;
+  const SlowTmpl *stmpl;
+  const uint32_t *slot_off;
+  const double *slot_c;
+  const PairDesc *pairs;
+  const double *thr;        // per template
+  const sncc_hit *cand;
+  const int *cand_count;
+  int cand_cap;
+  const RunDesc *runs;
+  const int *run_count;
+  int run_cap;
+  int *work;                // run counter, zero at launch
+  sncc_hit *out;
+  int out_cap;
+  int *out_count;
 };
 
 // Kernel arguments of the persistent tile kernel.
@@ -208,11 +268,8 @@ size_t sat_scratch_words(int B, int M, int N);
 
 int tile_cfg_count();
 TileCfg tile_cfg(int i);
-int launch_slow(const uint32_t *s, const uint32_t *s2, long long frame_stride, int P,
-                const DevTmpl *tmpls, const int4 *geom, const double *c64,
-                const PairDesc *pairs, const double *thr, const sncc_hit *cand,
-                const int *cand_count, int cand_cap, sncc_hit *out, int out_cap,
-                int *out_count, hipStream_t st);
+int launch_slow(const SlowArgs &a, int grid, int lds_bytes, hipStream_t st);
+int slow_occupancy(int lds_bytes);
 int launch_tile(int cfg, int sink, const TileArgs &a, int grid,
                 int lds_bytes, hipStream_t st);
 int tile_max_lds();

@@ -272,7 +272,7 @@ __device__ __forceinline__ void run_item(
       // offsets whose rho reaches the template's threshold are appended to
       // the survivor list with one atomic per wave, ordered by (du, dv) slot
       // and then by lane, so that neighbouring entries are neighbouring
-      // offsets of one row
+      // offsets of one row; the wave's entries form one run
       u64 m[R];
       int total = 0;
 #pragma unroll
@@ -287,7 +287,20 @@ __device__ __forceinline__ void run_item(
         }
       if (total > 0) {
         int base = 0;
-        if (lane == 0) base = atomicAdd(co.count, total);
+        if (lane == 0) {
+          base = atomicAdd(co.count, total);
+          const int ri = atomicAdd(co.run_count, 1);
+          if (ri < co.run_cap) {
+            RunDesc rd;
+            rd.start = base;
+            rd.count = total;
+            rd.pair = it.pair;
+            rd.u0 = u0;
+            rd.v0 = v0 + wave * RV;
+            rd.pad[0] = rd.pad[1] = rd.pad[2] = 0;
+            co.runs[ri] = rd;
+          }
+        }
         int pos = __builtin_amdgcn_readfirstlane(base);
         const u64 below = (1ull << lane) - 1ull;
 #pragma unroll
