@@ -640,7 +640,8 @@ int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride,
 // with buffer loads whose scalar offset is the segment's corner, blocks of
 // kSlowBlock segments loaded before they are summed in segment order.
 constexpr int kSlowBlock = 8;
-constexpr int kSlowBatch = 4;  // survivors per wave in the staged form
+constexpr int kSlowBatch = 4;  // survivors per wave in the staged form (four registers
+                               // in the scoring loop's asm operand list)
 
 // Sum over the segments of c_i F_i (Eq. (12), first term) for the window at
 // voff (bytes from the frame table's base); uniform segment list.
@@ -690,6 +691,36 @@ __device__ __forceinline__ double wave_total_f64(double x) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
   return __longlong_as_double((long long)(((u64)hi << 32) | lo));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_full_f64(double x) {  // every lane has a source
+  const u64 b = (u64)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((u64)hi << 32) | lo));
+}
+
+// Wave sums of four values at once: lane l returns the sum of a_(l mod 4)
+// over all 64 lanes.  Two exchange steps (lanes l and l ^ 1, then l ^ 2)
+// leave each lane with a partial sum of the value of its residue, then
+// four more steps (xor 4, 8 within rows of 16 lanes; 16, 32 across rows)
+// add the partials of the same residue.
+__device__ __forceinline__ double wave_sum4_f64(double a0, double a1, double a2, double a3,
+                                                int lane) {
+  const bool odd = lane & 1, hi2 = lane & 2;
+  double k01 = odd ? a1 : a0, g01 = odd ? a0 : a1;
+  double k23 = odd ? a3 : a2, g23 = odd ? a2 : a3;
+  k01 += dpp_full_f64<0xb1>(g01);  // quad_perm [1,0,3,2]: lane l ^ 1
+  k23 += dpp_full_f64<0xb1>(g23);
+  double k = hi2 ? k23 : k01, g = hi2 ? k01 : k23;
+  k += dpp_full_f64<0x4e>(g);      // quad_perm [2,3,0,1]: lane l ^ 2
+  k += dpp_full_f64<0x124>(k);     // row_ror:4
+  k += dpp_full_f64<0x128>(k);     // row_ror:8
+  k += __shfl_xor(k, 16);
+  k += __shfl_xor(k, 32);
+  return k;
 }
 
 __device__ __forceinline__ uint32_t lds_at(const uint32_t *region, int byte_off) {
@@ -774,40 +805,59 @@ __global__ __launch_bounds__(256) void slow_kernel(
         double acc[kSlowBatch];
 #pragma unroll
         for (int j = 0; j < kSlowBatch; ++j) acc[j] = 0.0;
-        // slot entries of the next block are requested before this one is used
-        uint32_t o = __builtin_amdgcn_raw_buffer_load_b32(rso, lane * 4, 0, 0);
-        double c = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rsc, lane * 8, 0, 0));
-        for (int it = 0; it < st.n_iter; ++it) {
-          const int nx = min(it + 1, st.n_iter - 1);
-          const uint32_t o_next = __builtin_amdgcn_raw_buffer_load_b32(rso, lane * 4, nx * 256, 0);
-          const double c_next = __builtin_bit_cast(
-              double, __builtin_amdgcn_raw_buffer_load_b64(rsc, lane * 8, nx * 512, 0));
+        // one block of 64 slots for the batch's survivors
+        auto block = [&](uint32_t o, double c) {
           const int top = (int)(o & 0xffffu), bot = (int)(o >> 16);
+          uint32_t D[kSlowBatch], Dp[kSlowBatch];
 #pragma unroll
-          for (int j = 0; j < kSlowBatch; ++j) {
-            const uint32_t D = lds_at(region, base[j] + bot) - lds_at(region, base[j] + top);
-            // previous boundary's difference (row_shr:1); kept a separate move:
-            // folded into the subtraction as v_subrev_u32_dpp it came out negated
-            uint32_t Dp = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)D, 0x111, 0xf, 0xf, false);
-            asm volatile("" : "+v"(Dp));
-            acc[j] = __builtin_fma((double)(D - Dp), c, acc[j]);
-          }
-          o = o_next;
-          c = c_next;
-        }
+          for (int j = 0; j < kSlowBatch; ++j)
+            D[j] = lds_at(region, base[j] + bot) - lds_at(region, base[j] + top);
+          // the previous boundary's difference (row_shr:1), kept separate moves:
+          // folded into the subtraction as v_subrev_u32_dpp it came out negated
 #pragma unroll
-        for (int j = 0; j < kSlowBatch; ++j) {
-          const double sum = wave_total_f64(acc[j]);
-          if (b + j < end) {
-            const int q = base[j], qh = q + td.H * st.pitch * 4, w4 = td.W * 4;
-            const uint32_t sf = (lds_at(region, qh + w4) - lds_at(region, qh)) -
-                                (lds_at(region, q + w4) - lds_at(region, q));  // Eq. (13)
-            const u64 sf2 = window_sq(rs2, (sv[j] * P + su[j]) * 4, 0, w4, P4, td.H,
-                                      td.sq_rows);  // Eq. (15)
-            const double rho = slow_rho(sum, sf, sf2, td);
-            if (lane == 0 && rho >= thr) emit(rd.pair, su[j], sv[j], rho);
-          }
+          for (int j = 0; j < kSlowBatch; ++j)
+            Dp[j] = (uint32_t)__builtin_amdgcn_mov_dpp((int)D[j], 0x111, 0xf, 0xf, true);
+          asm volatile("" : "+v"(Dp[0]), "+v"(Dp[1]), "+v"(Dp[2]), "+v"(Dp[3]));
+#pragma unroll
+          for (int j = 0; j < kSlowBatch; ++j)
+            acc[j] = __builtin_fma((double)(D[j] - Dp[j]), c, acc[j]);
+        };
+        auto load_o = [&](int i) {
+          return __builtin_amdgcn_raw_buffer_load_b32(rso, lane * 4, min(i, st.n_iter - 1) * 256, 0);
+        };
+        auto load_c = [&](int i) {
+          return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                rsc, lane * 8, min(i, st.n_iter - 1) * 512, 0));
+        };
+        // two blocks per step; the next step's slot entries are requested
+        // before this step's are used
+        uint32_t o0 = load_o(0), o1 = load_o(1);
+        double c0 = load_c(0), c1 = load_c(1);
+        int it = 0;
+        for (; it + 2 <= st.n_iter; it += 2) {
+          const uint32_t n0 = load_o(it + 2), n1 = load_o(it + 3);
+          const double m0 = load_c(it + 2), m1 = load_c(it + 3);
+          block(o0, c0);
+          block(o1, c1);
+          o0 = n0;
+          o1 = n1;
+          c0 = m0;
+          c1 = m1;
         }
+        if (it < st.n_iter) block(o0, c0);
+        // lane j < kSlowBatch finishes survivor b + j: its sum, then rho
+        // (Eqs. (12), (13), (15)-(18)) in FP64
+        const double sum = wave_sum4_f64(acc[0], acc[1], acc[2], acc[3], lane);
+        const int jj = lane & 3;
+        const int q = jj == 0 ? base[0] : jj == 1 ? base[1] : jj == 2 ? base[2] : base[3];
+        const int uu = jj == 0 ? su[0] : jj == 1 ? su[1] : jj == 2 ? su[2] : su[3];
+        const int vv = jj == 0 ? sv[0] : jj == 1 ? sv[1] : jj == 2 ? sv[2] : sv[3];
+        const int qh = q + td.H * st.pitch * 4, w4 = td.W * 4;
+        const uint32_t sf = (lds_at(region, qh + w4) - lds_at(region, qh)) -
+                            (lds_at(region, q + w4) - lds_at(region, q));  // Eq. (13)
+        const u64 sf2 = window_sq(rs2, (vv * P + uu) * 4, 0, w4, P4, td.H, td.sq_rows);
+        const double rho = slow_rho(sum, sf, sf2, td);
+        if (lane < kSlowBatch && b + lane < end && rho >= thr) emit(rd.pair, uu, vv, rho);
       }
     } else if (start < end) {
       for (int b = start + wave * 64; b < end; b += 256) {
