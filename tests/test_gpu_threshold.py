@@ -158,6 +158,29 @@ def test_small_batch_against_oracle(S, ctx):
         assert any(int(h["u"]) == px and int(h["v"]) == py for h in outs[p]), (fo, j)
 
 
+def test_staged_and_global_slow_forms_together(S, ctx):
+    """A small template (its runs' regions fit LDS: staged slow pass) and a
+    large one (110 x 100: scored from the global tables) in one call."""
+    rng = np.random.default_rng(91)
+    frames = [synth.scene(7600 + i, 320, 240) for i in range(2)]
+    templates = []
+    for j, (w, h) in enumerate([(24, 20), (110, 100)]):
+        t, _, _ = synth.crop_template(rng, frames[j], w, h, sigma_max=10)
+        templates.append(t)
+        px, py = int(rng.integers(0, 320 - w + 1)), int(rng.integers(0, 240 - h + 1))
+        frames[1 - j][py:py + h, px:px + w] = t
+    pairs = [(b, j) for b in range(2) for j in range(2)]
+    print("2 frames 320x240 x templates 24x20, 110x100", flush=True)
+    got = _run(S, ctx, frames, templates, pairs, cand_cap=1 << 17, out_cap=1 << 17)
+    cands, outs = _split(got["cand"], len(pairs)), _split(got["out"], len(pairs))
+    tot_m = 0
+    for p, (b, j) in enumerate(pairs):
+        res, fa, sl, fmap, tb = _oracle_pair(frames[b], templates[j])
+        _, nm = _compare_pair(cands[p], outs[p], res, sl, fmap, tb)
+        tot_m += nm
+    assert tot_m > 0 and got["n_out"] == tot_m
+
+
 def test_capacity_overflow_counts_and_truncates(S, ctx):
     frames = [synth.scene(7100, 160, 120)]
     rng = np.random.default_rng(5)
