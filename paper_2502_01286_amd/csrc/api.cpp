@@ -171,7 +171,8 @@ struct PlanHost {
   std::vector<WorkItem> items;
   std::vector<int> order;       // item indices, queue by queue
   std::vector<int> qbeg;        // nq + 1 offsets into order
-  // slow pass of the two-threshold search
+  // boundary-slot tables: of the slow approximations (two-threshold search)
+  // or of the fine ones (refine)
   std::vector<SlowTmpl> slow;
   std::vector<uint32_t> slot_off;
   std::vector<double> slot_c;
@@ -325,21 +326,36 @@ void plan_direct(const sncc_tmpl *tm, int t, int P, PlanHost &ph, DevTmpl &d) {
   ps.iv_begin = ps.iv_end = (int)ph.ivs.size();
   ps.seg_begin = (int)ph.recs.size();
   const std::vector<Seg> &segs = tm->segs[t];
-  for (size_t q = 0; q < segs.size(); ++q) {
-    const Seg &g = segs[q];
+  auto push = [&](int top, int bot, int area, float c) {
     DirectRec dr;
-    dr.tl = (g.y * P + g.x) * 4;
-    dr.bl = ((g.y + g.h) * P + g.x) * 4;
-    dr.w4 = g.w * 4;
-    dr.area = (int)g.area;
-    dr.c = (float)tm->c64[t][q];
-    dr.pad[0] = dr.pad[1] = dr.pad[2] = 0;
+    dr.top = top;
+    dr.bot = bot;
+    dr.area = area;
+    dr.c = c;
+    dr.pad[0] = dr.pad[1] = dr.pad[2] = dr.pad[3] = 0;
     TileRec two[2];
     static_assert(sizeof(two) == sizeof(DirectRec), "a direct record spans two slots");
     memcpy(two, &dr, sizeof dr);
     ph.recs.push_back(two[0]);
     ph.recs.push_back(two[1]);
+  };
+  // one record per boundary column of each horizontal chain: the column's
+  // entries in the chain's top and bottom rows, and A_i, c_i of the segment
+  // ending there (0 at the chain's first column)
+  int nrec = 0;
+  for (const std::vector<int> &pc : horizontal_chains(segs, 1 << 30)) {
+    const Seg &g0 = segs[pc[0]];
+    const int top = g0.y * P, bot = (g0.y + g0.h) * P;
+    push((top + g0.x) * 4, (bot + g0.x) * 4, 0, 0.f);
+    ++nrec;
+    for (int q : pc) {
+      const int x = segs[q].x + segs[q].w;
+      push((top + x) * 4, (bot + x) * 4, (int)segs[q].area, (float)tm->c64[t][q]);
+      ++nrec;
+    }
   }
+  // padded to whole groups of four with records that add exactly zero
+  for (; nrec % 4 != 0; ++nrec) push(0, 0, 0, 0.f);
   ps.seg_end = (int)ph.recs.size();
   ph.passes.push_back(ps);
   d.pass_end = (int)ph.passes.size();
@@ -519,19 +535,19 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int P, int n_pairs,
   return SNCC_OK;
 }
 
-// Boundary-slot tables of the slow approximations for the staged slow pass
-// (see SlowTmpl), for runs of the tile shape `tc`; templates whose region
-// does not fit kSlowRegionWords are scored from the global tables.
-void plan_slow(const sncc_tmpl *slow, const TileCfg &tc, PlanHost &ph) {
-  ph.slow.assign(slow->T, SlowTmpl{-1, 0, 0, 0});
+// Boundary-slot tables (see SlowTmpl) of a template set for runs of
+// span_u x span_v offsets: a template whose region, (span_v + H) rows of
+// span_u + W + 1 words, exceeds max_words keeps tbl = -1 (global form).
+void plan_slots(const sncc_tmpl *tm, int span_u, int span_v, int max_words, PlanHost &ph) {
+  ph.slow.assign(tm->T, SlowTmpl{-1, 0, 0, 0});
   ph.slot_off.clear();
   ph.slot_c.clear();
   ph.slow_lds = 0;
-  for (int t = 0; t < slow->T; ++t) {
-    const int W = slow->W[t], H = slow->H[t];
-    const int pitch = tc.bu() + W + 1, rows = tc.rv + H;
-    if ((long long)pitch * rows > kSlowRegionWords) continue;
-    const std::vector<Seg> &segs = slow->segs[t];
+  for (int t = 0; t < tm->T; ++t) {
+    const int W = tm->W[t], H = tm->H[t];
+    const int pitch = span_u + W + 1, rows = span_v + H;
+    if ((long long)pitch * rows > max_words) continue;
+    const std::vector<Seg> &segs = tm->segs[t];
     std::vector<std::vector<int>> pieces = horizontal_chains(segs, kSlowChainMax);
     // pieces in raster order of their first segment: a wave's slots then
     // read nearby rows
@@ -561,7 +577,7 @@ void plan_slow(const sncc_tmpl *slow, const TileCfg &tc, PlanHost &ph) {
       ph.slot_c.push_back(0.0);
       for (int i : pc) {
         ph.slot_off.push_back(slot(segs[i].x + segs[i].w));
-        ph.slot_c.push_back(slow->c64[t][i]);
+        ph.slot_c.push_back(tm->c64[t][i]);
       }
       fill += need;
     }
@@ -573,6 +589,12 @@ void plan_slow(const sncc_tmpl *slow, const TileCfg &tc, PlanHost &ph) {
     ph.slow[t] = st;
     ph.slow_lds = std::max(ph.slow_lds, pitch * rows * 4);
   }
+}
+
+// Slot tables of the slow approximations for the slow pass, whose runs are
+// one wave's part of a tile of shape `tc`, and the run capacity.
+void plan_slow(const sncc_tmpl *slow, const TileCfg &tc, PlanHost &ph) {
+  plan_slots(slow, tc.bu(), tc.rv, kSlowRegionWords, ph);
   long long tiles = 0;
   for (const WorkItem &it : ph.items) tiles += it.tile_end - it.tile_begin;
   ph.run_cap = (int)std::min<long long>(tiles * tc.nw, 1 << 30);
@@ -601,13 +623,18 @@ struct PlanDev {
     CHK(d_queue.reserve(zero_ints() * sizeof(int)));
     if (h.sink == kSinkTopk)
       CHK(d_partial.reserve(std::max<size_t>(16, h.items.size() * h.k * 8)));
-    if (h.sink == kSinkCompact) {
+    if (!h.slow.empty()) {
       CHK(d_slow.upload(h.slow, st));
       CHK(d_slot_off.upload(h.slot_off, st));
       CHK(d_slot_c.upload(h.slot_c, st));
-      CHK(d_runs.reserve(std::max<size_t>(16, (size_t)h.run_cap * sizeof(RunDesc))));
     }
+    if (h.sink == kSinkCompact)
+      CHK(d_runs.reserve(std::max<size_t>(16, (size_t)h.run_cap * sizeof(RunDesc))));
     return SNCC_OK;
+  }
+  SlotTables slots() {
+    return SlotTables{d_slow.as<SlowTmpl>(), d_slot_off.as<uint32_t>(), d_slot_c.as<double>(),
+                      h.slow_lds};
   }
   // work counters, then one floor key per pair (top-k sink) or the run and
   // slow-pass counters (compacting sink), zeroed per launch
@@ -1237,10 +1264,14 @@ int sncc_refine(sncc_ctx *ctx, const sncc_tmpl *fine, const uint32_t *d_s, const
     q.nv = N - fine->H[t] + 1;
   }
   CHK(pd->d_pairs.upload(h.pairs, ctx->stream));
+  plan_slots(fine, kRefineSpanU, kRefineSpanV, kRefineRegionWords, h);
+  CHK(pd->d_slow.upload(h.slow, ctx->stream));
+  CHK(pd->d_slot_off.upload(h.slot_off, ctx->stream));
+  CHK(pd->d_slot_c.upload(h.slot_c, ctx->stream));
   if (launch_refine(d_s, d_s2, (long long)(N + 1) * sat_pitch, sat_pitch,
                     fine->d_dev.as<DevTmpl>(), fine->d_geom.as<int4>(), fine->d_c64.as<double>(),
-                    fine->d_area.as<int>(), pd->d_pairs.as<PairDesc>(), n_pairs, d_cand, n_cand,
-                    radius, d_out, d_count, ctx->stream) != 0)
+                    pd->slots(), pd->d_pairs.as<PairDesc>(), n_pairs, d_cand, n_cand, radius,
+                    d_out, d_count, ctx->stream) != 0)
     SNCC_FAIL(SNCC_EDEVICE, "refine launch: %s", hipGetErrorString(hipGetLastError()));
   return retire(ctx, std::move(pd));
 }
@@ -1383,8 +1414,8 @@ int enqueue_stage(sncc_batch *b, int stage, hipStream_t st) {
     case 3:
       if (d.fine &&
           launch_refine(d.d_s, d.d_s2, fs, d.sat_pitch, d.fine->d_dev.as<DevTmpl>(),
-                        d.fine->d_geom.as<int4>(), d.fine->d_c64.as<double>(),
-                        d.fine->d_area.as<int>(), pd.d_pairs.as<PairDesc>(), d.n_pairs, d.d_topk,
+                        d.fine->d_geom.as<int4>(), d.fine->d_c64.as<double>(), pd.slots(),
+                        pd.d_pairs.as<PairDesc>(), d.n_pairs, d.d_topk,
                         d.k, d.radius, d.d_best, d.d_count, st) != 0)
         SNCC_FAIL(SNCC_EDEVICE, "refine launch");
       return SNCC_OK;
@@ -1601,6 +1632,7 @@ int sncc_batch_create(sncc_ctx *ctx, const sncc_batch_desc *desc, sncc_batch **o
   b->plan.reset(new PlanDev());
   CHK(build_plan(d.coarse, cfg, d.M, d.N, d.sat_pitch, d.n_pairs, b->pairs.data(), d.k, kSinkTopk,
                  ctx->num_cu, b->plan->h));
+  if (d.fine) plan_slots(d.fine, kRefineSpanU, kRefineSpanV, kRefineRegionWords, b->plan->h);
   CHK(b->plan->upload(ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
 

@@ -491,136 +491,6 @@ int launch_map_topk(const double *map, int pitch, int nu, int nv, int chunk, int
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// ------------------------------------------------------------- FP64 refine
-constexpr int REFINE_CAP = 4096;
-
-__global__ __launch_bounds__(256) void refine_kernel(
-    const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
-    int P, const DevTmpl *__restrict__ tmpls, const int4 *__restrict__ geom,
-    const double *__restrict__ c64, const PairDesc *__restrict__ pairs,
-    const sncc_match *__restrict__ cand, int n_cand, int radius,
-    sncc_match64 *__restrict__ out, int *__restrict__ count) {
-  __shared__ int list[REFINE_CAP];
-  __shared__ int wsum[4];
-  __shared__ double best_r[4];
-  __shared__ int best_i[4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int p = blockIdx.x;
-  const PairDesc pd = pairs[p];
-  const DevTmpl td = tmpls[pd.tmpl];
-  const int side = 2 * radius + 1, area = side * side;
-  const int total = n_cand * area;
-  int np = 1;
-  while (np < total) np <<= 1;
-  // candidate neighbourhoods, clipped; INT_MAX marks an empty slot
-  for (int e = tid; e < np; e += 256) {
-    int val = 0x7fffffff;
-    if (e < total) {
-      const int j = e / area, d = e - j * area;
-      const sncc_match c = cand[(long long)p * n_cand + j];
-      const int u = c.u + d % side - radius, v = c.v + d / side - radius;
-      if (c.u >= 0 && u >= 0 && u < pd.nu && v >= 0 && v < pd.nv) val = v * pd.nu + u;
-    }
-    list[e] = val;
-  }
-  __syncthreads();
-  // bitonic sort ascending
-  for (int size = 2; size <= np; size <<= 1)
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = tid; i < np; i += 256) {
-        const int j = i ^ stride;
-        if (j > i) {
-          const int a = list[i], b = list[j];
-          const bool up = (i & size) == 0;
-          if ((a > b) == up) {
-            list[i] = b;
-            list[j] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  // unique values: each thread owns a contiguous run of the sorted list
-  const int per = (np + 255) / 256;
-  const int r0 = min(np, tid * per), r1 = min(np, r0 + per);
-  int cnt = 0;
-  for (int i = r0; i < r1; ++i)
-    if (list[i] != 0x7fffffff && (i == 0 || list[i] != list[i - 1])) ++cnt;
-  const uint32_t incl = wave_incl_scan((uint32_t)cnt);
-  if (lane == 63) wsum[wave] = (int)incl;
-  __syncthreads();
-  int off = (int)incl - cnt;
-  for (int w = 0; w < wave; ++w) off += wsum[w];
-  const int L = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-  // gather unique entries into registers before compacting in place
-  int mine[16];
-  int m = 0;
-  for (int i = r0; i < r1 && m < 16; ++i)
-    if (list[i] != 0x7fffffff && (i == 0 || list[i] != list[i - 1])) mine[m++] = list[i];
-  __syncthreads();
-  for (int q = 0; q < m; ++q) list[off + q] = mine[q];
-  __syncthreads();
-  // FP64 scores with the fine approximation
-  const uint32_t *S = s + (long long)pd.frame * frame_stride;
-  const uint32_t *S2 = s2 + (long long)pd.frame * frame_stride;
-  double br = -__builtin_inf();
-  int bi = 0x7fffffff;
-  for (int i = tid; i < L; i += 256) {
-    const int idx = list[i];
-    const int v = idx / pd.nu, u = idx - v * pd.nu;
-    bool flat;
-    const double r = rho_plain(S, S2, P, u, v, td.W, td.H, td.K, td.sq_rows, td.q_k, td.r64,
-                               geom + td.seg_off, c64 + td.seg_off, flat);
-    if (r > br || (r == br && idx < bi)) {
-      br = r;
-      bi = idx;
-    }
-  }
-  for (int msk = 32; msk >= 1; msk >>= 1) {
-    const double orr = __shfl_xor(br, msk);
-    const int oi = __shfl_xor(bi, msk);
-    if (orr > br || (orr == br && oi < bi)) {
-      br = orr;
-      bi = oi;
-    }
-  }
-  if (lane == 0) {
-    best_r[wave] = br;
-    best_i[wave] = bi;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int w = 1; w < 4; ++w)
-      if (best_r[w] > br || (best_r[w] == br && best_i[w] < bi)) {
-        br = best_r[w];
-        bi = best_i[w];
-      }
-    sncc_match64 o;
-    if (L == 0) {
-      o.u = -1;
-      o.v = -1;
-      o.rho = -__builtin_inf();
-    } else {
-      o.v = bi / pd.nu;
-      o.u = bi - o.v * pd.nu;
-      o.rho = br;
-    }
-    out[p] = o;
-    if (count) count[p] = L;
-  }
-}
-
-int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride, int P,
-                  const DevTmpl *tmpls, const int4 *geom, const double *c64, const int *area,
-                  const PairDesc *pairs, int n_pairs, const sncc_match *cand, int n_cand,
-                  int radius, sncc_match64 *out, int *count, hipStream_t st) {
-  (void)area;
-  if (n_cand * (2 * radius + 1) * (2 * radius + 1) > REFINE_CAP) return -1;
-  hipLaunchKernelGGL(refine_kernel, dim3(n_pairs), dim3(256), 0, st, s, s2, frame_stride,
-                     P, tmpls, geom, c64, pairs, cand, n_cand, radius, out, count);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
 // --------------------------------------------------- two-threshold search
 // Section 5, steps 7g-j for the offsets that passed the fast test: rho with
 // the slow approximation in FP64, appended to the output when it reaches the
@@ -735,6 +605,69 @@ __device__ __forceinline__ double slow_rho(double acc, uint32_t sf, u64 sf2, con
   return V == 0 ? 0.0 : num / sqrt((double)V / (double)td.n * td.q_k);
 }
 
+// FP64 rho (Eqs. (12), (13), (15)-(18)) of four windows of one template
+// whose table entries are staged in LDS: base[j] is the region byte offset
+// of window j's top-left entry (row pitch `pitch` words), gof[j] its byte
+// offset in the global tables (for the f^2 sums).  Lanes run over the
+// template's boundary slots (see SlowTmpl), two 64-slot blocks per step with
+// the next step's slot entries requested ahead; per slot and window two LDS
+// reads give the column difference D, the lane below holds the previous
+// boundary's D, and c_i (D - D_prev) is added to the lane's FP64 sum.  Lane l
+// returns the rho of window l mod 4.
+__device__ __forceinline__ double staged_rho4(const uint32_t *region, int pitch,
+                                              const int (&base)[4], const int (&gof)[4],
+                                              __amdgpu_buffer_rsrc_t rso,
+                                              __amdgpu_buffer_rsrc_t rsc, int n_iter,
+                                              __amdgpu_buffer_rsrc_t rs2, int P4,
+                                              const DevTmpl &td, int lane) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  auto block = [&](uint32_t o, double c) {
+    const int top = (int)(o & 0xffffu), bot = (int)(o >> 16);
+    uint32_t D[4], Dp[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) D[j] = lds_at(region, base[j] + bot) - lds_at(region, base[j] + top);
+    // the previous boundary's difference (row_shr:1), kept separate moves:
+    // folded into the subtraction as v_subrev_u32_dpp it came out negated
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      Dp[j] = (uint32_t)__builtin_amdgcn_mov_dpp((int)D[j], 0x111, 0xf, 0xf, true);
+    asm volatile("" : "+v"(Dp[0]), "+v"(Dp[1]), "+v"(Dp[2]), "+v"(Dp[3]));
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = __builtin_fma((double)(D[j] - Dp[j]), c, acc[j]);
+  };
+  auto load_o = [&](int i) {
+    return __builtin_amdgcn_raw_buffer_load_b32(rso, lane * 4, min(i, n_iter - 1) * 256, 0);
+  };
+  auto load_c = [&](int i) {
+    return __builtin_bit_cast(
+        double, __builtin_amdgcn_raw_buffer_load_b64(rsc, lane * 8, min(i, n_iter - 1) * 512, 0));
+  };
+  uint32_t o0 = load_o(0), o1 = load_o(1);
+  double c0 = load_c(0), c1 = load_c(1);
+  int it = 0;
+  for (; it + 2 <= n_iter; it += 2) {
+    const uint32_t n0 = load_o(it + 2), n1 = load_o(it + 3);
+    const double m0 = load_c(it + 2), m1 = load_c(it + 3);
+    block(o0, c0);
+    block(o1, c1);
+    o0 = n0;
+    o1 = n1;
+    c0 = m0;
+    c1 = m1;
+  }
+  if (it < n_iter) block(o0, c0);
+  const double sum = wave_sum4_f64(acc[0], acc[1], acc[2], acc[3], lane);
+  const int jj = lane & 3;
+  const int q = jj == 0 ? base[0] : jj == 1 ? base[1] : jj == 2 ? base[2] : base[3];
+  const int g = jj == 0 ? gof[0] : jj == 1 ? gof[1] : jj == 2 ? gof[2] : gof[3];
+  const int qh = q + td.H * pitch * 4, w4 = td.W * 4;
+  const uint32_t sf = (lds_at(region, qh + w4) - lds_at(region, qh)) -
+                      (lds_at(region, q + w4) - lds_at(region, q));  // Eq. (13)
+  const u64 sf2 = window_sq(rs2, g, 0, w4, P4, td.H, td.sq_rows);  // Eq. (15)
+  return slow_rho(sum, sf, sf2, td);
+}
+
+
 // Kernel arguments are restrict-qualified pointers (not an argument block)
 // so that wave-uniform descriptor and segment reads become scalar loads.
 __global__ __launch_bounds__(256) void slow_kernel(
@@ -794,69 +727,21 @@ __global__ __launch_bounds__(256) void slow_kernel(
       const __amdgpu_buffer_rsrc_t rso = make_rsrc(slot_off + st.tbl, (uint32_t)st.n_iter * 256u);
       const __amdgpu_buffer_rsrc_t rsc = make_rsrc(slot_c + st.tbl, (uint32_t)st.n_iter * 512u);
       for (int b = start + wave * kSlowBatch; b < end; b += 4 * kSlowBatch) {
-        int su[kSlowBatch], sv[kSlowBatch], base[kSlowBatch];  // base: region bytes
+        int su[kSlowBatch], sv[kSlowBatch], base[kSlowBatch], gof[kSlowBatch];
 #pragma unroll
         for (int j = 0; j < kSlowBatch; ++j) {
           const sncc_hit h = cand[min(b + j, end - 1)];
           su[j] = h.u;
           sv[j] = h.v;
           base[j] = ((h.v - rd.v0) * st.pitch + (h.u - rd.u0)) * 4;
+          gof[j] = h.v * P4 + h.u * 4;
         }
-        double acc[kSlowBatch];
-#pragma unroll
-        for (int j = 0; j < kSlowBatch; ++j) acc[j] = 0.0;
-        // one block of 64 slots for the batch's survivors
-        auto block = [&](uint32_t o, double c) {
-          const int top = (int)(o & 0xffffu), bot = (int)(o >> 16);
-          uint32_t D[kSlowBatch], Dp[kSlowBatch];
-#pragma unroll
-          for (int j = 0; j < kSlowBatch; ++j)
-            D[j] = lds_at(region, base[j] + bot) - lds_at(region, base[j] + top);
-          // the previous boundary's difference (row_shr:1), kept separate moves:
-          // folded into the subtraction as v_subrev_u32_dpp it came out negated
-#pragma unroll
-          for (int j = 0; j < kSlowBatch; ++j)
-            Dp[j] = (uint32_t)__builtin_amdgcn_mov_dpp((int)D[j], 0x111, 0xf, 0xf, true);
-          asm volatile("" : "+v"(Dp[0]), "+v"(Dp[1]), "+v"(Dp[2]), "+v"(Dp[3]));
-#pragma unroll
-          for (int j = 0; j < kSlowBatch; ++j)
-            acc[j] = __builtin_fma((double)(D[j] - Dp[j]), c, acc[j]);
-        };
-        auto load_o = [&](int i) {
-          return __builtin_amdgcn_raw_buffer_load_b32(rso, lane * 4, min(i, st.n_iter - 1) * 256, 0);
-        };
-        auto load_c = [&](int i) {
-          return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                                rsc, lane * 8, min(i, st.n_iter - 1) * 512, 0));
-        };
-        // two blocks per step; the next step's slot entries are requested
-        // before this step's are used
-        uint32_t o0 = load_o(0), o1 = load_o(1);
-        double c0 = load_c(0), c1 = load_c(1);
-        int it = 0;
-        for (; it + 2 <= st.n_iter; it += 2) {
-          const uint32_t n0 = load_o(it + 2), n1 = load_o(it + 3);
-          const double m0 = load_c(it + 2), m1 = load_c(it + 3);
-          block(o0, c0);
-          block(o1, c1);
-          o0 = n0;
-          o1 = n1;
-          c0 = m0;
-          c1 = m1;
-        }
-        if (it < st.n_iter) block(o0, c0);
-        // lane j < kSlowBatch finishes survivor b + j: its sum, then rho
-        // (Eqs. (12), (13), (15)-(18)) in FP64
-        const double sum = wave_sum4_f64(acc[0], acc[1], acc[2], acc[3], lane);
+        // lane j < kSlowBatch holds survivor b + j
+        const double rho =
+            staged_rho4(region, st.pitch, base, gof, rso, rsc, st.n_iter, rs2, P4, td, lane);
         const int jj = lane & 3;
-        const int q = jj == 0 ? base[0] : jj == 1 ? base[1] : jj == 2 ? base[2] : base[3];
         const int uu = jj == 0 ? su[0] : jj == 1 ? su[1] : jj == 2 ? su[2] : su[3];
         const int vv = jj == 0 ? sv[0] : jj == 1 ? sv[1] : jj == 2 ? sv[2] : sv[3];
-        const int qh = q + td.H * st.pitch * 4, w4 = td.W * 4;
-        const uint32_t sf = (lds_at(region, qh + w4) - lds_at(region, qh)) -
-                            (lds_at(region, q + w4) - lds_at(region, q));  // Eq. (13)
-        const u64 sf2 = window_sq(rs2, (vv * P + uu) * 4, 0, w4, P4, td.H, td.sq_rows);
-        const double rho = slow_rho(sum, sf, sf2, td);
         if (lane < kSlowBatch && b + lane < end && rho >= thr) emit(rd.pair, uu, vv, rho);
       }
     } else if (start < end) {
@@ -888,6 +773,256 @@ int launch_slow(const SlowArgs &a, int grid, int lds_bytes, hipStream_t st) {
                      a.frame_stride, a.P, a.N, a.tmpls, a.geom, a.c64, a.stmpl, a.slot_off,
                      a.slot_c, a.pairs, a.thr, a.cand, a.cand_count, a.cand_cap, a.runs,
                      a.run_count, a.run_cap, a.work, a.out, a.out_cap, a.out_count);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ------------------------------------------------------------- FP64 refine
+// Section 5, steps 7f-i with the coarse pass's top-k as candidates: rho in
+// FP64 with the fine approximation at every offset within `radius` of a
+// candidate, and the best of them (rho descending, then v, then u).  One
+// workgroup per pair: the candidates' neighbourhoods are listed in LDS by a
+// key that orders offsets in column bands of 16 (band, v, u), sorted
+// (bitonic) and made unique.  The unique offsets are then scored in chunks
+// of at most kRefineChunk consecutive entries spanning at most kRefineSpanU
+// columns and kRefineSpanV rows, each from a staged region of the frame's
+// table, four offsets per wave at a time (staged_rho4); for templates whose
+// region does not fit LDS, one offset per thread from the global tables
+// (rho_plain).
+constexpr int REFINE_CAP = 4096;
+constexpr int kRefineChunk = 32;  // entries per chunk: two batches of four per wave
+
+__global__ __launch_bounds__(256) void refine_kernel(
+    const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
+    int P, const DevTmpl *__restrict__ tmpls, const int4 *__restrict__ geom,
+    const double *__restrict__ c64, const SlowTmpl *__restrict__ stmpl,
+    const uint32_t *__restrict__ slot_off, const double *__restrict__ slot_c,
+    const PairDesc *__restrict__ pairs, const sncc_match *__restrict__ cand, int n_cand,
+    int radius, int N, sncc_match64 *__restrict__ out, int *__restrict__ count) {
+  __shared__ uint32_t first[REFINE_CAP / 32];  // bit i: entry i starts a chunk
+  __shared__ int wsum[4];
+  __shared__ double best_r[4];
+  __shared__ int best_i[4];
+  extern __shared__ uint32_t dyn[];  // the offset list (np ints), then the region
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int p = blockIdx.x;
+  const PairDesc pd = pairs[p];
+  const DevTmpl td = tmpls[pd.tmpl];
+  const SlowTmpl st = stmpl[pd.tmpl];
+  const int side = 2 * radius + 1, area = side * side;
+  const int total = n_cand * area;
+  const int band_keys = pd.nv * 16;  // keys per column band
+  int np = 1;
+  while (np < total) np <<= 1;
+  int *const list = reinterpret_cast<int *>(dyn);
+  uint32_t *const region = dyn + np;
+  // candidate neighbourhoods, clipped; INT_MAX marks an empty slot
+  for (int e = tid; e < np; e += 256) {
+    int val = 0x7fffffff;
+    if (e < total) {
+      const int j = e / area, d = e - j * area;
+      const sncc_match c = cand[(long long)p * n_cand + j];
+      const int u = c.u + d % side - radius, v = c.v + d / side - radius;
+      if (c.u >= 0 && u >= 0 && u < pd.nu && v >= 0 && v < pd.nv)
+        val = (u >> 4) * band_keys + v * 16 + (u & 15);
+    }
+    list[e] = val;
+  }
+  __syncthreads();
+  // bitonic sort ascending
+  for (int size = 2; size <= np; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < np; i += 256) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const int a = list[i], b = list[j];
+          const bool up = (i & size) == 0;
+          if ((a > b) == up) {
+            list[i] = b;
+            list[j] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  // unique values: each thread owns a contiguous run of the sorted list
+  const int per = (np + 255) / 256;
+  const int r0 = min(np, tid * per), r1 = min(np, r0 + per);
+  int cnt = 0;
+  for (int i = r0; i < r1; ++i)
+    if (list[i] != 0x7fffffff && (i == 0 || list[i] != list[i - 1])) ++cnt;
+  const uint32_t incl = wave_incl_scan((uint32_t)cnt);
+  if (lane == 63) wsum[wave] = (int)incl;
+  __syncthreads();
+  int off = (int)incl - cnt;
+  for (int w = 0; w < wave; ++w) off += wsum[w];
+  const int L = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  // gather unique entries into registers before compacting in place
+  int mine[16];
+  int m = 0;
+  for (int i = r0; i < r1 && m < 16; ++i)
+    if (list[i] != 0x7fffffff && (i == 0 || list[i] != list[i - 1])) mine[m++] = list[i];
+  __syncthreads();
+  for (int q = 0; q < m; ++q) list[off + q] = mine[q];
+  __syncthreads();
+  // FP64 scores with the fine approximation, chunk by chunk
+  const uint32_t *S = s + (long long)pd.frame * frame_stride;
+  const uint32_t *S2 = s2 + (long long)pd.frame * frame_stride;
+  const uint32_t bytes = (uint32_t)(frame_stride * 4);
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(S, bytes);
+  const __amdgpu_buffer_rsrc_t rs2 = make_rsrc(S2, bytes);
+  const int P4 = P * 4;
+  auto decode = [&](int key, int &u, int &v) {
+    const int band = key / band_keys, rem = key - band * band_keys;
+    v = rem >> 4;
+    u = band * 16 + (rem & 15);
+  };
+  double br = -__builtin_inf();
+  int bi = 0x7fffffff;
+  auto offer = [&](double r, int idx) {
+    if (r > br || (r == br && idx < bi)) {
+      br = r;
+      bi = idx;
+    }
+  };
+  if (st.tbl < 0) {  // region too large for LDS: one offset per thread
+    for (int i = tid; i < L; i += 256) {
+      int u, v;
+      decode(list[i], u, v);
+      bool flat;
+      const double r = rho_plain(S, S2, P, u, v, td.W, td.H, td.K, td.sq_rows, td.q_k, td.r64,
+                                 geom + td.seg_off, c64 + td.seg_off, flat);
+      offer(r, v * pd.nu + u);
+    }
+  }
+  // chunks: runs of at most kRefineChunk consecutive entries whose offsets
+  // span at most kRefineSpanU columns and kRefineSpanV rows, cut greedily in
+  // list order (one thread; the list holds at most a few hundred entries)
+  for (int i = tid; i < REFINE_CAP / 32; i += 256) first[i] = 0;
+  __syncthreads();
+  if (tid == 0) {
+    int c0 = 0, umin = 0, umax = 0, vmin = 0, vmax = 0;
+    for (int i = 0; i < L; ++i) {
+      int u, v;
+      decode(list[i], u, v);
+      if (i == c0 || i - c0 == kRefineChunk || max(umax, u) - min(umin, u) >= kRefineSpanU ||
+          max(vmax, v) - min(vmin, v) >= kRefineSpanV) {
+        first[i >> 5] |= 1u << (i & 31);
+        c0 = i;
+        umin = umax = u;
+        vmin = vmax = v;
+      } else {
+        umin = min(umin, u);
+        umax = max(umax, u);
+        vmin = min(vmin, v);
+        vmax = max(vmax, v);
+      }
+    }
+  }
+  __syncthreads();
+  auto chunk_end = [&](int c0) {  // the next chunk's first entry, or L
+    for (int i = c0 + 1; i < L;) {
+      const uint32_t w = first[i >> 5] >> (i & 31);
+      if (w) return min(L, i + __builtin_ctz(w));
+      i = (i | 31) + 1;
+    }
+    return L;
+  };
+  for (int c0 = 0; st.tbl >= 0 && c0 < L;) {
+    const int c1 = __builtin_amdgcn_readfirstlane(chunk_end(c0));
+    const int n = c1 - c0;
+    int umin = 0x7fffffff, umax = -1, vmin = 0x7fffffff, vmax = -1;
+    for (int i = 0; i < n; ++i) {  // every thread, same values
+      int u, v;
+      decode(list[c0 + i], u, v);
+      umin = min(umin, u);
+      umax = max(umax, u);
+      vmin = min(vmin, v);
+      vmax = max(vmax, v);
+    }
+    umin = __builtin_amdgcn_readfirstlane(umin);
+    umax = __builtin_amdgcn_readfirstlane(umax);
+    vmin = __builtin_amdgcn_readfirstlane(vmin);
+    vmax = __builtin_amdgcn_readfirstlane(vmax);
+    // the entries the chunk's windows read: rows [vmin, vmax + H], columns
+    // [umin, umax + W] of the table, at the region's pitch
+    const int nrow = vmax - vmin + td.H + 1, ncol = umax - umin + td.W + 1;
+    for (int row = wave; row < nrow; row += 4) {
+      const int gy = min(vmin + row, N);
+      for (int c = lane; c < ncol; c += 64) {
+        const int gx = min(umin + c, P - 1);
+        region[row * st.pitch + c] =
+            __builtin_amdgcn_raw_buffer_load_b32(rs, (gy * P + gx) * 4, 0, 0);
+      }
+    }
+    __syncthreads();
+    const __amdgpu_buffer_rsrc_t rso = make_rsrc(slot_off + st.tbl, (uint32_t)st.n_iter * 256u);
+    const __amdgpu_buffer_rsrc_t rsc = make_rsrc(slot_c + st.tbl, (uint32_t)st.n_iter * 512u);
+    for (int e0 = wave * 4; e0 < n; e0 += 16) {  // four entries per wave
+      int su[4], sv[4], base[4], gof[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        decode(list[c0 + min(e0 + j, n - 1)], su[j], sv[j]);
+        base[j] = ((sv[j] - vmin) * st.pitch + (su[j] - umin)) * 4;
+        gof[j] = sv[j] * P4 + su[j] * 4;
+      }
+      // lane j < 4 holds entry c0 + e0 + j
+      const double r =
+          staged_rho4(region, st.pitch, base, gof, rso, rsc, st.n_iter, rs2, P4, td, lane);
+      const int jj = lane & 3;
+      const int uu = jj == 0 ? su[0] : jj == 1 ? su[1] : jj == 2 ? su[2] : su[3];
+      const int vv = jj == 0 ? sv[0] : jj == 1 ? sv[1] : jj == 2 ? sv[2] : sv[3];
+      if (lane < 4 && e0 + lane < n) offer(r, vv * pd.nu + uu);
+    }
+    __syncthreads();  // the region is rewritten for the next chunk
+    c0 = c1;
+  }
+  for (int msk = 32; msk >= 1; msk >>= 1) {
+    const double orr = __shfl_xor(br, msk);
+    const int oi = __shfl_xor(bi, msk);
+    if (orr > br || (orr == br && oi < bi)) {
+      br = orr;
+      bi = oi;
+    }
+  }
+  if (lane == 0) {
+    best_r[wave] = br;
+    best_i[wave] = bi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 4; ++w)
+      if (best_r[w] > br || (best_r[w] == br && best_i[w] < bi)) {
+        br = best_r[w];
+        bi = best_i[w];
+      }
+    sncc_match64 o;
+    if (L == 0) {
+      o.u = -1;
+      o.v = -1;
+      o.rho = -__builtin_inf();
+    } else {
+      o.v = bi / pd.nu;
+      o.u = bi - o.v * pd.nu;
+      o.rho = br;
+    }
+    out[p] = o;
+    if (count) count[p] = L;
+  }
+}
+
+int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride, int P,
+                  const DevTmpl *tmpls, const int4 *geom, const double *c64,
+                  const SlotTables &slots, const PairDesc *pairs, int n_pairs,
+                  const sncc_match *cand, int n_cand, int radius, sncc_match64 *out, int *count,
+                  hipStream_t st) {
+  const int total = n_cand * (2 * radius + 1) * (2 * radius + 1);
+  if (total > REFINE_CAP) return -1;
+  int np = 1;
+  while (np < total) np <<= 1;
+  const int N = (int)(frame_stride / P) - 1;
+  hipLaunchKernelGGL(refine_kernel, dim3(n_pairs), dim3(256), np * 4 + slots.lds_bytes, st, s, s2,
+                     frame_stride, P, tmpls, geom, c64, slots.tmpl, slots.off, slots.c, pairs,
+                     cand, n_cand, radius, N, out, count);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

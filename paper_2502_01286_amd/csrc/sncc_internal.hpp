@@ -57,13 +57,15 @@ struct TileRec {
   float c;
 };
 
-// One segment for the tile kernel's direct form (corners read from the
-// global table, no LDS): byte offsets of the top-left and bottom-left
-// corners relative to the window's top-left entry, 4 W_i, A_i and c_i.
+// One boundary column of a horizontal chain for the tile kernel's direct
+// form (entries read from the global table, no LDS): byte offsets of the
+// column's entries in the chain's top and bottom rows relative to the
+// window's top-left entry, and A_i, c_i of the segment ending at this column
+// (0, 0 for the chain's first column).  Two TileRec slots.
 struct DirectRec {
-  int tl, bl, w4, area;
+  int top, bot, area;
   float c;
-  int pad[3];
+  int pad[4];
 };
 
 // Rows [rel_row, rel_row + n_rows) of the window (template-relative,
@@ -145,6 +147,22 @@ struct SlowTmpl {
 constexpr int kSlowRegionWords = 13312;  // 52 KB: three workgroups per CU
 static_assert(kSlowRegionWords * 4 <= 65536, "slot byte offsets are 16-bit");
 constexpr int kSlowChainMax = 15;        // segments per chain piece (16 slots)
+
+// The refine kernel scores its offsets in chunks of 16 (in column bands of
+// 16): a chunk whose offsets span at most kRefineSpanU columns and
+// kRefineSpanV rows is scored from a staged region like the slow pass's, of
+// (kRefineSpanV + H) rows of kRefineSpanU + W + 1 words.
+constexpr int kRefineSpanU = 16, kRefineSpanV = 8;
+constexpr int kRefineRegionWords = 12288;  // 48 KB beside the 16 KB offset list
+static_assert(kRefineRegionWords * 4 <= 65536, "slot byte offsets are 16-bit");
+
+// Device view of a template set's slot tables.
+struct SlotTables {
+  const SlowTmpl *tmpl;
+  const uint32_t *off;
+  const double *c;
+  int lds_bytes;  // largest region of a staged template (0: none)
+};
 
 struct SlowArgs {
   const uint32_t *s;
@@ -283,7 +301,7 @@ int launch_map_topk(const double *map, int pitch, int nu, int nv, int chunk,
                     int k, unsigned long long *partial, hipStream_t st);
 int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride,
                   int sat_pitch, const DevTmpl *tmpls, const int4 *geom,
-                  const double *c64, const int *area, const PairDesc *pairs,
+                  const double *c64, const SlotTables &slots, const PairDesc *pairs,
                   int n_pairs, const sncc_match *cand, int n_cand, int radius,
                   sncc_match64 *out, int *count, hipStream_t st);
 

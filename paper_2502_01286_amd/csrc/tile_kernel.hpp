@@ -175,12 +175,17 @@ __device__ __forceinline__ void run_item(
     }
 
     if constexpr (LP == 0) {
-      // direct form: corners from the global table through buffer loads with
-      // the segment's corner offsets as scalar offsets; same arithmetic as
-      // the staged form, four segments per compensated step
+      // direct form: the template's horizontal chains from the global table,
+      // one record per boundary column (see plan_direct): buffer loads with
+      // the column's top and bottom entries as scalar offsets give its
+      // difference D; a segment's F_i (Eq. (11)) is D minus the previous
+      // column's D, then the staged form's arithmetic, four records per
+      // compensated step (first columns add A = c = 0; the list is padded
+      // to whole groups with records that add zero).  The next record's
+      // entries are requested before the current record's are used
       const PassDesc ps = passes[td.pass_begin];
       const DirectRec *dp = reinterpret_cast<const DirectRec *>(recs + ps.seg_begin);
-      const int nseg = (ps.seg_end - ps.seg_begin) >> 1;
+      const int nrec = (ps.seg_end - ps.seg_begin) >> 1;
       int vb[R];
 #pragma unroll
       for (int dv = 0; dv < RV; ++dv)
@@ -190,31 +195,34 @@ __device__ __forceinline__ void run_item(
           const int vc = min(v0 + wave * RV + dv, pd.nv - 1);
           vb[dv * RU + du] = (vc * P + uc) * 4;
         }
-      for (int i = 0; i < nseg; i += 4) {
+      uint32_t at[R], ab[R], nt[R], nbt[R], dprev[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) dprev[r] = 0;
+      auto column = [&](const DirectRec &e, uint32_t(&ct)[R], uint32_t(&cb)[R]) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          ct[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], e.top, 0);
+          cb[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], e.bot, 0);
+        }
+      };
+      if (nrec > 0) column(dp[0], at, ab);
+      for (int i = 0; i < nrec; i += 4) {
         float y[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) y[r] = -cmp[r];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          if (i + q < nseg) {
-            const DirectRec e = dp[i + q];
-            const int tr = e.tl + e.w4, br = e.bl + e.w4;
-            // all corners of the segment first, so that the loads of the
-            // lane's R offsets are in flight together
-            uint32_t a00[R], a01[R], a10[R], a11[R];
+          const DirectRec e = dp[i + q];
+          column(dp[min(i + q + 1, nrec - 1)], nt, nbt);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-              a00[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], e.tl, 0);
-              a01[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], tr, 0);
-              a10[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], e.bl, 0);
-              a11[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, vb[r], br, 0);
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-              const uint32_t F = (a11[r] - a10[r]) - (a01[r] - a00[r]);  // Eq. (11)
-              const int G = (int)F + __mul24(e.area, nb[r]);
-              y[r] = __builtin_fmaf((float)G, e.c, y[r]);
-            }
+          for (int r = 0; r < R; ++r) {
+            const uint32_t D = ab[r] - at[r];
+            const uint32_t F = D - dprev[r];  // Eq. (11)
+            dprev[r] = D;
+            const int G = (int)F + __mul24(e.area, nb[r]);
+            y[r] = __builtin_fmaf((float)G, e.c, y[r]);
+            at[r] = nt[r];
+            ab[r] = nbt[r];
           }
         }
 #pragma unroll
