@@ -789,7 +789,7 @@ int launch_slow(const SlowArgs &a, int grid, int lds_bytes, hipStream_t st) {
 // region does not fit LDS, one offset per thread from the global tables
 // (rho_plain).
 constexpr int REFINE_CAP = 4096;
-constexpr int kRefineChunk = 32;  // entries per chunk: two batches of four per wave
+constexpr int kRefineChunk = 64;  // entries per chunk: up to four batches of four per wave
 
 __global__ __launch_bounds__(256) void refine_kernel(
     const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
