@@ -412,14 +412,21 @@ __global__ __launch_bounds__(256) void merge_kernel(const PairDesc *__restrict__
   if (p >= n_pairs) return;
   const PairDesc pd = pairs[p];
   u64 lkey = 0, thr = 0;
-  for (int item = pd.item_begin; item < pd.item_end; ++item) {
-    const u64 mine = lane < k ? partial[(long long)item * k + lane] : 0;
-    for (int j = 0; j < k; ++j) {
-      const u64 key = lane_u64(mine, j);
-      if (key <= thr) break;
-      topk_insert(lkey, key, k, lane);
-      thr = lane_u64(lkey, k - 1);
-    }
+  // one load brings the partial lists of g = 64 / k items (lane l holds key
+  // l mod k of item l / k), so the load latency is paid once per g items
+  const int g = 64 / k;
+  for (int item = pd.item_begin; item < pd.item_end; item += g) {
+    const int mi = item + lane / k;
+    const u64 mine =
+        lane < g * k && mi < pd.item_end ? partial[(long long)mi * k + lane % k] : 0;
+    const int gi = min(g, pd.item_end - item);
+    for (int q = 0; q < gi; ++q)
+      for (int j = 0; j < k; ++j) {  // each item's list is in descending order
+        const u64 key = lane_u64(mine, q * k + j);
+        if (key <= thr) break;
+        topk_insert(lkey, key, k, lane);
+        thr = lane_u64(lkey, k - 1);
+      }
   }
   if (lane < k) {
     sncc_match m;
