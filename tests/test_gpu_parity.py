@@ -290,9 +290,18 @@ def test_topk_repeated_calls_match_fresh_contexts(S, ctx):
 
 
 # ------------------------------------------------------------------ refine
-def test_refine_parity(S, ctx):
+@pytest.mark.parametrize("case", ["default", "large_fine", "radius3"])
+def test_refine_parity(S, ctx, case):
+    """FP64 refine against the oracle's coarse-fine.  `large_fine` adds a
+    130 x 100 template, whose chunk region exceeds the LDS budget (scored from
+    the global tables); `radius3` uses +-3 px neighbourhoods."""
     import torch
-    frames, temps, _, pairs = _multi(70, sigmas=(16, 16, 16, 16))
+    if case == "large_fine":
+        frames, temps, _, pairs = _multi(71, B=2, M=300, N=220, sides=((24, 30), (130, 100)),
+                                         sigmas=(16, 16))
+    else:
+        frames, temps, _, pairs = _multi(70, sigmas=(16, 16, 16, 16))
+    print("case", case, flush=True)
     B, N, M = len(frames), frames[0].shape[0], frames[0].shape[1]
     coarse_s, fine_s = [16] * len(temps), [4] * len(temps)
     _, s, s2 = build_sats(S, ctx, frames)
@@ -300,7 +309,7 @@ def test_refine_parity(S, ctx):
     tas_c = oracle_templates(temps, coarse_s)
     tas_f = oracle_templates(temps, fine_s)
     tables = [O.sum_tables(f) for f in frames]
-    k, radius = 8, 2
+    k, radius = 8, (3 if case == "radius3" else 2)
     # candidates from the oracle's coarse pass, given to both sides as input
     cand = np.zeros((len(pairs), k, 3), np.int32)
     expected = []
