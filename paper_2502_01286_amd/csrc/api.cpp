@@ -361,9 +361,20 @@ void plan_direct(const sncc_tmpl *tm, int t, int P, PlanHost &ph, DevTmpl &d) {
   d.pass_end = (int)ph.passes.size();
 }
 
+// Split of a pair's tile columns between two launches: when the last
+// column of main_bu-wide tiles holds at most main_bu / 2 offsets, the main
+// launch (kSplitMain) leaves it out and a launch of half-width tiles
+// (kSplitEdge) scores it alone.
+constexpr int kSplitNone = 0, kSplitMain = 1, kSplitEdge = 2;
+
+bool has_edge(int nu, int main_bu) {
+  const int r = nu % main_bu;
+  return r > 0 && r <= main_bu / 2;
+}
+
 int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int P, int n_pairs,
                const int32_t *pairs, int k, int sink, int num_cu, PlanHost &ph,
-               const double *thr = nullptr) {
+               const double *thr = nullptr, int split = kSplitNone, int main_bu = 0) {
   if (cfg < 0 || cfg >= tile_cfg_count()) SNCC_FAIL(SNCC_EINVAL, "bad tile config %d", cfg);
   ph = PlanHost();
   ph.cfg = cfg;
@@ -443,14 +454,22 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int P, int n_pairs,
     pd.nv = N - tm->H[t] + 1;
     pd.ntu = (pd.nu + bu - 1) / bu;
     pd.ntv = (pd.nv + bv - 1) / bv;
+    pd.u_base = 0;
+    if (split == kSplitMain && has_edge(pd.nu, bu)) pd.ntu = pd.nu / bu;
+    if (split == kSplitEdge) {
+      pd.u_base = pd.nu / main_bu * main_bu;
+      pd.ntu = has_edge(pd.nu, main_bu) ? 1 : 0;
+    }
     const double staged = (double)(bu + tm->W[t] + 1) * (double)(bv + tm->H[t] + 1);
     tile_cost[p] = (double)bu * bv * (tm->K[t] + 8.0) + 0.5 * staged;
     total += tile_cost[p] * pd.ntu * pd.ntv;
-    ph.coarse_evals += (int64_t)pd.nu * pd.nv * tm->K[t];
+    if (split != kSplitEdge) {  // the split's evaluations are counted once, by the main plan
+      ph.coarse_evals += (int64_t)pd.nu * pd.nv * tm->K[t];
+      ph.n_offsets += (int64_t)pd.nu * pd.nv;
+    }
     ph.computed_evals += (int64_t)pd.ntu * bu * pd.ntv * bv * tm->K[t];
-    ph.n_offsets += (int64_t)pd.nu * pd.nv;
   }
-  const double target = total / (slots * 6.0);
+  const double target = std::max(total, 1.0) / (slots * 6.0);
   std::vector<double> item_cost;
   ph.order.clear();
   if (tc.frame_major) {
@@ -468,7 +487,7 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int P, int n_pairs,
     for (int p = 0; p < n_pairs; ++p) {
       PairDesc &pd = ph.pairs[p];
       pd.item_begin = (int)ph.items.size();
-      for (int b = 0; b * band_tiles < pd.ntv; ++b) {
+      for (int b = 0; pd.ntu > 0 && b * band_tiles < pd.ntv; ++b) {
         const int t0 = b * band_tiles * pd.ntu;
         const int t1 = std::min(pd.ntv, (b + 1) * band_tiles) * pd.ntu;
         const int ntiles = t1 - t0;
@@ -511,11 +530,12 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int P, int n_pairs,
     for (int p = 0; p < n_pairs; ++p) {
       PairDesc &pd = ph.pairs[p];
       const int ntiles = pd.ntu * pd.ntv;
+      pd.item_begin = pd.item_end = (int)ph.items.size();
+      if (ntiles == 0) continue;
       int per = (int)std::max(1.0, std::floor(target / tile_cost[p]));
       per = std::min(per, ntiles);
       const int nitems = (ntiles + per - 1) / per;
       per = (ntiles + nitems - 1) / nitems;  // even out
-      pd.item_begin = (int)ph.items.size();
       for (int a = 0; a < ntiles; a += per) {
         WorkItem it{p, a, std::min(ntiles, a + per), 0};
         ph.items.push_back(it);
@@ -1161,7 +1181,8 @@ int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uin
     if (launch_tile(pd->h.cfg, kSinkTopk, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0)
       SNCC_FAIL(SNCC_EDEVICE, "top-k launch: %s", hipGetErrorString(hipGetLastError()));
     ctx->mark(1);
-    if (launch_merge(pd->d_pairs.as<PairDesc>(), n_pairs, a.partial, k, d_out, ctx->stream) != 0)
+    if (launch_merge(pd->d_pairs.as<PairDesc>(), nullptr, n_pairs, a.partial, nullptr, k, d_out,
+                     ctx->stream) != 0)
       SNCC_FAIL(SNCC_EDEVICE, "top-k launch: %s", hipGetErrorString(hipGetLastError()));
     ctx->mark(2);
     if (ctx->timing) ctx->n_stages = 2;
@@ -1220,7 +1241,8 @@ int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uin
                         ctx->stream) != 0)
       SNCC_FAIL(SNCC_EDEVICE, "plain top-k launch: %s", hipGetErrorString(hipGetLastError()));
   }
-  if (launch_merge(pd->d_pairs.as<PairDesc>(), n_pairs, partial, k, d_out, ctx->stream) != 0)
+  if (launch_merge(pd->d_pairs.as<PairDesc>(), nullptr, n_pairs, partial, nullptr, k, d_out,
+                   ctx->stream) != 0)
     SNCC_FAIL(SNCC_EDEVICE, "merge launch: %s", hipGetErrorString(hipGetLastError()));
   return retire(ctx, std::move(pd));
 }
@@ -1371,6 +1393,7 @@ struct sncc_batch {
   sncc_batch_desc d{};
   std::vector<int32_t> pairs;
   std::unique_ptr<PlanDev> plan;
+  std::unique_ptr<PlanDev> edge;  // narrow last tile columns (second scoring launch)
   DevBuf sat_scratch;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -1406,9 +1429,21 @@ int enqueue_stage(sncc_batch *b, int stage, hipStream_t st) {
       if (launch_zero(a.queue, a.n_zero, st) != 0 ||
           launch_tile(pd.h.cfg, kSinkTopk, a, pd.h.grid, pd.h.lds_bytes, st) != 0)
         SNCC_FAIL(SNCC_EDEVICE, "scoring launch");
+      if (b->edge) {
+        // the last columns start from the floors the main launch published
+        PlanDev &pe = *b->edge;
+        TileArgs ae = pe.args(d.d_s, d.d_s2, fs, d.sat_pitch, d.M, d.N);
+        ae.pair_floor = a.pair_floor;
+        if (launch_zero(ae.queue, kQueueInts, st) != 0 ||
+            launch_tile(pe.h.cfg, kSinkTopk, ae, pe.h.grid, pe.h.lds_bytes, st) != 0)
+          SNCC_FAIL(SNCC_EDEVICE, "scoring launch (last columns)");
+      }
       return SNCC_OK;
     case 2:
-      if (launch_merge(pd.d_pairs.as<PairDesc>(), d.n_pairs, a.partial, d.k, d.d_topk, st) != 0)
+      if (launch_merge(pd.d_pairs.as<PairDesc>(),
+                       b->edge ? b->edge->d_pairs.as<PairDesc>() : nullptr, d.n_pairs, a.partial,
+                       b->edge ? b->edge->d_partial.as<unsigned long long>() : nullptr, d.k,
+                       d.d_topk, st) != 0)
         SNCC_FAIL(SNCC_EDEVICE, "merge launch");
       return SNCC_OK;
     case 3:
@@ -1629,11 +1664,31 @@ int sncc_batch_create(sncc_ctx *ctx, const sncc_batch_desc *desc, sncc_batch **o
       write_cache(d.tune_cache, key, cfg);
     }
   }
+  // a second launch of half-width tiles for last tile columns that are at
+  // most half full, when the chosen shape has a half-width twin
+  const TileCfg main_tc = tile_cfg(cfg);
+  int edge_cfg = -1;
+  for (int c = 0; c < tile_cfg_count() && main_tc.ru == 2; ++c) {
+    const TileCfg t = tile_cfg(c);
+    if (t.ru == 1 && t.rv == main_tc.rv && t.nw == main_tc.nw && t.wgs == main_tc.wgs &&
+        t.frame_major == main_tc.frame_major)
+      edge_cfg = c;
+  }
+  bool any_edge = false;
+  for (int p = 0; p < d.n_pairs && edge_cfg >= 0; ++p)
+    any_edge |= has_edge(d.M - d.coarse->W[b->pairs[2 * p + 1]] + 1, main_tc.bu());
+  const int split = any_edge ? kSplitMain : kSplitNone;
   b->plan.reset(new PlanDev());
   CHK(build_plan(d.coarse, cfg, d.M, d.N, d.sat_pitch, d.n_pairs, b->pairs.data(), d.k, kSinkTopk,
-                 ctx->num_cu, b->plan->h));
+                 ctx->num_cu, b->plan->h, nullptr, split));
   if (d.fine) plan_slots(d.fine, kRefineSpanU, kRefineSpanV, kRefineRegionWords, b->plan->h);
   CHK(b->plan->upload(ctx->stream));
+  if (any_edge) {
+    b->edge.reset(new PlanDev());
+    CHK(build_plan(d.coarse, edge_cfg, d.M, d.N, d.sat_pitch, d.n_pairs, b->pairs.data(), d.k,
+                   kSinkTopk, ctx->num_cu, b->edge->h, nullptr, kSplitEdge, main_tc.bu()));
+    CHK(b->edge->upload(ctx->stream));
+  }
   HIPCHK(hipStreamSynchronize(ctx->stream));
 
   HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
@@ -1660,11 +1715,11 @@ int sncc_batch_stats_get(sncc_batch *b, sncc_batch_stats *st) {
   const PlanHost &h = b->plan->h;
   memset(st, 0, sizeof *st);
   st->coarse_evals = h.coarse_evals;
-  st->computed_evals = h.computed_evals;
+  st->computed_evals = h.computed_evals + (b->edge ? b->edge->h.computed_evals : 0);
   st->n_passes = h.n_passes;
   st->n_offsets = h.n_offsets;
-  st->work_items = (int64_t)h.items.size();
-  st->n_launch_classes = 1;
+  st->work_items = (int64_t)h.items.size() + (b->edge ? (int64_t)b->edge->h.items.size() : 0);
+  st->n_launch_classes = b->edge ? 2 : 1;
   st->tile_u = h.tc.bu();
   st->tile_v = h.tc.bv();
   st->wg_threads = h.tc.threads();

@@ -403,9 +403,14 @@ int launch_zero(int *p, int n, hipStream_t st) {
 }
 
 // One wave per pair: merges the pair's item partials into the final top-k.
+// Per pair, the k best of its items' partial lists: the items of `pairs`
+// in `partial` and, when a second launch scored the pair's last tile
+// column, those of `pairs2` in `partial2`.
 __global__ __launch_bounds__(256) void merge_kernel(const PairDesc *__restrict__ pairs,
+                                                    const PairDesc *__restrict__ pairs2,
                                                     int n_pairs,
-                                                    const u64 *__restrict__ partial, int k,
+                                                    const u64 *__restrict__ partial,
+                                                    const u64 *__restrict__ partial2, int k,
                                                     sncc_match *__restrict__ out) {
   const int lane = threadIdx.x & 63;
   const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -415,18 +420,24 @@ __global__ __launch_bounds__(256) void merge_kernel(const PairDesc *__restrict__
   // one load brings the partial lists of g = 64 / k items (lane l holds key
   // l mod k of item l / k), so the load latency is paid once per g items
   const int g = 64 / k;
-  for (int item = pd.item_begin; item < pd.item_end; item += g) {
-    const int mi = item + lane / k;
-    const u64 mine =
-        lane < g * k && mi < pd.item_end ? partial[(long long)mi * k + lane % k] : 0;
-    const int gi = min(g, pd.item_end - item);
-    for (int q = 0; q < gi; ++q)
-      for (int j = 0; j < k; ++j) {  // each item's list is in descending order
-        const u64 key = lane_u64(mine, q * k + j);
-        if (key <= thr) break;
-        topk_insert(lkey, key, k, lane);
-        thr = lane_u64(lkey, k - 1);
-      }
+  auto merge_items = [&](const u64 *part, int ib, int ie) {
+    for (int item = ib; item < ie; item += g) {
+      const int mi = item + lane / k;
+      const u64 mine = lane < g * k && mi < ie ? part[(long long)mi * k + lane % k] : 0;
+      const int gi = min(g, ie - item);
+      for (int q = 0; q < gi; ++q)
+        for (int j = 0; j < k; ++j) {  // each item's list is in descending order
+          const u64 key = lane_u64(mine, q * k + j);
+          if (key <= thr) break;
+          topk_insert(lkey, key, k, lane);
+          thr = lane_u64(lkey, k - 1);
+        }
+    }
+  };
+  merge_items(partial, pd.item_begin, pd.item_end);
+  if (pairs2) {
+    const PairDesc pe = pairs2[p];
+    merge_items(partial2, pe.item_begin, pe.item_end);
   }
   if (lane < k) {
     sncc_match m;
@@ -444,10 +455,10 @@ __global__ __launch_bounds__(256) void merge_kernel(const PairDesc *__restrict__
   }
 }
 
-int launch_merge(const PairDesc *pairs, int n_pairs, const u64 *partial, int k,
-                 sncc_match *out, hipStream_t st) {
-  hipLaunchKernelGGL(merge_kernel, dim3((n_pairs + 3) / 4), dim3(256), 0, st, pairs,
-                     n_pairs, partial, k, out);
+int launch_merge(const PairDesc *pairs, const PairDesc *pairs2, int n_pairs, const u64 *partial,
+                 const u64 *partial2, int k, sncc_match *out, hipStream_t st) {
+  hipLaunchKernelGGL(merge_kernel, dim3((n_pairs + 3) / 4), dim3(256), 0, st, pairs, pairs2,
+                     n_pairs, partial, partial2, k, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -93,6 +93,8 @@ struct PairDesc {
   int nu, nv;              // offsets along u and v
   int ntu, ntv;            // tiles along u and v
   int item_begin, item_end;
+  int u_base;              // column of the first tile column (nonzero for the
+                           // narrow last column a second launch scores)
 };
 
 struct WorkItem {
@@ -294,9 +296,9 @@ int tile_max_lds();
 int tile_occupancy(int cfg, int sink, int lds_bytes);
 int launch_plain(const PlainArgs &a, hipStream_t st);
 int launch_zero(int *p, int n, hipStream_t st);
-int launch_merge(const PairDesc *pairs, int n_pairs,
-                 const unsigned long long *partial, int k,
-                 sncc_match *out, hipStream_t st);
+int launch_merge(const PairDesc *pairs, const PairDesc *pairs2, int n_pairs,
+                 const unsigned long long *partial, const unsigned long long *partial2,
+                 int k, sncc_match *out, hipStream_t st);
 int launch_map_topk(const double *map, int pitch, int nu, int nv, int chunk,
                     int k, unsigned long long *partial, hipStream_t st);
 int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride,

@@ -114,7 +114,7 @@ __device__ __forceinline__ void run_item(
 
   for (int tile = it.tile_begin; tile < it.tile_end; ++tile) {
     const int tv = tile / pd.ntu, tu = tile - tv * pd.ntu;
-    const int u0 = tu * BU, v0 = tv * BV;
+    const int u0 = pd.u_base + tu * BU, v0 = tv * BV;
 
     // the first pass's rows are requested before the prologue's loads so
     // that both latencies overlap
