@@ -556,31 +556,6 @@ __device__ __forceinline__ double slow_sum(__amdgpu_buffer_rsrc_t rs, int voff, 
   return acc;
 }
 
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_f64(double x) {
-  const u64 b = (u64)__double_as_longlong(x);
-  const uint32_t lo =
-      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROW_MASK, 0xf, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL,
-                                                            ROW_MASK, 0xf, false);
-  return __longlong_as_double((long long)(((u64)hi << 32) | lo));
-}
-
-// Sum of x over the wave, wave-uniform: an inclusive DPP scan (shifts
-// within rows of 16 lanes, then the row broadcasts) read at lane 63.
-__device__ __forceinline__ double wave_total_f64(double x) {
-  x += dpp_f64<0x111, 0xf>(x);
-  x += dpp_f64<0x112, 0xf>(x);
-  x += dpp_f64<0x114, 0xf>(x);
-  x += dpp_f64<0x118, 0xf>(x);
-  x += dpp_f64<0x142, 0xa>(x);
-  x += dpp_f64<0x143, 0xc>(x);
-  const u64 b = (u64)__double_as_longlong(x);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
-  return __longlong_as_double((long long)(((u64)hi << 32) | lo));
-}
-
 template <int CTRL>
 __device__ __forceinline__ double dpp_full_f64(double x) {  // every lane has a source
   const u64 b = (u64)__double_as_longlong(x);
