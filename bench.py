@@ -65,10 +65,11 @@ def kernel_source_hash():
 
 
 def load_traffic(workload):
-    """HBM bytes per scoring launch from the committed rocprofv3 --pmc summary
-    (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
-    copy kernel of known size), or None when it was taken on another kernel
-    source.  The summary is text: `key: value` lines, `#` comments."""
+    """HBM bytes of the scoring stage (its launches of tile_kernel) from the
+    committed rocprofv3 --pmc summary (FETCH_SIZE and WRITE_SIZE, each scaled
+    by what the counter reads for a copy kernel of known size), or None when
+    it was taken on another kernel source.  The summary is text: `key: value`
+    lines, `#` comments."""
     path = os.path.join(ROOT, "profiles", f"tile_kernel_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -82,7 +83,7 @@ def load_traffic(workload):
     if d.get("kernel_sources_sha256_16") != kernel_source_hash():
         return None
     try:
-        return int(d["bytes_per_launch"])
+        return int(d.get("scoring_stage_bytes", d["bytes_per_launch"]))
     except (KeyError, ValueError):
         return None
 
@@ -507,7 +508,9 @@ def main():
         roof = {"bound": "alu", "achieved": round(ops_tops, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "TOP/s (VALU lane ops)", "frac": round(ops_tops / VALU_PEAK_TOPS, 4),
                 "traffic": load_traffic(args.workload),
-                "kernel": "tile_kernel (scoring)", "kernel_ms": round(avg["ms_score"], 4),
+                "kernel": "tile_kernel (scoring stage: %d launch%s)"
+                          % (st["n_launch_classes"], "es" if st["n_launch_classes"] > 1 else ""),
+                "kernel_ms": round(avg["ms_score"], 4),
                 "ops_per_eval": OPS_PER_EVAL, "evals_per_launch": evals,
                 "lds": {"achieved_TBps": round(lds_tbs, 3), "peak_TBps": round(LDS_PEAK_TBS, 2),
                         "frac": round(lds_tbs / LDS_PEAK_TBS, 4), "bytes_per_eval": 16}}
