@@ -336,11 +336,23 @@ def test_refine_parity(S, ctx, case):
 
 
 # ------------------------------------------------------------------ batches
-def test_batch_graph_parity_and_replays(S, ctx):
+@pytest.mark.parametrize("case", ["mixed", "narrow"])
+def test_batch_graph_parity_and_replays(S, ctx, case):
+    """One graph-captured batch replayed three times, against the oracle.
+    Both cases have pairs whose last column of 128-wide tiles holds at most
+    64 offsets (scored by the second launch); in `narrow` a 150 px template
+    on 200 px frames leaves 51 offset columns, so its pairs have no tiles in
+    the main launch at all."""
     import torch
-    frames, temps, _, pairs = _multi(90, B=4, M=320, N=200,
-                                     sides=((24, 24), (40, 30), (64, 48), (33, 70), (90, 41)),
-                                     sigmas=(16, 16, 16, 16, 16))
+    if case == "narrow":
+        frames, temps, _, pairs = _multi(91, B=3, M=200, N=150,
+                                         sides=((150, 40), (70, 30), (24, 24)),
+                                         sigmas=(16, 16, 16))
+    else:
+        frames, temps, _, pairs = _multi(90, B=4, M=320, N=200,
+                                         sides=((24, 24), (40, 30), (64, 48), (33, 70), (90, 41)),
+                                         sigmas=(16, 16, 16, 16, 16))
+    print("case", case, flush=True)
     B, N, M = len(frames), frames[0].shape[0], frames[0].shape[1]
     k, radius = 16, 2
     f = torch.from_numpy(np.stack(frames)).cuda()
@@ -369,6 +381,7 @@ def test_batch_graph_parity_and_replays(S, ctx):
         assert torch.equal(a, results[0][0]) and torch.equal(b, results[0][1])
     st = batch.stats()
     assert st["coarse_evals"] > 0 and st["ms_total"] != 0
+    assert st["n_launch_classes"] == 2
     got = S.decode_matches(results[0][0])
     gbest = S.decode_matches64(results[0][1])
     for p, (b, ti) in enumerate(pairs):
