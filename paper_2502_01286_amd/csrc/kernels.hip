@@ -55,10 +55,36 @@ size_t sat_scratch_words(int B, int M, int N) {
   return (size_t)2 * B * (nTY * (size_t)M + (size_t)N * nTX + 2 * nTY * nTX);
 }
 
+// Pixels x0 .. x0 + 3 of a row (0 beyond M): one 32-bit load when all four
+// are inside the row and the address is 4-byte aligned, else byte loads.
 __device__ __forceinline__ void load_px4(const uint8_t *row, int x0, int M,
                                          uint32_t (&v)[4]) {
+  if (x0 + 3 < M && ((reinterpret_cast<uintptr_t>(row + x0) & 3) == 0)) {
+    const uint32_t w = *reinterpret_cast<const uint32_t *>(row + x0);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) v[q] = (x0 + q < M) ? (uint32_t)row[x0 + q] : 0u;
+    for (int q = 0; q < 4; ++q) v[q] = (w >> (8 * q)) & 0xffu;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = (x0 + q < M) ? (uint32_t)row[x0 + q] : 0u;
+  }
+}
+
+// Entries x0 .. x0 + 3 of a table row (up to column M): one 16-byte store
+// when all four are inside (the row's entries are 4-byte aligned, which a
+// multi-dword global store needs), else dword stores.
+__device__ __forceinline__ void store_4(uint32_t *o, int x0, int M, const uint32_t (&w)[4]) {
+  if (x0 + 3 < M) {
+    uint4 q4;
+    q4.x = w[0];
+    q4.y = w[1];
+    q4.z = w[2];
+    q4.w = w[3];
+    __builtin_memcpy(o + x0, &q4, 16);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (x0 + q < M) o[x0 + q] = w[q];
+  }
 }
 
 __global__ __launch_bounds__(64) void sat_totals(const uint8_t *__restrict__ f,
@@ -213,13 +239,14 @@ __global__ __launch_bounds__(64) void sat_scan(const uint8_t *__restrict__ f,
     const uint32_t base2 = (uint32_t)__builtin_amdgcn_readlane((int)L2, r) + ex2;
     uint32_t *o = sb + (size_t)(y + 1) * P + 1;
     uint32_t *o2 = s2b + (size_t)(y + 1) * P + 1;
+    uint32_t w[4], w2[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (x0 + q < M) {
-        o[x0 + q] = base + p[q];
-        o2[x0 + q] = base2 + p2[q];
-      }
+      w[q] = base + p[q];
+      w2[q] = base2 + p2[q];
     }
+    store_4(o, x0, M, w);
+    store_4(o2, x0, M, w2);
     if (J == 0 && lane == 0) {  // padded column 0
       sb[(size_t)(y + 1) * P] = 0;
       s2b[(size_t)(y + 1) * P] = 0;
