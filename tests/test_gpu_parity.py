@@ -342,7 +342,7 @@ def test_batch_graph_parity_and_replays(S, ctx, case):
     Both cases have pairs whose last column of 128-wide tiles holds at most
     64 offsets (scored by the second launch); in `narrow` a 150 px template
     on 200 px frames leaves 51 offset columns, so its pairs have no tiles in
-    the main launch at all."""
+    the main launch at all (and k = 64, radius 1)."""
     import torch
     if case == "narrow":
         frames, temps, _, pairs = _multi(91, B=3, M=200, N=150,
@@ -354,7 +354,7 @@ def test_batch_graph_parity_and_replays(S, ctx, case):
                                          sigmas=(16, 16, 16, 16, 16))
     print("case", case, flush=True)
     B, N, M = len(frames), frames[0].shape[0], frames[0].shape[1]
-    k, radius = 16, 2
+    k, radius = (64, 1) if case == "narrow" else (16, 2)   # k = 64: one item per merge load
     f = torch.from_numpy(np.stack(frames)).cuda()
     P = S.sncc_sat_pitch(M)
     s = torch.zeros((B, N + 1, P), dtype=torch.int32, device="cuda")
