@@ -255,14 +255,18 @@ int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index,
  * the match is the offset with the highest rho).  Ordering: higher rho
  * first, ties to the smaller v, then smaller u; no suppression of
  * neighbours.  SNCC_FP32_KAHAN runs every pair in one persistent launch
- * over a cost-ordered work list; SNCC_FP64 runs one launch per pair.
+ * over a cost-ordered work list; SNCC_FP64 runs one launch per pair.  The
+ * context keeps the FP32 form's work list of its last call on the device and
+ * reuses it when the next call has the same template set, sizes, pitch, k
+ * and pairs (calls on one context are ordered by its stream).
  *
  *   d_s, d_s2  sum tables of B frames (layout of sncc_build_sats)
  *   pairs      host, n_pairs x {frame, template}
  *   k          1 .. 64
  *   d_out      device, n_pairs x k matches; slots beyond the number of
  *              offsets get u = v = -1, rho = -infinity
- * Errors: SNCC_EINVAL, SNCC_EDEVICE, SNCC_ENOMEM.
+ * Errors: SNCC_EINVAL (also a frame table above SNCC_MAX_TABLE_BYTES),
+ *         SNCC_EDEVICE, SNCC_ENOMEM.
  */
 int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s,
               const uint32_t *d_s2, int B, int M, int N, int sat_pitch,
@@ -316,9 +320,13 @@ int sncc_refine(sncc_ctx *ctx, const sncc_tmpl *fine, const uint32_t *d_s,
  *   d_counts     device, 2 int32: survivors and matches found; either may
  *                exceed its capacity, and entries beyond it are not written
  *                (the slow pass then sees only the first cand_cap survivors)
- * Entries come in no particular order.
- * Errors: SNCC_EINVAL (NULL, sizes, thresholds, capacities < 1, alignment),
- *         SNCC_EDEVICE, SNCC_ENOMEM.
+ * Entries come in no particular order.  The context keeps the work list of
+ * its last call (with the slow pass's tables) on the device and reuses it
+ * when the next call has the same template sets, sizes, pitch, pairs and
+ * thresholds.
+ * Errors: SNCC_EINVAL (NULL, sizes, thresholds, capacities < 1, alignment,
+ *         a frame table above SNCC_MAX_TABLE_BYTES), SNCC_EDEVICE,
+ *         SNCC_ENOMEM.
  */
 int sncc_threshold_match(sncc_ctx *ctx, const sncc_tmpl *fast, const sncc_tmpl *slow,
                          const double *thr_fast, const double *thr_slow,
