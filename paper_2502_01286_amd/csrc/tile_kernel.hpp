@@ -278,11 +278,13 @@ __device__ __forceinline__ void run_item(
         }
     } else if (SINK == kSinkCompact) {
       // offsets whose rho reaches the template's threshold are appended to
-      // the survivor list with one atomic per wave, ordered by (du, dv) slot
-      // and then by lane, so that neighbouring entries are neighbouring
-      // offsets of one row; the wave's entries form one run
+      // the survivor list with one atomic per wave, ordered by du, then dv,
+      // then lane, so that neighbouring entries are neighbouring offsets of
+      // one row; the wave's entries of each 64-column half (du) form a run
       u64 m[R];
-      int total = 0;
+      int cnt[RU];
+#pragma unroll
+      for (int du = 0; du < RU; ++du) cnt[du] = 0;
 #pragma unroll
       for (int dv = 0; dv < RV; ++dv)
 #pragma unroll
@@ -291,30 +293,42 @@ __device__ __forceinline__ void run_item(
           const int u = u0 + lane + 64 * du, v = v0 + wave * RV + dv;
           acc[r] = (acc[r] - cmp[r]) * my_sc[r * NW * 64];  // acc now holds rho
           m[r] = __ballot(u < pd.nu && v < pd.nv && acc[r] >= td.thr);
-          total += __popcll(m[r]);
+          cnt[du] += __popcll(m[r]);
         }
+      int total = 0, n_runs = 0;
+#pragma unroll
+      for (int du = 0; du < RU; ++du) {
+        total += cnt[du];
+        n_runs += cnt[du] > 0;
+      }
       if (total > 0) {
         int base = 0;
         if (lane == 0) {
           base = atomicAdd(co.count, total);
-          const int ri = atomicAdd(co.run_count, 1);
-          if (ri < co.run_cap) {
-            RunDesc rd;
-            rd.start = base;
-            rd.count = total;
-            rd.pair = it.pair;
-            rd.u0 = u0;
-            rd.v0 = v0 + wave * RV;
-            rd.pad[0] = rd.pad[1] = rd.pad[2] = 0;
-            co.runs[ri] = rd;
+          int ri = atomicAdd(co.run_count, n_runs);
+          int start = base;
+#pragma unroll
+          for (int du = 0; du < RU; ++du) {
+            if (cnt[du] > 0 && ri < co.run_cap) {
+              RunDesc rd;
+              rd.start = start;
+              rd.count = cnt[du];
+              rd.pair = it.pair;
+              rd.u0 = u0 + 64 * du;
+              rd.v0 = v0 + wave * RV;
+              rd.pad[0] = rd.pad[1] = rd.pad[2] = 0;
+              co.runs[ri] = rd;
+            }
+            ri += cnt[du] > 0;
+            start += cnt[du];
           }
         }
         int pos = __builtin_amdgcn_readfirstlane(base);
         const u64 below = (1ull << lane) - 1ull;
 #pragma unroll
-        for (int dv = 0; dv < RV; ++dv)
+        for (int du = 0; du < RU; ++du)
 #pragma unroll
-          for (int du = 0; du < RU; ++du) {
+          for (int dv = 0; dv < RV; ++dv) {
             const int r = dv * RU + du;
             if ((m[r] >> lane) & 1ull) {
               const int at = pos + __popcll(m[r] & below);
