@@ -612,13 +612,13 @@ void plan_slots(const sncc_tmpl *tm, int span_u, int span_v, int max_words, Plan
 }
 
 // Slot tables of the slow approximations for the slow pass, whose runs are
-// one wave's part of a 64-column half of a tile of shape `tc`, and the run
+// one wave's part of kRunCols columns of a tile of shape `tc`, and the run
 // capacity.
 void plan_slow(const sncc_tmpl *slow, const TileCfg &tc, PlanHost &ph) {
-  plan_slots(slow, 64, tc.rv, kSlowRegionWords, ph);
+  plan_slots(slow, kRunCols, tc.rv, kSlowRegionWords, ph);
   long long tiles = 0;
   for (const WorkItem &it : ph.items) tiles += it.tile_end - it.tile_begin;
-  ph.run_cap = (int)std::min<long long>(tiles * tc.nw * tc.ru, 1 << 30);
+  ph.run_cap = (int)std::min<long long>(tiles * tc.nw * tc.ru * (64 / kRunCols), 1 << 30);
 }
 
 }  // namespace

@@ -109,10 +109,11 @@ constexpr int kSinkTopk = 0;
 constexpr int kSinkMap = 1;
 constexpr int kSinkCompact = 2;
 
-// A run of the survivor list: the survivors one wave found in one 64-column
-// half of a tile, written together at hits[start, start + count) (entries at
-// or beyond the list's capacity were not written).  They lie in offset rows
-// [v0, v0 + RV) and columns [u0, u0 + 64) of pair `pair`.
+// A run of the survivor list: the survivors one wave found in one group of
+// kRunCols columns of a tile, written together at hits[start, start + count)
+// (entries at or beyond the list's capacity were not written).  They lie in
+// offset rows [v0, v0 + RV) and columns [u0, u0 + kRunCols) of pair `pair`.
+constexpr int kRunCols = 32;
 struct RunDesc {
   int start, count, pair, u0, v0;
   int pad[3];
@@ -144,8 +145,8 @@ struct SlowTmpl {
   int rows;    // region rows
 };
 
-// Region of a run: rows [v0, v0 + RV + H), columns [u0, u0 + 64 + W] of the
-// frame's table; at most this many words.
+// Region of a run: rows [v0, v0 + RV + H), columns [u0, u0 + kRunCols + W]
+// of the frame's table; at most this many words.
 constexpr int kSlowRegionWords = 13312;  // 52 KB
 static_assert(kSlowRegionWords * 4 <= 65536, "slot byte offsets are 16-bit");
 constexpr int kSlowChainMax = 15;        // segments per chain piece (16 slots)

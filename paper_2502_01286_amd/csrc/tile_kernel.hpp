@@ -278,13 +278,16 @@ __device__ __forceinline__ void run_item(
         }
     } else if (SINK == kSinkCompact) {
       // offsets whose rho reaches the template's threshold are appended to
-      // the survivor list with one atomic per wave, ordered by du, then dv,
-      // then lane, so that neighbouring entries are neighbouring offsets of
-      // one row; the wave's entries of each 64-column half (du) form a run
+      // the survivor list with one atomic per wave, ordered by column group
+      // (du, then kRunCols lanes at a time), then dv, then lane, so that
+      // neighbouring entries are neighbouring offsets of one row; the wave's
+      // entries of each group of kRunCols columns form a run
+      constexpr int G = 64 / kRunCols, NQ = G * RU;
+      constexpr u64 kGroup = kRunCols == 64 ? ~0ull : (1ull << kRunCols) - 1ull;
       u64 m[R];
-      int cnt[RU];
+      int cnt[NQ];
 #pragma unroll
-      for (int du = 0; du < RU; ++du) cnt[du] = 0;
+      for (int q = 0; q < NQ; ++q) cnt[q] = 0;
 #pragma unroll
       for (int dv = 0; dv < RV; ++dv)
 #pragma unroll
@@ -293,13 +296,14 @@ __device__ __forceinline__ void run_item(
           const int u = u0 + lane + 64 * du, v = v0 + wave * RV + dv;
           acc[r] = (acc[r] - cmp[r]) * my_sc[r * NW * 64];  // acc now holds rho
           m[r] = __ballot(u < pd.nu && v < pd.nv && acc[r] >= td.thr);
-          cnt[du] += __popcll(m[r]);
+#pragma unroll
+          for (int g = 0; g < G; ++g) cnt[G * du + g] += __popcll(m[r] & (kGroup << (kRunCols * g)));
         }
       int total = 0, n_runs = 0;
 #pragma unroll
-      for (int du = 0; du < RU; ++du) {
-        total += cnt[du];
-        n_runs += cnt[du] > 0;
+      for (int q = 0; q < NQ; ++q) {
+        total += cnt[q];
+        n_runs += cnt[q] > 0;
       }
       if (total > 0) {
         int base = 0;
@@ -308,30 +312,31 @@ __device__ __forceinline__ void run_item(
           int ri = atomicAdd(co.run_count, n_runs);
           int start = base;
 #pragma unroll
-          for (int du = 0; du < RU; ++du) {
-            if (cnt[du] > 0 && ri < co.run_cap) {
+          for (int q = 0; q < NQ; ++q) {
+            if (cnt[q] > 0 && ri < co.run_cap) {
               RunDesc rd;
               rd.start = start;
-              rd.count = cnt[du];
+              rd.count = cnt[q];
               rd.pair = it.pair;
-              rd.u0 = u0 + 64 * du;
+              rd.u0 = u0 + kRunCols * q;
               rd.v0 = v0 + wave * RV;
               rd.pad[0] = rd.pad[1] = rd.pad[2] = 0;
               co.runs[ri] = rd;
             }
-            ri += cnt[du] > 0;
-            start += cnt[du];
+            ri += cnt[q] > 0;
+            start += cnt[q];
           }
         }
         int pos = __builtin_amdgcn_readfirstlane(base);
         const u64 below = (1ull << lane) - 1ull;
 #pragma unroll
-        for (int du = 0; du < RU; ++du)
+        for (int q = 0; q < NQ; ++q)
 #pragma unroll
           for (int dv = 0; dv < RV; ++dv) {
-            const int r = dv * RU + du;
-            if ((m[r] >> lane) & 1ull) {
-              const int at = pos + __popcll(m[r] & below);
+            const int du = q / G, r = dv * RU + du;
+            const u64 mq = m[r] & (kGroup << (kRunCols * (q % G)));
+            if ((mq >> lane) & 1ull) {
+              const int at = pos + __popcll(mq & below);
               if (at < co.cap) {
                 sncc_hit h;
                 h.pair = it.pair;
@@ -342,7 +347,7 @@ __device__ __forceinline__ void run_item(
                 co.hits[at] = h;
               }
             }
-            pos += __popcll(m[r]);
+            pos += __popcll(mq);
           }
       }
     } else {
