@@ -540,8 +540,8 @@ int launch_map_topk(const double *map, int pitch, int nu, int nv, int chunk, int
 // Section 5, steps 7g-j for the offsets that passed the fast test: rho with
 // the slow approximation in FP64, appended to the output when it reaches the
 // template's slow threshold.  Workgroups take runs of the survivor list (the
-// survivors one wave of the fast pass found in one 64-column half of a tile:
-// one pair, a few offset rows, 64 columns) from a counter.
+// survivors one wave of the fast pass found in one group of kRunCols columns
+// of a tile: one pair, a few offset rows) from a counter.
 //
 // Staged form: the workgroup copies the run's region of the frame's table
 // (every entry a window of the run reads) to LDS; each wave then scores four
