@@ -132,6 +132,17 @@ __device__ __forceinline__ uint32_t window_box(__amdgpu_buffer_rsrc_t r, int vof
   return (a11 - a10) - (a01 - a00);
 }
 
+// The four corner entries of a window through a buffer resource (top-left,
+// top-right, bottom-left, bottom-right at byte offsets voff, + cW, + cH,
+// + cH + cW); its box sum is (c[3] - c[2]) - (c[1] - c[0]).
+__device__ __forceinline__ void window_corners(__amdgpu_buffer_rsrc_t r, int voff, int cW, int cH,
+                                               uint32_t (&c)[4]) {
+  c[0] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0);
+  c[1] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, cW, 0);
+  c[2] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, cH, 0);
+  c[3] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, cH + cW, 0);
+}
+
 // Sum of f^2 over a W x H window (Eq. (15)) as an exact 64-bit value.  Each
 // box of at most kMaxSqBoxArea pixels is exact as a difference of four
 // entries of the modulo-2^32 table, so the window is taken in bands of

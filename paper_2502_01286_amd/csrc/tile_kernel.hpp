@@ -135,7 +135,9 @@ __device__ __forceinline__ void run_item(
     float acc[R], cmp[R];
     if (one_box) {
       // one exact box per window: V = n * sum f^2 - (sum f)^2 as one FP64 fma
-      // of integers below 2^53, hence exact
+      // of integers below 2^53, hence exact.  All offsets' corner loads are
+      // issued before any is used, so that their latencies overlap
+      uint32_t c1[R][4], c2[R][4];
 #pragma unroll
       for (int dv = 0; dv < RV; ++dv)
 #pragma unroll
@@ -144,8 +146,16 @@ __device__ __forceinline__ void run_item(
           const int uc = min(u0 + lane + 64 * du, pd.nu - 1);
           const int vc = min(v0 + wave * RV + dv, pd.nv - 1);
           const int wo = (vc * P + uc) * 4;
-          const uint32_t sf = window_box(rs, wo, 0, cW, cH);
-          const uint32_t sf2 = window_box(rs2, wo, 0, cW, cH);
+          window_corners(rs, wo, cW, cH, c1[r]);
+          window_corners(rs2, wo, cW, cH, c2[r]);
+        }
+#pragma unroll
+      for (int dv = 0; dv < RV; ++dv)
+#pragma unroll
+        for (int du = 0; du < RU; ++du) {
+          const int r = dv * RU + du;
+          const uint32_t sf = (c1[r][3] - c1[r][2]) - (c1[r][1] - c1[r][0]);   // Eq. (13)
+          const uint32_t sf2 = (c2[r][3] - c2[r][2]) - (c2[r][1] - c2[r][0]);  // Eq. (15)
           nb[r] = -(int)__builtin_rintf((float)sf * inv_n);
           const double fs = (double)sf;
           const double Vd = __builtin_fma((double)n, (double)sf2, -(fs * fs));
