@@ -613,6 +613,27 @@ __device__ __forceinline__ double wave_sum4_f64(double a0, double a1, double a2,
   return k;
 }
 
+// Copies rows [0, nrow) x columns [0, ncol) of the table window whose
+// top-left entry is (v0, u0) to LDS at `region` (row pitch `pitch` words),
+// table rows clamped to N and columns to P - 1, with LDS-direct buffer loads
+// (no registers, all in flight together), and waits for them.  Four waves.
+__device__ __forceinline__ void stage_region(__amdgpu_buffer_rsrc_t rs, int P, int N, int v0,
+                                             int u0, int nrow, int ncol, int pitch,
+                                             uint32_t *region, int wave, int lane) {
+  for (int row = wave; row < nrow; row += 4) {
+    const int gy = min(v0 + row, N);
+    for (int c0 = 0; c0 < ncol; c0 += 64) {
+      if (c0 + lane < ncol) {
+        const int gx = min(u0 + c0 + lane, P - 1);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void *)(region + row * pitch + c0), 4,
+            (gy * P + gx) * 4, 0, 0, 0);
+      }
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
 __device__ __forceinline__ uint32_t lds_at(const uint32_t *region, int byte_off) {
   return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(region) + byte_off);
 }
@@ -735,14 +756,7 @@ __global__ __launch_bounds__(256) void slow_kernel(
     if (start < end && st.tbl >= 0) {
       // region rows [v0, v0 + rows), columns [u0, u0 + pitch), clamped to
       // the table (clamped entries are never read by a window of the run)
-      for (int row = wave; row < st.rows; row += 4) {
-        const int gy = min(rd.v0 + row, N);
-        for (int c = lane; c < st.pitch; c += 64) {
-          const int gx = min(rd.u0 + c, P - 1);
-          region[row * st.pitch + c] =
-              __builtin_amdgcn_raw_buffer_load_b32(rs, (gy * P + gx) * 4, 0, 0);
-        }
-      }
+      stage_region(rs, P, N, rd.v0, rd.u0, st.rows, st.pitch, st.pitch, region, wave, lane);
       __syncthreads();
       const __amdgpu_buffer_rsrc_t rso = make_rsrc(slot_off + st.tbl, (uint32_t)st.n_iter * 256u);
       const __amdgpu_buffer_rsrc_t rsc = make_rsrc(slot_c + st.tbl, (uint32_t)st.n_iter * 512u);
@@ -966,14 +980,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
     // the entries the chunk's windows read: rows [vmin, vmax + H], columns
     // [umin, umax + W] of the table, at the region's pitch
     const int nrow = vmax - vmin + td.H + 1, ncol = umax - umin + td.W + 1;
-    for (int row = wave; row < nrow; row += 4) {
-      const int gy = min(vmin + row, N);
-      for (int c = lane; c < ncol; c += 64) {
-        const int gx = min(umin + c, P - 1);
-        region[row * st.pitch + c] =
-            __builtin_amdgcn_raw_buffer_load_b32(rs, (gy * P + gx) * 4, 0, 0);
-      }
-    }
+    stage_region(rs, P, N, vmin, umin, nrow, ncol, st.pitch, region, wave, lane);
     __syncthreads();
     const __amdgpu_buffer_rsrc_t rso = make_rsrc(slot_off + st.tbl, (uint32_t)st.n_iter * 256u);
     const __amdgpu_buffer_rsrc_t rsc = make_rsrc(slot_c + st.tbl, (uint32_t)st.n_iter * 512u);
