@@ -135,27 +135,28 @@ __device__ __forceinline__ void run_item(
     float acc[R], cmp[R];
     if (one_box) {
       // one exact box per window: V = n * sum f^2 - (sum f)^2 as one FP64 fma
-      // of integers below 2^53, hence exact.  All offsets' corner loads are
-      // issued before any is used, so that their latencies overlap
-      uint32_t c1[R][4], c2[R][4];
+      // of integers below 2^53, hence exact.  The corner loads of two offsets
+      // at a time are issued before any is used, so that their latencies
+      // overlap; larger batches push a value live across the item into
+      // scratch memory, a store per wave and item
+      constexpr int RH = R > 2 ? 2 : R;  // offsets per batch of loads
 #pragma unroll
-      for (int dv = 0; dv < RV; ++dv)
+      for (int h = 0; h < R; h += RH) {
+        uint32_t c1[RH][4], c2[RH][4];
 #pragma unroll
-        for (int du = 0; du < RU; ++du) {
-          const int r = dv * RU + du;
+        for (int j = 0; j < RH; ++j) {
+          const int r = h + j, dv = r / RU, du = r % RU;
           const int uc = min(u0 + lane + 64 * du, pd.nu - 1);
           const int vc = min(v0 + wave * RV + dv, pd.nv - 1);
           const int wo = (vc * P + uc) * 4;
-          window_corners(rs, wo, cW, cH, c1[r]);
-          window_corners(rs2, wo, cW, cH, c2[r]);
+          window_corners(rs, wo, cW, cH, c1[j]);
+          window_corners(rs2, wo, cW, cH, c2[j]);
         }
 #pragma unroll
-      for (int dv = 0; dv < RV; ++dv)
-#pragma unroll
-        for (int du = 0; du < RU; ++du) {
-          const int r = dv * RU + du;
-          const uint32_t sf = (c1[r][3] - c1[r][2]) - (c1[r][1] - c1[r][0]);   // Eq. (13)
-          const uint32_t sf2 = (c2[r][3] - c2[r][2]) - (c2[r][1] - c2[r][0]);  // Eq. (15)
+        for (int j = 0; j < RH; ++j) {
+          const int r = h + j;
+          const uint32_t sf = (c1[j][3] - c1[j][2]) - (c1[j][1] - c1[j][0]);   // Eq. (13)
+          const uint32_t sf2 = (c2[j][3] - c2[j][2]) - (c2[j][1] - c2[j][0]);  // Eq. (15)
           nb[r] = -(int)__builtin_rintf((float)sf * inv_n);
           const double fs = (double)sf;
           const double Vd = __builtin_fma((double)n, (double)sf2, -(fs * fs));
@@ -163,6 +164,7 @@ __device__ __forceinline__ void run_item(
           acc[r] = 0.f;
           cmp[r] = 0.f;
         }
+      }
     } else {
       // banded sum of f^2; V in 64-bit integers
 #pragma unroll
