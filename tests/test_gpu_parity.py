@@ -400,6 +400,55 @@ def test_batch_graph_parity_and_replays(S, ctx, case):
     assert _u32(s)[0, 0, 0] == 0
 
 
+def test_batch_every_tile_config(S, ctx, tmp_path):
+    """Every tile configuration the tuner can choose gives the oracle's top-k.
+    The first creation times them all and records the winner in the tuning
+    cache under the batch's key; each configuration is then forced by
+    rewriting that entry.  The shapes: 128x32, 128x16 (four or eight waves),
+    64x64, 64x32 and 64x16 offsets per tile, the 128-wide ones with their
+    last-column launch where they have a half-width twin (a 70 px template on
+    260 px frames leaves a last column of 63 offsets)."""
+    import re
+    import torch
+    frames, temps, _, pairs = _multi(92, B=3, M=260, N=170,
+                                     sides=((24, 24), (40, 30), (70, 41), (33, 60)),
+                                     sigmas=(16, 16, 16, 16))
+    B, N, M = len(frames), frames[0].shape[0], frames[0].shape[1]
+    k = 8
+    f = torch.from_numpy(np.stack(frames)).cuda()
+    P = S.sncc_sat_pitch(M)
+    s = torch.zeros((B, N + 1, P), dtype=torch.int32, device="cuda")
+    s2 = torch.zeros_like(s)
+    coarse = lib_templates(S, ctx, temps, [16] * len(temps))
+    topk = torch.zeros((len(pairs), k, 3), dtype=torch.int32, device="cuda")
+    cache = str(tmp_path / "tune.json")
+    S.sncc_batch_create(ctx, coarse, s, s2, B, M, N, pairs, k, topk, frames=f, tune=1,
+                        tune_cache=cache).destroy()
+    key = re.search(r'"([^"]+)"\s*:', open(cache).read()).group(1)
+    tas = oracle_templates(temps, [16] * len(temps))
+    tables = [O.sum_tables(fr) for fr in frames]
+    maps = [O.rho_map(frames[b], tas[ti], tables=tables[b]) for b, ti in pairs]
+    shapes = set()
+    for cfg in range(8):
+        with open(cache, "w") as fh:
+            fh.write('{\n  "%s": %d\n}\n' % (key, cfg))
+        print("tile config", cfg, flush=True)
+        batch = S.sncc_batch_create(ctx, coarse, s, s2, B, M, N, pairs, k, topk, frames=f,
+                                    tune=1, tune_cache=cache)
+        topk.zero_()
+        S.sncc_batch_run(batch)
+        S.sncc_sync(ctx)
+        st = batch.stats()
+        shapes.add((st["tile_u"], st["tile_v"], st["wg_threads"]))
+        got = S.decode_matches(topk)
+        for p in range(len(pairs)):
+            errs = topk_ok(maps[p], got[p], k, TOL32)
+            assert not errs, (cfg, p, errs[:4])
+        batch.destroy()
+    assert shapes == {(128, 32, 512), (128, 16, 256), (128, 16, 512), (64, 64, 512),
+                      (64, 32, 512), (64, 16, 256)}
+
+
 # ------------------------------------------------------------- edge cases
 def test_errors(S, ctx):
     import torch
