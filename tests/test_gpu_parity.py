@@ -400,19 +400,26 @@ def test_batch_graph_parity_and_replays(S, ctx, case):
     assert _u32(s)[0, 0, 0] == 0
 
 
-def test_batch_every_tile_config(S, ctx, tmp_path):
+@pytest.mark.parametrize("case", ["staged", "direct"])
+def test_batch_every_tile_config(S, ctx, tmp_path, case):
     """Every tile configuration the tuner can choose gives the oracle's top-k.
     The first creation times them all and records the winner in the tuning
     cache under the batch's key; each configuration is then forced by
     rewriting that entry.  The shapes: 128x32, 128x16 (four or eight waves),
     64x64, 64x32 and 64x16 offsets per tile, the 128-wide ones with their
     last-column launch where they have a half-width twin (a 70 px template on
-    260 px frames leaves a last column of 63 offsets)."""
+    260 px frames leaves a last column of 63 offsets).  In `direct` a 530 px
+    wide template is too wide for every LDS pitch class and is scored in the
+    direct form, next to a staged one."""
     import re
     import torch
-    frames, temps, _, pairs = _multi(92, B=3, M=260, N=170,
-                                     sides=((24, 24), (40, 30), (70, 41), (33, 60)),
-                                     sigmas=(16, 16, 16, 16))
+    if case == "direct":
+        frames, temps, _, pairs = _multi(93, B=2, M=700, N=160,
+                                         sides=((530, 36), (30, 30)), sigmas=(16, 16))
+    else:
+        frames, temps, _, pairs = _multi(92, B=3, M=260, N=170,
+                                         sides=((24, 24), (40, 30), (70, 41), (33, 60)),
+                                         sigmas=(16, 16, 16, 16))
     B, N, M = len(frames), frames[0].shape[0], frames[0].shape[1]
     k = 8
     f = torch.from_numpy(np.stack(frames)).cuda()
