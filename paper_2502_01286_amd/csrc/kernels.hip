@@ -910,6 +910,28 @@ __global__ __launch_bounds__(256) void refine_kernel(
     v = rem >> 4;
     u = band * 16 + (rem & 15);
   };
+  // the unique keys are rewritten as (v << 16 | u) when both fit 16 bits
+  // (the list keeps its order), so that the serial chunk cut and the
+  // per-chunk loops below unpack an entry with two operations instead of a
+  // division
+  const bool packed = pd.nu <= 65536 && pd.nv <= 65536;
+  if (packed) {
+    for (int i = tid; i < L; i += 256) {
+      int u, v;
+      decode(list[i], u, v);
+      list[i] = (v << 16) | u;
+    }
+    __syncthreads();
+  }
+  auto entry = [&](int i, int &u, int &v) {
+    const int x = list[i];
+    if (packed) {
+      u = x & 0xffff;
+      v = (int)((uint32_t)x >> 16);
+    } else {
+      decode(x, u, v);
+    }
+  };
   double br = -__builtin_inf();
   int bi = 0x7fffffff;
   auto offer = [&](double r, int idx) {
@@ -921,7 +943,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
   if (st.tbl < 0) {  // region too large for LDS: one offset per thread
     for (int i = tid; i < L; i += 256) {
       int u, v;
-      decode(list[i], u, v);
+      entry(i, u, v);
       bool flat;
       const double r = rho_plain(S, S2, P, u, v, td.W, td.H, td.K, td.sq_rows, td.q_k, td.r64,
                                  geom + td.seg_off, c64 + td.seg_off, flat);
@@ -937,7 +959,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
     int c0 = 0, umin = 0, umax = 0, vmin = 0, vmax = 0;
     for (int i = 0; i < L; ++i) {
       int u, v;
-      decode(list[i], u, v);
+      entry(i, u, v);
       if (i == c0 || i - c0 == kRefineChunk || max(umax, u) - min(umin, u) >= kRefineSpanU ||
           max(vmax, v) - min(vmin, v) >= kRefineSpanV) {
         first[i >> 5] |= 1u << (i & 31);
@@ -967,7 +989,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
     int umin = 0x7fffffff, umax = -1, vmin = 0x7fffffff, vmax = -1;
     for (int i = 0; i < n; ++i) {  // every thread, same values
       int u, v;
-      decode(list[c0 + i], u, v);
+      entry(c0 + i, u, v);
       umin = min(umin, u);
       umax = max(umax, u);
       vmin = min(vmin, v);
@@ -988,7 +1010,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
       int su[4], sv[4], base[4], gof[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        decode(list[c0 + min(e0 + j, n - 1)], su[j], sv[j]);
+        entry(c0 + min(e0 + j, n - 1), su[j], sv[j]);
         base[j] = ((sv[j] - vmin) * st.pitch + (su[j] - umin)) * 4;
         gof[j] = sv[j] * P4 + su[j] * 4;
       }
