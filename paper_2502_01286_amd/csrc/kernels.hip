@@ -619,8 +619,9 @@ __device__ __forceinline__ double wave_sum4_f64(double a0, double a1, double a2,
 // (no registers, all in flight together), and waits for them.  Four waves.
 __device__ __forceinline__ void stage_region(__amdgpu_buffer_rsrc_t rs, int P, int N, int v0,
                                              int u0, int nrow, int ncol, int pitch,
-                                             uint32_t *region, int wave, int lane) {
-  for (int row = wave; row < nrow; row += 4) {
+                                             uint32_t *region, int wave, int lane,
+                                             int n_waves = 4) {
+  for (int row = wave; row < nrow; row += n_waves) {
     const int gy = min(v0 + row, N);
     for (int c0 = 0; c0 < ncol; c0 += 64) {
       if (c0 + lane < ncol) {
@@ -823,9 +824,11 @@ int launch_slow(const SlowArgs &a, int grid, int lds_bytes, hipStream_t st) {
 // region does not fit LDS, one offset per thread from the global tables
 // (rho_plain).
 constexpr int REFINE_CAP = 4096;
-constexpr int kRefineChunk = 64;  // entries per chunk: up to four batches of four per wave
+constexpr int kRefineChunk = 64;  // entries per chunk: up to two batches of four per wave
+constexpr int kRefineWaves = 8;
+constexpr int kRefineThreads = 64 * kRefineWaves;
 
-__global__ __launch_bounds__(256) void refine_kernel(
+__global__ __launch_bounds__(kRefineThreads) void refine_kernel(
     const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
     int P, const DevTmpl *__restrict__ tmpls, const int4 *__restrict__ geom,
     const double *__restrict__ c64, const SlowTmpl *__restrict__ stmpl,
@@ -833,9 +836,9 @@ __global__ __launch_bounds__(256) void refine_kernel(
     const PairDesc *__restrict__ pairs, const sncc_match *__restrict__ cand, int n_cand,
     int radius, int N, sncc_match64 *__restrict__ out, int *__restrict__ count) {
   __shared__ uint32_t first[REFINE_CAP / 32];  // bit i: entry i starts a chunk
-  __shared__ int wsum[4];
-  __shared__ double best_r[4];
-  __shared__ int best_i[4];
+  __shared__ int wsum[kRefineWaves];
+  __shared__ double best_r[kRefineWaves];
+  __shared__ int best_i[kRefineWaves];
   extern __shared__ uint32_t dyn[];  // the offset list (np ints), then the region
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int p = blockIdx.x;
@@ -850,7 +853,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
   int *const list = reinterpret_cast<int *>(dyn);
   uint32_t *const region = dyn + np;
   // candidate neighbourhoods, clipped; INT_MAX marks an empty slot
-  for (int e = tid; e < np; e += 256) {
+  for (int e = tid; e < np; e += kRefineThreads) {
     int val = 0x7fffffff;
     if (e < total) {
       const int j = e / area, d = e - j * area;
@@ -865,7 +868,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
   // bitonic sort ascending
   for (int size = 2; size <= np; size <<= 1)
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = tid; i < np; i += 256) {
+      for (int i = tid; i < np; i += kRefineThreads) {
         const int j = i ^ stride;
         if (j > i) {
           const int a = list[i], b = list[j];
@@ -879,7 +882,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
       __syncthreads();
     }
   // unique values: each thread owns a contiguous run of the sorted list
-  const int per = (np + 255) / 256;
+  const int per = (np + kRefineThreads - 1) / kRefineThreads;
   const int r0 = min(np, tid * per), r1 = min(np, r0 + per);
   int cnt = 0;
   for (int i = r0; i < r1; ++i)
@@ -889,7 +892,8 @@ __global__ __launch_bounds__(256) void refine_kernel(
   __syncthreads();
   int off = (int)incl - cnt;
   for (int w = 0; w < wave; ++w) off += wsum[w];
-  const int L = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  int L = 0;
+  for (int w = 0; w < kRefineWaves; ++w) L += wsum[w];
   // gather unique entries into registers before compacting in place
   int mine[16];
   int m = 0;
@@ -916,7 +920,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
   // division
   const bool packed = pd.nu <= 65536 && pd.nv <= 65536;
   if (packed) {
-    for (int i = tid; i < L; i += 256) {
+    for (int i = tid; i < L; i += kRefineThreads) {
       int u, v;
       decode(list[i], u, v);
       list[i] = (v << 16) | u;
@@ -941,7 +945,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
     }
   };
   if (st.tbl < 0) {  // region too large for LDS: one offset per thread
-    for (int i = tid; i < L; i += 256) {
+    for (int i = tid; i < L; i += kRefineThreads) {
       int u, v;
       entry(i, u, v);
       bool flat;
@@ -953,7 +957,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
   // chunks: runs of at most kRefineChunk consecutive entries whose offsets
   // span at most kRefineSpanU columns and kRefineSpanV rows, cut greedily in
   // list order (one thread; the list holds at most a few hundred entries)
-  for (int i = tid; i < REFINE_CAP / 32; i += 256) first[i] = 0;
+  for (int i = tid; i < REFINE_CAP / 32; i += kRefineThreads) first[i] = 0;
   __syncthreads();
   if (tid == 0) {
     int c0 = 0, umin = 0, umax = 0, vmin = 0, vmax = 0;
@@ -1002,11 +1006,11 @@ __global__ __launch_bounds__(256) void refine_kernel(
     // the entries the chunk's windows read: rows [vmin, vmax + H], columns
     // [umin, umax + W] of the table, at the region's pitch
     const int nrow = vmax - vmin + td.H + 1, ncol = umax - umin + td.W + 1;
-    stage_region(rs, P, N, vmin, umin, nrow, ncol, st.pitch, region, wave, lane);
+    stage_region(rs, P, N, vmin, umin, nrow, ncol, st.pitch, region, wave, lane, kRefineWaves);
     __syncthreads();
     const __amdgpu_buffer_rsrc_t rso = make_rsrc(slot_off + st.tbl, (uint32_t)st.n_iter * 256u);
     const __amdgpu_buffer_rsrc_t rsc = make_rsrc(slot_c + st.tbl, (uint32_t)st.n_iter * 512u);
-    for (int e0 = wave * 4; e0 < n; e0 += 16) {  // four entries per wave
+    for (int e0 = wave * 4; e0 < n; e0 += 4 * kRefineWaves) {  // four entries per wave
       int su[4], sv[4], base[4], gof[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -1039,7 +1043,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
   }
   __syncthreads();
   if (tid == 0) {
-    for (int w = 1; w < 4; ++w)
+    for (int w = 1; w < kRefineWaves; ++w)
       if (best_r[w] > br || (best_r[w] == br && best_i[w] < bi)) {
         br = best_r[w];
         bi = best_i[w];
@@ -1069,9 +1073,9 @@ int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride,
   int np = 1;
   while (np < total) np <<= 1;
   const int N = (int)(frame_stride / P) - 1;
-  hipLaunchKernelGGL(refine_kernel, dim3(n_pairs), dim3(256), np * 4 + slots.lds_bytes, st, s, s2,
-                     frame_stride, P, tmpls, geom, c64, slots.tmpl, slots.off, slots.c, pairs,
-                     cand, n_cand, radius, N, out, count);
+  hipLaunchKernelGGL(refine_kernel, dim3(n_pairs), dim3(kRefineThreads), np * 4 + slots.lds_bytes,
+                     st, s, s2, frame_stride, P, tmpls, geom, c64, slots.tmpl, slots.off,
+                     slots.c, pairs, cand, n_cand, radius, N, out, count);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
