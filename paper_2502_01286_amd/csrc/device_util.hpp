@@ -133,14 +133,14 @@ __device__ __forceinline__ uint32_t window_box(__amdgpu_buffer_rsrc_t r, int vof
 }
 
 // The four corner entries of a window through a buffer resource (top-left,
-// top-right, bottom-left, bottom-right at byte offsets voff, + cW, + cH,
-// + cH + cW); its box sum is (c[3] - c[2]) - (c[1] - c[0]).
-__device__ __forceinline__ void window_corners(__amdgpu_buffer_rsrc_t r, int voff, int cW, int cH,
-                                               uint32_t (&c)[4]) {
-  c[0] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0);
-  c[1] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, cW, 0);
-  c[2] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, cH, 0);
-  c[3] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, cH + cW, 0);
+// top-right, bottom-left, bottom-right at byte offsets voff + so, + cW, + cH,
+// + cH + cW; so is wave-uniform); its box sum is (c[3] - c[2]) - (c[1] - c[0]).
+__device__ __forceinline__ void window_corners(__amdgpu_buffer_rsrc_t r, int voff, int so, int cW,
+                                               int cH, uint32_t (&c)[4]) {
+  c[0] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so, 0);
+  c[1] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so + cW, 0);
+  c[2] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so + cH, 0);
+  c[3] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, so + cH + cW, 0);
 }
 
 // Sum of f^2 over a W x H window (Eq. (15)) as an exact 64-bit value.  Each

@@ -131,6 +131,13 @@ __device__ __forceinline__ void run_item(
     // issued before the first staging wait so that their latency overlaps
     // it; offsets outside the valid range read the window of the nearest
     // valid offset (inside the table) and are masked in the epilogue
+    // byte offsets of the lane's windows in the table: a wave-uniform row
+    // part (scalar) and a per-lane column part, clamped to the valid range
+    int rowo[RV], colo[RU];
+#pragma unroll
+    for (int dv = 0; dv < RV; ++dv) rowo[dv] = min(v0 + wave * RV + dv, pd.nv - 1) * P * 4;
+#pragma unroll
+    for (int du = 0; du < RU; ++du) colo[du] = min(u0 + lane + 64 * du, pd.nu - 1) * 4;
     int nb[R];
     float acc[R], cmp[R];
     if (one_box) {
@@ -146,11 +153,8 @@ __device__ __forceinline__ void run_item(
 #pragma unroll
         for (int j = 0; j < RH; ++j) {
           const int r = h + j, dv = r / RU, du = r % RU;
-          const int uc = min(u0 + lane + 64 * du, pd.nu - 1);
-          const int vc = min(v0 + wave * RV + dv, pd.nv - 1);
-          const int wo = (vc * P + uc) * 4;
-          window_corners(rs, wo, cW, cH, c1[j]);
-          window_corners(rs2, wo, cW, cH, c2[j]);
+          window_corners(rs, colo[du], rowo[dv], cW, cH, c1[j]);
+          window_corners(rs2, colo[du], rowo[dv], cW, cH, c2[j]);
         }
 #pragma unroll
         for (int j = 0; j < RH; ++j) {
@@ -172,11 +176,8 @@ __device__ __forceinline__ void run_item(
 #pragma unroll
         for (int du = 0; du < RU; ++du) {
           const int r = dv * RU + du;
-          const int uc = min(u0 + lane + 64 * du, pd.nu - 1);
-          const int vc = min(v0 + wave * RV + dv, pd.nv - 1);
-          const int wo = (vc * P + uc) * 4;
-          const uint32_t sf = window_box(rs, wo, 0, cW, cH);
-          const u64 sf2 = window_sq(rs2, wo, 0, cW, P * 4, H, td.sq_rows);
+          const uint32_t sf = window_box(rs, colo[du], rowo[dv], cW, cH);
+          const u64 sf2 = window_sq(rs2, colo[du], rowo[dv], cW, P * 4, H, td.sq_rows);
           nb[r] = -(int)__builtin_rintf((float)sf * inv_n);
           const u64 V = (u64)(uint32_t)n * sf2 - (u64)sf * sf;
           const float x = (float)((double)V * qnd);
@@ -203,9 +204,7 @@ __device__ __forceinline__ void run_item(
       for (int dv = 0; dv < RV; ++dv)
 #pragma unroll
         for (int du = 0; du < RU; ++du) {
-          const int uc = min(u0 + lane + 64 * du, pd.nu - 1);
-          const int vc = min(v0 + wave * RV + dv, pd.nv - 1);
-          vb[dv * RU + du] = (vc * P + uc) * 4;
+          vb[dv * RU + du] = rowo[dv] + colo[du];
         }
       uint32_t at[R], ab[R], nt[R], nbt[R], dprev[R];
 #pragma unroll
@@ -416,7 +415,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   constexpr int kScaleWords = 64 * NW * RU * RV;
   __shared__ int item_sh;
   __shared__ uint32_t thr_sh[NW];  // high words of the waves' k-th keys (current item)
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wave index is made a scalar, so that what derives from it is too
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   // Work queues: queue j holds order[qbeg[j] .. qbeg[j + 1]) and its counter
   // sits at queue[16 j].  A workgroup drains the queue of the chiplet (XCD)
   // it runs on, whose L2 then holds the frame rows that queue's items share,
