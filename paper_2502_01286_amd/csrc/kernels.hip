@@ -724,7 +724,7 @@ __global__ __launch_bounds__(256) void slow_kernel(
     int *__restrict__ out_count) {
   extern __shared__ uint32_t region[];
   __shared__ int run_sh;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n_cand = min(*cand_count, cand_cap);
   const int n_runs = min(*run_count, run_cap);
   const int P4 = P * 4;
@@ -840,7 +840,7 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
   __shared__ double best_r[kRefineWaves];
   __shared__ int best_i[kRefineWaves];
   extern __shared__ uint32_t dyn[];  // the offset list (np ints), then the region
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int p = blockIdx.x;
   const PairDesc pd = pairs[p];
   const DevTmpl td = tmpls[pd.tmpl];
