@@ -397,6 +397,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="coarse-fine")
     ap.add_argument("--tune", type=int, default=1)
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of tuned tile configurations: read when it holds this "
+                         "batch's key, else the tuner's choice is written to it")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -471,7 +474,7 @@ def main():
     t0 = time.perf_counter()
     batch = S.sncc_batch_create(ctx, coarse, s, s2, B, M, N, wl.pairs, wl.k, topk, fine=fine,
                                 radius=2, best_out=best, count_out=cnt, frames=f,
-                                tune=args.tune)
+                                tune=args.tune, tune_cache=args.tune_cache)
     st = batch.stats()
     log(f"[bench] batch planned in {time.perf_counter() - t0:.2f} s: {st['work_items']} items, "
         f"tile {st['tile_u']}x{st['tile_v']}, {st['wg_threads']} threads, LDS {st['lds_bytes']} B, "

@@ -473,16 +473,19 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int P, int n_pairs,
   std::vector<double> item_cost;
   ph.order.clear();
   if (tc.frame_major) {
-    // Items are bands of kBandRows offset rows of one pair (split further
-    // only when a band alone exceeds the target cost).  A group is one band
-    // of one frame over all of that frame's templates.  Queues, one per XCD,
-    // take whole frames (frame mod kMaxQueues) when there are enough frames,
-    // else groups round-robin; each queue runs its groups in frame and band
-    // order, so the workgroups of one XCD read the same frame rows from
-    // their shared L2, and a pair's later bands start with the floor its
-    // earlier bands published.  Within a group the costliest items go first.
-    constexpr int kBandRows = 64;
-    const int band_tiles = std::max(1, kBandRows / bv);
+    // Items are bands of offset rows of one pair (split further only when a
+    // band alone exceeds the target cost).  A group is one band of one frame
+    // over all of that frame's templates.  Queues, one per XCD, take whole
+    // frames (frame mod kMaxQueues) when there are enough frames, else groups
+    // round-robin; each queue runs its groups in frame and band order, so the
+    // workgroups of one XCD read the same frame rows from their shared L2,
+    // and a pair's later bands start with the floor its earlier bands
+    // published.  Within a group the costliest items go first.  A band is
+    // kRowsInFlight / (workgroups per CU) rows high: an XCD's workgroups then
+    // work on about that many consecutive offset rows of a frame at once
+    // (plus the template height), whose two tables fit its L2.
+    constexpr int kRowsInFlight = 64;
+    const int band_tiles = std::max(1, kRowsInFlight / std::max(1, tc.wgs) / bv);
     std::vector<int64_t> group_of;
     for (int p = 0; p < n_pairs; ++p) {
       PairDesc &pd = ph.pairs[p];
