@@ -31,7 +31,10 @@ Parity status per function: every public function is pinned by the CPU tests
 under ``tests/`` (brute-force Eq. (1), closed forms, invariants, hand-derived
 golden fixtures).  ``threshold_match`` is pinned against brute-force Eq. (1)
 maps of both approximation images and a planted copy.  ``coarse_fine`` is
-pinned only through its parts; the quality
+pinned against a brute-force walk of steps 7f-i over brute-force Eq. (1) maps
+of both approximation images (full sort, Chebyshev test at every offset) and
+planted exact ties; ``neighbourhood`` against hand-derived unions at corners
+and edges; ``top2_margin`` against hand values and a full sort.  The quality
 of the coarse-to-fine heuristic itself (whether it finds the global maximum) has
 no reference value: parity unpinned for that property.
 """

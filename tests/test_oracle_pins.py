@@ -312,6 +312,98 @@ def test_p9_topk_matches_full_sort():
     assert O.argmax(rho)[:2] == want[0][:2]
 
 
+# ----------------------------------- coarse-to-fine selection (Sec. 5, 7f-i)
+def test_top2_margin_hand_values():
+    # best 0.9 twice: the margin of a tie is 0
+    assert O.top2_margin(np.array([[0.5, 0.9], [0.9, 0.1]])) == 0.0
+    # NaN (a map entry that was never scored) is never selected: 0.7 - 0.2
+    assert O.top2_margin(np.array([[np.nan, 0.2], [0.7, 0.1]])) == pytest.approx(0.5, abs=1e-15)
+    # a single offset has no runner-up
+    assert O.top2_margin(np.array([[0.3]])) == float("inf")
+    # negative scores: -0.1 - (-0.4)
+    assert O.top2_margin(np.array([[-0.4, -0.1, -0.9]])) == pytest.approx(0.3, abs=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_top2_margin_full_sort(seed):
+    rng = np.random.default_rng(20 + seed)
+    rho = np.round(rng.uniform(-1, 1, (5, 9)), 1 + seed)     # ties on the first seeds
+    vals = sorted(rho.ravel().tolist(), reverse=True)
+    assert O.top2_margin(rho) == pytest.approx(vals[0] - vals[1], abs=1e-15)
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_golden_neighbourhood_union(case):
+    d = _load("neighbourhood_union.json")["cases"][case]
+    cands = [(u, v, 0.0) for u, v in d["cands"]]
+    cu, cv = OSEL.neighbourhood(cands, d["radius"], d["nu"], d["nv"])
+    assert len(cu) == d["count"]
+    assert [[int(v), int(u)] for u, v in zip(cu, cv)] == d["sorted_vu"]
+
+
+def _brute_coarse_fine(f, coarse, fine, k, radius):
+    """Steps 7f-i from brute-force Eq. (1) maps of both approximation images:
+    the k best coarse offsets by a full sort, the set of offsets within
+    Chebyshev distance radius of one of them, and the best fine offset there
+    (ties to smaller v, then u)."""
+    bc = O.brute_ncc_map(f, O.approximation_image(coarse.W, coarse.H, coarse.segments))
+    bf = O.brute_ncc_map(f, O.approximation_image(fine.W, fine.H, fine.segments))
+    nv, nu = bc.shape
+    allc = sorted((-bc[v, u], v, u) for v in range(nv) for u in range(nu))
+    cands = [(u, v) for _, v, u in allc[:k]]
+    gap = allc[k - 1][0] - allc[k][0] if k < len(allc) else -np.inf
+    inset = [(v, u) for v in range(nv) for u in range(nu)
+             if min(max(abs(u - a), abs(v - b)) for a, b in cands) <= radius]
+    ranked = sorted((-bf[v, u], v, u) for v, u in inset)
+    return cands, -gap, inset, ranked, bf
+
+
+@pytest.mark.parametrize("seed,k,radius", [(0, 1, 2), (1, 3, 1), (2, 5, 2), (3, 2, 0)])
+def test_coarse_fine_equals_brute_force(seed, k, radius):
+    f, t, _, _ = _rand_case(700 + seed, M=26, N=19, W=6, H=5, smooth=seed % 2 == 0)
+    coarse = O.precompute_template_approximation(t, 30)
+    fine = O.precompute_template_approximation(t, 4)
+    N, M = f.shape
+    s, s2 = O.sum_tables(f)
+    res = O.coarse_fine(s, s2, coarse, fine, M, N, k=k, radius=radius)
+    cands, gap, inset, ranked, bf = _brute_coarse_fine(f, coarse, fine, k, radius)
+    assert gap > 1e-9                      # the candidate set is unique at these seeds
+    assert [(u, v) for u, v, _ in res["coarse"]] == cands
+    assert [(int(v), int(u)) for u, v in zip(res["fine_u"], res["fine_v"])] == inset
+    np.testing.assert_allclose(res["fine_rho"], [bf[v, u] for v, u in inset], atol=1e-12)
+    assert len(ranked) == 1 or ranked[1][0] - ranked[0][0] > 1e-9
+    (_, bv, bu) = ranked[0]
+    assert res["best"][:2] == (bu, bv)
+    assert res["best"][2] == pytest.approx(bf[bv, bu], abs=1e-12)
+
+
+def test_coarse_fine_ties_go_to_smaller_v_then_u():
+    """Two exact copies of the template score the same rho bit for bit with
+    either approximation; the result is the copy with the smaller v even
+    though its u is larger."""
+    rng = np.random.default_rng(77)
+    f = rng.integers(0, 256, (24, 30)).astype(np.uint8)
+    t = rng.integers(0, 256, (5, 6)).astype(np.uint8)
+    f[3:8, 12:18] = t                      # (u, v) = (12, 3)
+    f[9:14, 2:8] = t                       # (u, v) = (2, 9)
+    coarse = O.precompute_template_approximation(t, 60)
+    fine = O.precompute_template_approximation(t, 20)
+    N, M = f.shape
+    s, s2 = O.sum_tables(f)
+    res = O.coarse_fine(s, s2, coarse, fine, M, N, k=2, radius=1)
+    assert [(u, v) for u, v, _ in res["coarse"]] == [(12, 3), (2, 9)]
+    fr = dict(zip(zip(res["fine_u"].tolist(), res["fine_v"].tolist()), res["fine_rho"]))
+    assert fr[(12, 3)] == fr[(2, 9)] == max(fr.values())
+    assert res["best"][:2] == (12, 3)
+    assert res["best"][2] == pytest.approx(fine.rho_max, abs=1e-12)
+    # the same holds with the copies in one row: the smaller u wins
+    g = rng.integers(0, 256, (24, 30)).astype(np.uint8)
+    g[10:15, 20:26] = t
+    g[10:15, 4:10] = t
+    res = O.coarse_fine(*O.sum_tables(g), coarse, fine, M, N, k=2, radius=1)
+    assert res["best"][:2] == (4, 10)
+
+
 # ------------------------------------------------------------------ degenerate
 def test_p10_uniform_window_and_template():
     f = np.full((10, 10), 77, np.uint8)
@@ -416,6 +508,12 @@ def _pins_pass():
             test_p7_partition_invariants(seed)
         test_threshold_match_equals_brute_force(0)
         test_threshold_match_planted_copy(0)
+        test_top2_margin_hand_values()
+        test_top2_margin_full_sort(0)
+        for case in range(4):
+            test_golden_neighbourhood_union(case)
+        test_coarse_fine_equals_brute_force(1, 3, 1)
+        test_coarse_fine_ties_go_to_smaller_v_then_u()
     except (AssertionError, ValueError, IndexError, KeyError):
         return False
     return True
@@ -459,6 +557,23 @@ MUTANTS = {
                                 "rs = rho_at(s, s2, fast, cu, cv)"),
     "thresholds_swapped": (OSEL, "threshold_match",
                            "tf = precision * fast.rho_max", "tf = precision * slow.rho_max"),
+    "neighbourhood_radius_short": (OSEL, "neighbourhood",
+                                   "for dv in range(-radius, radius + 1):",
+                                   "for dv in range(-radius, radius):"),
+    "neighbourhood_clip_inclusive": (OSEL, "neighbourhood",
+                                     "if 0 <= uu < nu and 0 <= vv < nv:",
+                                     "if 0 <= uu <= nu and 0 <= vv < nv:"),
+    "fine_ties_by_u_first": (OSEL, "coarse_fine",
+                             "key=lambda i: (-fr[i], cv[i], cu[i])",
+                             "key=lambda i: (-fr[i], cu[i], cv[i])"),
+    "fine_scored_with_coarse": (OSEL, "coarse_fine",
+                                "fr = rho_at(s, s2, fine, cu, cv)",
+                                "fr = rho_at(s, s2, coarse, cu, cv)"),
+    "margin_of_single_offset_zero": (OSEL, "top2_margin",
+                                     'if len(best) > 1 else float("inf")',
+                                     "if len(best) > 1 else 0.0"),
+    "margin_sign_flipped": (OSEL, "top2_margin",
+                            "best = topk(rho, 2)", "best = topk(rho, 2)[::-1]"),
 }
 
 
