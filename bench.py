@@ -101,9 +101,12 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(wl, coarse_segs_k, budget_s=15.0, max_pairs=1024):
+def cpu_baseline(wl, coarse_segs_k, budget_s=15.0, max_pairs=1024, gpu_topk=None,
+                 gpu_best=None):
     """The oracle (NumPy FP64), as it stands, on a seeded sample of pairs of
-    the same workload, one pair per worker process."""
+    the same workload, one pair per worker process.  With the GPU's results
+    of the same step (top-k lists, and final matches when refining), an
+    untimed second pass compares them with the oracle on those pairs."""
     import numpy as np
     from concurrent.futures import ProcessPoolExecutor
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
@@ -125,13 +128,33 @@ def cpu_baseline(wl, coarse_segs_k, budget_s=15.0, max_pairs=1024):
     with ProcessPoolExecutor(max_workers=cores) as ex:
         preps = list(ex.map(_cpu_prep, jobs))
         t0 = time.perf_counter()
-        evals = sum(ex.map(_cpu_pair, jobs, preps))
+        res = list(ex.map(_cpu_pair, jobs, preps))
         dt = time.perf_counter() - t0
-    return {"value": evals / dt, "unit": UNIT, "cores": cores, "kind": "oracle",
-            "sample": f"{len(chosen)} seeded (frame, template) pairs of the same workload: "
-                      f"full coarse rho map (FP64) + top-{wl.k}"
-                      + (" + FP64 fine re-score of the +-2 px neighbourhoods" if wl.fine_sigma else "")
-                      + f", {dt:.1f} s wall on {cores} processes"}
+        evals = sum(r[0] for r in res)
+        parity = None
+        if gpu_topk is not None:
+            checks = list(ex.map(_cpu_check, jobs, preps, [r[1:] for r in res],
+                                 [gpu_topk[p] for p in chosen],
+                                 [gpu_best[p] if gpu_best is not None else None for p in chosen]))
+            parity = _summarise_checks(checks, wl.k)
+    out = {"value": evals / dt, "unit": UNIT, "cores": cores, "kind": "oracle",
+           "cpu_model": _cpu_model(),
+           "sample": f"{len(chosen)} seeded (frame, template) pairs of the same workload: "
+                     f"full coarse rho map (FP64) + top-{wl.k}"
+                     + (" + FP64 fine re-score of the +-2 px neighbourhoods" if wl.fine_sigma else "")
+                     + f", {dt:.1f} s wall on {cores} processes"}
+    return out, parity
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _cpu_prep(job):
@@ -143,17 +166,92 @@ def _cpu_prep(job):
 
 
 def _cpu_pair(job, prep):
+    """Timed oracle work of one pair: the whole coarse map, its top-k (and the
+    next entry, for the set gap) and, when refining, the coarse-fine result."""
+    import numpy as np
     import oracle as O
     f, t, sc, sf, k = job
     c, fi = prep
     tables = O.sum_tables(f)
     N, M = f.shape
     cmap = O.rho_map(f, c, tables=tables)
+    best = None
     if fi is not None:
-        O.coarse_fine(*tables, c, fi, M, N, k=k, radius=2, coarse_map=cmap)
+        res = O.coarse_fine(*tables, c, fi, M, N, k=k, radius=2, coarse_map=cmap)
+        ref, best = list(res["coarse"]), res["best"]
     else:
-        O.topk(cmap, k)
-    return cmap.size * c.K
+        ref = O.topk(cmap, k)
+    # the value of rank k + 1 (for the set gap only; a partial sort, a few ms)
+    flat = cmap.ravel()
+    if flat.size > k:
+        ref.append((-1, -1, float(np.partition(flat, flat.size - k - 1)[flat.size - k - 1])))
+    return cmap.size * c.K, ref, best
+
+
+SET_GAP = 2e-5      # rank-k / rank-k+1 oracle gap that fixes the top-k set (2 x 1e-5)
+
+
+def _cpu_check(job, prep, oracle_res, g_topk, g_best):
+    """Untimed: the GPU's results of one pair against the oracle.  Coarse:
+    rho at every reported offset, and the set of offsets where the oracle's
+    rank-k / rank-k+1 gap exceeds SET_GAP.  Final (refining workloads): the
+    oracle's fine step over the GPU's own candidates (Section 5, steps 7f-i),
+    which equals the oracle's whole coarse-fine result when the candidate set
+    is fixed; its argmax must be the GPU's wherever its fine top-2 margin
+    exceeds 1e-9."""
+    import numpy as np
+    import oracle as O
+    from oracle import select as OSEL
+    f, t, sc, sf, k = job
+    c, fi = prep
+    ref, cf_best = oracle_res
+    tables = O.sum_tables(f)
+    N, M = f.shape
+    nu, nv = M - c.W + 1, N - c.H + 1
+    u = np.array([m[0] for m in g_topk], np.int64)
+    v = np.array([m[1] for m in g_topk], np.int64)
+    r = np.array([m[2] for m in g_topk], np.float64)
+    ok = u >= 0
+    want = O.rho_at(*tables, c, u[ok], v[ok])
+    d = {"coarse_err": float(np.abs(want - r[ok]).max()) if ok.any() else 0.0,
+         "set_fixed": False, "set_equal": None}
+    gap = ref[k - 1][2] - ref[k][2] if len(ref) > k else np.inf
+    if gap > SET_GAP:
+        d["set_fixed"] = True
+        d["set_equal"] = {(int(a), int(b)) for a, b in zip(u[ok], v[ok])} == \
+            {(a, b) for a, b, _ in ref[:k]}
+    if g_best is not None and fi is not None:
+        cands = [(int(a), int(b), 0.0) for a, b in zip(u[ok], v[ok])]
+        cu, cv = OSEL.neighbourhood(cands, 2, nu, nv)
+        fr = O.rho_at(*tables, fi, cu, cv)
+        order = np.lexsort((cu, cv, -fr))
+        i0 = order[0]
+        margin = fr[i0] - fr[order[1]] if len(order) > 1 else np.inf
+        bu, bv, br = int(g_best[0]), int(g_best[1]), float(g_best[2])
+        d["fine_err"] = abs(br - float(O.rho_at(*tables, fi, bu, bv)))
+        d["final_decided"] = bool(margin > 1e-9)
+        d["final_match"] = (bu, bv) == (int(cu[i0]), int(cv[i0])) if margin > 1e-9 else \
+            br >= fr[i0] - 1e-9
+        if d["set_fixed"] and d["set_equal"]:
+            d["final_vs_oracle_cf"] = (bu, bv) == tuple(cf_best[:2]) or margin <= 1e-9
+    return d
+
+
+def _summarise_checks(checks, k):
+    out = {"pairs": len(checks),
+           "coarse_max_abs_drho": max(c["coarse_err"] for c in checks),
+           "topk_sets_fixed": sum(c["set_fixed"] for c in checks),
+           "topk_sets_equal": sum(bool(c["set_equal"]) for c in checks if c["set_fixed"]),
+           "k": k, "set_gap": SET_GAP, "tolerance": 1e-5}
+    if checks and "fine_err" in checks[0]:
+        out.update({
+            "fine_max_abs_drho": max(c["fine_err"] for c in checks),
+            "final_argmax_checked": len(checks),
+            "final_argmax_match": sum(bool(c["final_match"]) for c in checks),
+            "final_decided_by_margin_1e-9": sum(c["final_decided"] for c in checks),
+            "final_vs_oracle_coarse_fine": sum(bool(c.get("final_vs_oracle_cf")) for c in checks),
+            "fine_tolerance": 1e-9})
+    return out
 
 
 # ------------------------------------------------ the two-threshold search
@@ -542,11 +640,18 @@ def main():
                  "form": "one plain FP64 scoring launch per pair (+ per-pair top-k), no graph"}
         log(f"[bench] plain {pms:.2f} ms")
 
-    cpu = None
+    cpu = parity = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
-        cpu = cpu_baseline(wl, Kc, budget_s=args.cpu_budget)
+        g_top = S.decode_matches(topk)
+        g_top = [[(int(m["u"]), int(m["v"]), float(m["rho"])) for m in row] for row in g_top]
+        g_best = None
+        if best is not None:
+            g_best = [(int(m["u"]), int(m["v"]), float(m["rho"])) for m in S.decode_matches64(best)]
+        cpu, parity = cpu_baseline(wl, Kc, budget_s=args.cpu_budget, gpu_topk=g_top,
+                                   gpu_best=g_best)
         log(f"[bench] cpu {cpu}")
+        log(f"[bench] parity on the oracle's sample {parity}")
 
     batch.destroy()
     S.sncc_tmpl_destroy(coarse)
@@ -568,7 +673,7 @@ def main():
                             "and f32 rho (coarse), f64 refine"},
         "frames_per_s": B / (ms_per_step / 1e3),
         "stage_ms": avg, "prep_ms_host": prep_ms,
-        "roofline": roof, "plain_fp64": plain, "cpu_baseline": cpu,
+        "roofline": roof, "plain_fp64": plain, "cpu_baseline": cpu, "parity": parity,
     }
     print(json.dumps(line), flush=True)
 

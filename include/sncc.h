@@ -226,6 +226,8 @@ int sncc_tmpl_destroy(sncc_tmpl *tm);
 /* W, H, K and q_k of template `index` (any pointer nullable). */
 int sncc_tmpl_info(const sncc_tmpl *tm, int index, int *W, int *H, int *K,
                    double *q_k);
+/* Number of templates T in the set.  Errors: SNCC_EINVAL (NULL). */
+int sncc_tmpl_count(const sncc_tmpl *tm, int *T);
 
 /* ------------------------------------------------------------- scoring */
 /*

@@ -100,6 +100,7 @@ _SIGS = {
     "sncc_upload_templates": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
     "sncc_tmpl_destroy": (_i, [_vp]),
     "sncc_tmpl_info": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
+    "sncc_tmpl_count": (_i, [_vp, _vp]),
     "sncc_score": (_i, [_vp, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _i, _vp]),
     "sncc_topk": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _i, _i, _vp]),
     "sncc_argmax": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _i, _vp]),
@@ -204,19 +205,71 @@ def sncc_sat_pitch(M: int) -> int:
 
 
 # ------------------------------------------------------------------ device
-def _ptr(t, dtype=None, name="tensor"):
+def _chk(t, dtype, name, shape=None, min_numel=None):
+    """Checks a tensor argument's type, dtype, layout and size (the C side
+    sees raw pointers only, so these checks are what keeps a caller's slip from
+    becoming an out-of-bounds device access).  ``shape``: exact shape, None
+    entries matching any size; ``min_numel``: least number of elements.
+    None passes (nullable arguments)."""
     import torch
     if t is None:
-        return None
+        return
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
-    if not t.is_cuda:
-        raise ValueError(f"{name} must be a device tensor")
     if dtype is not None and t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
-    return t.data_ptr()
+    if shape is not None:
+        if t.dim() != len(shape) or any(w is not None and int(g) != int(w)
+                                        for g, w in zip(t.shape, shape)):
+            want = "(" + ", ".join("*" if w is None else str(int(w)) for w in shape) + ")"
+            raise ValueError(f"{name} must have shape {want}, got {tuple(t.shape)}")
+    if min_numel is not None and t.numel() < int(min_numel):
+        raise ValueError(f"{name} holds {t.numel()} elements, needs at least {int(min_numel)}")
+
+
+def _dev(**tensors):
+    """Every given tensor (None skipped) is a device tensor, all on one device."""
+    first = None
+    for name, t in tensors.items():
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+        if first is None:
+            first = (name, t.device)
+        elif t.device != first[1]:
+            raise ValueError(f"{name} is on {t.device}, {first[0]} on {first[1]}")
+
+
+def _p(t):
+    return None if t is None else t.data_ptr()
+
+
+def _tables(s, s2, B, N):
+    """Checks a pair of sum-table tensors for B frames of N rows (layout of
+    sncc_build_sats: B x (N + 1) x pitch int32, or (N + 1) x pitch for one
+    frame) and returns their pitch."""
+    import torch
+    for t, nm in ((s, "s"), (s2, "s2")):
+        if not isinstance(t, torch.Tensor) or t.dim() not in (2, 3):
+            raise ValueError(f"{nm} must be a 2-D or 3-D int32 tensor")
+    if tuple(s.shape) != tuple(s2.shape):
+        raise ValueError(f"s and s2 differ in shape: {tuple(s.shape)} vs {tuple(s2.shape)}")
+    P = int(s.shape[-1])
+    if int(s.shape[-2]) != int(N) + 1:
+        raise ValueError(f"s must have N + 1 = {int(N) + 1} rows per frame, got {int(s.shape[-2])}")
+    _chk(s, torch.int32, "s", min_numel=int(B) * (int(N) + 1) * P)
+    _chk(s2, torch.int32, "s2", min_numel=int(B) * (int(N) + 1) * P)
+    return P
+
+
+def _check_pairs(p, B, n_templates=None):
+    if p.size and (p[:, 0].min() < 0 or p[:, 0].max() >= int(B)):
+        raise ValueError(f"pair frame index outside [0, {int(B)})")
+    if n_templates is not None and p.size and (p[:, 1].min() < 0 or p[:, 1].max() >= n_templates):
+        raise ValueError(f"pair template index outside [0, {n_templates})")
 
 
 def sncc_ctx_create(device: int = 0, stream=None):
@@ -240,12 +293,17 @@ def sncc_build_sats(ctx, f, s, s2):
     """f: uint8 (B, N, M) or (N, M); s, s2: int32 (B, N+1, pitch) or (N+1, pitch)
     device tensors holding the uint32 tables."""
     import torch
+    if not isinstance(f, torch.Tensor) or f.dim() not in (2, 3):
+        raise ValueError("f must be a 2-D or 3-D uint8 tensor")
     if f.dim() == 2:
         f = f.unsqueeze(0)
     B, N, M = f.shape
-    P = s.shape[-1]
-    _check(lib.sncc_build_sats(ctx, _ptr(f, torch.uint8, "f"), B, M, N, M,
-                               _ptr(s, torch.int32, "s"), _ptr(s2, torch.int32, "s2"), P))
+    if s.dim() == 3 and int(s.shape[0]) != B:
+        raise ValueError(f"s holds {int(s.shape[0])} frames, f holds {B}")
+    P = _tables(s, s2, B, N)
+    _chk(f, torch.uint8, "f")
+    _dev(s=s, s2=s2, f=f)
+    _check(lib.sncc_build_sats(ctx, f.data_ptr(), B, M, N, M, s.data_ptr(), s2.data_ptr(), P))
 
 
 def sncc_upload_templates(ctx, seg_lists, W, H):
@@ -271,13 +329,33 @@ def sncc_tmpl_info(tm, index):
     return W.value, H.value, K.value, q.value
 
 
+def sncc_tmpl_count(tm):
+    """Number of templates in a set."""
+    n = C.c_int(0)
+    _check(lib.sncc_tmpl_count(tm, C.byref(n)))
+    return n.value
+
+
 def sncc_score(ctx, tm, index, s, s2, M, N, precision, rho, degen=None):
+    """rho: (N-H+1, pitch >= M-W+1) float32 (SNCC_FP32_KAHAN) or float64
+    (SNCC_FP64); degen: nullable uint8 tensor of rho's shape."""
     import torch
     want = torch.float32 if precision == SNCC_FP32_KAHAN else torch.float64
-    _check(lib.sncc_score(ctx, tm, int(index), _ptr(s, torch.int32, "s"),
-                          _ptr(s2, torch.int32, "s2"), int(M), int(N), s.shape[-1],
-                          int(precision), _ptr(rho, want, "rho"), rho.shape[-1],
-                          _ptr(degen, torch.uint8, "degen")))
+    P = _tables(s, s2, 1, N)
+    if not isinstance(rho, torch.Tensor) or rho.dim() != 2:
+        raise ValueError("rho must be a 2-D tensor")
+    _chk(rho, want, "rho")
+    _chk(degen, torch.uint8, "degen", shape=tuple(rho.shape))
+    W, H, _, _ = sncc_tmpl_info(tm, index)
+    nu, nv = int(M) - W + 1, int(N) - H + 1
+    if nu < 1 or nv < 1:
+        raise ValueError(f"template {W}x{H} larger than the image {int(M)}x{int(N)}")
+    pitch = int(rho.shape[-1])
+    if int(rho.shape[0]) != nv or pitch < nu:
+        raise ValueError(f"rho must have shape ({nv}, >= {nu}), got {tuple(rho.shape)}")
+    _dev(s=s, s2=s2, rho=rho, degen=degen)
+    _check(lib.sncc_score(ctx, tm, int(index), s.data_ptr(), s2.data_ptr(), int(M), int(N), P,
+                          int(precision), rho.data_ptr(), pitch, _p(degen)))
 
 
 def _pairs_array(pairs):
@@ -289,27 +367,43 @@ def sncc_topk(ctx, tm, s, s2, B, M, N, pairs, k, precision, out):
     """out: int32 device tensor (n_pairs, k, 3) = {u, v, rho bits}."""
     import torch
     p = _pairs_array(pairs)
-    _check(lib.sncc_topk(ctx, tm, _ptr(s, torch.int32, "s"), _ptr(s2, torch.int32, "s2"),
-                         int(B), int(M), int(N), s.shape[-1], len(p), p.ctypes.data, int(k),
-                         int(precision), _ptr(out, torch.int32, "out")))
+    P = _tables(s, s2, B, N)
+    _chk(out, torch.int32, "out", shape=(len(p), int(k), 3))
+    _dev(s=s, s2=s2, out=out)
+    _check_pairs(p, B, sncc_tmpl_count(tm))
+    _check(lib.sncc_topk(ctx, tm, s.data_ptr(), s2.data_ptr(), int(B), int(M), int(N), P,
+                         len(p), p.ctypes.data, int(k), int(precision), out.data_ptr()))
 
 
 def sncc_argmax(ctx, tm, s, s2, B, M, N, pairs, precision, out):
+    """out: int32 device tensor (n_pairs, 1, 3) or (n_pairs, 3)."""
     import torch
     p = _pairs_array(pairs)
-    _check(lib.sncc_argmax(ctx, tm, _ptr(s, torch.int32, "s"), _ptr(s2, torch.int32, "s2"),
-                           int(B), int(M), int(N), s.shape[-1], len(p), p.ctypes.data,
-                           int(precision), _ptr(out, torch.int32, "out")))
+    P = _tables(s, s2, B, N)
+    shape = (len(p), 1, 3) if isinstance(out, torch.Tensor) and out.dim() == 3 else (len(p), 3)
+    _chk(out, torch.int32, "out", shape=shape)
+    _dev(s=s, s2=s2, out=out)
+    _check_pairs(p, B, sncc_tmpl_count(tm))
+    _check(lib.sncc_argmax(ctx, tm, s.data_ptr(), s2.data_ptr(), int(B), int(M), int(N), P,
+                           len(p), p.ctypes.data, int(precision), out.data_ptr()))
 
 
 def sncc_refine(ctx, fine, s, s2, B, M, N, pairs, cand, radius, out, count=None):
-    """cand: int32 (n_pairs, n_cand, 3); out: int32 (n_pairs, 4) = {u, v, rho f64}."""
+    """cand: int32 (n_pairs, n_cand, 3); out: int32 (n_pairs, 4) = {u, v, rho f64};
+    count: nullable int32 (n_pairs,)."""
     import torch
     p = _pairs_array(pairs)
-    _check(lib.sncc_refine(ctx, fine, _ptr(s, torch.int32, "s"), _ptr(s2, torch.int32, "s2"),
-                           int(B), int(M), int(N), s.shape[-1], len(p), p.ctypes.data,
-                           _ptr(cand, torch.int32, "cand"), cand.shape[1], int(radius),
-                           _ptr(out, torch.int32, "out"), _ptr(count, torch.int32, "count")))
+    P = _tables(s, s2, B, N)
+    if not isinstance(cand, torch.Tensor) or cand.dim() != 3:
+        raise ValueError("cand must be an int32 (n_pairs, n_cand, 3) tensor")
+    _chk(cand, torch.int32, "cand", shape=(len(p), None, 3))
+    _chk(out, torch.int32, "out", shape=(len(p), 4))
+    _chk(count, torch.int32, "count", shape=(len(p),))
+    _dev(s=s, s2=s2, cand=cand, out=out, count=count)
+    _check_pairs(p, B, sncc_tmpl_count(fine))
+    _check(lib.sncc_refine(ctx, fine, s.data_ptr(), s2.data_ptr(), int(B), int(M), int(N), P,
+                           len(p), p.ctypes.data, cand.data_ptr(), int(cand.shape[1]),
+                           int(radius), out.data_ptr(), _p(count)))
 
 
 def sncc_ctx_set_timing(ctx, enable: bool):
@@ -331,20 +425,30 @@ def sncc_threshold_match(ctx, fast, slow, thr_fast, thr_slow, s, s2, B, M, N, pa
     rho f64); counts: int32 (2,) device."""
     import torch
     p = _pairs_array(pairs)
+    P = _tables(s, s2, B, N)
+    for t, nm in ((cand, "cand"), (out, "out")):
+        if not isinstance(t, torch.Tensor) or t.dim() != 2 or t.shape[1] != 6:
+            raise ValueError(f"{nm} must be an int32 (cap, 6) tensor")
+        _chk(t, torch.int32, nm)
+    _chk(counts, torch.int32, "counts", min_numel=2)
+    _dev(s=s, s2=s2, cand=cand, out=out, counts=counts)
+    T = sncc_tmpl_count(fast)
+    _check_pairs(p, B, T)
     tf = np.ascontiguousarray(thr_fast, dtype=np.float64)
     ts = np.ascontiguousarray(thr_slow, dtype=np.float64)
-    if cand.dim() != 2 or cand.shape[1] != 6 or out.dim() != 2 or out.shape[1] != 6:
-        raise ValueError("cand and out must be int32 (cap, 6) tensors")
+    if tf.shape != (T,) or ts.shape != (T,):
+        raise ValueError(f"need one fast and one slow threshold per template ({T})")
     _check(lib.sncc_threshold_match(ctx, fast, slow, tf.ctypes.data, ts.ctypes.data,
-                                    _ptr(s, torch.int32, "s"), _ptr(s2, torch.int32, "s2"),
-                                    int(B), int(M), int(N), s.shape[-1], len(p), p.ctypes.data,
-                                    _ptr(cand, torch.int32, "cand"), cand.shape[0],
-                                    _ptr(out, torch.int32, "out"), out.shape[0],
-                                    _ptr(counts, torch.int32, "counts")))
+                                    s.data_ptr(), s2.data_ptr(), int(B), int(M), int(N), P,
+                                    len(p), p.ctypes.data, cand.data_ptr(), int(cand.shape[0]),
+                                    out.data_ptr(), int(out.shape[0]), counts.data_ptr()))
 
 
 class Batch:
-    """Owns a sncc_batch handle and the host copies its descriptor points to."""
+    """Owns a sncc_batch handle.  The captured graph holds raw pointers to the
+    buffers and template sets it was created with, so ``_keep`` holds
+    references to all of them (and to the host copies the descriptor points
+    to) for the life of the batch."""
 
     def __init__(self, handle, keep):
         self.handle = handle
@@ -362,6 +466,7 @@ class Batch:
         if self.handle:
             _check(lib.sncc_batch_destroy(self.handle))
             self.handle = None
+            self._keep = None
 
 
 def sncc_batch_create(ctx, coarse, s, s2, B, M, N, pairs, k, topk_out, fine=None,
@@ -369,28 +474,39 @@ def sncc_batch_create(ctx, coarse, s, s2, B, M, N, pairs, k, topk_out, fine=None
                       tune_cache=None):
     import torch
     p = _pairs_array(pairs)
+    P = _tables(s, s2, B, N)
+    _chk(frames, torch.uint8, "frames", shape=(int(B), int(N), int(M)))
+    _chk(topk_out, torch.int32, "topk_out", shape=(len(p), int(k), 3))
+    if fine is not None and best_out is None:
+        raise ValueError("a batch with a fine template set needs best_out")
+    _chk(best_out, torch.int32, "best_out", shape=(len(p), 4))
+    _chk(count_out, torch.int32, "count_out", shape=(len(p),))
+    _dev(s=s, s2=s2, frames=frames, topk_out=topk_out, best_out=best_out, count_out=count_out)
+    _check_pairs(p, B, sncc_tmpl_count(coarse))
+    if fine is not None and sncc_tmpl_count(fine) != sncc_tmpl_count(coarse):
+        raise ValueError("coarse and fine template sets differ in size")
     d = sncc_batch_desc()
     d.coarse = coarse
     d.fine = fine
-    d.d_f = _ptr(frames, torch.uint8, "frames") if frames is not None else None
+    d.d_f = _p(frames)
     d.f_pitch = int(M)
-    d.d_s = _ptr(s, torch.int32, "s")
-    d.d_s2 = _ptr(s2, torch.int32, "s2")
-    d.sat_pitch = s.shape[-1]
+    d.d_s = s.data_ptr()
+    d.d_s2 = s2.data_ptr()
+    d.sat_pitch = P
     d.B, d.M, d.N = int(B), int(M), int(N)
     d.n_pairs = len(p)
     d.pairs = p.ctypes.data
     d.k = int(k)
     d.radius = int(radius)
-    d.d_topk = _ptr(topk_out, torch.int32, "topk_out")
-    d.d_best = _ptr(best_out, torch.int32, "best_out") if best_out is not None else None
-    d.d_count = _ptr(count_out, torch.int32, "count_out") if count_out is not None else None
+    d.d_topk = topk_out.data_ptr()
+    d.d_best = _p(best_out)
+    d.d_count = _p(count_out)
     d.tune = int(tune)
     cache = tune_cache.encode() if tune_cache else None
     d.tune_cache = cache
     h = C.c_void_p()
     _check(lib.sncc_batch_create(ctx, C.byref(d), C.byref(h)))
-    return Batch(h, (p, cache))
+    return Batch(h, (p, cache, coarse, fine, s, s2, frames, topk_out, best_out, count_out))
 
 
 def sncc_batch_run(batch: Batch):

@@ -923,6 +923,7 @@ int sncc_ctx_create(int device, uintptr_t hip_stream, sncc_ctx **out) {
   HIPCHK(hipSetDevice(device));
   hipDeviceProp_t prop;
   HIPCHK(hipGetDeviceProperties(&prop, device));
+
   sncc_ctx *c = new (std::nothrow) sncc_ctx();
   if (!c) SNCC_FAIL(SNCC_ENOMEM, "context allocation");
   c->device = device;
@@ -1101,6 +1102,13 @@ int sncc_tmpl_info(const sncc_tmpl *tm, int index, int *W, int *H, int *K, doubl
   if (H) *H = tm->H[index];
   if (K) *K = tm->K[index];
   if (q_k) *q_k = tm->q_k[index];
+  return SNCC_OK;
+}
+
+int sncc_tmpl_count(const sncc_tmpl *tm, int *T) {
+  g_err.clear();
+  if (!tm || !T) SNCC_FAIL(SNCC_EINVAL, "NULL template set or output");
+  *T = tm->T;
   return SNCC_OK;
 }
 

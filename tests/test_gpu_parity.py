@@ -468,9 +468,11 @@ def test_errors(S, ctx):
     with pytest.raises(S.SnccError) as e:
         S.sncc_topk(ctx, tm, s, s2, 1, 50, 40, [(0, 0)], 1, S.SNCC_FP32_KAHAN, out)
     assert e.value.code == S.SNCC_EINVAL
-    with pytest.raises(S.SnccError) as e:
+    with pytest.raises(ValueError):                            # frame index out of range
         S.sncc_topk(ctx, tm, s, s2, 1, 50, 40, [(1, 0)], 1, S.SNCC_FP32_KAHAN, out)
-    assert e.value.code == S.SNCC_EINVAL
+    p = np.array([[1, 0]], np.int32)                          # the C side checks it too
+    assert S.lib.sncc_topk(ctx, tm, s.data_ptr(), s2.data_ptr(), 1, 50, 40, s.shape[-1], 1,
+                           p.ctypes.data, 1, S.SNCC_FP32_KAHAN, out.data_ptr()) == S.SNCC_EINVAL
     halves = np.zeros(2, S.SEGMENT_DTYPE)                     # area above the exact bound
     halves[0] = (0, 0, 2048, 2049, 0, 2048 * 2049, 0)
     halves[1] = (2048, 0, 2048, 2049, 2048 * 2049 * 9, 2048 * 2049, 0)

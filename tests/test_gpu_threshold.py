@@ -293,9 +293,15 @@ def test_errors(S, ctx):
     with pytest.raises(S.SnccError):      # threshold not finite
         S.sncc_threshold_match(ctx, fast, slow, [np.nan], ts, s, s2, 1, 64, 48, [(0, 0)], cand,
                                out, counts)
-    with pytest.raises(S.SnccError):      # pair out of range
+    with pytest.raises(ValueError):       # pair out of range (binding)
         S.sncc_threshold_match(ctx, fast, slow, tf, ts, s, s2, 1, 64, 48, [(1, 0)], cand, out,
                                counts)
+    p = np.array([[1, 0]], np.int32)      # and the C side
+    tfa, tsa = np.asarray(tf, np.float64), np.asarray(ts, np.float64)
+    assert S.lib.sncc_threshold_match(ctx, fast, slow, tfa.ctypes.data, tsa.ctypes.data,
+                                      s.data_ptr(), s2.data_ptr(), 1, 64, 48, s.shape[-1], 1,
+                                      p.ctypes.data, cand.data_ptr(), 16, out.data_ptr(), 16,
+                                      counts.data_ptr()) == S.SNCC_EINVAL
     for h in (fast, slow, other):
         S.sncc_tmpl_destroy(h)
 
