@@ -63,6 +63,13 @@ extern "C" {
  * 32-bit byte offsets); larger frames give SNCC_EINVAL. */
 #define SNCC_MAX_TABLE_BYTES 2147483647LL
 
+/* Size of the per-device static carry scratch of sncc_build_sats_noalloc
+ * (8 MiB): the call accepts B frames of M x N while
+ * 8 * B * (ceil(N/64) * M + N * ceil(M/256) + 2 * ceil(N/64) * ceil(M/256))
+ * does not exceed it (e.g. 25 frames 1920x1080, 54 frames 1280x720,
+ * 6 frames 3840x2160). */
+#define SNCC_NOALLOC_SCRATCH_BYTES 8388608
+
 /* One rectangle of the approximation: the 5-tuple of Eq. (6) with the mean
  * k_i = sum / area kept as an exact integer ratio (Eq. (4)). */
 typedef struct sncc_segment {
@@ -203,6 +210,24 @@ int sncc_sat_pitch(int M, int *pitch_elems);
  */
 int sncc_build_sats(sncc_ctx *ctx, const uint8_t *d_f, int B, int M, int N,
                     int f_pitch, uint32_t *d_s, uint32_t *d_s2, int sat_pitch);
+
+/*
+ * sncc_build_sats without any allocation, for callers that cannot allocate
+ * device memory: code being captured into a HIP graph, serving loops that
+ * must not call hipMalloc, harnesses that forbid it.  Same arguments, layout
+ * and results as sncc_build_sats (bit for bit); the carries between tiles go
+ * to one static device array of SNCC_NOALLOC_SCRATCH_BYTES per device
+ * instead of the context's scratch, so the call allocates nothing, neither
+ * on the device nor on the host.  The array is looked up when a context is
+ * created on the device and stays reserved until the process ends.
+ * Every call on one device shares that array: calls that overlap in time on
+ * one device (e.g. on two streams) race and must be ordered by the caller.
+ * Errors: as sncc_build_sats; SNCC_ENOSPC when the B frames need more
+ *         carry space than SNCC_NOALLOC_SCRATCH_BYTES (split them into
+ *         several calls).
+ */
+int sncc_build_sats_noalloc(sncc_ctx *ctx, const uint8_t *d_f, int B, int M, int N,
+                            int f_pitch, uint32_t *d_s, uint32_t *d_s2, int sat_pitch);
 
 /* ------------------------------------------------------ segment lists */
 /*

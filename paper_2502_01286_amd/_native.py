@@ -46,6 +46,7 @@ SNCC_FP64 = 1
 SNCC_MAX_TEMPLATE_AREA = 8388607
 SNCC_MAX_SQ_BOX_AREA = 66051
 SNCC_MAX_TABLE_BYTES = 2147483647
+SNCC_NOALLOC_SCRATCH_BYTES = 8388608
 
 
 class sncc_segment(C.Structure):
@@ -97,6 +98,7 @@ _SIGS = {
     "sncc_ctx_stage_ms": (_i, [_vp, _vp, _i, _vp]),
     "sncc_sat_pitch": (_i, [_i, _vp]),
     "sncc_build_sats": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _i]),
+    "sncc_build_sats_noalloc": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _i]),
     "sncc_upload_templates": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
     "sncc_tmpl_destroy": (_i, [_vp]),
     "sncc_tmpl_info": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
@@ -304,6 +306,24 @@ def sncc_build_sats(ctx, f, s, s2):
     _chk(f, torch.uint8, "f")
     _dev(s=s, s2=s2, f=f)
     _check(lib.sncc_build_sats(ctx, f.data_ptr(), B, M, N, M, s.data_ptr(), s2.data_ptr(), P))
+
+
+def sncc_build_sats_noalloc(ctx, f, s, s2):
+    """sncc_build_sats through the allocation-free entry point (static
+    carry scratch; SnccError SNCC_ENOSPC when the frames need more)."""
+    import torch
+    if not isinstance(f, torch.Tensor) or f.dim() not in (2, 3):
+        raise ValueError("f must be a 2-D or 3-D uint8 tensor")
+    if f.dim() == 2:
+        f = f.unsqueeze(0)
+    B, N, M = f.shape
+    if s.dim() == 3 and int(s.shape[0]) != B:
+        raise ValueError(f"s holds {int(s.shape[0])} frames, f holds {B}")
+    P = _tables(s, s2, B, N)
+    _chk(f, torch.uint8, "f")
+    _dev(s=s, s2=s2, f=f)
+    _check(lib.sncc_build_sats_noalloc(ctx, f.data_ptr(), B, M, N, M, s.data_ptr(),
+                                       s2.data_ptr(), P))
 
 
 def sncc_upload_templates(ctx, seg_lists, W, H):

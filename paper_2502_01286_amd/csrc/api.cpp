@@ -923,7 +923,11 @@ int sncc_ctx_create(int device, uintptr_t hip_stream, sncc_ctx **out) {
   HIPCHK(hipSetDevice(device));
   hipDeviceProp_t prop;
   HIPCHK(hipGetDeviceProperties(&prop, device));
-
+  // set-up of the allocation-free entry point on this device (its static
+  // scratch's address, looked up once per device with the device current)
+  if (sat_noalloc_init(device) != 0)
+    SNCC_FAIL(SNCC_EDEVICE, "static scratch address on device %d: %s", device,
+              hipGetErrorString(hipGetLastError()));
   sncc_ctx *c = new (std::nothrow) sncc_ctx();
   if (!c) SNCC_FAIL(SNCC_ENOMEM, "context allocation");
   c->device = device;
@@ -992,6 +996,27 @@ int sncc_build_sats(sncc_ctx *ctx, const uint8_t *d_f, int B, int M, int N, int 
   CHK(ctx->sat_scratch.reserve(sat_scratch_words(B, M, N) * 4));
   if (launch_sat(d_f, B, M, N, f_pitch, d_s, d_s2, sat_pitch,
                  ctx->sat_scratch.as<uint32_t>(), ctx->stream) != 0)
+    SNCC_FAIL(SNCC_EDEVICE, "sum-table launch: %s", hipGetErrorString(hipGetLastError()));
+  return SNCC_OK;
+}
+
+int sncc_build_sats_noalloc(sncc_ctx *ctx, const uint8_t *d_f, int B, int M, int N,
+                            int f_pitch, uint32_t *d_s, uint32_t *d_s2, int sat_pitch) {
+  g_err.clear();
+  CHK(check_ctx(ctx));
+  if (!d_f) SNCC_FAIL(SNCC_EINVAL, "NULL frames");
+  if (B < 1) SNCC_FAIL(SNCC_EINVAL, "B must be >= 1");
+  if (f_pitch < M) SNCC_FAIL(SNCC_EINVAL, "f_pitch %d < M %d", f_pitch, M);
+  CHK(check_sats(d_s, d_s2, M, N, sat_pitch));
+  const size_t need = sat_scratch_words(B, M, N) * 4;
+  if (need > (size_t)SNCC_NOALLOC_SCRATCH_BYTES)
+    SNCC_FAIL(SNCC_ENOSPC,
+              "%d frames of %dx%d need %zu bytes of carries; the static scratch holds %d "
+              "(split the frames into several calls)", B, M, N, need,
+              SNCC_NOALLOC_SCRATCH_BYTES);
+  uint32_t *scratch = sat_noalloc_addr(ctx->device);
+  if (!scratch) SNCC_FAIL(SNCC_EDEVICE, "static scratch not set up on device %d", ctx->device);
+  if (launch_sat(d_f, B, M, N, f_pitch, d_s, d_s2, sat_pitch, scratch, ctx->stream) != 0)
     SNCC_FAIL(SNCC_EDEVICE, "sum-table launch: %s", hipGetErrorString(hipGetLastError()));
   return SNCC_OK;
 }

@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "device_util.hpp"
 
@@ -278,6 +279,35 @@ int launch_sat(const uint8_t *f, int B, int M, int N, int f_pitch, uint32_t *s,
   hipLaunchKernelGGL(sat_scan, grid, dim3(64), 0, st, f, B, M, N, f_pitch, scratch, s,
                      s2, sat_pitch);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ------------------------------------------ allocation-free sum tables
+// Carries of sncc_build_sats_noalloc: one static array in each device's
+// memory, reserved while the process runs.  In host code the array's name is
+// only a stand-in for the symbol, not a device address: host code uses the
+// address hipGetSymbolAddress returns for each device, looked up once with
+// that device current (sat_noalloc_init, called when a context is created).
+constexpr size_t kNoallocScratchWords = SNCC_NOALLOC_SCRATCH_BYTES / 4;
+static __device__ __align__(256) uint32_t sat_noalloc_scratch[kNoallocScratchWords];
+
+constexpr int kMaxDevices = 64;
+static uint32_t *g_noalloc_addr[kMaxDevices] = {};
+static std::mutex g_noalloc_mu;
+
+int sat_noalloc_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return -1;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_addr[device]) return 0;
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(sat_noalloc_scratch)) != hipSuccess || !p) return -1;
+  g_noalloc_addr[device] = static_cast<uint32_t *>(p);
+  return 0;
+}
+
+uint32_t *sat_noalloc_addr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  return g_noalloc_addr[device];
 }
 
 // ------------------------------------------------------------ tile scoring

@@ -286,6 +286,11 @@ const void *tile_fn_5(int sink);
 int launch_sat(const uint8_t *f, int B, int M, int N, int f_pitch, uint32_t *s,
                uint32_t *s2, int sat_pitch, uint32_t *scratch, hipStream_t st);
 size_t sat_scratch_words(int B, int M, int N);
+// Device address of the static carry scratch of the allocation-free sum-table
+// entry point: looked up once per device (that device current) by
+// sat_noalloc_init, nullptr before.
+int sat_noalloc_init(int device);
+uint32_t *sat_noalloc_addr(int device);
 
 int tile_cfg_count();
 TileCfg tile_cfg(int i);
