@@ -488,6 +488,182 @@ def run_prep(args):
     print(json.dumps(line), flush=True)
 
 
+# ------------------------------------------- per-configuration measurements
+def _band_map(job):
+    """Oracle map of offset rows [v0, v1) of one frame (the map of image rows
+    [v0, v1 + H - 1)), in sub-bands of 16 rows that keep NumPy's arrays in
+    cache; box sums are the same integers from any table origin."""
+    import numpy as np
+    import oracle as O
+    rows, ta, nvb = job
+    out = np.empty((nvb, rows.shape[1] - ta.W + 1))
+    for a in range(0, nvb, 16):
+        b = min(nvb, a + 16)
+        out[a:b] = O.rho_map(rows[a:b + ta.H - 1], ta)
+    return out
+
+
+def _oracle_map(ex, n_proc, f, ta):
+    import numpy as np
+    nv = f.shape[0] - ta.H + 1
+    step = max(16, -(-nv // (4 * n_proc)))
+    jobs = [(np.ascontiguousarray(f[v0:min(nv, v0 + step) + ta.H - 1]), ta, min(nv, v0 + step) - v0)
+            for v0 in range(0, nv, step)]
+    return np.concatenate(list(ex.map(_band_map, jobs)), axis=0)
+
+
+def _events_ms(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _single_config(S, torch, ctx, ex, n_proc, wl, sigma, k_max, full_oracle, reps=5):
+    """One frame, one template: device times of the sum tables, the FP32
+    map, the FP32 top-1 (batched persistent form) and the plain FP64 map;
+    FP32 and FP64 against the oracle (whole map, or a seeded sample of
+    offsets plus the neighbourhoods of both sides' best offsets)."""
+    import numpy as np
+    import oracle as O
+    f, t = wl.frames[0], wl.templates[0]
+    N, M = f.shape
+    H, W = t.shape
+    segs, su, _ = S.sncc_segment_template(t, sigma, k_max)
+    K = len(segs)
+    tm = S.sncc_upload_templates(ctx, [segs], [W], [H])
+    d = torch.from_numpy(f).cuda().unsqueeze(0)
+    P = S.sncc_sat_pitch(M)
+    s = torch.empty((1, N + 1, P), dtype=torch.int32, device="cuda")
+    s2 = torch.empty_like(s)
+    nu, nv = M - W + 1, N - H + 1
+    r32 = torch.empty((nv, nu), dtype=torch.float32, device="cuda")
+    r64 = torch.empty((nv, nu), dtype=torch.float64, device="cuda")
+    top1 = torch.zeros((1, 1, 3), dtype=torch.int32, device="cuda")
+    ms_sat = _events_ms(torch, lambda: S.sncc_build_sats(ctx, d, s, s2), reps)
+    ms32 = _events_ms(torch, lambda: S.sncc_score(ctx, tm, 0, s, s2, M, N, S.SNCC_FP32_KAHAN,
+                                                  r32), reps)
+    ms_top1 = _events_ms(torch, lambda: S.sncc_argmax(ctx, tm, s, s2, 1, M, N, [(0, 0)],
+                                                      S.SNCC_FP32_KAHAN, top1), reps)
+    ms64 = _events_ms(torch, lambda: S.sncc_score(ctx, tm, 0, s, s2, M, N, S.SNCC_FP64, r64),
+                      max(2, reps // 2))
+    g32 = r32.cpu().numpy().astype(np.float64)
+    g64 = r64.cpu().numpy()
+    b1 = S.decode_matches(top1)[0, 0]
+    S.sncc_tmpl_destroy(tm)
+    evals = nu * nv * K
+    ta = O.precompute_template_approximation(t, sigma, k_max)
+    a32 = np.unravel_index(int(np.argmax(g32)), g32.shape)[::-1]
+    a64 = np.unravel_index(int(np.argmax(g64)), g64.shape)[::-1]
+    out = {"frame": f"{M}x{N}", "template": f"{W}x{H}", "sigma": sigma,
+           "K_max": k_max if k_max < 10 ** 8 else None, "sigma_used": su, "K": K,
+           "offsets": nu * nv, "evals": evals,
+           "ms_sat": round(ms_sat, 4), "ms_fp32_map": round(ms32, 4),
+           "ms_fp32_top1": round(ms_top1, 4), "ms_fp64_map": round(ms64, 4),
+           "fp32_map_evals_per_s": evals / (ms32 / 1e3),
+           "fp32_top1_evals_per_s": evals / (ms_top1 / 1e3),
+           "plain_fp64_evals_per_s": evals / (ms64 / 1e3),
+           "speedup_fp32_top1_vs_plain_fp64": round(ms64 / ms_top1, 2),
+           "fp32_vs_gpu_fp64_max_abs_drho": float(np.abs(g32 - g64).max())}
+    if full_oracle:
+        want = _oracle_map(ex, n_proc, f, ta)
+        margin = O.top2_margin(want)
+        u, v, r = O.argmax(want)
+        out.update({"oracle": "whole map",
+                    "fp32_max_abs_drho": float(np.abs(g32 - want).max()),
+                    "fp64_max_abs_drho": float(np.abs(g64 - want).max()),
+                    "oracle_argmax": [u, v], "oracle_top2_margin": margin,
+                    "argmax_fp32_map": list(map(int, a32)), "argmax_fp64_map": list(map(int, a64)),
+                    "argmax_fp32_top1": [int(b1["u"]), int(b1["v"])],
+                    "argmax_match": bool(margin <= 1e-4 or (
+                        tuple(a32) == tuple(a64) == (u, v) == (int(b1["u"]), int(b1["v"]))))})
+    else:
+        rng = np.random.default_rng(77)
+        us, vs = rng.integers(0, nu, 4000), rng.integers(0, nv, 4000)
+        extra = [(int(c[0]) + du, int(c[1]) + dv) for c in (a32, a64)
+                 for du in range(-2, 3) for dv in range(-2, 3)]
+        extra = [(a, b) for a, b in extra if 0 <= a < nu and 0 <= b < nv]
+        us = np.concatenate([us, [a for a, _ in extra]])
+        vs = np.concatenate([vs, [b for _, b in extra]])
+        tables = O.sum_tables(f)
+        want = O.rho_at(*tables, ta, us, vs)
+        out.update({"oracle": f"{len(us)} offsets (4000 seeded + the neighbourhoods of the "
+                              "GPU's best offsets)",
+                    "fp32_max_abs_drho": float(np.abs(g32[vs, us] - want).max()),
+                    "fp64_max_abs_drho": float(np.abs(g64[vs, us] - want).max()),
+                    "argmax_fp32_map": list(map(int, a32)), "argmax_fp64_map": list(map(int, a64)),
+                    "argmax_fp32_top1": [int(b1["u"]), int(b1["v"])],
+                    "argmax_match": bool(tuple(a32) == tuple(a64) ==
+                                         (int(b1["u"]), int(b1["v"])))})
+    return out
+
+
+def run_configs(S, torch, ctx, args):
+    """The single-frame configurations (640x480 with a 32x32 template at
+    sigma 8; 1920x1080 with a 64x64 template at sigma 4, 8, 16; 3840x2160
+    textures with 128x128 and 256x256 templates at sigma 4, K_max 5000, and
+    the 128x128 one uncapped) and the 16 x 64 batch (top-5), each with its
+    FP32 throughput, the plain FP64 form's, and its error against the oracle."""
+    from concurrent.futures import ProcessPoolExecutor
+    from workloads import synth
+    n_proc = max(1, min(16, len(os.sched_getaffinity(0))))
+    res = {}
+    with ProcessPoolExecutor(max_workers=n_proc) as ex:
+        cases = [("scene_640x480_t32_s8", synth.scene_640x480(), 8, 5000, True)]
+        cases += [(f"scene_1920x1080_t64_s{sg}", synth.scene_1920x1080(sg), sg, 5000, True)
+                  for sg in (4, 8, 16)]
+        cases += [(f"texture_3840x2160_t{sz}_s4" + ("" if km == 5000 else "_uncapped"),
+                   synth.texture_3840x2160(sz, k_max=km), 4, km, args.full_parity)
+                  for sz, km in ((128, 5000), (256, 5000), (128, 10 ** 9))]
+        for name, wl, sg, km, full in cases:
+            t0 = time.perf_counter()
+            res[name] = _single_config(S, torch, ctx, ex, n_proc, wl, sg, km, full)
+            log(f"[bench] {name}: {res[name]} ({time.perf_counter() - t0:.1f} s)")
+    # the 16 x 64 batch: one tuned graph launch per step, against the plain form
+    wl = synth.batch_16x64()
+    B, N, M = len(wl.frames), wl.N, wl.M
+    segs = [S.sncc_segment_template(t, sg, wl.k_max)[0] for t, sg in zip(wl.templates, wl.sigmas)]
+    Kc = [len(a) for a in segs]
+    tm = S.sncc_upload_templates(ctx, segs, [t.shape[1] for t in wl.templates],
+                                 [t.shape[0] for t in wl.templates])
+    f = torch.from_numpy(__import__("numpy").stack(wl.frames)).cuda()
+    P = S.sncc_sat_pitch(M)
+    s = torch.empty((B, N + 1, P), dtype=torch.int32, device="cuda")
+    s2 = torch.empty_like(s)
+    n = len(wl.pairs)
+    topk = torch.zeros((n, wl.k, 3), dtype=torch.int32, device="cuda")
+    batch = S.sncc_batch_create(ctx, tm, s, s2, B, M, N, wl.pairs, wl.k, topk, frames=f,
+                                tune=args.tune, tune_cache=args.tune_cache)
+    ms_step = _events_ms(torch, batch.run, 5)
+    st = batch.stats()
+    evals = st["coarse_evals"]
+    out64 = torch.zeros_like(topk)
+    ms64 = _events_ms(torch, lambda: S.sncc_topk(ctx, tm, s, s2, B, M, N, wl.pairs, wl.k,
+                                                 S.SNCC_FP64, out64), 1)
+    batch.run()
+    torch.cuda.synchronize()
+    g_top = [[(int(m["u"]), int(m["v"]), float(m["rho"])) for m in row]
+             for row in S.decode_matches(topk)]
+    cpu, parity = cpu_baseline(wl, Kc, budget_s=min(8.0, args.cpu_budget), gpu_topk=g_top)
+    res["batch_16x64_top5"] = {
+        "frames": B, "templates": len(wl.templates), "pairs": n, "K": [min(Kc), max(Kc)],
+        "evals": evals, "ms_step": round(ms_step, 3), "ms_score": st["ms_score"],
+        "evals_per_s": evals / (ms_step / 1e3), "frames_per_s": B / (ms_step / 1e3),
+        "tile": f"{st['tile_u']}x{st['tile_v']}", "plain_fp64_ms": round(ms64, 3),
+        "plain_fp64_evals_per_s": evals / (ms64 / 1e3),
+        "speedup_vs_plain_fp64": round(ms64 / ms_step, 2),
+        "cpu_oracle_evals_per_s": cpu["value"], "parity": parity}
+    log(f"[bench] batch_16x64_top5: {res['batch_16x64_top5']}")
+    batch.destroy()
+    S.sncc_tmpl_destroy(tm)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -504,6 +680,10 @@ def main():
     ap.add_argument("--k", type=int, default=0, help="top-k per pair (default: the workload's)")
     ap.add_argument("--coarse-sigma", type=float, default=0,
                     help="override the coarse threshold of every template")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the per-configuration measurements (single frames, 16x64 batch)")
+    ap.add_argument("--full-parity", action="store_true",
+                    help="whole oracle maps for the 3840x2160 configurations too (minutes)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a buffer of this size (a known-size kernel for "
                          "scaling HBM counters)")
@@ -657,6 +837,10 @@ def main():
     S.sncc_tmpl_destroy(coarse)
     if fine:
         S.sncc_tmpl_destroy(fine)
+    configs = None
+    if not args.no_configs and args.workload == "coarse-fine":
+        log("[bench] per-configuration measurements")
+        configs = run_configs(S, torch, ctx, args)
     S.sncc_ctx_destroy(ctx)
 
     line = {
@@ -674,6 +858,7 @@ def main():
         "frames_per_s": B / (ms_per_step / 1e3),
         "stage_ms": avg, "prep_ms_host": prep_ms,
         "roofline": roof, "plain_fp64": plain, "cpu_baseline": cpu, "parity": parity,
+        "configs": configs,
     }
     print(json.dumps(line), flush=True)
 
