@@ -264,8 +264,11 @@ int sncc_tmpl_count(const sncc_tmpl *tm, int *T);
  *
  *   precision  SNCC_FP32_KAHAN: d_rho is float; box sums minus (area x the
  *              window mean rounded to an integer) are accumulated in FP32
- *              with compensated summation.  SNCC_FP64: d_rho is double; box
- *              sums are accumulated in FP64, one launch per call.
+ *              with compensated summation (the context keeps the work list
+ *              of its last such call and reuses it when the next has the
+ *              same template set, index, sizes and pitch).  SNCC_FP64: d_rho
+ *              is double; box sums are accumulated in FP64, one launch per
+ *              call.
  *   d_rho      device, (N-H+1) rows x rho_pitch elements (>= M-W+1)
  *   d_degenerate  device, nullable, (N-H+1) x rho_pitch bytes: 1 where the
  *              window is uniform (rho written as 0), else 0

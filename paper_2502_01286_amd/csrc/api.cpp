@@ -1172,10 +1172,20 @@ int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint32_t *d_
     return SNCC_OK;
   }
   if (precision != SNCC_FP32_KAHAN) SNCC_FAIL(SNCC_EINVAL, "unknown precision %d", precision);
-  std::unique_ptr<PlanDev> pd(new PlanDev());
+  // the plan of the last map call is kept and reused when the call repeats
+  // (same template set and index, sizes and pitch)
   const int32_t pair[2] = {0, index};
-  CHK(build_plan(tm, 0, M, N, sat_pitch, 1, pair, 0, kSinkMap, ctx->num_cu, pd->h));
-  CHK(pd->upload(ctx->stream));
+  PlanKey key;
+  key.sink = kSinkMap;
+  key.tmpl = tm->serial;
+  key.M = M;
+  key.N = N;
+  key.P = sat_pitch;
+  key.pairs.assign(pair, pair + 2);
+  PlanDev *pd = nullptr;
+  CHK(cached_plan(ctx, std::move(key), [&](PlanDev &d) {
+    return build_plan(tm, 0, M, N, sat_pitch, 1, pair, 0, kSinkMap, ctx->num_cu, d.h);
+  }, &pd));
   TileArgs a = pd->args(d_s, d_s2, (long long)(N + 1) * sat_pitch, sat_pitch, M, N);
   a.rho = d_rho;
   a.rho_pitch = rho_pitch;
@@ -1183,7 +1193,7 @@ int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint32_t *d_
   if (launch_zero(a.queue, a.n_zero, ctx->stream) != 0 ||
       launch_tile(pd->h.cfg, kSinkMap, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0)
     SNCC_FAIL(SNCC_EDEVICE, "tile launch: %s", hipGetErrorString(hipGetLastError()));
-  return retire(ctx, std::move(pd));
+  return SNCC_OK;
 }
 
 int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uint32_t *d_s2,

@@ -56,18 +56,17 @@ size_t sat_scratch_words(int B, int M, int N) {
   return (size_t)2 * B * (nTY * (size_t)M + (size_t)N * nTX + 2 * nTY * nTX);
 }
 
-// Pixels x0 .. x0 + 3 of a row (0 beyond M): one 32-bit load when all four
-// are inside the row and the address is 4-byte aligned, else byte loads.
-__device__ __forceinline__ void load_px4(const uint8_t *row, int x0, int M,
-                                         uint32_t (&v)[4]) {
-  if (x0 + 3 < M && ((reinterpret_cast<uintptr_t>(row + x0) & 3) == 0)) {
-    const uint32_t w = *reinterpret_cast<const uint32_t *>(row + x0);
+// Pixels x0 .. x0 + 3 of a row packed into one word (byte q = pixel x0 + q,
+// 0 beyond M): one 32-bit load when all four are inside the row and the
+// address is 4-byte aligned, else byte loads.
+__device__ __forceinline__ uint32_t load_pk4(const uint8_t *row, int x0, int M) {
+  if (x0 + 3 < M && ((reinterpret_cast<uintptr_t>(row + x0) & 3) == 0))
+    return *reinterpret_cast<const uint32_t *>(row + x0);
+  uint32_t w = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = (w >> (8 * q)) & 0xffu;
-  } else {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = (x0 + q < M) ? (uint32_t)row[x0 + q] : 0u;
-  }
+  for (int q = 0; q < 4; ++q)
+    if (x0 + q < M) w |= (uint32_t)row[x0 + q] << (8 * q);
+  return w;
 }
 
 // Entries x0 .. x0 + 3 of a table row (up to column M): one 16-byte store
@@ -88,53 +87,105 @@ __device__ __forceinline__ void store_4(uint32_t *o, int x0, int M, const uint32
   }
 }
 
-__global__ __launch_bounds__(64) void sat_totals(const uint8_t *__restrict__ f,
-                                                 int B, int M, int N, int f_pitch,
-                                                 uint32_t *__restrict__ scratch) {
+// Each 64 x 256 tile is one workgroup of four waves; wave w takes the tile's
+// rows 16w .. 16w + 15 (a short serial chain per wave), lanes four columns.
+constexpr int SAT_WAVES = 4;
+constexpr int SAT_WR = SAT_TY / SAT_WAVES;  // rows per wave
+
+// A lane's four columns over one wave's rows, requested before any is used.
+__device__ __forceinline__ void load_wave_rows(const uint8_t *fb, int y0, int r0, int rows,
+                                               int f_pitch, int x0, int M,
+                                               uint32_t (&pk)[SAT_WR]) {
+#pragma unroll
+  for (int r = 0; r < SAT_WR; ++r)
+    pk[r] = (r0 + r < rows && x0 < M) ? load_pk4(fb + (size_t)(y0 + r0 + r) * f_pitch, x0, M)
+                                      : 0u;
+}
+
+__global__ __launch_bounds__(256) void sat_totals(const uint8_t *__restrict__ f,
+                                                  int B, int M, int N, int f_pitch,
+                                                  uint32_t *__restrict__ scratch) {
+  __shared__ uint32_t wcol[SAT_WAVES][8][64];  // per wave: column totals of f, f^2
   SatScratch sc = sat_layout(scratch, B, M, N);
-  const int lane = threadIdx.x, J = blockIdx.x, I = blockIdx.y, b = blockIdx.z;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int J = blockIdx.x, I = blockIdx.y, b = blockIdx.z;
   const int x0 = J * SAT_TX + 4 * lane;
   const int y0 = I * SAT_TY;
   const int rows = min(SAT_TY, N - y0);
+  const int r0 = w * SAT_WR;
   const uint8_t *fb = f + (size_t)b * N * f_pitch;
+  uint32_t pk[SAT_WR];
+  load_wave_rows(fb, y0, r0, rows, f_pitch, x0, M, pk);
   uint32_t cs[4] = {0, 0, 0, 0}, cs2[4] = {0, 0, 0, 0};
   const size_t plane_row = (size_t)B * N * sc.nTX;
-  for (int r = 0; r < rows; ++r) {
-    const int y = y0 + r;
-    uint32_t v[4];
-    load_px4(fb + (size_t)y * f_pitch, x0, M, v);
+#pragma unroll
+  for (int r = 0; r < SAT_WR; ++r) {
+    if (r0 + r >= rows) continue;  // uniform; every pk index stays a constant
     uint32_t rs = 0, rs2 = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      cs[q] += v[q];
-      cs2[q] += v[q] * v[q];
-      rs += v[q];
-      rs2 += v[q] * v[q];
+      const uint32_t v = (pk[r] >> (8 * q)) & 0xffu;
+      cs[q] += v;
+      cs2[q] += v * v;
+      rs += v;
+      rs2 += v * v;
     }
     rs = wave_sum(rs);
     rs2 = wave_sum(rs2);
     if (lane == 0) {
-      const size_t o = ((size_t)b * N + y) * sc.nTX + J;
+      const size_t o = ((size_t)b * N + y0 + r0 + r) * sc.nTX + J;
       sc.rowT[o] = rs;
       sc.rowT[plane_row + o] = rs2;
     }
   }
-  const size_t plane_col = (size_t)B * sc.nTY * M;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    if (x0 + q < M) {
-      const size_t o = ((size_t)b * sc.nTY + I) * M + x0 + q;
-      sc.colT[o] = cs[q];
-      sc.colT[plane_col + o] = cs2[q];
+    wcol[w][q][lane] = cs[q];
+    wcol[w][4 + q][lane] = cs2[q];
+  }
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      for (int u = 1; u < SAT_WAVES; ++u) {
+        cs[q] += wcol[u][q][lane];
+        cs2[q] += wcol[u][4 + q][lane];
+      }
+    const size_t plane_col = (size_t)B * sc.nTY * M;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (x0 + q < M) {
+        const size_t o = ((size_t)b * sc.nTY + I) * M + x0 + q;
+        sc.colT[o] = cs[q];
+        sc.colT[plane_col + o] = cs2[q];
+      }
+    }
+    uint32_t tt = wave_sum(cs[0] + cs[1] + cs[2] + cs[3]);
+    uint32_t tt2 = wave_sum(cs2[0] + cs2[1] + cs2[2] + cs2[3]);
+    if (lane == 0) {
+      const size_t o = ((size_t)b * sc.nTY + I) * sc.nTX + J;
+      const size_t plane_t = (size_t)B * sc.nTY * sc.nTX;
+      sc.T[o] = tt;
+      sc.T[plane_t + o] = tt2;
     }
   }
-  uint32_t tt = wave_sum(cs[0] + cs[1] + cs[2] + cs[3]);
-  uint32_t tt2 = wave_sum(cs2[0] + cs2[1] + cs2[2] + cs2[3]);
-  if (lane == 0) {
-    const size_t o = ((size_t)b * sc.nTY + I) * sc.nTX + J;
-    const size_t plane_t = (size_t)B * sc.nTY * sc.nTX;
-    sc.T[o] = tt;
-    sc.T[plane_t + o] = tt2;
+}
+
+// Exclusive prefix, in place, of n words at p[0], p[stride], ...: the loads
+// of each group of 16 are issued together, then the group is summed.
+__device__ __forceinline__ void excl_prefix_inplace(uint32_t *__restrict__ p, size_t stride,
+                                                    int n) {
+  uint32_t run = 0;
+  for (int i0 = 0; i0 < n; i0 += 16) {
+    uint32_t t[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t[q] = i0 + q < n ? p[(size_t)(i0 + q) * stride] : 0u;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (i0 + q < n) {
+        p[(size_t)(i0 + q) * stride] = run;
+        run += t[q];
+      }
   }
 }
 
@@ -145,62 +196,92 @@ __global__ __launch_bounds__(256) void sat_prefix(int B, int M, int N,
   SatScratch sc = sat_layout(scratch, B, M, N);
   const long long job = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long nA = (long long)B * M, nB = (long long)B * N, nC = (long long)B * sc.nTX;
-  if (job < nA) {
-    const int b = (int)(job / M), x = (int)(job % M);
+  if (job < 2 * nA) {
+    const int p = (int)(job / nA);
+    const long long j = job - p * nA;
+    const int b = (int)(j / M), x = (int)(j % M);
     const size_t plane = (size_t)B * sc.nTY * M;
-    for (int p = 0; p < 2; ++p) {
-      uint32_t run = 0;
-      for (int I = 0; I < sc.nTY; ++I) {
-        const size_t o = p * plane + ((size_t)b * sc.nTY + I) * M + x;
-        const uint32_t t = sc.colT[o];
-        sc.colT[o] = run;
-        run += t;
-      }
-    }
-  } else if (job < nA + nB) {
-    const long long j = job - nA;
+    excl_prefix_inplace(sc.colT + p * plane + (size_t)b * sc.nTY * M + x, (size_t)M, sc.nTY);
+  } else if (job < 2 * nA + 2 * nB) {
+    const long long jj = job - 2 * nA;
+    const int p = (int)(jj / nB);
+    const long long j = jj - p * nB;
     const int b = (int)(j / N), y = (int)(j % N);
     const size_t plane = (size_t)B * N * sc.nTX;
-    for (int p = 0; p < 2; ++p) {
-      uint32_t run = 0;
-      for (int J = 0; J < sc.nTX; ++J) {
-        const size_t o = p * plane + ((size_t)b * N + y) * sc.nTX + J;
-        const uint32_t t = sc.rowT[o];
-        sc.rowT[o] = run;
-        run += t;
-      }
-    }
-  } else if (job < nA + nB + nC) {
-    const long long j = job - nA - nB;
+    excl_prefix_inplace(sc.rowT + p * plane + ((size_t)b * N + y) * sc.nTX, 1, sc.nTX);
+  } else if (job < 2 * nA + 2 * nB + 2 * nC) {
+    const long long jj = job - 2 * nA - 2 * nB;
+    const int p = (int)(jj / nC);
+    const long long j = jj - p * nC;
     const int b = (int)(j / sc.nTX), J = (int)(j % sc.nTX);
     const size_t plane = (size_t)B * sc.nTY * sc.nTX;
-    for (int p = 0; p < 2; ++p) {
-      uint32_t acc = 0;
-      for (int I = 0; I < sc.nTY; ++I) {
-        const size_t row = p * plane + ((size_t)b * sc.nTY + I) * sc.nTX;
-        sc.corner[row + J] = acc;
-        for (int Jp = 0; Jp < J; ++Jp) acc += sc.T[row + Jp];
+    const uint32_t *T = sc.T + p * plane + (size_t)b * sc.nTY * sc.nTX;
+    uint32_t *corner = sc.corner + p * plane + (size_t)b * sc.nTY * sc.nTX;
+    uint32_t acc = 0;
+    for (int I0 = 0; I0 < sc.nTY; I0 += 16) {
+      uint32_t left[16];  // per tile row: the tiles left of column J
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        left[q] = 0;
+        if (I0 + q < sc.nTY)
+          for (int Jp = 0; Jp < J; ++Jp) left[q] += T[(size_t)(I0 + q) * sc.nTX + Jp];
       }
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (I0 + q < sc.nTY) {
+          corner[(size_t)(I0 + q) * sc.nTX + J] = acc;
+          acc += left[q];
+        }
     }
   }
 }
 
-__global__ __launch_bounds__(64) void sat_scan(const uint8_t *__restrict__ f,
-                                               int B, int M, int N, int f_pitch,
-                                               const uint32_t *__restrict__ scratch,
-                                               uint32_t *__restrict__ s,
-                                               uint32_t *__restrict__ s2,
-                                               int P) {
+__global__ __launch_bounds__(256) void sat_scan(const uint8_t *__restrict__ f,
+                                                int B, int M, int N, int f_pitch,
+                                                const uint32_t *__restrict__ scratch,
+                                                uint32_t *__restrict__ s,
+                                                uint32_t *__restrict__ s2,
+                                                int P) {
+  __shared__ uint32_t wcol[SAT_WAVES][8][64];  // per wave: column totals of f, f^2
   SatScratch sc = sat_layout(const_cast<uint32_t *>(scratch), B, M, N);
-  const int lane = threadIdx.x, J = blockIdx.x, I = blockIdx.y, b = blockIdx.z;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int J = blockIdx.x, I = blockIdx.y, b = blockIdx.z;
   const int x0 = J * SAT_TX + 4 * lane;
   const int y0 = I * SAT_TY;
   const int rows = min(SAT_TY, N - y0);
+  const int r0 = w * SAT_WR;
   const uint8_t *fb = f + (size_t)b * N * f_pitch;
   uint32_t *sb = s + (size_t)b * (N + 1) * P;
   uint32_t *s2b = s2 + (size_t)b * (N + 1) * P;
 
-  // running column sums start at the sum of all rows above the tile
+  uint32_t pk[SAT_WR];
+  load_wave_rows(fb, y0, r0, rows, f_pitch, x0, M, pk);
+  // this wave's column totals, for the waves below it (rows past the frame
+  // are 0).  Sums of f as two 16-bit halves of a word (16 rows of bytes stay
+  // below 2^16), squares as byte dot products: other instructions than the
+  // row loop's, so the compiler does not keep the products of all 16 rows
+  // live for the loop to reuse.
+  {
+    uint32_t lo = 0, hi = 0, t2[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < SAT_WR; ++r) {
+      const uint32_t x = pk[r];
+      lo += x & 0x00ff00ffu;           // columns 0 and 2
+      hi += (x >> 8) & 0x00ff00ffu;    // columns 1 and 3
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t m = x & (0xffu << (8 * q));
+        t2[q] = __builtin_amdgcn_udot4(m, m, t2[q], false);
+      }
+    }
+    wcol[w][0][lane] = lo & 0xffffu;
+    wcol[w][1][lane] = hi & 0xffffu;
+    wcol[w][2][lane] = lo >> 16;
+    wcol[w][3][lane] = hi >> 16;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wcol[w][4 + q][lane] = t2[q];
+  }
+  // running column sums start at the sum of all rows above this wave's rows
   uint32_t cs[4], cs2[4];
   const size_t plane_col = (size_t)B * sc.nTY * M;
 #pragma unroll
@@ -221,33 +302,41 @@ __global__ __launch_bounds__(64) void sat_scan(const uint8_t *__restrict__ f,
   const size_t plane_t = (size_t)B * sc.nTY * sc.nTX;
   const uint32_t L = sc.corner[oc] + wave_incl_scan(rl);
   const uint32_t L2 = sc.corner[plane_t + oc] + wave_incl_scan(rl2);
+  __syncthreads();
+  for (int u = 0; u < w; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cs[q] += wcol[u][q][lane];
+      cs2[q] += wcol[u][4 + q][lane];
+    }
 
-  for (int r = 0; r < rows; ++r) {
-    const int y = y0 + r;
-    uint32_t v[4];
-    load_px4(fb + (size_t)y * f_pitch, x0, M, v);
+#pragma unroll
+  for (int r = 0; r < SAT_WR; ++r) {
+    if (r0 + r >= rows) continue;  // uniform; every pk index stays a constant
+    const int y = y0 + r0 + r;
     uint32_t p[4], p2[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      cs[q] += v[q];
-      cs2[q] += v[q] * v[q];
+      const uint32_t v = (pk[r] >> (8 * q)) & 0xffu;
+      cs[q] += v;
+      cs2[q] += v * v;
       p[q] = (q ? p[q - 1] : 0u) + cs[q];
       p2[q] = (q ? p2[q - 1] : 0u) + cs2[q];
     }
     const uint32_t ex = wave_incl_scan(p[3]) - p[3];
     const uint32_t ex2 = wave_incl_scan(p2[3]) - p2[3];
-    const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)L, r) + ex;
-    const uint32_t base2 = (uint32_t)__builtin_amdgcn_readlane((int)L2, r) + ex2;
+    const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)L, r0 + r) + ex;
+    const uint32_t base2 = (uint32_t)__builtin_amdgcn_readlane((int)L2, r0 + r) + ex2;
     uint32_t *o = sb + (size_t)(y + 1) * P + 1;
     uint32_t *o2 = s2b + (size_t)(y + 1) * P + 1;
-    uint32_t w[4], w2[4];
+    uint32_t wv[4], wv2[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      w[q] = base + p[q];
-      w2[q] = base2 + p2[q];
+      wv[q] = base + p[q];
+      wv2[q] = base2 + p2[q];
     }
-    store_4(o, x0, M, w);
-    store_4(o2, x0, M, w2);
+    store_4(o, x0, M, wv);
+    store_4(o2, x0, M, wv2);
     if (J == 0 && lane == 0) {  // padded column 0
       sb[(size_t)(y + 1) * P] = 0;
       s2b[(size_t)(y + 1) * P] = 0;
@@ -258,8 +347,11 @@ __global__ __launch_bounds__(64) void sat_scan(const uint8_t *__restrict__ f,
         s2b[(size_t)(y + 1) * P + c] = 0;
       }
     }
+    // rows one after another: keeps the scheduler from interleaving all of a
+    // wave's rows (which held every row's partial sums live at once)
+    __builtin_amdgcn_sched_barrier(0);
   }
-  if (I == 0) {  // padded row 0
+  if (I == 0 && w == 0) {  // padded row 0
     for (int c = J * SAT_TX + lane; c < (J + 1) * SAT_TX + (J == sc.nTX - 1 ? P : 0) && c < P;
          c += 64) {
       sb[c] = 0;
@@ -272,12 +364,13 @@ int launch_sat(const uint8_t *f, int B, int M, int N, int f_pitch, uint32_t *s,
                uint32_t *s2, int sat_pitch, uint32_t *scratch, hipStream_t st) {
   const int nTX = (M + SAT_TX - 1) / SAT_TX, nTY = (N + SAT_TY - 1) / SAT_TY;
   dim3 grid(nTX, nTY, B);
-  hipLaunchKernelGGL(sat_totals, grid, dim3(64), 0, st, f, B, M, N, f_pitch, scratch);
-  const long long jobs = (long long)B * M + (long long)B * N + (long long)B * nTX;
+  hipLaunchKernelGGL(sat_totals, grid, dim3(64 * SAT_WAVES), 0, st, f, B, M, N, f_pitch,
+                     scratch);
+  const long long jobs = 2 * ((long long)B * M + (long long)B * N + (long long)B * nTX);
   hipLaunchKernelGGL(sat_prefix, dim3((unsigned)((jobs + 255) / 256)), dim3(256), 0, st,
                      B, M, N, scratch);
-  hipLaunchKernelGGL(sat_scan, grid, dim3(64), 0, st, f, B, M, N, f_pitch, scratch, s,
-                     s2, sat_pitch);
+  hipLaunchKernelGGL(sat_scan, grid, dim3(64 * SAT_WAVES), 0, st, f, B, M, N, f_pitch, scratch,
+                     s, s2, sat_pitch);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -481,14 +574,18 @@ __global__ __launch_bounds__(256) void merge_kernel(const PairDesc *__restrict__
     for (int item = ib; item < ie; item += g) {
       const int mi = item + lane / k;
       const u64 mine = lane < g * k && mi < ie ? part[(long long)mi * k + lane % k] : 0;
-      const int gi = min(g, ie - item);
-      for (int q = 0; q < gi; ++q)
-        for (int j = 0; j < k; ++j) {  // each item's list is in descending order
-          const u64 key = lane_u64(mine, q * k + j);
-          if (key <= thr) break;
-          topk_insert(lkey, key, k, lane);
-          thr = lane_u64(lkey, k - 1);
-        }
+      // only keys above the current k-th can enter; the lanes holding them are
+      // visited in lane order (item by item, each item's keys in descending
+      // order), and a key is checked again against the k-th as it rises
+      u64 cand = __ballot(mine > thr);
+      while (cand) {
+        const int l = __ffsll((long long)cand) - 1;
+        cand &= cand - 1;
+        const u64 key = lane_u64(mine, l);
+        if (key <= thr) continue;
+        topk_insert(lkey, key, k, lane);
+        thr = lane_u64(lkey, k - 1);
+      }
     }
   };
   merge_items(partial, pd.item_begin, pd.item_end);

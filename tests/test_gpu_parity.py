@@ -289,6 +289,40 @@ def test_topk_repeated_calls_match_fresh_contexts(S, ctx):
         S.sncc_tmpl_destroy(h)
 
 
+def test_map_repeated_calls_match_fresh_contexts(S, ctx):
+    """A context keeps the plan of its last FP32 map call; calls that change
+    the template index, the template set or the tables must give exactly what
+    a fresh context gives."""
+    import torch
+    frames, temps, sigmas, _ = _multi(95, B=2)
+    N, M = frames[0].shape
+    _, s, s2 = build_sats(S, ctx, frames[:1])
+    _, r, r2 = build_sats(S, ctx, frames[1:])
+    tm = lib_templates(S, ctx, temps, sigmas)
+    tm2 = lib_templates(S, ctx, temps[::-1], sigmas[::-1])
+
+    def run(c, t, i, tabs):
+        W, H, _, _ = S.sncc_tmpl_info(t, i)
+        out = torch.full((N - H + 1, M - W + 1), 7.0, dtype=torch.float32, device="cuda")
+        S.sncc_score(c, t, i, tabs[0], tabs[1], M, N, S.SNCC_FP32_KAHAN, out)
+        S.sncc_sync(c)
+        return out.cpu().numpy()
+
+    calls = [(tm, 0, (s, s2)), (tm, 0, (s, s2)), (tm, 1, (s, s2)), (tm, 1, (r, r2)),
+             (tm2, 2, (r, r2)), (tm, 0, (s, s2))]
+    got = [run(ctx, *c) for c in calls]
+    for i, (c, g) in enumerate(zip(calls, got)):
+        fresh = S.sncc_ctx_create(0)
+        try:
+            want = run(fresh, *c)
+        finally:
+            S.sncc_ctx_destroy(fresh)
+        assert np.array_equal(g, want), i
+    assert np.array_equal(got[0], got[1]) and np.array_equal(got[0], got[-1])
+    for h in (tm, tm2):
+        S.sncc_tmpl_destroy(h)
+
+
 # ------------------------------------------------------------------ refine
 @pytest.mark.parametrize("case", ["default", "large_fine", "radius3"])
 def test_refine_parity(S, ctx, case):
