@@ -552,6 +552,19 @@ def _single_config(S, torch, ctx, ex, n_proc, wl, sigma, k_max, full_oracle, rep
                                                       S.SNCC_FP32_KAHAN, top1), reps)
     ms64 = _events_ms(torch, lambda: S.sncc_score(ctx, tm, 0, s, s2, M, N, S.SNCC_FP64, r64),
                       max(2, reps // 2))
+    # from the frame: tile-local sum tables (when the template allows) and the
+    # global form (tables of the frame, then the map)
+    rf = torch.empty((nv, nu), dtype=torch.float32, device="cuda")
+    fr = d[0]
+    forms = {}
+    for name, form in (("tile_local", S.SNCC_FORM_TILE_LOCAL), ("global", S.SNCC_FORM_GLOBAL)):
+        try:
+            forms[name] = round(_events_ms(torch, lambda: S.sncc_score_frame(
+                ctx, tm, 0, fr, rf, form=form), reps), 4)
+        except S.SnccError:
+            forms[name] = None
+    forms["auto_picks"] = "tile_local" if S.sncc_score_frame(ctx, tm, 0, fr, rf) == \
+        S.SNCC_FORM_TILE_LOCAL else "global"
     g32 = r32.cpu().numpy().astype(np.float64)
     g64 = r64.cpu().numpy()
     b1 = S.decode_matches(top1)[0, 0]
@@ -569,6 +582,7 @@ def _single_config(S, torch, ctx, ex, n_proc, wl, sigma, k_max, full_oracle, rep
            "fp32_top1_evals_per_s": evals / (ms_top1 / 1e3),
            "plain_fp64_evals_per_s": evals / (ms64 / 1e3),
            "speedup_fp32_top1_vs_plain_fp64": round(ms64 / ms_top1, 2),
+           "ms_map_from_frame": forms,
            "fp32_vs_gpu_fp64_max_abs_drho": float(np.abs(g32 - g64).max())}
     if full_oracle:
         want = _oracle_map(ex, n_proc, f, ta)

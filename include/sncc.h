@@ -280,6 +280,37 @@ int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index,
                int sat_pitch, int precision, void *d_rho, int rho_pitch,
                uint8_t *d_degenerate);
 
+/* Forms of sncc_score_frame */
+#define SNCC_FORM_AUTO 0        /* tile-local when allowed and K <= 40         */
+#define SNCC_FORM_TILE_LOCAL 1  /* sum tables built per tile in LDS            */
+#define SNCC_FORM_GLOBAL 2      /* the frame's tables first, then sncc_score   */
+
+/*
+ * rho of Eq. (18) at every offset of one frame for template `index`, FP32
+ * compensated (as sncc_score with SNCC_FP32_KAHAN), taken straight from the
+ * frame: no sum tables are passed in.  In the tile-local form each tile of
+ * 64 x 16 offsets builds the sum tables (Eqs. (10), (14)) of its image region
+ * (16 + H rows, 64 + W columns) in LDS and reads every window and segment box
+ * sum (Eqs. (11), (13), (15)) from them; box sums are the same integers from
+ * any table origin.  It applies when W * H <= SNCC_MAX_SQ_BOX_AREA, W <= 511
+ * and (17 + H) x (pitch class >= 65 + W) words fit 160 KB of LDS (e.g. up to
+ * 128 x 128 templates).  The global form builds the frame's tables (context
+ * scratch) and runs sncc_score.
+ *
+ *   d_f        device, N rows x f_pitch bytes
+ *   form       SNCC_FORM_AUTO, SNCC_FORM_TILE_LOCAL (SNCC_ERANGE when the
+ *              template does not allow it) or SNCC_FORM_GLOBAL
+ *   d_rho      device float, (N-H+1) rows x rho_pitch (>= M-W+1)
+ *   d_degenerate  nullable, as in sncc_score
+ *   d_energy   device, nullable, int64 at the same positions as d_rho: the
+ *              exact window energy n * sum f^2 - (sum f)^2 (n times Eq. (16))
+ *   form_used  host, nullable: the form that ran
+ * Errors: SNCC_EINVAL, SNCC_ERANGE, SNCC_ENOMEM, SNCC_EDEVICE.
+ */
+int sncc_score_frame(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint8_t *d_f,
+                     int M, int N, int f_pitch, int form, float *d_rho, int rho_pitch,
+                     uint8_t *d_degenerate, int64_t *d_energy, int *form_used);
+
 /*
  * The k highest-scoring offsets of each (frame, template) pair (Section 2:
  * the match is the offset with the highest rho).  Ordering: higher rho

@@ -43,6 +43,9 @@ SNCC_EDEGENERATE = -5
 SNCC_EDEVICE = -6
 SNCC_FP32_KAHAN = 0
 SNCC_FP64 = 1
+SNCC_FORM_AUTO = 0
+SNCC_FORM_TILE_LOCAL = 1
+SNCC_FORM_GLOBAL = 2
 SNCC_MAX_TEMPLATE_AREA = 8388607
 SNCC_MAX_SQ_BOX_AREA = 66051
 SNCC_MAX_TABLE_BYTES = 2147483647
@@ -104,6 +107,7 @@ _SIGS = {
     "sncc_tmpl_info": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "sncc_tmpl_count": (_i, [_vp, _vp]),
     "sncc_score": (_i, [_vp, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _i, _vp]),
+    "sncc_score_frame": (_i, [_vp, _vp, _i, _vp, _i, _i, _i, _i, _vp, _i, _vp, _vp, _vp]),
     "sncc_topk": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _i, _i, _vp]),
     "sncc_argmax": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _i, _vp]),
     "sncc_refine": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _vp, _i, _i, _vp, _vp]),
@@ -376,6 +380,35 @@ def sncc_score(ctx, tm, index, s, s2, M, N, precision, rho, degen=None):
     _dev(s=s, s2=s2, rho=rho, degen=degen)
     _check(lib.sncc_score(ctx, tm, int(index), s.data_ptr(), s2.data_ptr(), int(M), int(N), P,
                           int(precision), rho.data_ptr(), pitch, _p(degen)))
+
+
+def sncc_score_frame(ctx, tm, index, f, rho, form=SNCC_FORM_AUTO, degen=None, energy=None):
+    """FP32-compensated rho map of one frame (uint8 (N, M) device tensor)
+    for template `index`, without sum tables passed in; rho: float32
+    (N-H+1, pitch >= M-W+1); degen: nullable uint8 and energy: nullable int64
+    tensors of rho's shape.  Returns the form that ran."""
+    import torch
+    if not isinstance(f, torch.Tensor) or f.dim() != 2:
+        raise ValueError("f must be a 2-D uint8 tensor")
+    N, M = int(f.shape[0]), int(f.shape[1])
+    _chk(f, torch.uint8, "f")
+    if not isinstance(rho, torch.Tensor) or rho.dim() != 2:
+        raise ValueError("rho must be a 2-D float32 tensor")
+    _chk(rho, torch.float32, "rho")
+    _chk(degen, torch.uint8, "degen", shape=tuple(rho.shape))
+    _chk(energy, torch.int64, "energy", shape=tuple(rho.shape))
+    W, H, _, _ = sncc_tmpl_info(tm, index)
+    nu, nv = M - W + 1, N - H + 1
+    if nu < 1 or nv < 1:
+        raise ValueError(f"template {W}x{H} larger than the image {M}x{N}")
+    if int(rho.shape[0]) != nv or int(rho.shape[1]) < nu:
+        raise ValueError(f"rho must have shape ({nv}, >= {nu}), got {tuple(rho.shape)}")
+    _dev(f=f, rho=rho, degen=degen, energy=energy)
+    used = C.c_int(-1)
+    _check(lib.sncc_score_frame(ctx, tm, int(index), f.data_ptr(), M, N, M, int(form),
+                                rho.data_ptr(), int(rho.shape[1]), _p(degen), _p(energy),
+                                C.byref(used)))
+    return used.value
 
 
 def _pairs_array(pairs):

@@ -26,7 +26,7 @@ ARCH = os.environ.get("SNCC_OFFLOAD_ARCH", "gfx950")
 # separate objects built from one source so that they compile in parallel.
 N_TILE_SHAPES = 6
 SOURCES = [("segment.cpp", [], "segment.o"), ("api.cpp", [], "api.o"),
-           ("kernels.hip", [], "kernels.o")] + [
+           ("kernels.hip", [], "kernels.o"), ("fused_kernel.hip", [], "fused_kernel.o")] + [
     ("tile_entry.hip", [f"-DSNCC_TILE_ENTRY_ID={i}"], f"tile_entry_{i}.o")
     for i in range(N_TILE_SHAPES)]
 

@@ -125,6 +125,7 @@ struct sncc_ctx {
   int num_cu = 0;
   DevBuf sat_scratch;
   DevBuf map_scratch;
+  DevBuf frame_s, frame_s2;  // one frame's tables (global form of sncc_score_frame)
   std::vector<std::unique_ptr<PlanDev>> retired;  // awaiting completion
   bool timing = false;                             // record stage events
   hipEvent_t tev[4] = {};
@@ -150,7 +151,7 @@ struct sncc_tmpl {
   std::vector<std::vector<double>> c64;
   std::vector<double> q_k, r64;
   std::vector<DevTmpl> dev;  // generic (plain / refine) descriptors
-  DevBuf d_geom, d_c64, d_area, d_dev;
+  DevBuf d_geom, d_c64, d_area, d_dev, d_c32;
 };
 
 namespace {
@@ -370,6 +371,25 @@ constexpr int kSplitNone = 0, kSplitMain = 1, kSplitEdge = 2;
 bool has_edge(int nu, int main_bu) {
   const int r = nu % main_bu;
   return r > 0 && r <= main_bu / 2;
+}
+
+// Tile configuration of the one-call entry points (no tuner): 128 x 32
+// tiles in eight-wave workgroups, two per CU (on single frames it beat the
+// 128 x 16 four-wave shape the tuner picks for the batches, whose smaller LDS
+// budget sends large templates to the direct form), or 64 x 16 tiles when the
+// pairs hold fewer 128 x 32 tiles than half the CUs (a small frame would
+// leave most CUs idle).
+int one_call_cfg(const sncc_tmpl *tm, int M, int N, int n_pairs, const int32_t *pairs,
+                 int num_cu) {
+  constexpr int kWide = 0, kNarrow = 6;
+  const TileCfg tc = tile_cfg(kWide);
+  long long tiles = 0;
+  for (int p = 0; p < n_pairs; ++p) {
+    const int t = pairs[2 * p + 1];
+    const long long nu = M - tm->W[t] + 1, nv = N - tm->H[t] + 1;
+    tiles += ((nu + tc.bu() - 1) / tc.bu()) * ((nv + tc.bv() - 1) / tc.bv());
+  }
+  return 2 * tiles >= (long long)std::max(1, num_cu) ? kWide : kNarrow;
 }
 
 int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int P, int n_pairs,
@@ -1100,8 +1120,10 @@ int sncc_upload_templates(sncc_ctx *ctx, int T, const sncc_segment *const *segs,
     tm->c64.push_back(std::move(c));
     tm->dev.push_back(d);
   }
+  std::vector<float> c32all(c64all.begin(), c64all.end());
   CHK(tm->d_geom.upload(geom, ctx->stream));
   CHK(tm->d_c64.upload(c64all, ctx->stream));
+  CHK(tm->d_c32.upload(c32all, ctx->stream));
   CHK(tm->d_area.upload(areas, ctx->stream));
   CHK(tm->d_dev.upload(tm->dev, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1184,7 +1206,8 @@ int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint32_t *d_
   key.pairs.assign(pair, pair + 2);
   PlanDev *pd = nullptr;
   CHK(cached_plan(ctx, std::move(key), [&](PlanDev &d) {
-    return build_plan(tm, 0, M, N, sat_pitch, 1, pair, 0, kSinkMap, ctx->num_cu, d.h);
+    return build_plan(tm, one_call_cfg(tm, M, N, 1, pair, ctx->num_cu), M, N, sat_pitch, 1,
+                      pair, 0, kSinkMap, ctx->num_cu, d.h);
   }, &pd));
   TileArgs a = pd->args(d_s, d_s2, (long long)(N + 1) * sat_pitch, sat_pitch, M, N);
   a.rho = d_rho;
@@ -1193,6 +1216,78 @@ int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint32_t *d_
   if (launch_zero(a.queue, a.n_zero, ctx->stream) != 0 ||
       launch_tile(pd->h.cfg, kSinkMap, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0)
     SNCC_FAIL(SNCC_EDEVICE, "tile launch: %s", hipGetErrorString(hipGetLastError()));
+  return SNCC_OK;
+}
+
+constexpr int kTileLocalMaxK = 40;
+
+int sncc_score_frame(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint8_t *d_f,
+                     int M, int N, int f_pitch, int form, float *d_rho, int rho_pitch,
+                     uint8_t *d_degenerate, int64_t *d_energy, int *form_used) {
+  g_err.clear();
+  CHK(check_ctx(ctx));
+  if (!tm || index < 0 || index >= tm->T) SNCC_FAIL(SNCC_EINVAL, "bad template index");
+  if (!d_f || !aligned16(d_f)) SNCC_FAIL(SNCC_EINVAL, "NULL or misaligned frame");
+  if (M < 1 || N < 1 || f_pitch < M) SNCC_FAIL(SNCC_EINVAL, "bad frame size %dx%d, pitch %d", M,
+                                                N, f_pitch);
+  if (!d_rho || !aligned16(d_rho)) SNCC_FAIL(SNCC_EINVAL, "NULL or misaligned rho map");
+  if (d_energy && ((uintptr_t)d_energy & 7u)) SNCC_FAIL(SNCC_EINVAL, "misaligned energy map");
+  if (form < SNCC_FORM_AUTO || form > SNCC_FORM_GLOBAL) SNCC_FAIL(SNCC_EINVAL, "bad form %d", form);
+  const int W = tm->W[index], H = tm->H[index];
+  const int nu = M - W + 1, nv = N - H + 1;
+  if (nu < 1 || nv < 1) SNCC_FAIL(SNCC_EINVAL, "template larger than image");
+  if (rho_pitch < nu) SNCC_FAIL(SNCC_EINVAL, "rho_pitch %d < %d", rho_pitch, nu);
+  const bool local_ok = (long long)W * H <= kMaxSqBoxArea && fused_lp(W) > 0 &&
+                        fused_lds_bytes(W, H) <= (size_t)kFusedMaxLds;
+  if (form == SNCC_FORM_TILE_LOCAL && !local_ok)
+    SNCC_FAIL(SNCC_ERANGE, "template %dx%d does not allow the tile-local form", W, H);
+  // automatic choice: the tile-local form reads four LDS entries per segment
+  // and offset where the batched kernel's chains read fewer, so it wins only
+  // while building the frame's tables costs more than the segments (measured
+  // on one MI355X: 2x faster at K = 23, 1.2x at K = 12, 0.9x at K = 72)
+  const bool local = form == SNCC_FORM_TILE_LOCAL ||
+                     (form == SNCC_FORM_AUTO && local_ok && tm->K[index] <= kTileLocalMaxK);
+  const int used = local ? SNCC_FORM_TILE_LOCAL : SNCC_FORM_GLOBAL;
+  if (used == SNCC_FORM_TILE_LOCAL) {
+    FusedArgs a;
+    a.f = d_f;
+    a.M = M;
+    a.N = N;
+    a.f_pitch = f_pitch;
+    a.W = W;
+    a.H = H;
+    a.K = tm->K[index];
+    a.nu = nu;
+    a.nv = nv;
+    a.geom = tm->d_geom.as<int4>() + tm->seg_off[index];
+    a.area = tm->d_area.as<int>() + tm->seg_off[index];
+    a.c32 = tm->d_c32.as<float>() + tm->seg_off[index];
+    a.q_k = tm->q_k[index];
+    a.rho = d_rho;
+    a.rho_pitch = rho_pitch;
+    a.degen = d_degenerate;
+    a.energy = reinterpret_cast<long long *>(d_energy);
+    if (launch_fused(a, ctx->stream) != 0)
+      SNCC_FAIL(SNCC_EDEVICE, "tile-local launch: %s", hipGetErrorString(hipGetLastError()));
+  } else {
+    int P = 0;
+    sncc_sat_pitch(M, &P);
+    const size_t bytes = (size_t)(N + 1) * P * 4;
+    CHK(ctx->frame_s.reserve(bytes));
+    CHK(ctx->frame_s2.reserve(bytes));
+    CHK(ctx->sat_scratch.reserve(sat_scratch_words(1, M, N) * 4));
+    uint32_t *s = ctx->frame_s.as<uint32_t>(), *s2 = ctx->frame_s2.as<uint32_t>();
+    if (launch_sat(d_f, 1, M, N, f_pitch, s, s2, P, ctx->sat_scratch.as<uint32_t>(),
+                   ctx->stream) != 0)
+      SNCC_FAIL(SNCC_EDEVICE, "sum-table launch: %s", hipGetErrorString(hipGetLastError()));
+    CHK(sncc_score(ctx, tm, index, s, s2, M, N, P, SNCC_FP32_KAHAN, d_rho, rho_pitch,
+                   d_degenerate));
+    if (d_energy && launch_energy(s, s2, P, nu, nv, W, H, tm->dev[index].sq_rows,
+                                  reinterpret_cast<long long *>(d_energy), rho_pitch,
+                                  ctx->stream) != 0)
+      SNCC_FAIL(SNCC_EDEVICE, "energy launch: %s", hipGetErrorString(hipGetLastError()));
+  }
+  if (form_used) *form_used = used;
   return SNCC_OK;
 }
 
@@ -1218,7 +1313,8 @@ int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uin
     key.pairs.assign(pairs, pairs + 2 * n_pairs);
     PlanDev *pd = nullptr;
     CHK(cached_plan(ctx, std::move(key), [&](PlanDev &d) {
-      return build_plan(tm, 0, M, N, sat_pitch, n_pairs, pairs, k, kSinkTopk, ctx->num_cu, d.h);
+      return build_plan(tm, one_call_cfg(tm, M, N, n_pairs, pairs, ctx->num_cu), M, N,
+                        sat_pitch, n_pairs, pairs, k, kSinkTopk, ctx->num_cu, d.h);
     }, &pd));
     TileArgs a = pd->args(d_s, d_s2, fs, sat_pitch, M, N);
     ctx->n_stages = 0;

@@ -541,6 +541,31 @@ int launch_plain(const PlainArgs &a, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Exact window energy V = n * sum f^2 - (sum f)^2 (n times Eq. (16)) at every
+// offset, from the frame's tables (the f^2 sum banded when the window exceeds
+// one exact box).
+__global__ __launch_bounds__(256) void energy_kernel(const uint32_t *__restrict__ S,
+                                                     const uint32_t *__restrict__ S2, int P,
+                                                     int nu, int nv, int W, int H, int sq_rows,
+                                                     long long *__restrict__ energy, int pitch) {
+  const int u = blockIdx.x * 64 + (threadIdx.x & 63), v = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (u >= nu || v >= nv) return;
+  const uint32_t *a0 = S + (long long)v * P + u;
+  const uint32_t *a1 = a0 + (long long)H * P;
+  const uint32_t sf = (a1[W] - a1[0]) - (a0[W] - a0[0]);
+  const u64 sf2 = window_sq(S2 + (long long)v * P + u, W, H, P, sq_rows);
+  const u64 n = (u64)W * (u64)H;
+  energy[(long long)v * pitch + u] = (long long)(n * sf2 - (u64)sf * sf);
+}
+
+int launch_energy(const uint32_t *s, const uint32_t *s2, int P, int nu, int nv, int W, int H,
+                  int sq_rows, long long *energy, int pitch, hipStream_t st) {
+  dim3 grid((nu + 63) / 64, (nv + 3) / 4);
+  hipLaunchKernelGGL(energy_kernel, grid, dim3(256), 0, st, s, s2, P, nu, nv, W, H, sq_rows,
+                     energy, pitch);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // ---------------------------------------------------------- small kernels
 __global__ void zero_kernel(int *p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

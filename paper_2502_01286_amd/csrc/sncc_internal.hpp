@@ -239,6 +239,23 @@ struct PlainArgs {
   uint8_t *degen;
 };
 
+// Tile-local form (fused_kernel.hip): one frame, one template, sum tables
+// built per tile in LDS from the frame.
+struct FusedArgs {
+  const uint8_t *f;
+  int M, N, f_pitch;
+  int W, H, K, nu, nv;
+  const int4 *geom;        // x, y, w, h
+  const int *area;
+  const float *c32;        // c_i rounded to FP32
+  double q_k;
+  float *rho;
+  int rho_pitch;
+  uint8_t *degen;
+  long long *energy;
+};
+constexpr int kFusedMaxLds = 160 * 1024 - 64;
+
 // Tile kernel configuration: offsets per lane RU (u, stride 64) x RV (v),
 // NW waves per workgroup, each wave owning RV offset rows; `wgs` is the
 // number of workgroups per CU the LDS budget is sized for; with
@@ -301,6 +318,11 @@ int launch_tile(int cfg, int sink, const TileArgs &a, int grid,
 int tile_max_lds();
 int tile_occupancy(int cfg, int sink, int lds_bytes);
 int launch_plain(const PlainArgs &a, hipStream_t st);
+int fused_lp(int W);
+size_t fused_lds_bytes(int W, int H);
+int launch_fused(const FusedArgs &a, hipStream_t st);
+int launch_energy(const uint32_t *s, const uint32_t *s2, int P, int nu, int nv, int W, int H,
+                  int sq_rows, long long *energy, int pitch, hipStream_t st);
 int launch_zero(int *p, int n, hipStream_t st);
 int launch_merge(const PairDesc *pairs, const PairDesc *pairs2, int n_pairs,
                  const unsigned long long *partial, const unsigned long long *partial2,
