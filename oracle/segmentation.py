@@ -115,54 +115,56 @@ def _same_mean(a: Segment, b: Segment) -> bool:
     return a.total * b.area == b.total * a.area
 
 
+def _absorb_runs(k: List[Segment], order, follows, grow) -> None:
+    """One pass of ``merge_redundant_segments``: sort by ``order``, then walk
+    the list keeping the segment that currently heads a run.  A segment that
+    ``follows`` the head (adjacent along the pass's axis, same extent across
+    it) and has the same exact mean is absorbed by the head (``grow`` adds its
+    extent; sums and areas add, so the head's mean is unchanged) and left
+    empty; any other segment heads the next run."""
+    k.sort(key=order)
+    head = None
+    for seg in k:
+        if head is not None and follows(head, seg) and _same_mean(head, seg):
+            grow(head, seg)
+            head.total += seg.total
+            head.area += seg.area
+        else:
+            head = seg
+
+
+def _grow_down(head: Segment, seg: Segment) -> None:
+    head.h += seg.h
+    seg.h = 0
+
+
+def _grow_right(head: Segment, seg: Segment) -> None:
+    head.w += seg.w
+    seg.w = 0
+
+
 def merge_redundant_segments(segs: List[Segment]) -> List[Segment]:
     """``merge_redundant_segments`` of Section 5, on a copy of the list.
 
-    Sort by (x, y) and merge vertically adjacent segments with the same x,
-    the same width and equal means; sort by (y, x) and merge horizontally
-    adjacent ones with the same y, the same height and equal means; drop the
-    emptied segments; repeat while the drop removed anything.
+    In the paper's order: sort by (x, y) and join vertically adjacent segments
+    with the same x, the same width and equal means; sort by (y, x) and join
+    horizontally adjacent ones with the same y, the same height and equal
+    means; drop the emptied segments; repeat while the drop removed anything.
+    An emptied segment (height or width 0) never matches a live one, since
+    their extents across the pass differ.
     """
     k = [Segment(*s.as_tuple()) for s in segs]
     while True:
-        # vertical pass (steps 1-2)
-        k.sort(key=lambda s: (s.x, s.y))
-        i = 0
-        while i < len(k) - 1:
-            if k[i].w == 0 or k[i].h == 0:
-                i += 1
-                continue
-            j = i + 1
-            while (j < len(k) and k[i].x == k[j].x and k[i].w == k[j].w
-                   and k[i].y + k[i].h == k[j].y and _same_mean(k[i], k[j])):
-                k[i].h += k[j].h
-                k[i].total += k[j].total
-                k[i].area += k[j].area
-                k[j].h = 0
-                j += 1
-            i = j
-        # horizontal pass (steps 3-4)
-        k.sort(key=lambda s: (s.y, s.x))
-        i = 0
-        while i < len(k) - 1:
-            if k[i].w == 0 or k[i].h == 0:
-                i += 1
-                continue
-            j = i + 1
-            while (j < len(k) and k[i].y == k[j].y and k[i].h == k[j].h
-                   and k[i].x + k[i].w == k[j].x and _same_mean(k[i], k[j])):
-                k[i].w += k[j].w
-                k[i].total += k[j].total
-                k[i].area += k[j].area
-                k[j].w = 0
-                j += 1
-            i = j
-        # steps 5-6
+        _absorb_runs(k, lambda s: (s.x, s.y),
+                     lambda a, b: a.x == b.x and a.w == b.w and a.y + a.h == b.y,
+                     _grow_down)
+        _absorb_runs(k, lambda s: (s.y, s.x),
+                     lambda a, b: a.y == b.y and a.h == b.h and a.x + a.w == b.x,
+                     _grow_right)
         kept = [s for s in k if s.w != 0 and s.h != 0]
-        changed = len(kept) != len(k)
+        if len(kept) == len(k):
+            return kept
         k = kept
-        if not changed:
-            return k
 
 
 def approximation_image(W: int, H: int, segs: List[Segment]) -> np.ndarray:

@@ -1,7 +1,8 @@
 // Host-side segmented template approximation (split-and-merge).
 //
 // precompute_template_approximation, split_segment and
-// merge_redundant_segments of Section 5; the deviation test is Eq. (2).
+// merge_redundant_segments of Section 5 (same results, computed with a work
+// list and a corner grid); the deviation test is Eq. (2).
 // Sums over a rectangle come from an int64 summed-area table of the template,
 // so every split decision costs O(1).  The test "population standard
 // deviation < sigma_max" is decided exactly: with S = sum t, S2 = sum t^2 and
@@ -105,42 +106,48 @@ bool std_below(int64_t S, int64_t S2, int64_t A, double sigma) {
 
 namespace {
 
-struct Split {
-  const std::vector<int64_t> &sat, &sat2;  // (H+1) x (W+1)
-  int W;
-  double sigma;
-  std::vector<Seg> *out;
-
+// Pixel sums of the template over rectangles from integral images of t and
+// t^2 (int64, (H + 1) x (W + 1), zero first row and column).
+struct Tables {
+  std::vector<int64_t> s, s2;
+  int P;  // row pitch, W + 1
   int64_t box(const std::vector<int64_t> &t, int x, int y, int w, int h) const {
-    const int P = W + 1;
     return t[(size_t)(y + h) * P + x + w] - t[(size_t)(y + h) * P + x] -
            t[(size_t)y * P + x + w] + t[(size_t)y * P + x];
   }
+};
 
-  // split_segment: recursive halving across the larger side.
-  void run(int x, int y, int w, int h) {
-    int64_t S = box(sat, x, y, w, h);
-    if (w == 1 && h == 1) {
-      out->push_back(Seg{x, y, 1, 1, S, 1});
-      return;
-    }
-    int64_t S2 = box(sat2, x, y, w, h);
-    int64_t A = (int64_t)w * h;
-    if (std_below(S, S2, A, sigma)) {
-      out->push_back(Seg{x, y, w, h, S, A});
-      return;
-    }
-    if (w > h) {
-      int a = (w + 1) / 2;
-      run(x, y, a, h);
-      run(x + a, y, w / 2, h);
+struct Rect {
+  int x, y, w, h;
+};
+
+// The halving rule of split_segment: a rectangle is kept when it is one
+// pixel or when its population deviation is below sigma (Eq. (2)); otherwise
+// it is cut across its larger side (the width when w > h), the first part
+// taking the ceiling.  Rectangles wait on an explicit work list; the leaves
+// come out in the list's order, which neither the leaf count nor the merged
+// result depends on.
+void split_leaves(const Tables &tb, double sigma, int W, int H, std::vector<Seg> &leaves) {
+  std::vector<Rect> todo;
+  todo.push_back(Rect{0, 0, W, H});
+  while (!todo.empty()) {
+    const Rect r = todo.back();
+    todo.pop_back();
+    const int64_t S = tb.box(tb.s, r.x, r.y, r.w, r.h);
+    const int64_t A = (int64_t)r.w * r.h;
+    if (A == 1 || std_below(S, tb.box(tb.s2, r.x, r.y, r.w, r.h), A, sigma)) {
+      leaves.push_back(Seg{r.x, r.y, r.w, r.h, S, A});
+    } else if (r.w > r.h) {
+      const int a = (r.w + 1) / 2;
+      todo.push_back(Rect{r.x + a, r.y, r.w - a, r.h});
+      todo.push_back(Rect{r.x, r.y, a, r.h});
     } else {
-      int a = (h + 1) / 2;
-      run(x, y, w, a);
-      run(x, y + a, w, h / 2);
+      const int a = (r.h + 1) / 2;
+      todo.push_back(Rect{r.x, r.y + a, r.w, r.h - a});
+      todo.push_back(Rect{r.x, r.y, r.w, a});
     }
   }
-};
+}
 
 bool same_mean(const Seg &a, const Seg &b) {
   return (__int128)a.sum * b.area == (__int128)b.sum * a.area;
@@ -148,90 +155,85 @@ bool same_mean(const Seg &a, const Seg &b) {
 
 }  // namespace
 
-// merge_redundant_segments: vertical pass over (x, y) order, horizontal pass
-// over (y, x) order, drop emptied segments, repeat while anything dropped.
-void merge_segments(std::vector<Seg> &k) {
-  for (;;) {
-    std::sort(k.begin(), k.end(), [](const Seg &a, const Seg &b) {
-      return a.x != b.x ? a.x < b.x : a.y < b.y;
-    });
-    size_t i = 0;
-    while (k.size() > 0 && i < k.size() - 1) {
-      if (k[i].w == 0 || k[i].h == 0) {
-        ++i;
-        continue;
+// merge_redundant_segments, as rounds over a grid of the template's pixels
+// that holds, at the top-left corner of every live segment, its index (-1
+// elsewhere).  In a round every maximal vertical run (segments of equal x and
+// width, each starting where the one above ends, equal exact means) becomes
+// its top segment, then every maximal horizontal run (equal y and height,
+// side by side, equal means) its leftmost one; rounds repeat until one merges
+// nothing.  The neighbour below segment s starts at (x_s, y_s + h_s), the one
+// to its right at (x_s + w_s, y_s); a row-major walk over the grid reaches a
+// run's first segment before the rest of the run.  The segments of a
+// partition have distinct corners, so each grid cell holds at most one.  The
+// result lists the segments in row-major order of their corners.
+void merge_segments(std::vector<Seg> &k, int W, int H) {
+  std::vector<int> at((size_t)W * H, -1);
+  for (size_t i = 0; i < k.size(); ++i) at[(size_t)k[i].y * W + k[i].x] = (int)i;
+  for (bool merged = true; merged;) {
+    merged = false;
+    for (int vertical = 1; vertical >= 0; --vertical) {
+      for (size_t cell = 0; cell < at.size(); ++cell) {
+        if (at[cell] < 0) continue;
+        Seg &s = k[at[cell]];
+        for (;;) {
+          const int nx = vertical ? s.x : s.x + s.w, ny = vertical ? s.y + s.h : s.y;
+          if (nx >= W || ny >= H) break;
+          const size_t nc = (size_t)ny * W + nx;
+          if (at[nc] < 0) break;
+          const Seg &t = k[at[nc]];
+          if ((vertical ? t.w != s.w : t.h != s.h) || !same_mean(s, t)) break;
+          if (vertical)
+            s.h += t.h;
+          else
+            s.w += t.w;
+          s.sum += t.sum;
+          s.area += t.area;
+          at[nc] = -1;
+          merged = true;
+        }
       }
-      size_t j = i + 1;
-      while (j < k.size() && k[i].x == k[j].x && k[i].w == k[j].w &&
-             k[i].y + k[i].h == k[j].y && same_mean(k[i], k[j])) {
-        k[i].h += k[j].h;
-        k[i].sum += k[j].sum;
-        k[i].area += k[j].area;
-        k[j].h = 0;
-        ++j;
-      }
-      i = j;
     }
-    std::sort(k.begin(), k.end(), [](const Seg &a, const Seg &b) {
-      return a.y != b.y ? a.y < b.y : a.x < b.x;
-    });
-    i = 0;
-    while (k.size() > 0 && i < k.size() - 1) {
-      if (k[i].w == 0 || k[i].h == 0) {
-        ++i;
-        continue;
-      }
-      size_t j = i + 1;
-      while (j < k.size() && k[i].y == k[j].y && k[i].h == k[j].h &&
-             k[i].x + k[i].w == k[j].x && same_mean(k[i], k[j])) {
-        k[i].w += k[j].w;
-        k[i].sum += k[j].sum;
-        k[i].area += k[j].area;
-        k[j].w = 0;
-        ++j;
-      }
-      i = j;
-    }
-    size_t before = k.size();
-    k.erase(std::remove_if(k.begin(), k.end(),
-                           [](const Seg &s) { return s.w == 0 || s.h == 0; }),
-            k.end());
-    if (k.size() == before) return;
   }
+  std::vector<Seg> out;
+  for (size_t cell = 0; cell < at.size(); ++cell)
+    if (at[cell] >= 0) out.push_back(k[at[cell]]);
+  k.swap(out);
 }
 
 int segment_template(const uint8_t *t, int W, int H, int stride, double sigma,
                      int K_max, std::vector<Seg> &out, int *k_before_merge,
                      double *sigma_used, double *rho_max) {
-  const int P = W + 1;
-  std::vector<int64_t> sat((size_t)(H + 1) * P, 0), sat2((size_t)(H + 1) * P, 0);
+  Tables tb;
+  tb.P = W + 1;
+  const int P = tb.P;
+  tb.s.assign((size_t)(H + 1) * P, 0);
+  tb.s2.assign((size_t)(H + 1) * P, 0);
   for (int y = 0; y < H; ++y) {
     int64_t row = 0, row2 = 0;
     for (int x = 0; x < W; ++x) {
       int64_t v = t[(size_t)y * stride + x];
       row += v;
       row2 += v * v;
-      sat[(size_t)(y + 1) * P + x + 1] = sat[(size_t)y * P + x + 1] + row;
-      sat2[(size_t)(y + 1) * P + x + 1] = sat2[(size_t)y * P + x + 1] + row2;
+      tb.s[(size_t)(y + 1) * P + x + 1] = tb.s[(size_t)y * P + x + 1] + row;
+      tb.s2[(size_t)(y + 1) * P + x + 1] = tb.s2[(size_t)y * P + x + 1] + row2;
     }
   }
   std::vector<Seg> leaves;
   double used = sigma;
   for (;;) {  // the K_max loop: raise the threshold by one until K <= K_max
     leaves.clear();
-    Split sp{sat, sat2, W, sigma, &leaves};
-    sp.run(0, 0, W, H);
+    split_leaves(tb, sigma, W, H, leaves);
     used = sigma;
     sigma = sigma + 1.0;
     if ((int64_t)leaves.size() <= K_max) break;
   }
   if (k_before_merge) *k_before_merge = (int)leaves.size();
   if (sigma_used) *sigma_used = used;
-  merge_segments(leaves);
+  merge_segments(leaves, W, H);
   out = leaves;
 
   const int64_t n = (int64_t)W * H;
-  const int64_t T = sat[(size_t)H * P + W];
+  const int64_t T = tb.s[(size_t)H * P + W];
   bool uniform = true;
   for (const Seg &s : out)
     if ((__int128)s.sum * n != (__int128)T * s.area) uniform = false;

@@ -19,7 +19,7 @@ struct Seg {
 };
 
 bool std_below(int64_t S, int64_t S2, int64_t A, double sigma);
-void merge_segments(std::vector<Seg> &k);
+void merge_segments(std::vector<Seg> &k, int W, int H);
 int segment_template(const uint8_t *t, int W, int H, int stride, double sigma,
                      int K_max, std::vector<Seg> &out, int *k_before_merge,
                      double *sigma_used, double *rho_max);

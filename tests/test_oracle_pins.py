@@ -545,8 +545,11 @@ MUTANTS = {
                          "first = (w + 1) // 2", "first = w // 2"),
     "split_wide_on_ties": (OSEG, "split_segment", "if w > h:", "if w >= h:"),
     "merge_ignores_width": (OSEG, "merge_redundant_segments",
-                            "k[i].x == k[j].x and k[i].w == k[j].w",
-                            "k[i].x == k[j].x"),
+                            "a.x == b.x and a.w == b.w and a.y + a.h == b.y",
+                            "a.x == b.x and a.y + a.h == b.y"),
+    "merge_ignores_adjacency": (OSEG, "merge_redundant_segments",
+                                "a.y == b.y and a.h == b.h and a.x + a.w == b.x",
+                                "a.y == b.y and a.h == b.h"),
     "mean_term_uses_wrong_area": (ONCC, "_rho",
                                   "b -= fbar * seg.area", "b -= fbar * seg.w"),
     "fast_test_inverted": (OSEL, "threshold_match",
