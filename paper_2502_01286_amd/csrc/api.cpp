@@ -58,6 +58,17 @@ using namespace sncc;
 
 namespace {
 
+// Failure injection for tests of the allocation-failure paths: with
+// SNCC_TEST_FAIL_ALLOC set to a positive byte count in the environment, every
+// device allocation of at least that many bytes fails as if the device were
+// out of memory (read at each allocation, so a test can set and clear it).
+bool alloc_fails_by_request(size_t n) {
+  const char *v = std::getenv("SNCC_TEST_FAIL_ALLOC");
+  if (!v || !*v) return false;
+  const long long lim = std::atoll(v);
+  return lim > 0 && (long long)n >= lim;
+}
+
 // Device buffer owned by a handle; grows on demand, freed on destruction.
 struct DevBuf {
   void *p = nullptr;
@@ -75,6 +86,8 @@ struct DevBuf {
       p = nullptr;
       bytes = 0;
     }
+    if (alloc_fails_by_request(n))
+      SNCC_FAIL(SNCC_ENOMEM, "hipMalloc(%zu): refused (SNCC_TEST_FAIL_ALLOC)", n);
     hipError_t e = hipMalloc(&p, n);
     if (e != hipSuccess) {
       p = nullptr;
@@ -522,7 +535,7 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int P, int n_pairs,
           WorkItem it{p, a, std::min(t1, a + per), 0};
           ph.items.push_back(it);
           item_cost.push_back(tile_cost[p] * (it.tile_end - it.tile_begin));
-          group_of.push_back((int64_t)pd.frame * 65536 + b);
+          group_of.push_back((int64_t)pd.frame << 32 | b);
         }
       }
       pd.item_end = (int)ph.items.size();
@@ -536,7 +549,7 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int P, int n_pairs,
     std::vector<int> gid(idx.size()), fid(idx.size());
     for (size_t i = 0; i < idx.size(); ++i) {
       if (i > 0 && group_of[idx[i]] != group_of[idx[i - 1]]) ++n_groups;
-      if (i > 0 && group_of[idx[i]] >> 16 != group_of[idx[i - 1]] >> 16) ++n_frames;
+      if (i > 0 && group_of[idx[i]] >> 32 != group_of[idx[i - 1]] >> 32) ++n_frames;
       gid[i] = n_groups;
       fid[i] = n_frames;
     }
@@ -810,6 +823,80 @@ int check_pairs(const sncc_tmpl *tm, int B, int M, int N, int n_pairs, const int
   return SNCC_OK;
 }
 
+// Checks T segment lists (each must partition its W x H template) and fills
+// the host side of a template set: sizes, segment lists and the constants of
+// Section 5, steps 3-4 (Eq. (7), c_i, q_k), plus the generic per-segment
+// arrays the device copies are made from.  No device work.
+int fill_templates(sncc_tmpl *tm, int T, const sncc_segment *const *segs, const int *K,
+                   const int *W, const int *H, std::vector<int4> &geom,
+                   std::vector<double> &c64all, std::vector<int> &areas) {
+  for (int t = 0; t < T; ++t) {
+    const int w = W[t], h = H[t], k = K[t];
+    if (w < 1 || h < 1 || k < 1 || !segs[t]) SNCC_FAIL(SNCC_EINVAL, "template %d: bad size or list", t);
+    const long long n = (long long)w * h;
+    if (n > SNCC_MAX_TEMPLATE_AREA || w > kMaxSqBoxArea)
+      SNCC_FAIL(SNCC_ERANGE, "template %d: %dx%d outside the exact range (area <= %d, width <= %d)",
+                t, w, h, SNCC_MAX_TEMPLATE_AREA, kMaxSqBoxArea);
+    std::vector<char> cover((size_t)n, 0);
+    std::vector<Seg> list;
+    int64_t total = 0;
+    for (int i = 0; i < k; ++i) {
+      const sncc_segment &g = segs[t][i];
+      if (g.w < 1 || g.h < 1 || g.x < 0 || g.y < 0 || g.x + g.w > w || g.y + g.h > h ||
+          g.area != g.w * g.h || g.sum < 0 || g.sum > 255LL * g.area)
+        SNCC_FAIL(SNCC_EINVAL, "template %d segment %d invalid", t, i);
+      for (int y = g.y; y < g.y + g.h; ++y)
+        for (int x = g.x; x < g.x + g.w; ++x) {
+          if (cover[(size_t)y * w + x]) SNCC_FAIL(SNCC_EINVAL, "template %d: segments overlap", t);
+          cover[(size_t)y * w + x] = 1;
+        }
+      list.push_back(Seg{g.x, g.y, g.w, g.h, g.sum, g.area});
+      total += g.sum;
+    }
+    for (char c : cover)
+      if (!c) SNCC_FAIL(SNCC_EINVAL, "template %d: segments do not cover the template", t);
+    bool uniform = true;
+    for (const Seg &g : list)
+      if ((__int128)g.sum * n != (__int128)total * g.area) uniform = false;
+    if (uniform) SNCC_FAIL(SNCC_EDEGENERATE, "template %d: uniform approximation (q_k = 0)", t);
+    // Eq. (7) and the zero-mean values of step 3; q_k of step 4 (area-weighted)
+    double kbar = 0;
+    for (const Seg &g : list) kbar += (double)g.area * ((double)g.sum / (double)g.area);
+    kbar /= (double)n;
+    std::vector<double> c(k);
+    double qk = 0, r = 0;
+    for (int i = 0; i < k; ++i) {
+      c[i] = (double)list[i].sum / (double)list[i].area - kbar;
+      qk += (double)list[i].area * c[i] * c[i];
+      r += (double)list[i].area * c[i];
+    }
+    DevTmpl d{};
+    d.W = w;
+    d.H = h;
+    d.K = k;
+    d.n = (int)n;
+    d.q_k = qk;
+    d.r64 = r;
+    d.sq_rows = n <= kMaxSqBoxArea ? h : kMaxSqBoxArea / w;
+    d.seg_off = (int)geom.size();
+    tm->W.push_back(w);
+    tm->H.push_back(h);
+    tm->K.push_back(k);
+    tm->seg_off.push_back(d.seg_off);
+    tm->q_k.push_back(qk);
+    tm->r64.push_back(r);
+    for (int i = 0; i < k; ++i) {
+      geom.push_back(make_int4(list[i].x, list[i].y, list[i].w, list[i].h));
+      c64all.push_back(c[i]);
+      areas.push_back((int)list[i].area);
+    }
+    tm->segs.push_back(std::move(list));
+    tm->c64.push_back(std::move(c));
+    tm->dev.push_back(d);
+  }
+  return SNCC_OK;
+}
+
 }  // namespace
 
 // ================================================================ C-ABI
@@ -1056,70 +1143,7 @@ int sncc_upload_templates(sncc_ctx *ctx, int T, const sncc_segment *const *segs,
   std::vector<int4> geom;
   std::vector<double> c64all;
   std::vector<int> areas;
-  for (int t = 0; t < T; ++t) {
-    const int w = W[t], h = H[t], k = K[t];
-    if (w < 1 || h < 1 || k < 1 || !segs[t]) SNCC_FAIL(SNCC_EINVAL, "template %d: bad size or list", t);
-    const long long n = (long long)w * h;
-    if (n > SNCC_MAX_TEMPLATE_AREA || w > kMaxSqBoxArea)
-      SNCC_FAIL(SNCC_ERANGE, "template %d: %dx%d outside the exact range (area <= %d, width <= %d)",
-                t, w, h, SNCC_MAX_TEMPLATE_AREA, kMaxSqBoxArea);
-    std::vector<char> cover((size_t)n, 0);
-    std::vector<Seg> list;
-    int64_t total = 0;
-    for (int i = 0; i < k; ++i) {
-      const sncc_segment &g = segs[t][i];
-      if (g.w < 1 || g.h < 1 || g.x < 0 || g.y < 0 || g.x + g.w > w || g.y + g.h > h ||
-          g.area != g.w * g.h || g.sum < 0 || g.sum > 255LL * g.area)
-        SNCC_FAIL(SNCC_EINVAL, "template %d segment %d invalid", t, i);
-      for (int y = g.y; y < g.y + g.h; ++y)
-        for (int x = g.x; x < g.x + g.w; ++x) {
-          if (cover[(size_t)y * w + x]) SNCC_FAIL(SNCC_EINVAL, "template %d: segments overlap", t);
-          cover[(size_t)y * w + x] = 1;
-        }
-      list.push_back(Seg{g.x, g.y, g.w, g.h, g.sum, g.area});
-      total += g.sum;
-    }
-    for (char c : cover)
-      if (!c) SNCC_FAIL(SNCC_EINVAL, "template %d: segments do not cover the template", t);
-    bool uniform = true;
-    for (const Seg &g : list)
-      if ((__int128)g.sum * n != (__int128)total * g.area) uniform = false;
-    if (uniform) SNCC_FAIL(SNCC_EDEGENERATE, "template %d: uniform approximation (q_k = 0)", t);
-    // Eq. (7) and the zero-mean values of step 3; q_k of step 4 (area-weighted)
-    double kbar = 0;
-    for (const Seg &g : list) kbar += (double)g.area * ((double)g.sum / (double)g.area);
-    kbar /= (double)n;
-    std::vector<double> c(k);
-    double qk = 0, r = 0;
-    for (int i = 0; i < k; ++i) {
-      c[i] = (double)list[i].sum / (double)list[i].area - kbar;
-      qk += (double)list[i].area * c[i] * c[i];
-      r += (double)list[i].area * c[i];
-    }
-    DevTmpl d{};
-    d.W = w;
-    d.H = h;
-    d.K = k;
-    d.n = (int)n;
-    d.q_k = qk;
-    d.r64 = r;
-    d.sq_rows = n <= kMaxSqBoxArea ? h : kMaxSqBoxArea / w;
-    d.seg_off = (int)geom.size();
-    tm->W.push_back(w);
-    tm->H.push_back(h);
-    tm->K.push_back(k);
-    tm->seg_off.push_back(d.seg_off);
-    tm->q_k.push_back(qk);
-    tm->r64.push_back(r);
-    for (int i = 0; i < k; ++i) {
-      geom.push_back(make_int4(list[i].x, list[i].y, list[i].w, list[i].h));
-      c64all.push_back(c[i]);
-      areas.push_back((int)list[i].area);
-    }
-    tm->segs.push_back(std::move(list));
-    tm->c64.push_back(std::move(c));
-    tm->dev.push_back(d);
-  }
+  CHK(fill_templates(tm.get(), T, segs, K, W, H, geom, c64all, areas));
   std::vector<float> c32all(c64all.begin(), c64all.end());
   CHK(tm->d_geom.upload(geom, ctx->stream));
   CHK(tm->d_c64.upload(c64all, ctx->stream));

@@ -22,11 +22,6 @@
 
 namespace sncc {
 
-constexpr int kFusedRV = 4;                  // offset rows per lane
-constexpr int kFusedNW = 4;                  // waves per workgroup
-constexpr int kFusedBU = 64;                 // offset columns per tile
-constexpr int kFusedBV = kFusedRV * kFusedNW;  // offset rows per tile
-
 // Four pixels x .. x + 3 of frame row y, 0 outside the frame.
 __device__ __forceinline__ uint32_t fused_px4(const uint8_t *__restrict__ f, int M, int N,
                                               int f_pitch, bool dword_rows, int x, int y,
@@ -195,19 +190,6 @@ __global__ __launch_bounds__(64 * kFusedNW) void fused_kernel(
       if (energy) energy[o] = V[dv];
     }
   }
-}
-
-// Rows of the region's table in LDS for a template of height H: the largest
-// template height that fits `lds_bytes` at pitch LP is lds_bytes / (4 LP) - 17.
-int fused_lp(int W) {
-  for (int i = 0; i < kNumLpClasses; ++i)
-    if (kLpClasses[i] >= kFusedBU + W + 1) return kLpClasses[i];
-  return 0;
-}
-
-size_t fused_lds_bytes(int W, int H) {
-  const int LP = fused_lp(W);
-  return LP ? (size_t)(kFusedBV + H + 1) * LP * 4 : 0;
 }
 
 int launch_fused(const FusedArgs &a, hipStream_t st) {

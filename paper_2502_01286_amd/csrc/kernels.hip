@@ -422,22 +422,9 @@ static_assert(sizeof(kTileEntries) / sizeof(kTileEntries[0]) == kNumTileShapes,
               "one table entry per tile shape");
 static const int kNumTileEntries = kNumTileShapes;
 
-// Tile configurations the planner and the tuner choose from: kernel entry
-// and workgroups per CU the LDS budget is sized for.
-struct CfgEntry {
-  int entry, wgs, frame_major;
-};
-static const CfgEntry kCfgs[] = {
-    {0, 2, 1}, {0, 2, 0}, {1, 4, 1}, {3, 2, 1}, {3, 3, 1}, {4, 2, 1}, {5, 4, 1}, {2, 2, 1},
-};
-static const int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
-
 int tile_cfg_count() { return kNumCfgs; }
-TileCfg tile_cfg(int i) {
-  const TileEntry &e = kTileEntries[kCfgs[i].entry];
-  return TileCfg{e.ru, e.rv, e.nw, kCfgs[i].wgs, kCfgs[i].frame_major};
-}
-int tile_max_lds() { return 160 * 1024; }
+TileCfg tile_cfg(int i) { return tile_cfg_of(i); }
+int tile_max_lds() { return kTileMaxLds; }
 
 static const void *tile_fn(int cfg, int sink) {
   return kTileEntries[kCfgs[cfg].entry].fn(sink);

@@ -255,6 +255,10 @@ struct FusedArgs {
   long long *energy;
 };
 constexpr int kFusedMaxLds = 160 * 1024 - 64;
+constexpr int kFusedRV = 4;                    // offset rows per lane
+constexpr int kFusedNW = 4;                    // waves per workgroup
+constexpr int kFusedBU = 64;                   // offset columns per tile
+constexpr int kFusedBV = kFusedRV * kFusedNW;  // offset rows per tile
 
 // Tile kernel configuration: offsets per lane RU (u, stride 64) x RV (v),
 // NW waves per workgroup, each wave owning RV offset rows; `wgs` is the
@@ -291,6 +295,23 @@ constexpr int kTileShapes[kNumTileShapes][3] = {
     {1, 4, 8},  //  64 x 32
     {1, 4, 4},  //  64 x 16
 };
+// Tile configurations the planner and the tuner choose from: tile shape
+// (index into kTileShapes), workgroups per CU the LDS budget is sized for,
+// and the work order (frame-major queues per XCD, or one queue).
+struct CfgEntry {
+  int entry, wgs, frame_major;
+};
+constexpr CfgEntry kCfgs[] = {
+    {0, 2, 1}, {0, 2, 0}, {1, 4, 1}, {3, 2, 1}, {3, 3, 1}, {4, 2, 1}, {5, 4, 1}, {2, 2, 1},
+};
+constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
+constexpr int kTileMaxLds = 160 * 1024;  // LDS of one CU (gfx950)
+inline TileCfg tile_cfg_of(int i) {
+  const int e = kCfgs[i].entry;
+  return TileCfg{kTileShapes[e][0], kTileShapes[e][1], kTileShapes[e][2], kCfgs[i].wgs,
+                 kCfgs[i].frame_major};
+}
+
 // Host stubs of tile shape i's kernels (tile_entry.hip), one per sink.
 const void *tile_fn_0(int sink);
 const void *tile_fn_1(int sink);
@@ -318,8 +339,18 @@ int launch_tile(int cfg, int sink, const TileArgs &a, int grid,
 int tile_max_lds();
 int tile_occupancy(int cfg, int sink, int lds_bytes);
 int launch_plain(const PlainArgs &a, hipStream_t st);
-int fused_lp(int W);
-size_t fused_lds_bytes(int W, int H);
+// LDS row pitch (words) of the tile-local form for templates W wide: the
+// smallest pitch class holding the region's 64 + W + 1 table columns (0: none).
+inline int fused_lp(int W) {
+  for (int i = 0; i < kNumLpClasses; ++i)
+    if (kLpClasses[i] >= kFusedBU + W + 1) return kLpClasses[i];
+  return 0;
+}
+// LDS bytes of the tile-local form's region table: 16 + H + 1 rows.
+inline size_t fused_lds_bytes(int W, int H) {
+  const int LP = fused_lp(W);
+  return LP ? (size_t)(kFusedBV + H + 1) * LP * 4 : 0;
+}
 int launch_fused(const FusedArgs &a, hipStream_t st);
 int launch_energy(const uint32_t *s, const uint32_t *s2, int P, int nu, int nv, int W, int H,
                   int sq_rows, long long *energy, int pitch, hipStream_t st);

@@ -1,0 +1,85 @@
+"""Guards on the machine code of the built library (gfx950 code objects of
+libsncc.so, disassembled with the ROCm LLVM tools; no GPU needed).
+
+The slow pass and the refine kernel take the previous boundary's column
+difference from the lane below with a separate row_shr:1 DPP move; the
+subtraction that uses it must stay an ordinary VALU subtraction, not a
+subtraction with a DPP source operand (see the comment in staged_rho4).  A
+compiler change that folds the move again would fail here, on the CPU,
+before any GPU run.
+"""
+
+import os
+import re
+import shutil
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2502_01286_amd", "libsncc.so")
+LLVM = "/opt/rocm/llvm/bin"
+MAGIC = b"__CLANG_OFFLOAD_BUNDLE__"
+
+
+def _tool(name):
+    p = os.path.join(LLVM, name)
+    return p if os.path.exists(p) else shutil.which(name)
+
+
+def _disassembly():
+    objcopy, bundler, objdump = (_tool("llvm-objcopy"), _tool("clang-offload-bundler"),
+                                 _tool("llvm-objdump"))
+    if not (objcopy and bundler and objdump and os.path.exists(LIB)):
+        pytest.skip("ROCm LLVM tools or the built library not available")
+    out = []
+    with tempfile.TemporaryDirectory() as d:
+        fb = os.path.join(d, "fatbin")
+        subprocess.run([objcopy, "--dump-section", f".hip_fatbin={fb}", LIB], check=True)
+        data = open(fb, "rb").read()
+        starts = [m.start() for m in re.finditer(re.escape(MAGIC), data)] + [len(data)]
+        for i, (a, b) in enumerate(zip(starts, starts[1:])):
+            part = os.path.join(d, f"b{i}")
+            with open(part, "wb") as fh:
+                fh.write(data[a:b])
+            co = os.path.join(d, f"b{i}.co")
+            r = subprocess.run([bundler, "--unbundle", "--type=o", f"--input={part}",
+                                "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", f"--output={co}"],
+                               capture_output=True)
+            if r.returncode != 0 or not os.path.getsize(co):
+                continue
+            r = subprocess.run([objdump, "-d", "--mcpu=gfx950", co], capture_output=True,
+                               text=True, check=True)
+            out.append(r.stdout)
+    return "\n".join(out)
+
+
+def _functions(text):
+    """Disassembly split by function symbol: {mangled name: body}."""
+    funcs, name, body = {}, None, []
+    for line in text.splitlines():
+        m = re.match(r"^[0-9a-f]+ <(.+)>:$", line)
+        if m:
+            if name:
+                funcs[name] = "\n".join(body)
+            name, body = m.group(1), []
+        elif name:
+            body.append(line)
+    if name:
+        funcs[name] = "\n".join(body)
+    return funcs
+
+
+def test_row_shift_moves_are_not_folded_into_subtractions():
+    funcs = _functions(_disassembly())
+    kernels = {n: b for n, b in funcs.items()
+               if "slow_kernel" in n or "refine_kernel" in n}
+    assert kernels, "slow_kernel / refine_kernel not found in the code objects"
+    for name, body in kernels.items():
+        folded = [ln for ln in body.splitlines()
+                  if re.search(r"v_sub(rev)?_u32_dpp", ln) and "row_shr" in ln]
+        assert not folded, (name, folded[:3])
+        moves = [ln for ln in body.splitlines()
+                 if "v_mov_b32_dpp" in ln and "row_shr:1" in ln]
+        assert moves, name
