@@ -252,78 +252,110 @@ std::vector<std::vector<int>> horizontal_chains(const std::vector<Seg> &segs,
   return pieces;
 }
 
-// Splits a template's chains into passes whose staged rows fit `rows_budget`
-// LDS rows of pitch LP; appends passes, intervals and records.  Returns the
-// largest number of rows any pass stages, -1 when one chain alone does not
-// fit, -2 when a segment's area does not fit the 24-bit multiply.
+// Width of a template's column bands for tiles bu offsets wide: the whole
+// template when its staged row fits 512 words, else equal bands of at most
+// 512 - bu - 1 columns (multiples of 4, so that band windows start on 16-byte
+// chunks).  Rows of at most 512 words leave a staged chain's rows small
+// enough for two workgroups per CU where 576-word rows would allow one.
+int band_width(int W, int bu) {
+  const int widest = (kLpClasses[kNumLpClasses - 2] - bu - 1) & ~3;
+  if (W <= widest) return W;
+  const int n = (W + widest - 1) / widest;
+  return ((W + n - 1) / n + 3) & ~3;
+}
+
+// Splits a template into column bands (band_width) and each band's chains
+// into passes whose staged rows fit `rows_budget` LDS rows of pitch LP;
+// appends passes, intervals and records.  Segments are cut at band edges
+// (each piece keeps c_i; its area is its own, so the pieces' integer terms
+// F - A b add up to the segment's).  Returns the largest number of rows any
+// pass stages, -1 when one chain alone does not fit, -2 when a segment's area
+// does not fit the 24-bit multiply.
 int plan_template(const sncc_tmpl *tm, int t, const TileCfg &tc, int LP, int rows_budget,
                   PlanHost &ph, DevTmpl &d) {
-  const int H = tm->H[t], bv = tc.bv();
+  const int W = tm->W[t], H = tm->H[t], bv = tc.bv(), bu = tc.bu();
   const int span = H + bv;  // rows 0 .. H + bv - 1
-  const std::vector<Seg> &segs = tm->segs[t];
-  for (const Seg &g : segs)
+  const std::vector<Seg> &all = tm->segs[t];
+  for (const Seg &g : all)
     if (g.area >= (1 << 23)) return -2;
-  const std::vector<std::vector<int>> pieces = horizontal_chains(segs);
+  const int bw = band_width(W, bu);
   d.pass_begin = (int)ph.passes.size();
   int max_rows = 0;
-  size_t i = 0;
-  while (i < pieces.size()) {
-    std::vector<char> cov(span, 0);
-    int count = 0;
-    size_t j = i;
-    if (span <= rows_budget) {
-      std::fill(cov.begin(), cov.end(), 1);
-      count = span;
-      j = pieces.size();
-    } else {
-      while (j < pieces.size()) {  // the pieces of a chain share their rows
-        const Seg &g = segs[pieces[j][0]];
-        const int add = rows_needed(cov, g, bv);
-        if (count + add > rows_budget) break;
-        mark_rows(cov, g, bv, count);
-        ++j;
-      }
-      if (j == i) return -1;  // one chain does not fit
+  for (int col0 = 0; col0 < W; col0 += bw) {
+    const int col1 = std::min(W, col0 + bw);
+    // the band's pieces, in band-relative columns, and their segments' indices
+    std::vector<Seg> segs;
+    std::vector<int> orig;
+    for (size_t k = 0; k < all.size(); ++k) {
+      const Seg &g = all[k];
+      const int a = std::max(g.x, col0), b = std::min(g.x + g.w, col1);
+      if (a >= b) continue;
+      segs.push_back(Seg{a - col0, g.y, b - a, g.h, 0, (int64_t)(b - a) * g.h});
+      orig.push_back((int)k);
     }
-    PassDesc ps;
-    ps.iv_begin = (int)ph.ivs.size();
-    std::vector<int> slot(span, -1);
-    int lds_row = 0;
-    for (int r = 0; r < span;) {
-      if (!cov[r]) {
-        ++r;
-        continue;
+    const int stage_w4 = (bu + (col1 - col0) + 1 + 3) >> 2;
+    const std::vector<std::vector<int>> pieces = horizontal_chains(segs);
+    size_t i = 0;
+    while (i < pieces.size()) {
+      std::vector<char> cov(span, 0);
+      int count = 0;
+      size_t j = i;
+      if (span <= rows_budget) {
+        std::fill(cov.begin(), cov.end(), 1);
+        count = span;
+        j = pieces.size();
+      } else {
+        while (j < pieces.size()) {  // the pieces of a chain share their rows
+          const Seg &g = segs[pieces[j][0]];
+          const int add = rows_needed(cov, g, bv);
+          if (count + add > rows_budget) break;
+          mark_rows(cov, g, bv, count);
+          ++j;
+        }
+        if (j == i) return -1;  // one chain does not fit
       }
-      int e = r;
-      while (e < span && cov[e]) ++e;
-      Interval iv{r, e - r, lds_row, 0};
-      ph.ivs.push_back(iv);
-      for (int q = r; q < e; ++q) slot[q] = lds_row + (q - r);
-      lds_row += e - r;
-      r = e;
-    }
-    ps.iv_end = (int)ph.ivs.size();
-    ps.seg_begin = (int)ph.recs.size();
-    for (int L = kMaxChain; L >= 1; --L) {
-      ps.n_chain[L - 1] = 0;
-      for (size_t q = i; q < j; ++q) {
-        const std::vector<int> &pc = pieces[q];
-        if ((int)pc.size() != L) continue;
-        ++ps.n_chain[L - 1];
-        const Seg &g0 = segs[pc[0]];
-        const int top = slot[g0.y] * LP, bot = slot[g0.y + g0.h] * LP;
-        ph.recs.push_back(TileRec{top + g0.x, bot + g0.x, 0, 0.f});  // left boundary
-        for (int k : pc) {
-          const Seg &g = segs[k];
-          ph.recs.push_back(TileRec{top + g.x + g.w, bot + g.x + g.w, (int)g.area,
-                                    (float)tm->c64[t][k]});
+      PassDesc ps{};
+      ps.col0 = col0;
+      ps.stage_w4 = stage_w4;
+      ps.iv_begin = (int)ph.ivs.size();
+      std::vector<int> slot(span, -1);
+      int lds_row = 0;
+      for (int r = 0; r < span;) {
+        if (!cov[r]) {
+          ++r;
+          continue;
+        }
+        int e = r;
+        while (e < span && cov[e]) ++e;
+        Interval iv{r, e - r, lds_row, 0};
+        ph.ivs.push_back(iv);
+        for (int q = r; q < e; ++q) slot[q] = lds_row + (q - r);
+        lds_row += e - r;
+        r = e;
+      }
+      ps.iv_end = (int)ph.ivs.size();
+      ps.seg_begin = (int)ph.recs.size();
+      for (int L = kMaxChain; L >= 1; --L) {
+        ps.n_chain[L - 1] = 0;
+        for (size_t q = i; q < j; ++q) {
+          const std::vector<int> &pc = pieces[q];
+          if ((int)pc.size() != L) continue;
+          ++ps.n_chain[L - 1];
+          const Seg &g0 = segs[pc[0]];
+          const int top = slot[g0.y] * LP, bot = slot[g0.y + g0.h] * LP;
+          ph.recs.push_back(TileRec{top + g0.x, bot + g0.x, 0, 0.f});  // left boundary
+          for (int k : pc) {
+            const Seg &g = segs[k];
+            ph.recs.push_back(TileRec{top + g.x + g.w, bot + g.x + g.w, (int)g.area,
+                                      (float)tm->c64[t][orig[k]]});
+          }
         }
       }
+      ps.seg_end = (int)ph.recs.size();
+      ph.passes.push_back(ps);
+      max_rows = std::max(max_rows, lds_row);
+      i = j;
     }
-    ps.seg_end = (int)ph.recs.size();
-    ph.passes.push_back(ps);
-    max_rows = std::max(max_rows, lds_row);
-    i = j;
   }
   d.pass_end = (int)ph.passes.size();
   return max_rows;
@@ -438,9 +470,10 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int P, int n_pairs,
       d.pass_begin = d.pass_end = 0;
       d.thr = thr ? (float)thr[t] : 0.f;
       if (used[t]) {
-        // LDS staging when a row class holds the staged width and every
-        // segment fits the packed record; the direct form otherwise
-        const int cls = lp_class_for(bu + tm->W[t] + 1);
+        // LDS staging (in column bands when one LDS row cannot hold the
+        // template's width) when every segment fits the packed record and
+        // each chain's rows fit the budget; the direct form otherwise
+        const int cls = lp_class_for(bu + band_width(tm->W[t], bu) + 1);
         const size_t mark_recs = ph.recs.size(), mark_ivs = ph.ivs.size();
         const size_t mark_passes = ph.passes.size();
         int rows = -2;

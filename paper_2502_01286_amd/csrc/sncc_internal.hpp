@@ -74,7 +74,10 @@ struct Interval {
   int rel_row, n_rows, lds_row, pad;
 };
 
-// A staged pass: its row intervals and its records.  The records form
+// A staged pass: its row intervals, its column window and its records.  A
+// template too wide for one LDS row is split into column bands (segments cut
+// at band edges; a box sum is the sum of its pieces' box sums), each staged
+// by passes of its own.  The records form
 // horizontal chains (segments with equal y and h, each starting where the
 // previous one ends); a chain of L segments has L + 1 records, one per
 // boundary column.  Chains are grouped by length: n_chain[L - 1] chains of
@@ -84,6 +87,11 @@ struct PassDesc {
   int seg_begin, seg_end;  // TileRec range
   int iv_begin, iv_end;    // Interval range
   int n_chain[4];          // chains of length 1, 2, 3, 4
+  int col0;                // first template column of the staged window (a
+                           // multiple of 4; 0 unless the template is split
+                           // into column bands)
+  int stage_w4;            // 16-byte chunks staged per row
+  int pad[2];
 };
 
 constexpr int kMaxChain = 4;  // longer chains are cut into pieces

@@ -21,7 +21,7 @@ __device__ __forceinline__ void stage_pass(__amdgpu_buffer_rsrc_t rs, int P, int
                                            const Interval *__restrict__ ivs, int iv_begin,
                                            int iv_end, int u0, int v0, int stage_w4,
                                            uint32_t *lds, int wave, int lane) {
-  const int w4 = min(stage_w4, (P - u0) >> 2);  // P and u0 are multiples of 64
+  const int w4 = min(stage_w4, (P - u0) >> 2);  // P and u0 are multiples of 4
   for (int iv = iv_begin; iv < iv_end; ++iv) {
     const Interval I = ivs[iv];
     const int rows = min(I.n_rows, N + 1 - (v0 + I.rel_row));
@@ -108,7 +108,6 @@ __device__ __forceinline__ void run_item(
   const float inv_n = 1.0f / (float)n;
   const double qnd = td.q_k / (double)n;  // energy * q_k = V * q_k / n
   const bool one_box = n <= kMaxSqBoxArea;
-  const int stage_w4 = (BU + W + 1 + 3) >> 2;
   const int lbase = wave * RV * LP + lane;
   const int cW = W * 4, cH = H * P * 4;  // byte offsets of the window corners
 
@@ -121,8 +120,8 @@ __device__ __forceinline__ void run_item(
     if constexpr (LP != 0) {
       __syncthreads();
       const PassDesc ps = passes[td.pass_begin];
-      stage_pass<LP, NW>(rs, P, N, ivs, ps.iv_begin, ps.iv_end, u0, v0, stage_w4, lds, wave,
-                         lane);
+      stage_pass<LP, NW>(rs, P, N, ivs, ps.iv_begin, ps.iv_end, u0 + ps.col0, v0, ps.stage_w4,
+                         lds, wave, lane);
     }
 
     // per offset: window sums of f and f^2 (Eqs. (13), (15)), the integer
@@ -250,8 +249,8 @@ __device__ __forceinline__ void run_item(
       const PassDesc ps = passes[p];
       if (p != td.pass_begin) {
         __syncthreads();
-        stage_pass<LP, NW>(rs, P, N, ivs, ps.iv_begin, ps.iv_end, u0, v0, stage_w4, lds,
-                           wave, lane);
+        stage_pass<LP, NW>(rs, P, N, ivs, ps.iv_begin, ps.iv_end, u0 + ps.col0, v0,
+                           ps.stage_w4, lds, wave, lane);
       }
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();

@@ -67,6 +67,7 @@ int launch_refine(const uint32_t *, const uint32_t *, long long, int, const DevT
 using namespace sncc;
 
 static int g_fail = 0;
+static long long g_banded = 0;  // passes of column bands after the first
 #define CHECK(cond, ...)                                  \
   do {                                                    \
     if (!(cond)) {                                        \
@@ -204,6 +205,11 @@ static void check_plan(const sncc_tmpl &tm, const PlanHost &ph, int n_pairs, int
       CHECK(ps.seg_begin >= 0 && ps.seg_end <= (int)ph.recs.size() && ps.seg_begin <= ps.seg_end,
             "pass records %d..%d of %zu", ps.seg_begin, ps.seg_end, ph.recs.size());
       CHECK(ps.iv_begin >= 0 && ps.iv_end <= (int)ph.ivs.size(), "pass intervals");
+      CHECK(ps.col0 >= 0 && ps.col0 % 4 == 0 && ps.col0 < tm.W[t], "band start %d", ps.col0);
+      g_banded += ps.col0 > 0;
+      CHECK(ps.stage_w4 * 4 <= LP && ps.stage_w4 * 4 >= tc.bu() + 1 &&
+                ps.col0 + ps.stage_w4 * 4 >= std::min(tm.W[t], ps.col0 + 1),
+            "staged width %d words at pitch %d", ps.stage_w4 * 4, LP);
       int rows = 0;
       for (int iv = ps.iv_begin; iv < ps.iv_end && iv < (int)ph.ivs.size(); ++iv)
         rows = std::max(rows, ph.ivs[iv].lds_row + ph.ivs[iv].n_rows);
@@ -250,7 +256,7 @@ int main(int argc, char **argv) {
   for (int i = 0; i < std::max(1, iters / 40); ++i) {
     sncc_tmpl tm;
     const int T = 1 + (int)(rng() % 5);
-    if (!make_set(rng, T, i % 5 == 0 ? 400 : 100, tm)) {
+    if (!make_set(rng, T, i % 5 == 0 ? 400 : i % 7 == 0 ? 1100 : 100, tm)) {
       CHECK(false, "fill_templates failed");
       continue;
     }
@@ -304,6 +310,7 @@ int main(int argc, char **argv) {
       }
     }
   }
-  std::printf("host checks: %d segmentations, %d plans, %d failures\n", n_seg, n_plan, g_fail);
+  std::printf("host checks: %d segmentations, %d plans (%lld passes of later column bands), "
+              "%d failures\n", n_seg, n_plan, g_banded, g_fail);
   return g_fail == 0 ? 0 : 1;
 }

@@ -2,12 +2,12 @@
 templates too wide for the LDS-staged form (MI355X).
 
 Windows of more than 66051 pixels take their sum of f^2 in bands of rows
-(each band exact as a difference of four modulo-2^32 entries); templates whose
-staged row would not fit an LDS pitch class, or whose segments do not fit the
-packed record, are scored in the direct form (corners read from the global
-table).  The oracle computes with unbounded integers, so its maps are the
-reference at these sizes too; the frames are bright so that the windows'
-sums of f^2 exceed 2^32.
+(each band exact as a difference of four modulo-2^32 entries); templates too
+wide for one LDS row are staged in column bands, and those whose chains need
+more staged rows than the LDS holds are scored in the direct form (corners
+read from the global table).  The oracle computes with unbounded integers, so
+its maps are the reference at these sizes too; the frames are bright so that
+the windows' sums of f^2 exceed 2^32.
 """
 
 import numpy as np
@@ -89,7 +89,8 @@ def _check(f, t, sigma, g32, g64, top):
 
 @pytest.mark.parametrize("shape,frame,sigma", [
     ((400, 300), (1024, 768), 12),    # n = 120000, staged in LDS (row pitch 448)
-    ((150, 600), (1280, 720), 12),    # n = 90000, too wide to stage: direct form
+    ((150, 600), (1280, 720), 12),    # n = 90000, wider than one LDS row: column bands
+    ((90, 1000), (1400, 300), 8),     # three column bands
 ])
 def test_large_templates(S, ctx, shape, frame, sigma):
     H, W = shape

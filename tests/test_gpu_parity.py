@@ -443,8 +443,10 @@ def test_batch_every_tile_config(S, ctx, tmp_path, case):
     64x64, 64x32 and 64x16 offsets per tile, the 128-wide ones with their
     last-column launch where they have a half-width twin (a 70 px template on
     260 px frames leaves a last column of 63 offsets).  In `direct` a 530 px
-    wide template is too wide for every LDS pitch class and is scored in the
-    direct form, next to a staged one."""
+    wide template is too wide for one LDS row: the 16-row tiles stage it in
+    two column bands (384 + 146 columns); for the 32- and 64-row tiles a
+    chain of its 36 px tall segments needs more band rows than the LDS holds,
+    so they score it in the direct form; next to a staged template."""
     import re
     import torch
     if case == "direct":
