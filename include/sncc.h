@@ -315,7 +315,10 @@ int sncc_score_frame(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint8_
  * The k highest-scoring offsets of each (frame, template) pair (Section 2:
  * the match is the offset with the highest rho).  Ordering: higher rho
  * first, ties to the smaller v, then smaller u; no suppression of
- * neighbours.  SNCC_FP32_KAHAN runs every pair in one persistent launch
+ * neighbours.  The order is that of the rho the precision computes: FP32
+ * values for SNCC_FP32_KAHAN, the FP64 values themselves for SNCC_FP64 (two
+ * offsets whose doubles differ are never tied, even where the reported
+ * float rho is the same).  SNCC_FP32_KAHAN runs every pair in one persistent launch
  * over a cost-ordered work list; SNCC_FP64 runs one launch per pair.  The
  * context keeps the FP32 form's work list of its last call on the device and
  * reuses it when the next call has the same template set, sizes, pitch, k

@@ -1413,8 +1413,8 @@ int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uin
   }
   CHK(ctx->map_scratch.reserve(max_map * sizeof(double)));
   CHK(pd->d_pairs.upload(h.pairs, ctx->stream));
-  CHK(pd->d_partial.reserve((size_t)n_chunks * k * 8));
-  unsigned long long *partial = pd->d_partial.as<unsigned long long>();
+  CHK(pd->d_partial.reserve((size_t)n_chunks * k * sizeof(Key96)));
+  Key96 *partial = pd->d_partial.as<Key96>();
   for (int p = 0; p < n_pairs; ++p) {
     const PairDesc &q = h.pairs[p];
     const int t = q.tmpl;
@@ -1437,12 +1437,11 @@ int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uin
     a.rho_pitch = q.nu;
     a.degen = nullptr;
     if (launch_plain(a, ctx->stream) != 0 ||
-        launch_map_topk(a.rho, q.nu, q.nu, q.nv, chunk, k, partial + (size_t)q.item_begin * k,
-                        ctx->stream) != 0)
+        launch_map_topk64(a.rho, q.nu, q.nu, q.nv, chunk, k,
+                          partial + (size_t)q.item_begin * k, ctx->stream) != 0)
       SNCC_FAIL(SNCC_EDEVICE, "plain top-k launch: %s", hipGetErrorString(hipGetLastError()));
   }
-  if (launch_merge(pd->d_pairs.as<PairDesc>(), nullptr, n_pairs, partial, nullptr, k, d_out,
-                   ctx->stream) != 0)
+  if (launch_merge64(pd->d_pairs.as<PairDesc>(), n_pairs, partial, k, d_out, ctx->stream) != 0)
     SNCC_FAIL(SNCC_EDEVICE, "merge launch: %s", hipGetErrorString(hipGetLastError()));
   return retire(ctx, std::move(pd));
 }

@@ -114,6 +114,44 @@ __device__ __forceinline__ void topk_offer(u64 &lkey, u64 (&cand)[R], int k, int
   }
 }
 
+// Exact selection keys for FP64 values: the order-preserving 64-bit code of
+// the double (larger value -> larger code) and a 32-bit word that breaks ties
+// by the smaller index (its complement).  (0, 0) is the empty key.
+__device__ __forceinline__ u64 double_order(double d) {
+  const u64 u = (u64)__double_as_longlong(d);
+  return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+__device__ __forceinline__ double double_unorder(u64 o) {
+  return __longlong_as_double((long long)((o >> 63) ? (o & ~(1ull << 63)) : ~o));
+}
+__device__ __forceinline__ bool key96_gt(u64 ah, uint32_t al, u64 bh, uint32_t bl) {
+  return ah > bh || (ah == bh && al > bl);
+}
+
+// Per-wave top-k list of 96-bit keys: lane j < k holds the j-th best.
+__device__ __forceinline__ void topk96_insert(u64 &lh, uint32_t &ll, u64 kh, uint32_t kl, int k,
+                                              int lane) {
+  const bool better = lane < k && key96_gt(lh, ll, kh, kl);
+  const int pos = __popcll(__ballot(better));
+  const u64 uh = shfl_up_u64(lh, 1);
+  const uint32_t ul = (uint32_t)__shfl_up((int)ll, 1);
+  if (lane == pos) {
+    lh = kh;
+    ll = kl;
+  } else if (lane > pos && lane < k) {
+    lh = uh;
+    ll = ul;
+  }
+}
+
+// Largest 96-bit key over the wave (high parts first, then the low words of
+// the lanes holding the largest high part).
+__device__ __forceinline__ void wave_max96(u64 h, uint32_t l, u64 &mh, uint32_t &ml) {
+  mh = wave_max_u64(h);
+  const uint32_t lo = h == mh ? l : 0u;
+  ml = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(lo), 63);
+}
+
 // Buffer resource over `bytes` bytes at `p` (GFX9 raw buffer: loads at or
 // beyond `bytes` return zero).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {

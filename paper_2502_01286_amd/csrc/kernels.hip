@@ -628,50 +628,113 @@ int launch_merge(const PairDesc *pairs, const PairDesc *pairs2, int n_pairs, con
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// Top-k over a double map, one chunk of `chunk` offsets per workgroup.
-__global__ __launch_bounds__(256) void map_topk_kernel(const double *__restrict__ map,
-                                                       int pitch, int nu, int nv, int chunk,
-                                                       int k, u64 *__restrict__ partial) {
-  __shared__ u64 buf[4 * 64];
+// Top-k over a double map with exact keys (the value's 64-bit order code and
+// the index), one chunk of `chunk` offsets per workgroup; partial lists of
+// k keys per chunk, best first, as {code, ~index} pairs.
+__global__ __launch_bounds__(256) void map_topk64_kernel(const double *__restrict__ map,
+                                                         int pitch, int nu, int nv, int chunk,
+                                                         int k, Key96 *__restrict__ partial) {
+  __shared__ u64 bh[4 * 64];
+  __shared__ uint32_t bl[4 * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long total = (long long)nu * nv;
   const long long c0 = (long long)blockIdx.x * chunk;
   const long long c1 = min(total, c0 + chunk);
-  u64 lkey = 0;
-  for (long long e0 = c0 + wave * 64; e0 < c1; e0 += 4 * 256) {
-    u64 cand[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const long long e = e0 + lane + 256 * q;
-      cand[q] = 0;
-      if (e < c1) {
-        const int v = (int)(e / nu), u = (int)(e - (long long)v * nu);
-        cand[q] = make_key((float)map[(long long)v * pitch + u], (int)e);
-      }
+  u64 lh = 0;
+  uint32_t ll = 0;
+  for (long long e0 = c0 + wave * 64; e0 < c1; e0 += 4 * 64) {
+    const long long e = e0 + lane;
+    u64 ch = 0;
+    uint32_t cl = 0;
+    if (e < c1) {
+      const int v = (int)(e / nu), u = (int)(e - (long long)v * nu);
+      ch = double_order(map[(long long)v * pitch + u]);
+      cl = 0xffffffffu - (uint32_t)e;
     }
-    topk_offer<4>(lkey, cand, k, lane);
+    // offer the wave's 64 candidates, best first, while they beat the k-th
+    u64 th = lane_u64(lh, k - 1);
+    uint32_t tl = (uint32_t)__builtin_amdgcn_readlane((int)ll, k - 1);
+    if (!key96_gt(ch, cl, th, tl)) ch = 0, cl = 0;
+    for (;;) {
+      if (__ballot(ch != 0 || cl != 0) == 0) break;
+      u64 mh;
+      uint32_t ml;
+      wave_max96(ch, cl, mh, ml);
+      topk96_insert(lh, ll, mh, ml, k, lane);
+      if (ch == mh && cl == ml) ch = 0, cl = 0;
+      th = lane_u64(lh, k - 1);
+      tl = (uint32_t)__builtin_amdgcn_readlane((int)ll, k - 1);
+      if (!key96_gt(ch, cl, th, tl)) ch = 0, cl = 0;
+    }
   }
-  if (lane < k) buf[wave * k + lane] = lkey;
+  if (lane < k) {
+    bh[wave * k + lane] = lh;
+    bl[wave * k + lane] = ll;
+  }
   __syncthreads();
   if (wave == 0) {
-    u64 thr = lane_u64(lkey, k - 1);
     for (int w = 1; w < 4; ++w)
       for (int j = 0; j < k; ++j) {
-        const u64 key = buf[w * k + j];
-        if (key <= thr) break;
-        topk_insert(lkey, key, k, lane);
-        thr = lane_u64(lkey, k - 1);
+        const u64 kh = bh[w * k + j];
+        const uint32_t kl = bl[w * k + j];
+        const u64 th = lane_u64(lh, k - 1);
+        const uint32_t tl = (uint32_t)__builtin_amdgcn_readlane((int)ll, k - 1);
+        if (!key96_gt(kh, kl, th, tl)) break;  // each wave's list is in descending order
+        topk96_insert(lh, ll, kh, kl, k, lane);
       }
-    if (lane < k) partial[(long long)blockIdx.x * k + lane] = lkey;
+    if (lane < k) partial[(long long)blockIdx.x * k + lane] = Key96{lh, ll, 0};
   }
 }
 
-int launch_map_topk(const double *map, int pitch, int nu, int nv, int chunk, int k,
-                    u64 *partial, hipStream_t st) {
+int launch_map_topk64(const double *map, int pitch, int nu, int nv, int chunk, int k,
+                      Key96 *partial, hipStream_t st) {
   const long long total = (long long)nu * nv;
   const int blocks = (int)((total + chunk - 1) / chunk);
-  hipLaunchKernelGGL(map_topk_kernel, dim3(blocks), dim3(256), 0, st, map, pitch, nu, nv,
+  hipLaunchKernelGGL(map_topk64_kernel, dim3(blocks), dim3(256), 0, st, map, pitch, nu, nv,
                      chunk, k, partial);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// One wave per pair: the k best of the pair's chunk lists (exact keys); the
+// matches report rho rounded to float.
+__global__ __launch_bounds__(256) void merge64_kernel(const PairDesc *__restrict__ pairs,
+                                                      int n_pairs,
+                                                      const Key96 *__restrict__ partial, int k,
+                                                      sncc_match *__restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (p >= n_pairs) return;
+  const PairDesc pd = pairs[p];
+  u64 lh = 0;
+  uint32_t ll = 0;
+  for (int item = pd.item_begin; item < pd.item_end; ++item)
+    for (int j = 0; j < k; ++j) {
+      const Key96 e = partial[(long long)item * k + j];
+      const u64 th = lane_u64(lh, k - 1);
+      const uint32_t tl = (uint32_t)__builtin_amdgcn_readlane((int)ll, k - 1);
+      if (!key96_gt(e.hi, e.lo, th, tl)) break;  // each list is in descending order
+      topk96_insert(lh, ll, e.hi, e.lo, k, lane);
+    }
+  if (lane < k) {
+    sncc_match m;
+    if (lh == 0 && ll == 0) {
+      m.u = -1;
+      m.v = -1;
+      m.rho = -__builtin_inff();
+    } else {
+      const int idx = (int)(0xffffffffu - ll);
+      m.v = idx / pd.nu;
+      m.u = idx - m.v * pd.nu;
+      m.rho = (float)double_unorder(lh);
+    }
+    out[(long long)p * k + lane] = m;
+  }
+}
+
+int launch_merge64(const PairDesc *pairs, int n_pairs, const Key96 *partial, int k,
+                   sncc_match *out, hipStream_t st) {
+  hipLaunchKernelGGL(merge64_kernel, dim3((n_pairs + 3) / 4), dim3(256), 0, st, pairs, n_pairs,
+                     partial, k, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

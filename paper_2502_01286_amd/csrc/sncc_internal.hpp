@@ -366,8 +366,17 @@ int launch_zero(int *p, int n, hipStream_t st);
 int launch_merge(const PairDesc *pairs, const PairDesc *pairs2, int n_pairs,
                  const unsigned long long *partial, const unsigned long long *partial2,
                  int k, sncc_match *out, hipStream_t st);
-int launch_map_topk(const double *map, int pitch, int nu, int nv, int chunk,
-                    int k, unsigned long long *partial, hipStream_t st);
+// Exact selection key of an FP64 value: order code of the double, then the
+// complement of the index (ties to the smaller index).
+struct Key96 {
+  unsigned long long hi;
+  uint32_t lo;
+  uint32_t pad;
+};
+int launch_map_topk64(const double *map, int pitch, int nu, int nv, int chunk, int k,
+                      Key96 *partial, hipStream_t st);
+int launch_merge64(const PairDesc *pairs, int n_pairs, const Key96 *partial, int k,
+                   sncc_match *out, hipStream_t st);
 int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride,
                   int sat_pitch, const DevTmpl *tmpls, const int4 *geom,
                   const double *c64, const SlotTables &slots, const PairDesc *pairs,

@@ -53,7 +53,10 @@ int launch_merge(const PairDesc *, const PairDesc *, int, const unsigned long lo
                  const unsigned long long *, int, sncc_match *, hipStream_t) {
   return -1;
 }
-int launch_map_topk(const double *, int, int, int, int, int, unsigned long long *, hipStream_t) {
+int launch_map_topk64(const double *, int, int, int, int, int, Key96 *, hipStream_t) {
+  return -1;
+}
+int launch_merge64(const PairDesc *, int, const Key96 *, int, sncc_match *, hipStream_t) {
   return -1;
 }
 int launch_refine(const uint32_t *, const uint32_t *, long long, int, const DevTmpl *,

@@ -235,6 +235,49 @@ def test_topk_parity(S, ctx, k, precision):
         assert not errs, (p, errs[:5])
 
 
+def test_fp64_topk_orders_by_the_double_value(S, ctx):
+    """Two copies of the template, the second with one pixel raised and one
+    lowered by a grey level (chosen so that its rho exceeds the first copy's by
+    about 1.2e-8, below float resolution at 0.9999): the FP64 top-k ranks by the
+    double value, so the second copy (larger offset index) comes first, and
+    the whole list is the order of a full sort of the FP64 map with key
+    (rho desc, v, u).  A float key would tie the two and put the first copy
+    first."""
+    import torch
+    rng = np.random.default_rng(123)
+    M, N, W, H = 300, 200, 20, 16
+    f = rng.integers(0, 200, (N, M)).astype(np.uint8)
+    t = rng.integers(10, 200, (H, W)).astype(np.uint8)
+    (x1, y1), (x2, y2) = (40, 20), (200, 150)
+    f[y1:y1 + H, x1:x1 + W] = t
+    f[y2:y2 + H, x2:x2 + W] = t
+    f[y2 + 7, x2 + 15] += 1
+    f[y2 + 14, x2 + 19] -= 1
+    ta = O.precompute_template_approximation(t, 6)
+    s_o, s2_o = O.sum_tables(f)
+    r1 = float(O.rho_at(s_o, s2_o, ta, x1, y1))
+    r2 = float(O.rho_at(s_o, s2_o, ta, x2, y2))
+    assert 1e-9 < r2 - r1 < 3e-8 and np.float32(r1) == np.float32(r2)
+    _, s, s2 = build_sats(S, ctx, [f])
+    tm = lib_templates(S, ctx, [t], [6])
+    nu, nv = M - W + 1, N - H + 1
+    r64 = torch.empty((nv, nu), dtype=torch.float64, device="cuda")
+    out = torch.zeros((1, 8, 3), dtype=torch.int32, device="cuda")
+    S.sncc_score(ctx, tm, 0, s, s2, M, N, S.SNCC_FP64, r64)
+    S.sncc_topk(ctx, tm, s, s2, 1, M, N, [(0, 0)], 8, S.SNCC_FP64, out)
+    S.sncc_sync(ctx)
+    S.sncc_tmpl_destroy(tm)
+    m = r64.cpu().numpy()
+    flat = [(-m[v, u], v, u) for v in range(nv) for u in range(nu)]
+    flat.sort()
+    want = [(u, v) for _, v, u in flat[:8]]
+    got = S.decode_matches(out)[0]
+    order = [(int(a), int(b)) for a, b in zip(got["u"], got["v"])]
+    assert order == want
+    assert np.array_equal(got["rho"], np.float32([-x for x, _, _ in flat[:8]]))
+    assert order[:2] == [(x2, y2), (x1, y1)]
+
+
 def test_topk_more_slots_than_offsets(S, ctx):
     import torch
     f = synth.scene(9, 40, 30)
