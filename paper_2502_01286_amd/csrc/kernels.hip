@@ -870,8 +870,11 @@ __device__ __forceinline__ double staged_rho4(const uint32_t *region, int pitch,
     uint32_t D[4], Dp[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) D[j] = lds_at(region, base[j] + bot) - lds_at(region, base[j] + top);
-    // the previous boundary's difference (row_shr:1), kept separate moves:
-    // folded into the subtraction as v_subrev_u32_dpp it came out negated
+    // the previous boundary's difference (row_shr:1), kept separate moves.
+    // Folded, the compiler writes D - shr(D) as v_subrev_u32_dpp d, D, D,
+    // which on gfx950 computes shr(src1) - src0 instead of src1 - shr(src0)
+    // (a one-wave probe with distinct registers shows the shift applied to
+    // src1): the negated difference.  The empty asm keeps the move separate.
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       Dp[j] = (uint32_t)__builtin_amdgcn_mov_dpp((int)D[j], 0x111, 0xf, 0xf, true);

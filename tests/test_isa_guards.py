@@ -4,9 +4,12 @@ libsncc.so, disassembled with the ROCm LLVM tools; no GPU needed).
 The slow pass and the refine kernel take the previous boundary's column
 difference from the lane below with a separate row_shr:1 DPP move; the
 subtraction that uses it must stay an ordinary VALU subtraction, not a
-subtraction with a DPP source operand (see the comment in staged_rho4).  A
-compiler change that folds the move again would fail here, on the CPU,
-before any GPU run.
+subtraction with a DPP source operand.  On gfx950 the folded form
+v_subrev_u32_dpp d, a, b (which the compiler emits for b - shr(a)) computes
+shr(b) - a: the shift lands on the other operand (see the comment in
+staged_rho4).  No kernel may contain any operand-reversed VOP2 op with a DPP
+source.  A compiler change that folds such a move would fail here, on the
+CPU, before any GPU run.
 """
 
 import os
@@ -83,3 +86,11 @@ def test_row_shift_moves_are_not_folded_into_subtractions():
         moves = [ln for ln in body.splitlines()
                  if "v_mov_b32_dpp" in ln and "row_shr:1" in ln]
         assert moves, name
+
+
+def test_no_operand_reversed_dpp_ops_anywhere():
+    funcs = _functions(_disassembly())
+    assert funcs
+    bad = [(n, ln.strip()) for n, b in funcs.items() for ln in b.splitlines()
+           if re.search(r"\bv_\w*rev\w*_dpp\b", ln)]
+    assert not bad, bad[:3]
