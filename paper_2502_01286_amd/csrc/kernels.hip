@@ -69,21 +69,22 @@ __device__ __forceinline__ uint32_t load_pk4(const uint8_t *row, int x0, int M) 
   return w;
 }
 
-// Entries x0 .. x0 + 3 of a table row (up to column M): one 16-byte store
-// when all four are inside (the row's entries are 4-byte aligned, which a
-// multi-dword global store needs), else dword stores.
-__device__ __forceinline__ void store_4(uint32_t *o, int x0, int M, const uint32_t (&w)[4]) {
-  if (x0 + 3 < M) {
+// Table columns x0 .. x0 + 3 of a row (x0 a multiple of 4, the row 256-byte
+// aligned): one aligned 16-byte store when all four are columns 0 .. M, else
+// dword stores of the columns below the pitch P, 0 past column M.
+__device__ __forceinline__ void store_cols4(uint32_t *o, int x0, int M, int P,
+                                            const uint32_t (&w)[4]) {
+  if (x0 + 3 <= M) {
     uint4 q4;
     q4.x = w[0];
     q4.y = w[1];
     q4.z = w[2];
     q4.w = w[3];
-    __builtin_memcpy(o + x0, &q4, 16);
+    *reinterpret_cast<uint4 *>(o + x0) = q4;
   } else {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      if (x0 + q < M) o[x0 + q] = w[q];
+      if (x0 + q < P) o[x0 + q] = x0 + q <= M ? w[q] : 0u;
   }
 }
 
@@ -327,24 +328,30 @@ __global__ __launch_bounds__(256) void sat_scan(const uint8_t *__restrict__ f,
     const uint32_t ex2 = wave_incl_scan(p2[3]) - p2[3];
     const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)L, r0 + r) + ex;
     const uint32_t base2 = (uint32_t)__builtin_amdgcn_readlane((int)L2, r0 + r) + ex2;
-    uint32_t *o = sb + (size_t)(y + 1) * P + 1;
-    uint32_t *o2 = s2b + (size_t)(y + 1) * P + 1;
+    // the lane writes table columns x0 .. x0 + 3, whose entries sum the
+    // pixel columns left of them: its base plus the exclusive prefix of its
+    // quad (column 0 of the first tile gets 0).  The 16-byte stores are then
+    // aligned, and a wave's row is whole cache lines
+    uint32_t *o = sb + (size_t)(y + 1) * P;
+    uint32_t *o2 = s2b + (size_t)(y + 1) * P;
     uint32_t wv[4], wv2[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      wv[q] = base + p[q];
-      wv2[q] = base2 + p2[q];
+      wv[q] = base + (q ? p[q - 1] : 0u);
+      wv2[q] = base2 + (q ? p2[q - 1] : 0u);
     }
-    store_4(o, x0, M, wv);
-    store_4(o2, x0, M, wv2);
-    if (J == 0 && lane == 0) {  // padded column 0
-      sb[(size_t)(y + 1) * P] = 0;
-      s2b[(size_t)(y + 1) * P] = 0;
-    }
-    if (J == sc.nTX - 1) {  // padding columns M+1 .. P-1
-      for (int c = M + 1 + lane; c < P; c += 64) {
-        sb[(size_t)(y + 1) * P + c] = 0;
-        s2b[(size_t)(y + 1) * P + c] = 0;
+    store_cols4(o, x0, M, P, wv);
+    store_cols4(o2, x0, M, P, wv2);
+    if (J == sc.nTX - 1) {
+      // column M (the row's total) when it lies past the last tile, then
+      // the padding columns M+1 .. P-1 past the last tile
+      if (M == SAT_TX * sc.nTX && lane == 63) {
+        o[M] = base + p[3];
+        o2[M] = base2 + p2[3];
+      }
+      for (int c = max(M + 1, SAT_TX * sc.nTX) + lane; c < P; c += 64) {
+        o[c] = 0;
+        o2[c] = 0;
       }
     }
     // rows one after another: keeps the scheduler from interleaving all of a

@@ -62,6 +62,34 @@ def test_sat_bit_exact(S, ctx, shape):
         assert (gs2[b].astype(np.uint64) == want).all()
 
 
+@pytest.mark.parametrize("M", [1, 3, 4, 5, 63, 64, 65, 252, 255, 256, 257, 511, 512, 640,
+                               1280, 1281])
+def test_sat_every_entry_written(S, ctx, M):
+    """Tables pre-filled with a sentinel: every entry of every row, the zero
+    column, the row total at column M and the padding columns up to the
+    pitch, is written (widths at and around multiples of the 256-column tile
+    and of the 64-word pitch)."""
+    import torch
+    N = 67
+    rng = np.random.default_rng(M)
+    frames = [rng.integers(0, 256, (N, M)).astype(np.uint8) for _ in range(2)]
+    f = torch.from_numpy(np.stack(frames)).cuda()
+    P = S.sncc_sat_pitch(M)
+    print("case", M, P, flush=True)
+    s = torch.full((2, N + 1, P), -0x21524111, dtype=torch.int32, device="cuda")
+    s2 = torch.full_like(s, -0x21524111)
+    S.sncc_build_sats(ctx, f, s, s2)
+    S.sncc_sync(ctx)
+    gs, gs2 = _u32(s), _u32(s2)
+    for b in range(2):
+        os_, os2 = O.sum_tables(frames[b])
+        want = np.zeros((N + 1, P), np.uint64)
+        want[:, :M + 1] = os_ % (1 << 32)
+        assert (gs[b].astype(np.uint64) == want).all()
+        want[:, :M + 1] = os2 % (1 << 32)
+        assert (gs2[b].astype(np.uint64) == want).all()
+
+
 def test_sat_wraps_modulo_2_32_and_windows_stay_exact(S, ctx):
     # all-255 frame: s^2 exceeds 2^32 many times over; 256x256 windows of f^2
     # (the largest template of the workloads) are still exact
