@@ -44,8 +44,15 @@ UNIT = "offset×segment evals/s"
 OPS_PER_EVAL = 9
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: non-packed VALU lane operations/s
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# LDS: 128 bytes/clock/CU x 256 CUs x 2.4 GHz; 16 bytes (4 corners) per eval
-LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12
+# LDS read bandwidth measured on MI355X with paper_2502_01286_amd/lds_probe
+# (profiles/lds_read_bandwidth.txt), bytes/clock/CU at 2.4 GHz x 256 CUs: the
+# widest read form (ds_read_b128) is the peak; ds_read2st64_b32, the form the
+# scoring kernel's corner reads use, is reported beside it.  16 bytes (4
+# corners) per eval by the method's definition.
+LDS_B128_B_PER_CLK = 171.7
+LDS_READ2ST64_B_PER_CLK = 102.7
+LDS_PEAK_TBS = LDS_B128_B_PER_CLK * 256 * 2.4e9 / 1e12
+LDS_READ2ST64_TBS = LDS_READ2ST64_B_PER_CLK * 256 * 2.4e9 / 1e12
 
 
 def log(*a):
@@ -808,7 +815,10 @@ def main():
                 "kernel_ms": round(avg["ms_score"], 4),
                 "ops_per_eval": OPS_PER_EVAL, "evals_per_launch": evals,
                 "lds": {"achieved_TBps": round(lds_tbs, 3), "peak_TBps": round(LDS_PEAK_TBS, 2),
-                        "frac": round(lds_tbs / LDS_PEAK_TBS, 4), "bytes_per_eval": 16}}
+                        "frac": round(lds_tbs / LDS_PEAK_TBS, 4), "bytes_per_eval": 16,
+                        "peak_form": "ds_read_b128 (measured)",
+                        "read2st64_TBps": round(LDS_READ2ST64_TBS, 2),
+                        "frac_of_read2st64": round(lds_tbs / LDS_READ2ST64_TBS, 4)}}
         if avg["ms_sat"]:
             px = B * M * N
             roof["sat"] = {"bound": "hbm", "achieved_GBps": round(9 * px / (avg["ms_sat"] / 1e3) / 1e9, 1),

@@ -20,6 +20,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsncc.so")
+PROBE = os.path.join(HERE, "lds_probe")  # LDS bandwidth probe (a program of its own)
 ARCH = os.environ.get("SNCC_OFFLOAD_ARCH", "gfx950")
 
 # (source, extra flags, object name): the scoring kernel's tile shapes are
@@ -29,6 +30,8 @@ SOURCES = [("segment.cpp", [], "segment.o"), ("api.cpp", [], "api.o"),
            ("kernels.hip", [], "kernels.o"), ("fused_kernel.hip", [], "fused_kernel.o")] + [
     ("tile_entry.hip", [f"-DSNCC_TILE_ENTRY_ID={i}"], f"tile_entry_{i}.o")
     for i in range(N_TILE_SHAPES)]
+
+PROBE_SRC = os.path.join(CSRC, "lds_probe.hip")
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-x", "hip", f"--offload-arch={ARCH}",
@@ -59,8 +62,19 @@ def build(verbose: bool = False) -> str:
             if r.returncode != 0:
                 raise RuntimeError(f"compiling {src} failed:\n{r.stdout}\n{r.stderr}")
             return obj
-        with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4, 16)) as ex:
+        def build_probe():
+            # the LDS bandwidth probe: a separate program, not linked into the library
+            cmd = [hipcc, "-O3", "-std=c++17", "-x", "hip", f"--offload-arch={ARCH}",
+                   "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", PROBE_SRC,
+                   "-o", PROBE + ".tmp"]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError(f"compiling lds_probe.hip failed:\n{r.stdout}\n{r.stderr}")
+            os.replace(PROBE + ".tmp", PROBE)
+        with ThreadPoolExecutor(max_workers=min(len(SOURCES) + 1, os.cpu_count() or 4, 16)) as ex:
+            probe = ex.submit(build_probe)
             objs = list(ex.map(compile_one, SOURCES))
+            probe.result()
         out_tmp = LIB + ".tmp"
         cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out_tmp]
         r = subprocess.run(cmd, capture_output=True, text=True)
