@@ -856,6 +856,13 @@ __device__ __forceinline__ double slow_rho(double acc, uint32_t sf, u64 sf2, con
   return V == 0 ? 0.0 : num / sqrt((double)V / (double)td.n * td.q_k);
 }
 
+// Whether four windows are consecutive offsets of one row (region byte
+// offsets 4 apart); the answer is made wave-uniform.
+__device__ __forceinline__ bool consecutive4(const int (&base)[4]) {
+  const bool c = base[1] == base[0] + 4 && base[2] == base[0] + 8 && base[3] == base[0] + 12;
+  return __builtin_amdgcn_readfirstlane((int)c) != 0;
+}
+
 // FP64 rho (Eqs. (12), (13), (15)-(18)) of four windows of one template
 // whose table entries are staged in LDS: base[j] is the region byte offset
 // of window j's top-left entry (row pitch `pitch` words), gof[j] its byte
@@ -864,7 +871,10 @@ __device__ __forceinline__ double slow_rho(double acc, uint32_t sf, u64 sf2, con
 // the next step's slot entries requested ahead; per slot and window two LDS
 // reads give the column difference D, the lane below holds the previous
 // boundary's D, and c_i (D - D_prev) is added to the lane's FP64 sum.  Lane l
-// returns the rho of window l mod 4.
+// returns the rho of window l mod 4.  CONSEC: the four windows are
+// consecutive offsets of one row (base[j] = base[0] + 4 j), so one address per
+// slot serves all four reads, with immediate offsets.
+template <bool CONSEC>
 __device__ __forceinline__ double staged_rho4(const uint32_t *region, int pitch,
                                               const int (&base)[4], const int (&gof)[4],
                                               __amdgpu_buffer_rsrc_t rso,
@@ -875,8 +885,17 @@ __device__ __forceinline__ double staged_rho4(const uint32_t *region, int pitch,
   auto block = [&](uint32_t o, double c) {
     const int top = (int)(o & 0xffffu), bot = (int)(o >> 16);
     uint32_t D[4], Dp[4];
+    if constexpr (CONSEC) {
+      const char *rb = reinterpret_cast<const char *>(region) + base[0];
+      const uint32_t *pb = reinterpret_cast<const uint32_t *>(rb + bot);
+      const uint32_t *pt = reinterpret_cast<const uint32_t *>(rb + top);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) D[j] = lds_at(region, base[j] + bot) - lds_at(region, base[j] + top);
+      for (int j = 0; j < 4; ++j) D[j] = pb[j] - pt[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        D[j] = lds_at(region, base[j] + bot) - lds_at(region, base[j] + top);
+    }
     // the previous boundary's difference (row_shr:1), kept separate moves.
     // Folded, the compiler writes D - shr(D) as v_subrev_u32_dpp d, D, D,
     // which on gfx950 computes shr(src1) - src0 instead of src1 - shr(src0)
@@ -985,7 +1004,11 @@ __global__ __launch_bounds__(256) void slow_kernel(
         }
         // lane j < kSlowBatch holds survivor b + j
         const double rho =
-            staged_rho4(region, st.pitch, base, gof, rso, rsc, st.n_iter, rs2, P4, td, lane);
+            consecutive4(base)
+                ? staged_rho4<true>(region, st.pitch, base, gof, rso, rsc, st.n_iter, rs2, P4,
+                                    td, lane)
+                : staged_rho4<false>(region, st.pitch, base, gof, rso, rsc, st.n_iter, rs2, P4,
+                                     td, lane);
         const int jj = lane & 3;
         const int uu = jj == 0 ? su[0] : jj == 1 ? su[1] : jj == 2 ? su[2] : su[3];
         const int vv = jj == 0 ? sv[0] : jj == 1 ? sv[1] : jj == 2 ? sv[2] : sv[3];
@@ -1232,7 +1255,11 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
       }
       // lane j < 4 holds entry c0 + e0 + j
       const double r =
-          staged_rho4(region, st.pitch, base, gof, rso, rsc, st.n_iter, rs2, P4, td, lane);
+          consecutive4(base)
+              ? staged_rho4<true>(region, st.pitch, base, gof, rso, rsc, st.n_iter, rs2, P4, td,
+                                  lane)
+              : staged_rho4<false>(region, st.pitch, base, gof, rso, rsc, st.n_iter, rs2, P4, td,
+                                   lane);
       const int jj = lane & 3;
       const int uu = jj == 0 ? su[0] : jj == 1 ? su[1] : jj == 2 ? su[2] : su[3];
       const int vv = jj == 0 ? sv[0] : jj == 1 ? sv[1] : jj == 2 ? sv[2] : sv[3];
