@@ -819,6 +819,19 @@ def main():
                         "peak_form": "ds_read_b128 (measured)",
                         "read2st64_TBps": round(LDS_READ2ST64_TBS, 2),
                         "frac_of_read2st64": round(lds_tbs / LDS_READ2ST64_TBS, 4)}}
+        if avg.get("ms_refine") and cnt is not None:
+            # FP64 re-score (steps 7f-i): unique neighbourhood offsets of each
+            # pair x the fine approximation's segments, 5 method ops per eval
+            # (as for the slow pass of the two-threshold search)
+            Kf = [len(a) for a in fine_l]
+            per_pair = cnt.cpu().numpy().astype(np.int64)
+            fine_evals = int(sum(int(c) * Kf[t] for c, (_, t) in zip(per_pair, wl.pairs)))
+            rtops = 5 * fine_evals / (avg["ms_refine"] / 1e3) / 1e12
+            roof["refine"] = {"bound": "alu", "unit": "TOP/s (FP64 VALU lane ops)",
+                              "achieved": round(rtops, 3), "peak": round(FP64_VALU_PEAK_TOPS, 2),
+                              "frac": round(rtops / FP64_VALU_PEAK_TOPS, 4),
+                              "ops_per_eval": 5, "evals": fine_evals,
+                              "ms": round(avg["ms_refine"], 4)}
         if avg["ms_sat"]:
             px = B * M * N
             roof["sat"] = {"bound": "hbm", "achieved_GBps": round(9 * px / (avg["ms_sat"] / 1e3) / 1e9, 1),
