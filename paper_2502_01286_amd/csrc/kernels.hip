@@ -1050,9 +1050,10 @@ int launch_slow(const SlowArgs &a, int grid, int lds_bytes, hipStream_t st) {
 // Section 5, steps 7f-i with the coarse pass's top-k as candidates: rho in
 // FP64 with the fine approximation at every offset within `radius` of a
 // candidate, and the best of them (rho descending, then v, then u).  One
-// workgroup per pair: the candidates' neighbourhoods are listed in LDS by a
-// key that orders offsets in column bands of 16 (band, v, u), sorted
-// (bitonic) and made unique.  The unique offsets are then scored in chunks
+// workgroup per pair: the candidates are ordered by (column band of 16, v, u)
+// in one wave, and their neighbourhoods are listed in LDS in that order, each
+// offset once (by the first candidate whose neighbourhood holds it).  The
+// unique offsets are then scored in chunks
 // of at most kRefineChunk consecutive entries spanning at most kRefineSpanU
 // columns and kRefineSpanV rows, each from a staged region of the frame's
 // table, four offsets per wave at a time (staged_rho4); for templates whose
@@ -1074,6 +1075,7 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
   __shared__ int wsum[kRefineWaves];
   __shared__ double best_r[kRefineWaves];
   __shared__ int best_i[kRefineWaves];
+  __shared__ int cand_u[64], cand_v[64];  // the candidates in (band, v, u) order
   extern __shared__ uint32_t dyn[];  // the offset list (np ints), then the region
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int p = blockIdx.x;
@@ -1087,56 +1089,63 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
   while (np < total) np <<= 1;
   int *const list = reinterpret_cast<int *>(dyn);
   uint32_t *const region = dyn + np;
-  // candidate neighbourhoods, clipped; INT_MAX marks an empty slot
-  for (int e = tid; e < np; e += kRefineThreads) {
-    int val = 0x7fffffff;
-    if (e < total) {
-      const int j = e / area, d = e - j * area;
-      const sncc_match c = cand[(long long)p * n_cand + j];
-      const int u = c.u + d % side - radius, v = c.v + d / side - radius;
-      if (c.u >= 0 && u >= 0 && u < pd.nu && v >= 0 && v < pd.nv)
-        val = (u >> 4) * band_keys + v * 16 + (u & 15);
+  // entries are (v << 16 | u) when both fit 16 bits, else the row-major index
+  const bool packed = pd.nu <= 65536 && pd.nv <= 65536;
+  // the candidates, ordered by (column band of 16, v, u) with a bitonic sort
+  // in wave 0's lanes (k <= 64); invalid candidates sort last
+  if (wave == 0) {
+    int key = 0x7fffffff;
+    if (lane < n_cand) {
+      const sncc_match c = cand[(long long)p * n_cand + lane];
+      if (c.u >= 0) key = (c.u >> 4) * band_keys + c.v * 16 + (c.u & 15);
     }
-    list[e] = val;
+    for (int size = 2; size <= 64; size <<= 1)
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        const int other = __shfl_xor(key, stride);
+        const bool up = (lane & size) == 0, low = (lane & stride) == 0;
+        key = (low == up) ? min(key, other) : max(key, other);
+      }
+    int cu = -1, cv = -1;
+    if (key != 0x7fffffff) {
+      const int band = key / band_keys, rem = key - band * band_keys;
+      cv = rem >> 4;
+      cu = band * 16 + (rem & 15);
+    }
+    if (lane < n_cand) {
+      cand_u[lane] = cu;
+      cand_v[lane] = cv;
+    }
   }
   __syncthreads();
-  // bitonic sort ascending
-  for (int size = 2; size <= np; size <<= 1)
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = tid; i < np; i += kRefineThreads) {
-        const int j = i ^ stride;
-        if (j > i) {
-          const int a = list[i], b = list[j];
-          const bool up = (i & size) == 0;
-          if ((a > b) == up) {
-            list[i] = b;
-            list[j] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  // unique values: each thread owns a contiguous run of the sorted list
-  const int per = (np + kRefineThreads - 1) / kRefineThreads;
-  const int r0 = min(np, tid * per), r1 = min(np, r0 + per);
-  int cnt = 0;
-  for (int i = r0; i < r1; ++i)
-    if (list[i] != 0x7fffffff && (i == 0 || list[i] != list[i - 1])) ++cnt;
-  const uint32_t incl = wave_incl_scan((uint32_t)cnt);
-  if (lane == 63) wsum[wave] = (int)incl;
-  __syncthreads();
-  int off = (int)incl - cnt;
-  for (int w = 0; w < wave; ++w) off += wsum[w];
+  // the union of the neighbourhoods: an offset is listed by the first
+  // candidate (in that order) whose neighbourhood holds it, so every offset
+  // once; entries follow the candidates, each neighbourhood row by row
   int L = 0;
-  for (int w = 0; w < kRefineWaves; ++w) L += wsum[w];
-  // gather unique entries into registers before compacting in place
-  int mine[16];
-  int m = 0;
-  for (int i = r0; i < r1 && m < 16; ++i)
-    if (list[i] != 0x7fffffff && (i == 0 || list[i] != list[i - 1])) mine[m++] = list[i];
-  __syncthreads();
-  for (int q = 0; q < m; ++q) list[off + q] = mine[q];
-  __syncthreads();
+  for (int e0 = 0; e0 < total; e0 += kRefineThreads) {
+    const int e = e0 + tid;
+    int u = 0, v = 0;
+    bool own = false;
+    if (e < total) {
+      const int j = e / area, d = e - j * area;
+      const int cu = cand_u[j], cv = cand_v[j];
+      u = cu + d % side - radius;
+      v = cv + d / side - radius;
+      own = cu >= 0 && u >= 0 && u < pd.nu && v >= 0 && v < pd.nv;
+      for (int i = 0; own && i < j; ++i)
+        own = !(abs(u - cand_u[i]) <= radius && abs(v - cand_v[i]) <= radius);
+    }
+    const uint32_t incl = wave_incl_scan(own ? 1u : 0u);
+    if (lane == 63) wsum[wave] = (int)incl;
+    __syncthreads();
+    int pos = L + (int)incl - (own ? 1 : 0), add = 0;
+    for (int w = 0; w < kRefineWaves; ++w) {
+      pos += w < wave ? wsum[w] : 0;
+      add += wsum[w];
+    }
+    if (own) list[pos] = packed ? (v << 16) | u : v * pd.nu + u;
+    L += add;
+    __syncthreads();  // wsum is rewritten by the next round
+  }
   // FP64 scores with the fine approximation, chunk by chunk
   const uint32_t *S = s + (long long)pd.frame * frame_stride;
   const uint32_t *S2 = s2 + (long long)pd.frame * frame_stride;
@@ -1144,31 +1153,14 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(S, bytes);
   const __amdgpu_buffer_rsrc_t rs2 = make_rsrc(S2, bytes);
   const int P4 = P * 4;
-  auto decode = [&](int key, int &u, int &v) {
-    const int band = key / band_keys, rem = key - band * band_keys;
-    v = rem >> 4;
-    u = band * 16 + (rem & 15);
-  };
-  // the unique keys are rewritten as (v << 16 | u) when both fit 16 bits
-  // (the list keeps its order), so that the serial chunk cut and the
-  // per-chunk loops below unpack an entry with two operations instead of a
-  // division
-  const bool packed = pd.nu <= 65536 && pd.nv <= 65536;
-  if (packed) {
-    for (int i = tid; i < L; i += kRefineThreads) {
-      int u, v;
-      decode(list[i], u, v);
-      list[i] = (v << 16) | u;
-    }
-    __syncthreads();
-  }
   auto entry = [&](int i, int &u, int &v) {
     const int x = list[i];
     if (packed) {
       u = x & 0xffff;
       v = (int)((uint32_t)x >> 16);
     } else {
-      decode(x, u, v);
+      v = x / pd.nu;
+      u = x - v * pd.nu;
     }
   };
   double br = -__builtin_inf();
@@ -1192,25 +1184,34 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
   // chunks: runs of at most kRefineChunk consecutive entries whose offsets
   // span at most kRefineSpanU columns and kRefineSpanV rows, cut greedily in
   // list order (one thread; the list holds at most a few hundred entries)
+  // (wave 0: the entries are read 64 at a time into lanes and walked with
+  // lane reads, so the serial walk waits on no LDS read)
   for (int i = tid; i < REFINE_CAP / 32; i += kRefineThreads) first[i] = 0;
   __syncthreads();
-  if (tid == 0) {
+  if (wave == 0) {
     int c0 = 0, umin = 0, umax = 0, vmin = 0, vmax = 0;
-    for (int i = 0; i < L; ++i) {
-      int u, v;
-      entry(i, u, v);
-      if (i == c0 || i - c0 == kRefineChunk || max(umax, u) - min(umin, u) >= kRefineSpanU ||
-          max(vmax, v) - min(vmin, v) >= kRefineSpanV) {
-        first[i >> 5] |= 1u << (i & 31);
-        c0 = i;
-        umin = umax = u;
-        vmin = vmax = v;
-      } else {
-        umin = min(umin, u);
-        umax = max(umax, u);
-        vmin = min(vmin, v);
-        vmax = max(vmax, v);
+    for (int i0 = 0; i0 < L; i0 += 64) {
+      int lu = 0, lv = 0;
+      if (i0 + lane < L) entry(i0 + lane, lu, lv);
+      const int n64 = min(64, L - i0);
+      uint64_t starts = 0;
+      for (int q = 0; q < n64; ++q) {
+        const int i = i0 + q;
+        const int u = __builtin_amdgcn_readlane(lu, q), v = __builtin_amdgcn_readlane(lv, q);
+        if (i == c0 || i - c0 == kRefineChunk || max(umax, u) - min(umin, u) >= kRefineSpanU ||
+            max(vmax, v) - min(vmin, v) >= kRefineSpanV) {
+          starts |= 1ull << q;
+          c0 = i;
+          umin = umax = u;
+          vmin = vmax = v;
+        } else {
+          umin = min(umin, u);
+          umax = max(umax, u);
+          vmin = min(vmin, v);
+          vmax = max(vmax, v);
+        }
       }
+      if (lane < 2) first[(i0 >> 5) + lane] = (uint32_t)(starts >> (32 * lane));
     }
   }
   __syncthreads();
@@ -1224,20 +1225,16 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
   };
   for (int c0 = 0; st.tbl >= 0 && c0 < L;) {
     const int c1 = __builtin_amdgcn_readfirstlane(chunk_end(c0));
-    const int n = c1 - c0;
-    int umin = 0x7fffffff, umax = -1, vmin = 0x7fffffff, vmax = -1;
-    for (int i = 0; i < n; ++i) {  // every thread, same values
-      int u, v;
-      entry(c0 + i, u, v);
-      umin = min(umin, u);
-      umax = max(umax, u);
-      vmin = min(vmin, v);
-      vmax = max(vmax, v);
-    }
-    umin = __builtin_amdgcn_readfirstlane(umin);
-    umax = __builtin_amdgcn_readfirstlane(umax);
-    vmin = __builtin_amdgcn_readfirstlane(vmin);
-    vmax = __builtin_amdgcn_readfirstlane(vmax);
+    const int n = c1 - c0;  // at most 64: lane i takes entry c0 + i
+    int eu = 0, ev = 0;
+    if (lane < n) entry(c0 + lane, eu, ev);
+    // bounds by wave maxima (the minima as maxima of complements; lanes past
+    // n give 0 to every maximum)
+    const bool in = lane < n;
+    const int umax = (int)__builtin_amdgcn_readlane((int)wave_incl_max(in ? (uint32_t)eu : 0u), 63);
+    const int vmax = (int)__builtin_amdgcn_readlane((int)wave_incl_max(in ? (uint32_t)ev : 0u), 63);
+    const int umin = (int)~__builtin_amdgcn_readlane((int)wave_incl_max(in ? ~(uint32_t)eu : 0u), 63);
+    const int vmin = (int)~__builtin_amdgcn_readlane((int)wave_incl_max(in ? ~(uint32_t)ev : 0u), 63);
     // the entries the chunk's windows read: rows [vmin, vmax + H], columns
     // [umin, umax + W] of the table, at the region's pitch
     const int nrow = vmax - vmin + td.H + 1, ncol = umax - umin + td.W + 1;
