@@ -1091,60 +1091,115 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
   uint32_t *const region = dyn + np;
   // entries are (v << 16 | u) when both fit 16 bits, else the row-major index
   const bool packed = pd.nu <= 65536 && pd.nv <= 65536;
-  // the candidates, ordered by (column band of 16, v, u) with a bitonic sort
-  // in wave 0's lanes (k <= 64); invalid candidates sort last
-  if (wave == 0) {
-    int key = 0x7fffffff;
-    if (lane < n_cand) {
-      const sncc_match c = cand[(long long)p * n_cand + lane];
-      if (c.u >= 0) key = (c.u >> 4) * band_keys + c.v * 16 + (c.u & 15);
-    }
-    for (int size = 2; size <= 64; size <<= 1)
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        const int other = __shfl_xor(key, stride);
-        const bool up = (lane & size) == 0, low = (lane & stride) == 0;
-        key = (low == up) ? min(key, other) : max(key, other);
-      }
-    int cu = -1, cv = -1;
-    if (key != 0x7fffffff) {
-      const int band = key / band_keys, rem = key - band * band_keys;
-      cv = rem >> 4;
-      cu = band * 16 + (rem & 15);
-    }
-    if (lane < n_cand) {
-      cand_u[lane] = cu;
-      cand_v[lane] = cv;
-    }
-  }
-  __syncthreads();
-  // the union of the neighbourhoods: an offset is listed by the first
-  // candidate (in that order) whose neighbourhood holds it, so every offset
-  // once; entries follow the candidates, each neighbourhood row by row
   int L = 0;
-  for (int e0 = 0; e0 < total; e0 += kRefineThreads) {
-    const int e = e0 + tid;
-    int u = 0, v = 0;
-    bool own = false;
-    if (e < total) {
-      const int j = e / area, d = e - j * area;
-      const int cu = cand_u[j], cv = cand_v[j];
-      u = cu + d % side - radius;
-      v = cv + d / side - radius;
-      own = cu >= 0 && u >= 0 && u < pd.nu && v >= 0 && v < pd.nv;
-      for (int i = 0; own && i < j; ++i)
-        own = !(abs(u - cand_u[i]) <= radius && abs(v - cand_v[i]) <= radius);
+  auto to_entry = [&](int u, int v) { return packed ? (v << 16) | u : v * pd.nu + u; };
+  if (n_cand <= 64) {
+    // the candidates, ordered by (column band of 16, v, u) with a bitonic sort
+    // in wave 0's lanes (k <= 64); invalid candidates sort last
+    if (wave == 0) {
+      int key = 0x7fffffff;
+      if (lane < n_cand) {
+        const sncc_match c = cand[(long long)p * n_cand + lane];
+        if (c.u >= 0) key = (c.u >> 4) * band_keys + c.v * 16 + (c.u & 15);
+      }
+      for (int size = 2; size <= 64; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+          const int other = __shfl_xor(key, stride);
+          const bool up = (lane & size) == 0, low = (lane & stride) == 0;
+          key = (low == up) ? min(key, other) : max(key, other);
+        }
+      int cu = -1, cv = -1;
+      if (key != 0x7fffffff) {
+        const int band = key / band_keys, rem = key - band * band_keys;
+        cv = rem >> 4;
+        cu = band * 16 + (rem & 15);
+      }
+      if (lane < n_cand) {
+        cand_u[lane] = cu;
+        cand_v[lane] = cv;
+      }
     }
-    const uint32_t incl = wave_incl_scan(own ? 1u : 0u);
+    __syncthreads();
+    // the union of the neighbourhoods: an offset is listed by the first
+    // candidate (in that order) whose neighbourhood holds it, so every offset
+    // once; entries follow the candidates, each neighbourhood row by row
+    for (int e0 = 0; e0 < total; e0 += kRefineThreads) {
+      const int e = e0 + tid;
+      int u = 0, v = 0;
+      bool own = false;
+      if (e < total) {
+        const int j = e / area, d = e - j * area;
+        const int cu = cand_u[j], cv = cand_v[j];
+        u = cu + d % side - radius;
+        v = cv + d / side - radius;
+        own = cu >= 0 && u >= 0 && u < pd.nu && v >= 0 && v < pd.nv;
+        for (int i = 0; own && i < j; ++i)
+          own = !(abs(u - cand_u[i]) <= radius && abs(v - cand_v[i]) <= radius);
+      }
+      const uint32_t incl = wave_incl_scan(own ? 1u : 0u);
+      if (lane == 63) wsum[wave] = (int)incl;
+      __syncthreads();
+      int pos = L + (int)incl - (own ? 1 : 0), add = 0;
+      for (int w = 0; w < kRefineWaves; ++w) {
+        pos += w < wave ? wsum[w] : 0;
+        add += wsum[w];
+      }
+      if (own) list[pos] = to_entry(u, v);
+      L += add;
+      __syncthreads();  // wsum is rewritten by the next round
+    }
+  } else {
+    // more candidates than a wave's lanes: the neighbourhoods' keys (band, v,
+    // u) are sorted (bitonic, in LDS) and made unique, then rewritten as
+    // entries in place
+    for (int e = tid; e < np; e += kRefineThreads) {
+      int val = 0x7fffffff;
+      if (e < total) {
+        const int j = e / area, d = e - j * area;
+        const sncc_match c = cand[(long long)p * n_cand + j];
+        const int u = c.u + d % side - radius, v = c.v + d / side - radius;
+        if (c.u >= 0 && u >= 0 && u < pd.nu && v >= 0 && v < pd.nv)
+          val = (u >> 4) * band_keys + v * 16 + (u & 15);
+      }
+      list[e] = val;
+    }
+    __syncthreads();
+    for (int size = 2; size <= np; size <<= 1)
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = tid; i < np; i += kRefineThreads) {
+          const int j = i ^ stride;
+          if (j > i) {
+            const int x = list[i], y = list[j];
+            const bool up = (i & size) == 0;
+            if ((x > y) == up) {
+              list[i] = y;
+              list[j] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    // unique keys: each thread owns a contiguous run of the sorted list (at
+    // most 4096 / kRefineThreads = 8 entries)
+    const int per = (np + kRefineThreads - 1) / kRefineThreads;
+    const int r0 = min(np, tid * per), r1 = min(np, r0 + per);
+    int mine[8];
+    int m = 0;
+    for (int i = r0; i < r1; ++i)
+      if (list[i] != 0x7fffffff && (i == 0 || list[i] != list[i - 1])) {
+        const int key = list[i];
+        const int band = key / band_keys, rem = key - band * band_keys;
+        mine[m++] = to_entry(band * 16 + (rem & 15), rem >> 4);
+      }
+    const uint32_t incl = wave_incl_scan((uint32_t)m);
     if (lane == 63) wsum[wave] = (int)incl;
     __syncthreads();
-    int pos = L + (int)incl - (own ? 1 : 0), add = 0;
-    for (int w = 0; w < kRefineWaves; ++w) {
-      pos += w < wave ? wsum[w] : 0;
-      add += wsum[w];
-    }
-    if (own) list[pos] = packed ? (v << 16) | u : v * pd.nu + u;
-    L += add;
-    __syncthreads();  // wsum is rewritten by the next round
+    int off = (int)incl - m;
+    for (int w = 0; w < wave; ++w) off += wsum[w];
+    for (int w = 0; w < kRefineWaves; ++w) L += wsum[w];
+    __syncthreads();  // every run read before the list is compacted in place
+    for (int q = 0; q < m; ++q) list[off + q] = mine[q];
+    __syncthreads();
   }
   // FP64 scores with the fine approximation, chunk by chunk
   const uint32_t *S = s + (long long)pd.frame * frame_stride;

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from oracle import select as OSEL
 from workloads import synth
 
 from gpu_util import build_sats, lib_templates, oracle_templates, topk_ok
@@ -438,6 +439,55 @@ def test_refine_parity(S, ctx, case):
         assert counts[p] == len(res["fine_u"])
         assert (int(got[p]["u"]), int(got[p]["v"])) == res["best"][:2], p
         assert abs(float(got[p]["rho"]) - res["best"][2]) <= TOL64
+
+
+@pytest.mark.parametrize("n_cand,radius", [(96, 1), (300, 0), (64, 2), (65, 2)])
+def test_refine_many_candidates(S, ctx, n_cand, radius):
+    """Candidate lists longer than a wavefront (up to n_cand (2 radius + 1)^2 =
+    4096 entries are allowed): clustered and scattered offsets, duplicates and
+    empty slots.  Count = the oracle's neighbourhood union, best = the
+    oracle's FP64 argmax over it (rho desc, then v, then u)."""
+    import torch
+    frames, temps, _, pairs = _multi(72, sigmas=(16, 16, 16, 16))
+    print("case", n_cand, radius, flush=True)
+    B, N, M = len(frames), frames[0].shape[0], frames[0].shape[1]
+    _, s, s2 = build_sats(S, ctx, frames)
+    fine = lib_templates(S, ctx, temps, [4] * len(temps))
+    tas_f = oracle_templates(temps, [4] * len(temps))
+    tables = [O.sum_tables(f) for f in frames]
+    rng = np.random.default_rng(n_cand * 10 + radius)
+    cand = np.zeros((len(pairs), n_cand, 3), np.int32)
+    for p, (b, ti) in enumerate(pairs):
+        nu, nv = M - temps[ti].shape[1] + 1, N - temps[ti].shape[0] + 1
+        cu, cv = int(rng.integers(0, nu)), int(rng.integers(0, nv))
+        for j in range(n_cand):
+            if j % 3 == 0:      # scattered
+                u, v = int(rng.integers(0, nu)), int(rng.integers(0, nv))
+            else:               # a cluster, reaching past the edges
+                u = int(np.clip(cu + rng.integers(-6, 7), -2, nu + 1))
+                v = int(np.clip(cv + rng.integers(-6, 7), -2, nv + 1))
+                u, v = min(max(u, 0), nu - 1), min(max(v, 0), nv - 1)
+            cand[p, j] = (u, v, 0)
+        cand[p, 5] = cand[p, 2]              # a duplicate
+        cand[p, n_cand - 1] = (-1, -1, 0)    # an empty slot
+    dcand = torch.from_numpy(cand).cuda()
+    out = torch.zeros((len(pairs), 4), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(len(pairs), dtype=torch.int32, device="cuda")
+    S.sncc_refine(ctx, fine, s, s2, B, M, N, pairs, dcand, radius, out, cnt)
+    S.sncc_sync(ctx)
+    got = S.decode_matches64(out)
+    counts = cnt.cpu().numpy()
+    for p, (b, ti) in enumerate(pairs):
+        nu, nv = M - temps[ti].shape[1] + 1, N - temps[ti].shape[0] + 1
+        valid = [(int(u), int(v), 0.0) for u, v, _ in cand[p] if u >= 0]
+        us, vs = OSEL.neighbourhood(valid, radius, nu, nv)
+        assert counts[p] == len(us), (p, counts[p], len(us))
+        rho = np.array([float(O.rho_at(*tables[b], tas_f[ti], int(u), int(v)))
+                        for u, v in zip(us, vs)])
+        order = sorted(range(len(us)), key=lambda i: (-rho[i], vs[i], us[i]))
+        best = order[0]
+        assert (int(got[p]["u"]), int(got[p]["v"])) == (int(us[best]), int(vs[best])), p
+        assert abs(float(got[p]["rho"]) - rho[best]) <= TOL64
 
 
 # ------------------------------------------------------------------ batches
