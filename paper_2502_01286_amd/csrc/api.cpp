@@ -627,14 +627,21 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int P, int n_pairs,
 // Boundary-slot tables (see SlowTmpl) of a template set for runs of
 // span_u x span_v offsets: a template whose region, (span_v + H) rows of
 // span_u + W + 1 words, exceeds max_words keeps tbl = -1 (global form).
-void plan_slots(const sncc_tmpl *tm, int span_u, int span_v, int max_words, PlanHost &ph) {
+void plan_slots(const sncc_tmpl *tm, int span_u, int span_v, int max_words, PlanHost &ph,
+                int narrow_u = 0, int narrow_v = 0) {
   ph.slow.assign(tm->T, SlowTmpl{-1, 0, 0, 0});
   ph.slot_off.clear();
   ph.slot_c.clear();
   ph.slow_lds = 0;
   for (int t = 0; t < tm->T; ++t) {
     const int W = tm->W[t], H = tm->H[t];
-    const int pitch = span_u + W + 1, rows = span_v + H;
+    // the region of (span_u, span_v) offsets, or of the narrower spans when
+    // that one exceeds the budget
+    int pitch = span_u + W + 1, rows = span_v + H;
+    if ((long long)pitch * rows > max_words && narrow_u > 0) {
+      pitch = narrow_u + W + 1;
+      rows = narrow_v + H;
+    }
     if ((long long)pitch * rows > max_words) continue;
     const std::vector<Seg> &segs = tm->segs[t];
     std::vector<std::vector<int>> pieces = horizontal_chains(segs, kSlowChainMax);
@@ -1485,7 +1492,8 @@ int sncc_refine(sncc_ctx *ctx, const sncc_tmpl *fine, const uint32_t *d_s, const
     q.nv = N - fine->H[t] + 1;
   }
   CHK(pd->d_pairs.upload(h.pairs, ctx->stream));
-  plan_slots(fine, kRefineSpanU, kRefineSpanV, kRefineRegionWords, h);
+  plan_slots(fine, kRefineWideSpanU, kRefineWideSpanV, kRefineRegionWords, h, kRefineSpanU,
+             kRefineSpanV);
   CHK(pd->d_slow.upload(h.slow, ctx->stream));
   CHK(pd->d_slot_off.upload(h.slot_off, ctx->stream));
   CHK(pd->d_slot_c.upload(h.slot_c, ctx->stream));
@@ -1880,7 +1888,8 @@ int sncc_batch_create(sncc_ctx *ctx, const sncc_batch_desc *desc, sncc_batch **o
   b->plan.reset(new PlanDev());
   CHK(build_plan(d.coarse, cfg, d.M, d.N, d.sat_pitch, d.n_pairs, b->pairs.data(), d.k, kSinkTopk,
                  ctx->num_cu, b->plan->h, nullptr, split));
-  if (d.fine) plan_slots(d.fine, kRefineSpanU, kRefineSpanV, kRefineRegionWords, b->plan->h);
+  if (d.fine) plan_slots(d.fine, kRefineWideSpanU, kRefineWideSpanV, kRefineRegionWords, b->plan->h,
+                          kRefineSpanU, kRefineSpanV);
   CHK(b->plan->upload(ctx->stream));
   if (any_edge) {
     b->edge.reset(new PlanDev());

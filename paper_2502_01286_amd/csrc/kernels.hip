@@ -1054,13 +1054,14 @@ int launch_slow(const SlowArgs &a, int grid, int lds_bytes, hipStream_t st) {
 // in one wave, and their neighbourhoods are listed in LDS in that order, each
 // offset once (by the first candidate whose neighbourhood holds it).  The
 // unique offsets are then scored in chunks
-// of at most kRefineChunk consecutive entries spanning at most kRefineSpanU
-// columns and kRefineSpanV rows, each from a staged region of the frame's
+// of at most kRefineChunk consecutive entries spanning at most the
+// template's region spans (32 x 16 offsets where that region fits the LDS
+// budget, else 16 x 8), each from a staged region of the frame's
 // table, four offsets per wave at a time (staged_rho4); for templates whose
 // region does not fit LDS, one offset per thread from the global tables
 // (rho_plain).
 constexpr int REFINE_CAP = 4096;
-constexpr int kRefineChunk = 64;  // entries per chunk: up to two batches of four per wave
+constexpr int kRefineChunk = 128;  // entries per chunk: up to four batches of four per wave
 constexpr int kRefineWaves = 8;
 constexpr int kRefineThreads = 64 * kRefineWaves;
 
@@ -1237,12 +1238,14 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
     }
   }
   // chunks: runs of at most kRefineChunk consecutive entries whose offsets
-  // span at most kRefineSpanU columns and kRefineSpanV rows, cut greedily in
+  // span at most the template's region spans (its pitch less W + 1 columns,
+  // its rows less H), cut greedily in
   // list order (one thread; the list holds at most a few hundred entries)
   // (wave 0: the entries are read 64 at a time into lanes and walked with
   // lane reads, so the serial walk waits on no LDS read)
   for (int i = tid; i < REFINE_CAP / 32; i += kRefineThreads) first[i] = 0;
   __syncthreads();
+  const int span_u = st.pitch - td.W - 1, span_v = st.rows - td.H;
   if (wave == 0) {
     int c0 = 0, umin = 0, umax = 0, vmin = 0, vmax = 0;
     for (int i0 = 0; i0 < L; i0 += 64) {
@@ -1253,8 +1256,8 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
       for (int q = 0; q < n64; ++q) {
         const int i = i0 + q;
         const int u = __builtin_amdgcn_readlane(lu, q), v = __builtin_amdgcn_readlane(lv, q);
-        if (i == c0 || i - c0 == kRefineChunk || max(umax, u) - min(umin, u) >= kRefineSpanU ||
-            max(vmax, v) - min(vmin, v) >= kRefineSpanV) {
+        if (i == c0 || i - c0 == kRefineChunk || max(umax, u) - min(umin, u) >= span_u ||
+            max(vmax, v) - min(vmin, v) >= span_v) {
           starts |= 1ull << q;
           c0 = i;
           umin = umax = u;
@@ -1280,16 +1283,22 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
   };
   for (int c0 = 0; st.tbl >= 0 && c0 < L;) {
     const int c1 = __builtin_amdgcn_readfirstlane(chunk_end(c0));
-    const int n = c1 - c0;  // at most 64: lane i takes entry c0 + i
-    int eu = 0, ev = 0;
-    if (lane < n) entry(c0 + lane, eu, ev);
-    // bounds by wave maxima (the minima as maxima of complements; lanes past
-    // n give 0 to every maximum)
-    const bool in = lane < n;
-    const int umax = (int)__builtin_amdgcn_readlane((int)wave_incl_max(in ? (uint32_t)eu : 0u), 63);
-    const int vmax = (int)__builtin_amdgcn_readlane((int)wave_incl_max(in ? (uint32_t)ev : 0u), 63);
-    const int umin = (int)~__builtin_amdgcn_readlane((int)wave_incl_max(in ? ~(uint32_t)eu : 0u), 63);
-    const int vmin = (int)~__builtin_amdgcn_readlane((int)wave_incl_max(in ? ~(uint32_t)ev : 0u), 63);
+    const int n = c1 - c0;  // at most kRefineChunk = 128: lane i takes entries c0 + i, + 64
+    // bounds by wave maxima (the minima as maxima of complements; absent
+    // entries give 0 to every maximum)
+    uint32_t mu = 0, mv = 0, nu_ = 0, nv_ = 0;
+    for (int i = lane; i < n; i += 64) {
+      int eu, ev;
+      entry(c0 + i, eu, ev);
+      mu = max(mu, (uint32_t)eu);
+      mv = max(mv, (uint32_t)ev);
+      nu_ = max(nu_, ~(uint32_t)eu);
+      nv_ = max(nv_, ~(uint32_t)ev);
+    }
+    const int umax = (int)__builtin_amdgcn_readlane((int)wave_incl_max(mu), 63);
+    const int vmax = (int)__builtin_amdgcn_readlane((int)wave_incl_max(mv), 63);
+    const int umin = (int)~__builtin_amdgcn_readlane((int)wave_incl_max(nu_), 63);
+    const int vmin = (int)~__builtin_amdgcn_readlane((int)wave_incl_max(nv_), 63);
     // the entries the chunk's windows read: rows [vmin, vmax + H], columns
     // [umin, umax + W] of the table, at the region's pitch
     const int nrow = vmax - vmin + td.H + 1, ncol = umax - umin + td.W + 1;

@@ -159,11 +159,13 @@ constexpr int kSlowRegionWords = 13312;  // 52 KB
 static_assert(kSlowRegionWords * 4 <= 65536, "slot byte offsets are 16-bit");
 constexpr int kSlowChainMax = 15;        // segments per chain piece (16 slots)
 
-// The refine kernel scores its offsets in chunks of 16 (in column bands of
-// 16): a chunk whose offsets span at most kRefineSpanU columns and
-// kRefineSpanV rows is scored from a staged region like the slow pass's, of
-// (kRefineSpanV + H) rows of kRefineSpanU + W + 1 words.
+// The refine kernel scores its offsets in chunks: a chunk whose offsets span
+// at most span_u columns and span_v rows is scored from a staged region like
+// the slow pass's, of (span_v + H) rows of span_u + W + 1 words.  The spans
+// are the wide ones when that region fits kRefineRegionWords (fewer, larger
+// chunks: less of the table is staged per offset), else the narrow ones.
 constexpr int kRefineSpanU = 16, kRefineSpanV = 8;
+constexpr int kRefineWideSpanU = 32, kRefineWideSpanV = 16;
 constexpr int kRefineRegionWords = 12288;  // 48 KB beside the 16 KB offset list
 static_assert(kRefineRegionWords * 4 <= 65536, "slot byte offsets are 16-bit");
 

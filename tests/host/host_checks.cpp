@@ -307,7 +307,8 @@ int main(int argc, char **argv) {
         CHECK(build_plan(&tm, e, M, N, P, n_pairs, pairs.data(), k, kSinkTopk, 256, edge_ph,
                          nullptr, kSplitEdge, tc.bu()) == SNCC_OK, "edge plan");
         check_plan(tm, edge_ph, n_pairs, kSplitEdge);
-        plan_slots(&tm, kRefineSpanU, kRefineSpanV, kRefineRegionWords, edge_ph);
+        plan_slots(&tm, kRefineWideSpanU, kRefineWideSpanV, kRefineRegionWords, edge_ph,
+                   kRefineSpanU, kRefineSpanV);
         check_slots(tm, edge_ph);
         ++n_plan;
       }
