@@ -624,6 +624,29 @@ int build_plan(const sncc_tmpl *tm, int cfg, int M, int N, int P, int n_pairs,
   return SNCC_OK;
 }
 
+// Plan of a one-call entry point: one_call_cfg's shape; when the wide
+// 128 x 32 tiles' rows do not fit two workgroups per CU (tall templates: the
+// plan fell back to one), the 128 x 16 eight-wave shape instead if its rows,
+// half as many per segment, keep two (3840 x 2160 with a 256 x 256
+// template: 8.5 -> 7.3 ms).
+int build_one_call_plan(const sncc_tmpl *tm, int M, int N, int P, int n_pairs,
+                        const int32_t *pairs, int k, int sink, int num_cu, PlanHost &ph) {
+  constexpr int kWide = 0, kTall = 3;
+  static_assert(kCfgs[kTall].entry == 3 && kTileShapes[3][0] == 2 && kTileShapes[3][1] == 2 &&
+                    kTileShapes[3][2] == 8 && kCfgs[kTall].wgs == 2,
+                "kTall: 128 x 16 tiles, eight waves, two workgroups per CU");
+  const int cfg = one_call_cfg(tm, M, N, n_pairs, pairs, num_cu);
+  CHK(build_plan(tm, cfg, M, N, P, n_pairs, pairs, k, sink, num_cu, ph));
+  if (cfg == kWide && ph.lds_bytes > tile_max_lds() / 2) {
+    PlanHost alt;
+    if (build_plan(tm, kTall, M, N, P, n_pairs, pairs, k, sink, num_cu, alt) == SNCC_OK &&
+        alt.lds_bytes <= tile_max_lds() / 2)
+      ph = std::move(alt);
+    g_err.clear();
+  }
+  return SNCC_OK;
+}
+
 // Boundary-slot tables (see SlowTmpl) of a template set for runs of
 // span_u x span_v offsets: a template whose region, (span_v + H) rows of
 // span_u + W + 1 words, exceeds max_words keeps tbl = -1 (global form).
@@ -1270,8 +1293,7 @@ int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint32_t *d_
   key.pairs.assign(pair, pair + 2);
   PlanDev *pd = nullptr;
   CHK(cached_plan(ctx, std::move(key), [&](PlanDev &d) {
-    return build_plan(tm, one_call_cfg(tm, M, N, 1, pair, ctx->num_cu), M, N, sat_pitch, 1,
-                      pair, 0, kSinkMap, ctx->num_cu, d.h);
+    return build_one_call_plan(tm, M, N, sat_pitch, 1, pair, 0, kSinkMap, ctx->num_cu, d.h);
   }, &pd));
   TileArgs a = pd->args(d_s, d_s2, (long long)(N + 1) * sat_pitch, sat_pitch, M, N);
   a.rho = d_rho;
@@ -1377,8 +1399,8 @@ int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uin
     key.pairs.assign(pairs, pairs + 2 * n_pairs);
     PlanDev *pd = nullptr;
     CHK(cached_plan(ctx, std::move(key), [&](PlanDev &d) {
-      return build_plan(tm, one_call_cfg(tm, M, N, n_pairs, pairs, ctx->num_cu), M, N,
-                        sat_pitch, n_pairs, pairs, k, kSinkTopk, ctx->num_cu, d.h);
+      return build_one_call_plan(tm, M, N, sat_pitch, n_pairs, pairs, k, kSinkTopk,
+                                 ctx->num_cu, d.h);
     }, &pd));
     TileArgs a = pd->args(d_s, d_s2, fs, sat_pitch, M, N);
     ctx->n_stages = 0;
