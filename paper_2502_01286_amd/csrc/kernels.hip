@@ -1239,10 +1239,9 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
   }
   // chunks: runs of at most kRefineChunk consecutive entries whose offsets
   // span at most the template's region spans (its pitch less W + 1 columns,
-  // its rows less H), cut greedily in
-  // list order (one thread; the list holds at most a few hundred entries)
-  // (wave 0: the entries are read 64 at a time into lanes and walked with
-  // lane reads, so the serial walk waits on no LDS read)
+  // its rows less H), cut greedily in list order by wave 0, which reads the
+  // entries 64 at a time into lanes and walks them with lane reads (the
+  // serial walk waits on no LDS read)
   for (int i = tid; i < REFINE_CAP / 32; i += kRefineThreads) first[i] = 0;
   __syncthreads();
   const int span_u = st.pitch - td.W - 1, span_v = st.rows - td.H;
