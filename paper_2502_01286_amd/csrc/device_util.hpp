@@ -114,6 +114,97 @@ __device__ __forceinline__ void topk_offer(u64 &lkey, u64 (&cand)[R], int k, int
   }
 }
 
+// Value of lane l ^ m of a 64-bit register.
+__device__ __forceinline__ u64 shfl_xor_u64(u64 x, int m) {
+  const unsigned lo = (unsigned)__shfl_xor((int)(unsigned)x, m);
+  const unsigned hi = (unsigned)__shfl_xor((int)(unsigned)(x >> 32), m);
+  return ((u64)hi << 32) | lo;
+}
+
+// Bitonic sort of one 64-bit key per lane across the wave: afterwards lane j
+// holds the j-th largest key.
+__device__ __forceinline__ u64 wave_sort_desc_u64(u64 key, int lane) {
+#pragma unroll
+  for (int size = 2; size <= 64; size <<= 1)
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const u64 other = shfl_xor_u64(key, stride);
+      // pairs (l, l ^ stride) inside blocks of `size` lanes: descending
+      // blocks where bit `size` of l is 0, ascending otherwise
+      const bool desc = (lane & size) == 0 || size == 64;
+      const bool lower = (lane & stride) == 0;
+      const u64 hi = key > other ? key : other, lo = key > other ? other : key;
+      key = (lower == desc) ? hi : lo;
+    }
+  return key;
+}
+
+// Merges a wave-sorted list of keys (`sorted`, lane j the j-th largest) into
+// the top-k list `lkey` (lane j < k the j-th best): the k best of both.  The
+// lane-wise maxima of one list and the other reversed form a bitonic
+// sequence holding the 64 largest keys of the union, which six
+// compare-exchange steps put in descending order.
+__device__ __forceinline__ void topk_merge_sorted(u64 &lkey, u64 sorted, int k, int lane) {
+  const unsigned rlo = (unsigned)__shfl((int)(unsigned)sorted, 63 - lane);
+  const unsigned rhi = (unsigned)__shfl((int)(unsigned)(sorted >> 32), 63 - lane);
+  const u64 rev = ((u64)rhi << 32) | rlo;
+  const u64 mine = lane < k ? lkey : 0;
+  u64 c = mine > rev ? mine : rev;
+#pragma unroll
+  for (int stride = 32; stride > 0; stride >>= 1) {
+    const u64 other = shfl_xor_u64(c, stride);
+    const bool lower = (lane & stride) == 0;
+    const u64 hi = c > other ? c : other, lo = c > other ? other : c;
+    c = lower ? hi : lo;
+  }
+  lkey = lane < k ? c : 0;
+}
+
+// Batched offers to a wave's top-k list, for a batch of many keys.  Keys
+// above the list's k-th key (and above `floor`) are appended to a 64-entry
+// buffer in LDS (low words at lo[j], high words at hi[j], j < 64, stored
+// as float bit patterns; the wave's own memory); a full buffer, and finally the remainder, is sorted
+// across the lanes and merged into the list.  The k-th key that filters is
+// that of the last merge, never above the current one, so no key of the
+// final top k is dropped.
+__device__ __forceinline__ void topk_flush(u64 &lkey, float *lo, float *hi, int &cnt, int k,
+                                           int lane) {
+  const u64 b = lane < cnt ? ((u64)__float_as_uint(hi[lane]) << 32) | __float_as_uint(lo[lane])
+                           : 0;
+  topk_merge_sorted(lkey, wave_sort_desc_u64(b, lane), k, lane);
+  cnt = 0;
+}
+
+template <int R>
+__device__ __forceinline__ void topk_offer_batched(u64 &lkey, const u64 (&cand)[R], int k,
+                                                   int lane, u64 floor, float *lo, float *hi) {
+  int cnt = 0;
+  u64 thr = lane_u64(lkey, k - 1);
+  thr = thr > floor ? thr : floor;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    bool take = cand[r] > thr;
+    u64 m = __ballot(take);
+    if (m == 0) continue;
+    if (cnt + __popcll(m) > 64) {
+      topk_flush(lkey, lo, hi, cnt, k, lane);
+      thr = lane_u64(lkey, k - 1);
+      thr = thr > floor ? thr : floor;
+      take = cand[r] > thr;
+      m = __ballot(take);
+      if (m == 0) continue;
+    }
+    const int j = cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (take) {
+      lo[j] = __uint_as_float((uint32_t)cand[r]);
+      hi[j] = __uint_as_float((uint32_t)(cand[r] >> 32));
+    }
+    cnt += __popcll(m);
+  }
+  if (cnt > 0) topk_flush(lkey, lo, hi, cnt, k, lane);
+}
+
 // Exact selection keys for FP64 values: the order-preserving 64-bit code of
 // the double (larger value -> larger code) and a 32-bit word that breaks ties
 // by the smaller index (its complement).  (0, 0) is the empty key.

@@ -437,10 +437,19 @@ static const void *tile_fn(int cfg, int sink) {
   return kTileEntries[kCfgs[cfg].entry].fn(sink);
 }
 
+// Allows a tile kernel dynamic LDS up to what its static LDS leaves of a CU's.
+static hipError_t allow_dynamic_lds(const void *fn) {
+  hipFuncAttributes fa;
+  const hipError_t e = hipFuncGetAttributes(&fa, fn);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             tile_max_lds() - (int)fa.sharedSizeBytes);
+}
+
 int tile_occupancy(int cfg, int sink, int lds_bytes) {
   if (cfg < 0 || cfg >= kNumCfgs) return 0;
   const void *fn = tile_fn(cfg, sink);
-  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, tile_max_lds() - 64);
+  if (allow_dynamic_lds(fn) != hipSuccess) return 0;
   int blocks = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, tile_cfg(cfg).threads(),
                                                    (size_t)lds_bytes) != hipSuccess)
@@ -455,9 +464,7 @@ int launch_tile(int cfg, int sink, const TileArgs &a, int grid, int lds_bytes,
   static bool attr_done[3][kNumTileEntries] = {};
   const int ent = kCfgs[cfg].entry;
   if (!attr_done[sink][ent]) {
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            tile_max_lds() - 64) != hipSuccess)
-      return -1;
+    if (allow_dynamic_lds(fn) != hipSuccess) return -1;
     attr_done[sink][ent] = true;
   }
   long long fs = a.frame_stride;

@@ -393,7 +393,21 @@ __device__ __forceinline__ void run_item(
             cand[r] = rho[r] >= fth && rho[r] != -__builtin_inff()
                           ? make_key(rho[r], v * pd.nu + u) : 0;
           }
-        topk_offer<R>(lkey, cand, k, lane, (u64)fh << 32);
+        // a few keys go into the list one by one; a larger batch (a wave's
+        // first tiles) through the sort-and-merge buffer, which takes the
+        // wave's scale slots (read above for this tile; the next prologue
+        // rewrites them): low words in r = 0's, high words in r = 1's
+        const u64 fl = (u64)fh << 32;
+        const u64 thr = max(lane_u64(lkey, k - 1), fl);
+        int n = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) n += __popcll(__ballot(cand[r] > thr));
+        if (n <= 2) {
+          topk_offer<R>(lkey, cand, k, lane, fl);
+        } else {
+          float *slot0 = scl + wave * 64;
+          topk_offer_batched<R>(lkey, cand, k, lane, fl, slot0, slot0 + NW * 64);
+        }
         if (lane == 0) thr_sh[wave] = (uint32_t)(lane_u64(lkey, k - 1) >> 32);
       }
     }
