@@ -494,15 +494,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
       if (lane < k) buf[wave * k + lane] = lkey;
       __syncthreads();
       if (wave == 0) {
-        u64 thr = lane_u64(lkey, k - 1);
-        for (int w = 1; w < NW; ++w) {
-          for (int j = 0; j < k; ++j) {
-            const u64 key = buf[w * k + j];
-            if (key <= thr) break;
-            topk_insert(lkey, key, k, lane);
-            thr = lane_u64(lkey, k - 1);
-          }
-        }
+        // each wave's list is sorted: one bitonic merge per wave
+        for (int w = 1; w < NW; ++w)
+          topk_merge_sorted(lkey, lane < k ? buf[w * k + lane] : 0ull, k, lane);
         if (lane < k) partial[(long long)item * k + lane] = lkey;
         const u64 kth = lane_u64(lkey, k - 1);
         if (lane == 0 && kth != 0) atomicMax(pair_floor + it.pair, kth);
