@@ -393,8 +393,9 @@ __device__ __forceinline__ void run_item(
             cand[r] = rho[r] >= fth && rho[r] != -__builtin_inff()
                           ? make_key(rho[r], v * pd.nu + u) : 0;
           }
-        // a few keys go into the list one by one; a larger batch (a wave's
-        // first tiles) through the sort-and-merge buffer, which takes the
+        // a few keys go into the list one by one (best first, so at most k
+        // insertions); a larger batch with a larger k (a wave's first tiles)
+        // through the sort-and-merge buffer, which takes the
         // wave's scale slots (read above for this tile; the next prologue
         // rewrites them): low words in r = 0's, high words in r = 1's
         const u64 fl = (u64)fh << 32;
@@ -402,7 +403,7 @@ __device__ __forceinline__ void run_item(
         int n = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) n += __popcll(__ballot(cand[r] > thr));
-        if (n <= 2) {
+        if (n <= 2 || k <= 2) {
           topk_offer<R>(lkey, cand, k, lane, fl);
         } else {
           float *slot0 = scl + wave * 64;
@@ -494,9 +495,21 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
       if (lane < k) buf[wave * k + lane] = lkey;
       __syncthreads();
       if (wave == 0) {
-        // each wave's list is sorted: one bitonic merge per wave
-        for (int w = 1; w < NW; ++w)
-          topk_merge_sorted(lkey, lane < k ? buf[w * k + lane] : 0ull, k, lane);
+        // each wave's list is sorted: one bitonic merge per wave, or for a
+        // small k insertions until a wave's next key falls short
+        if (k >= 8) {
+          for (int w = 1; w < NW; ++w)
+            topk_merge_sorted(lkey, lane < k ? buf[w * k + lane] : 0ull, k, lane);
+        } else {
+          u64 thr = lane_u64(lkey, k - 1);
+          for (int w = 1; w < NW; ++w)
+            for (int j = 0; j < k; ++j) {
+              const u64 key = buf[w * k + j];
+              if (key <= thr) break;
+              topk_insert(lkey, key, k, lane);
+              thr = lane_u64(lkey, k - 1);
+            }
+        }
         if (lane < k) partial[(long long)item * k + lane] = lkey;
         const u64 kth = lane_u64(lkey, k - 1);
         if (lane == 0 && kth != 0) atomicMax(pair_floor + it.pair, kth);
