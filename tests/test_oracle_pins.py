@@ -587,4 +587,6 @@ def test_planted_mistake_is_caught(monkeypatch, which):
     monkeypatch.setattr(module, name, bad)
     if hasattr(O, name):
         monkeypatch.setattr(O, name, bad)
-    assert not _pins_pass()
+    # a mutant may give a negative energy; its sqrt warning is expected noise
+    with np.errstate(invalid="ignore"):
+        assert not _pins_pass()
