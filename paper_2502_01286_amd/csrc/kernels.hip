@@ -45,7 +45,7 @@ __host__ __device__ inline SatScratch sat_layout(uint32_t *base, int B, int M, i
   sc.nTX = (M + SAT_TX - 1) / SAT_TX;
   sc.nTY = (N + SAT_TY - 1) / SAT_TY;
   sc.colT = base;                                          // [2][B][nTY][M]
-  sc.rowT = sc.colT + (size_t)2 * B * sc.nTY * M;          // [2][B][N][nTX]
+  sc.rowT = sc.colT + (size_t)2 * B * sc.nTY * M;          // [2][B][nTX][N]
   sc.T = sc.rowT + (size_t)2 * B * N * sc.nTX;             // [2][B][nTY][nTX]
   sc.corner = sc.T + (size_t)2 * B * sc.nTY * sc.nTX;      // [2][B][nTY][nTX]
   return sc;
@@ -103,10 +103,25 @@ __device__ __forceinline__ void load_wave_rows(const uint8_t *fb, int y0, int r0
                                       : 0u;
 }
 
+// DPP add within quads of lanes: lanes 0-1 and 2-3 exchanged (quad_perm
+// [1,0,3,2]), then the pairs (quad_perm [2,3,0,1]); every lane of a quad
+// ends with the quad's sum.
+__device__ __forceinline__ uint32_t quad_sum(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, false);
+  return v;
+}
+
+// Column totals, row totals and the tile total of f and f^2.  A lane's row
+// sums over its four pixels are byte dot products (with ones for f, with
+// themselves for f^2), added over quads of lanes with DPP; the quads' sums
+// go through LDS, where lane r of the wave adds row r's sixteen, so that a
+// wave's sixteen row totals leave as one coalesced store per table.
 __global__ __launch_bounds__(256) void sat_totals(const uint8_t *__restrict__ f,
                                                   int B, int M, int N, int f_pitch,
                                                   uint32_t *__restrict__ scratch) {
-  __shared__ uint32_t wcol[SAT_WAVES][8][64];  // per wave: column totals of f, f^2
+  __shared__ uint32_t wcol[SAT_WAVES][8][64];   // per wave: column totals of f, f^2
+  __shared__ uint2 rq[SAT_WAVES][SAT_WR][17];   // per wave and row: quads' sums (padded)
   SatScratch sc = sat_layout(scratch, B, M, N);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int J = blockIdx.x, I = blockIdx.y, b = blockIdx.z;
@@ -116,35 +131,47 @@ __global__ __launch_bounds__(256) void sat_totals(const uint8_t *__restrict__ f,
   const int r0 = w * SAT_WR;
   const uint8_t *fb = f + (size_t)b * N * f_pitch;
   uint32_t pk[SAT_WR];
-  load_wave_rows(fb, y0, r0, rows, f_pitch, x0, M, pk);
-  uint32_t cs[4] = {0, 0, 0, 0}, cs2[4] = {0, 0, 0, 0};
-  const size_t plane_row = (size_t)B * N * sc.nTX;
+  load_wave_rows(fb, y0, r0, rows, f_pitch, x0, M, pk);  // 0 past the frame
+  // column sums: f as two 16-bit halves of a word (16 rows of bytes stay
+  // below 2^16), f^2 as byte dot products of one byte each
+  uint32_t lo = 0, hi = 0, t2[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int r = 0; r < SAT_WR; ++r) {
-    if (r0 + r >= rows) continue;  // uniform; every pk index stays a constant
-    uint32_t rs = 0, rs2 = 0;
+    const uint32_t x = pk[r];
+    lo += x & 0x00ff00ffu;         // columns 0 and 2
+    hi += (x >> 8) & 0x00ff00ffu;  // columns 1 and 3
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const uint32_t v = (pk[r] >> (8 * q)) & 0xffu;
-      cs[q] += v;
-      cs2[q] += v * v;
-      rs += v;
-      rs2 += v * v;
-    }
-    rs = wave_sum(rs);
-    rs2 = wave_sum(rs2);
-    if (lane == 0) {
-      const size_t o = ((size_t)b * N + y0 + r0 + r) * sc.nTX + J;
-      sc.rowT[o] = rs;
-      sc.rowT[plane_row + o] = rs2;
+      const uint32_t m = x & (0xffu << (8 * q));
+      t2[q] = __builtin_amdgcn_udot4(m, m, t2[q], false);
     }
   }
 #pragma unroll
+  for (int r = 0; r < SAT_WR; ++r) {
+    const uint32_t a = quad_sum(__builtin_amdgcn_udot4(pk[r], 0x01010101u, 0u, false));
+    const uint32_t a2 = quad_sum(__builtin_amdgcn_udot4(pk[r], pk[r], 0u, false));
+    if ((lane & 3) == 0) rq[w][r][lane >> 2] = make_uint2(a, a2);
+  }
+  uint32_t cs[4] = {lo & 0xffffu, hi & 0xffffu, lo >> 16, hi >> 16}, cs2[4];
+#pragma unroll
   for (int q = 0; q < 4; ++q) {
+    cs2[q] = t2[q];
     wcol[w][q][lane] = cs[q];
     wcol[w][4 + q][lane] = cs2[q];
   }
   __syncthreads();
+  if (lane < SAT_WR && r0 + lane < rows) {
+    uint32_t a = 0, a2 = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const uint2 e = rq[w][lane][i];
+      a += e.x;
+      a2 += e.y;
+    }
+    const size_t o = ((size_t)b * sc.nTX + J) * N + y0 + r0 + lane;
+    sc.rowT[o] = a;
+    sc.rowT[(size_t)B * N * sc.nTX + o] = a2;
+  }
   if (w == 0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -153,21 +180,26 @@ __global__ __launch_bounds__(256) void sat_totals(const uint8_t *__restrict__ f,
         cs2[q] += wcol[u][4 + q][lane];
       }
     const size_t plane_col = (size_t)B * sc.nTY * M;
+    const size_t o = ((size_t)b * sc.nTY + I) * M + x0;
+    if (x0 + 3 < M && (M & 3) == 0) {  // 16-byte aligned: M and x0 are multiples of 4
+      *reinterpret_cast<uint4 *>(sc.colT + o) = make_uint4(cs[0], cs[1], cs[2], cs[3]);
+      *reinterpret_cast<uint4 *>(sc.colT + plane_col + o) =
+          make_uint4(cs2[0], cs2[1], cs2[2], cs2[3]);
+    } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (x0 + q < M) {
-        const size_t o = ((size_t)b * sc.nTY + I) * M + x0 + q;
-        sc.colT[o] = cs[q];
-        sc.colT[plane_col + o] = cs2[q];
-      }
+      for (int q = 0; q < 4; ++q)
+        if (x0 + q < M) {
+          sc.colT[o + q] = cs[q];
+          sc.colT[plane_col + o + q] = cs2[q];
+        }
     }
     uint32_t tt = wave_sum(cs[0] + cs[1] + cs[2] + cs[3]);
     uint32_t tt2 = wave_sum(cs2[0] + cs2[1] + cs2[2] + cs2[3]);
     if (lane == 0) {
-      const size_t o = ((size_t)b * sc.nTY + I) * sc.nTX + J;
+      const size_t ot = ((size_t)b * sc.nTY + I) * sc.nTX + J;
       const size_t plane_t = (size_t)B * sc.nTY * sc.nTX;
-      sc.T[o] = tt;
-      sc.T[plane_t + o] = tt2;
+      sc.T[ot] = tt;
+      sc.T[plane_t + ot] = tt2;
     }
   }
 }
@@ -209,7 +241,7 @@ __global__ __launch_bounds__(256) void sat_prefix(int B, int M, int N,
     const long long j = jj - p * nB;
     const int b = (int)(j / N), y = (int)(j % N);
     const size_t plane = (size_t)B * N * sc.nTX;
-    excl_prefix_inplace(sc.rowT + p * plane + ((size_t)b * N + y) * sc.nTX, 1, sc.nTX);
+    excl_prefix_inplace(sc.rowT + p * plane + (size_t)b * sc.nTX * N + y, (size_t)N, sc.nTX);
   } else if (job < 2 * nA + 2 * nB + 2 * nC) {
     const long long jj = job - 2 * nA - 2 * nB;
     const int p = (int)(jj / nC);
@@ -295,7 +327,7 @@ __global__ __launch_bounds__(256) void sat_scan(const uint8_t *__restrict__ f,
   const size_t plane_row = (size_t)B * N * sc.nTX;
   uint32_t rl = 0, rl2 = 0;
   if (lane < rows) {
-    const size_t o = ((size_t)b * N + y0 + lane) * sc.nTX + J;
+    const size_t o = ((size_t)b * sc.nTX + J) * N + y0 + lane;
     rl = sc.rowT[o];
     rl2 = sc.rowT[plane_row + o];
   }

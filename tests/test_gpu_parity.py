@@ -44,7 +44,7 @@ def _u32(t):
 
 # ------------------------------------------------------------------ tables
 @pytest.mark.parametrize("shape", [(3, 37, 29), (2, 130, 301), (1, 64, 256), (1, 1, 1),
-                                   (2, 300, 517)])
+                                   (2, 300, 517), (3, 150, 1028), (2, 720, 1280)])
 def test_sat_bit_exact(S, ctx, shape):
     B, N, M = shape
     rng = np.random.default_rng(B * 1000 + N + M)
