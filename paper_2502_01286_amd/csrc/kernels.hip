@@ -902,24 +902,20 @@ __device__ __forceinline__ bool consecutive4(const int (&base)[4]) {
   return __builtin_amdgcn_readfirstlane((int)c) != 0;
 }
 
-// FP64 rho (Eqs. (12), (13), (15)-(18)) of four windows of one template
-// whose table entries are staged in LDS: base[j] is the region byte offset
-// of window j's top-left entry (row pitch `pitch` words), gof[j] its byte
-// offset in the global tables (for the f^2 sums).  Lanes run over the
+// FP64 sum of c_i F_i over the segments (Eq. (12), first term) for four
+// windows of one template whose table entries are staged in LDS: base[j] is
+// the region byte offset of window j's top-left entry.  Lanes run over the
 // template's boundary slots (see SlowTmpl), two 64-slot blocks per step with
 // the next step's slot entries requested ahead; per slot and window two LDS
 // reads give the column difference D, the lane below holds the previous
 // boundary's D, and c_i (D - D_prev) is added to the lane's FP64 sum.  Lane l
-// returns the rho of window l mod 4.  CONSEC: the four windows are
+// returns the sum of window l mod 4.  CONSEC: the four windows are
 // consecutive offsets of one row (base[j] = base[0] + 4 j), so one address per
 // slot serves all four reads, with immediate offsets.
 template <bool CONSEC>
-__device__ __forceinline__ double staged_rho4(const uint32_t *region, int pitch,
-                                              const int (&base)[4], const int (&gof)[4],
+__device__ __forceinline__ double staged_num4(const uint32_t *region, const int (&base)[4],
                                               __amdgpu_buffer_rsrc_t rso,
-                                              __amdgpu_buffer_rsrc_t rsc, int n_iter,
-                                              __amdgpu_buffer_rsrc_t rs2, int P4,
-                                              const DevTmpl &td, int lane) {
+                                              __amdgpu_buffer_rsrc_t rsc, int n_iter, int lane) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   auto block = [&](uint32_t o, double c) {
     const int top = (int)(o & 0xffffu), bot = (int)(o >> 16);
@@ -968,15 +964,36 @@ __device__ __forceinline__ double staged_rho4(const uint32_t *region, int pitch,
     c1 = m1;
   }
   if (it < n_iter) block(o0, c0);
-  const double sum = wave_sum4_f64(acc[0], acc[1], acc[2], acc[3], lane);
-  const int jj = lane & 3;
-  const int q = jj == 0 ? base[0] : jj == 1 ? base[1] : jj == 2 ? base[2] : base[3];
-  const int g = jj == 0 ? gof[0] : jj == 1 ? gof[1] : jj == 2 ? gof[2] : gof[3];
+  return wave_sum4_f64(acc[0], acc[1], acc[2], acc[3], lane);
+}
+
+// FP64 rho (Eqs. (13), (15)-(18)) of the window whose top-left entry is at
+// region byte offset q (row pitch `pitch` words) and global byte offset g,
+// given its segment sum.
+__device__ __forceinline__ double staged_rho(double sum, const uint32_t *region, int pitch, int q,
+                                             int g, __amdgpu_buffer_rsrc_t rs2, int P4,
+                                             const DevTmpl &td) {
   const int qh = q + td.H * pitch * 4, w4 = td.W * 4;
   const uint32_t sf = (lds_at(region, qh + w4) - lds_at(region, qh)) -
                       (lds_at(region, q + w4) - lds_at(region, q));  // Eq. (13)
   const u64 sf2 = window_sq(rs2, g, 0, w4, P4, td.H, td.sq_rows);  // Eq. (15)
   return slow_rho(sum, sf, sf2, td);
+}
+
+// rho of four windows (staged_num4, then staged_rho for lane l's window
+// l mod 4; gof[j] is window j's byte offset in the global tables).
+template <bool CONSEC>
+__device__ __forceinline__ double staged_rho4(const uint32_t *region, int pitch,
+                                              const int (&base)[4], const int (&gof)[4],
+                                              __amdgpu_buffer_rsrc_t rso,
+                                              __amdgpu_buffer_rsrc_t rsc, int n_iter,
+                                              __amdgpu_buffer_rsrc_t rs2, int P4,
+                                              const DevTmpl &td, int lane) {
+  const double sum = staged_num4<CONSEC>(region, base, rso, rsc, n_iter, lane);
+  const int jj = lane & 3;
+  const int q = jj == 0 ? base[0] : jj == 1 ? base[1] : jj == 2 ? base[2] : base[3];
+  const int g = jj == 0 ? gof[0] : jj == 1 ? gof[1] : jj == 2 ? gof[2] : gof[3];
+  return staged_rho(sum, region, pitch, q, g, rs2, P4, td);
 }
 
 
@@ -1096,8 +1113,9 @@ int launch_slow(const SlowArgs &a, int grid, int lds_bytes, hipStream_t st) {
 // of at most kRefineChunk consecutive entries spanning at most the
 // template's region spans (32 x 16 offsets where that region fits the LDS
 // budget, else 16 x 8), each from a staged region of the frame's
-// table, four offsets per wave at a time (staged_rho4); for templates whose
-// region does not fit LDS, one offset per thread from the global tables
+// table: the segment sums four offsets per wave at a time (staged_num4),
+// then rho one offset per thread (staged_rho); for templates whose region
+// does not fit LDS, one offset per thread from the global tables
 // (rho_plain).
 constexpr int REFINE_CAP = 4096;
 constexpr int kRefineChunk = 128;  // entries per chunk: up to four batches of four per wave
@@ -1116,7 +1134,9 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
   __shared__ double best_r[kRefineWaves];
   __shared__ int best_i[kRefineWaves];
   __shared__ int cand_u[64], cand_v[64];  // the candidates in (band, v, u) order
-  extern __shared__ uint32_t dyn[];  // the offset list (np ints), then the region
+  // the chunk's segment sums (kRefineChunk doubles), the offset list (np
+  // ints), then the region
+  extern __shared__ __align__(16) uint32_t dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int p = blockIdx.x;
   const PairDesc pd = pairs[p];
@@ -1127,8 +1147,9 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
   const int band_keys = pd.nv * 16;  // keys per column band
   int np = 1;
   while (np < total) np <<= 1;
-  int *const list = reinterpret_cast<int *>(dyn);
-  uint32_t *const region = dyn + np;
+  double *const num = reinterpret_cast<double *>(dyn);
+  int *const list = reinterpret_cast<int *>(dyn + 2 * kRefineChunk);
+  uint32_t *const region = dyn + 2 * kRefineChunk + np;
   // entries are (v << 16 | u) when both fit 16 bits, else the row-major index
   const bool packed = pd.nu <= 65536 && pd.nv <= 65536;
   int L = 0;
@@ -1345,26 +1366,29 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
     const __amdgpu_buffer_rsrc_t rso = make_rsrc(slot_off + st.tbl, (uint32_t)st.n_iter * 256u);
     const __amdgpu_buffer_rsrc_t rsc = make_rsrc(slot_c + st.tbl, (uint32_t)st.n_iter * 512u);
     for (int e0 = wave * 4; e0 < n; e0 += 4 * kRefineWaves) {  // four entries per wave
-      int su[4], sv[4], base[4], gof[4];
+      int base[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        entry(c0 + min(e0 + j, n - 1), su[j], sv[j]);
-        base[j] = ((sv[j] - vmin) * st.pitch + (su[j] - umin)) * 4;
-        gof[j] = sv[j] * P4 + su[j] * 4;
+        int su, sv;
+        entry(c0 + min(e0 + j, n - 1), su, sv);
+        base[j] = ((sv - vmin) * st.pitch + (su - umin)) * 4;
       }
-      // lane j < 4 holds entry c0 + e0 + j
-      const double r =
-          consecutive4(base)
-              ? staged_rho4<true>(region, st.pitch, base, gof, rso, rsc, st.n_iter, rs2, P4, td,
-                                  lane)
-              : staged_rho4<false>(region, st.pitch, base, gof, rso, rsc, st.n_iter, rs2, P4, td,
-                                   lane);
-      const int jj = lane & 3;
-      const int uu = jj == 0 ? su[0] : jj == 1 ? su[1] : jj == 2 ? su[2] : su[3];
-      const int vv = jj == 0 ? sv[0] : jj == 1 ? sv[1] : jj == 2 ? sv[2] : sv[3];
-      if (lane < 4 && e0 + lane < n) offer(r, vv * pd.nu + uu);
+      // lane j < 4 holds the sum of entry c0 + e0 + j
+      const double sum = consecutive4(base)
+                             ? staged_num4<true>(region, base, rso, rsc, st.n_iter, lane)
+                             : staged_num4<false>(region, base, rso, rsc, st.n_iter, lane);
+      if (lane < 4 && e0 + lane < n) num[e0 + lane] = sum;
     }
-    __syncthreads();  // the region is rewritten for the next chunk
+    __syncthreads();
+    // rho of the chunk's entries, one per thread: the window sums and the
+    // division are a lane's work, not a wave's per four windows
+    for (int i = tid; i < n; i += kRefineThreads) {
+      int u, v;
+      entry(c0 + i, u, v);
+      const int q = ((v - vmin) * st.pitch + (u - umin)) * 4;
+      offer(staged_rho(num[i], region, st.pitch, q, v * P4 + u * 4, rs2, P4, td), v * pd.nu + u);
+    }
+    __syncthreads();  // the region and the sums are rewritten for the next chunk
     c0 = c1;
   }
   for (int msk = 32; msk >= 1; msk >>= 1) {
@@ -1411,7 +1435,8 @@ int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride,
   int np = 1;
   while (np < total) np <<= 1;
   const int N = (int)(frame_stride / P) - 1;
-  hipLaunchKernelGGL(refine_kernel, dim3(n_pairs), dim3(kRefineThreads), np * 4 + slots.lds_bytes,
+  hipLaunchKernelGGL(refine_kernel, dim3(n_pairs), dim3(kRefineThreads),
+                     kRefineChunk * 8 + np * 4 + slots.lds_bytes,
                      st, s, s2, frame_stride, P, tmpls, geom, c64, slots.tmpl, slots.off,
                      slots.c, pairs, cand, n_cand, radius, N, out, count);
   return hipGetLastError() == hipSuccess ? 0 : -1;

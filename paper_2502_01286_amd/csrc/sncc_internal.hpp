@@ -166,7 +166,7 @@ constexpr int kSlowChainMax = 15;        // segments per chain piece (16 slots)
 // chunks: less of the table is staged per offset), else the narrow ones.
 constexpr int kRefineSpanU = 16, kRefineSpanV = 8;
 constexpr int kRefineWideSpanU = 32, kRefineWideSpanV = 16;
-constexpr int kRefineRegionWords = 12288;  // 48 KB beside the 16 KB offset list
+constexpr int kRefineRegionWords = 12032;  // 47 KB beside the 16 KB offset list and 1 KB of sums
 static_assert(kRefineRegionWords * 4 <= 65536, "slot byte offsets are 16-bit");
 
 // Device view of a template set's slot tables.
