@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <limits>
 #include <map>
 #include <memory>
 #include <sstream>
@@ -189,7 +190,7 @@ struct PlanHost {
   // or of the fine ones (refine)
   std::vector<SlowTmpl> slow;
   std::vector<uint32_t> slot_off;
-  std::vector<double> slot_c;
+  std::vector<double> slot_w;
   int slow_lds = 0;             // bytes of the largest staged region
   int run_cap = 0;              // (tile, wave) pairs of the plan
   int64_t coarse_evals = 0, n_offsets = 0;
@@ -654,7 +655,7 @@ void plan_slots(const sncc_tmpl *tm, int span_u, int span_v, int max_words, Plan
                 int narrow_u = 0, int narrow_v = 0) {
   ph.slow.assign(tm->T, SlowTmpl{-1, 0, 0, 0});
   ph.slot_off.clear();
-  ph.slot_c.clear();
+  ph.slot_w.clear();
   ph.slow_lds = 0;
   for (int t = 0; t < tm->T; ++t) {
     const int W = tm->W[t], H = tm->H[t];
@@ -667,10 +668,11 @@ void plan_slots(const sncc_tmpl *tm, int span_u, int span_v, int max_words, Plan
     }
     if ((long long)pitch * rows > max_words) continue;
     const std::vector<Seg> &segs = tm->segs[t];
-    std::vector<std::vector<int>> pieces = horizontal_chains(segs, kSlowChainMax);
-    // pieces in raster order of their first segment: a wave's slots then
-    // read nearby rows
-    std::stable_sort(pieces.begin(), pieces.end(),
+    // whole chains (the slots carry no order constraint), in raster order
+    // of their first segment: a wave's slots then read nearby rows
+    std::vector<std::vector<int>> chains =
+        horizontal_chains(segs, std::numeric_limits<int>::max());
+    std::stable_sort(chains.begin(), chains.end(),
                      [&](const std::vector<int> &a, const std::vector<int> &b) {
                        const Seg &x = segs[a[0]], &y = segs[b[0]];
                        return x.y != y.y ? x.y < y.y : x.x < y.x;
@@ -679,30 +681,23 @@ void plan_slots(const sncc_tmpl *tm, int span_u, int span_v, int max_words, Plan
     st.tbl = (int)ph.slot_off.size();
     st.pitch = pitch;
     st.rows = rows;
-    int fill = 0;  // slots used in the current 16-lane row
-    for (const std::vector<int> &pc : pieces) {
-      const int need = (int)pc.size() + 1;
-      if (fill + need > 16) {
-        for (; fill < 16; ++fill) {
-          ph.slot_off.push_back(0);
-          ph.slot_c.push_back(0.0);
-        }
-      }
-      fill %= 16;
-      const Seg &g0 = segs[pc[0]];
+    const std::vector<double> &c = tm->c64[t];
+    for (const std::vector<int> &ch : chains) {
+      const Seg &g0 = segs[ch[0]];
       const uint32_t top = (uint32_t)(g0.y * pitch), bot = (uint32_t)((g0.y + g0.h) * pitch);
       auto slot = [&](int x) { return ((top + x) * 4) | (((bot + x) * 4) << 16); };  // bytes
+      // boundary j: w_j = c_j - c_(j+1), c_0 = c_(L+1) = 0
       ph.slot_off.push_back(slot(g0.x));
-      ph.slot_c.push_back(0.0);
-      for (int i : pc) {
-        ph.slot_off.push_back(slot(segs[i].x + segs[i].w));
-        ph.slot_c.push_back(tm->c64[t][i]);
+      ph.slot_w.push_back(-c[ch[0]]);
+      for (size_t k = 0; k < ch.size(); ++k) {
+        const Seg &g = segs[ch[k]];
+        ph.slot_off.push_back(slot(g.x + g.w));
+        ph.slot_w.push_back(k + 1 < ch.size() ? c[ch[k]] - c[ch[k + 1]] : c[ch[k]]);
       }
-      fill += need;
     }
     while (ph.slot_off.size() % 64 != 0) {
       ph.slot_off.push_back(0);
-      ph.slot_c.push_back(0.0);
+      ph.slot_w.push_back(0.0);
     }
     st.n_iter = ((int)ph.slot_off.size() - st.tbl) / 64;
     ph.slow[t] = st;
@@ -726,7 +721,7 @@ void plan_slow(const sncc_tmpl *slow, const TileCfg &tc, PlanHost &ph) {
 struct PlanDev {
   PlanHost h;
   DevBuf d_tmpls, d_passes, d_ivs, d_recs, d_pairs, d_items, d_order, d_qbeg, d_queue,
-      d_partial, d_thr, d_slow, d_slot_off, d_slot_c, d_runs;
+      d_partial, d_thr, d_slow, d_slot_off, d_slot_w, d_runs;
   hipEvent_t done = nullptr;
   ~PlanDev() {
     if (done) (void)hipEventDestroy(done);
@@ -746,14 +741,14 @@ struct PlanDev {
     if (!h.slow.empty()) {
       CHK(d_slow.upload(h.slow, st));
       CHK(d_slot_off.upload(h.slot_off, st));
-      CHK(d_slot_c.upload(h.slot_c, st));
+      CHK(d_slot_w.upload(h.slot_w, st));
     }
     if (h.sink == kSinkCompact)
       CHK(d_runs.reserve(std::max<size_t>(16, (size_t)h.run_cap * sizeof(RunDesc))));
     return SNCC_OK;
   }
   SlotTables slots() {
-    return SlotTables{d_slow.as<SlowTmpl>(), d_slot_off.as<uint32_t>(), d_slot_c.as<double>(),
+    return SlotTables{d_slow.as<SlowTmpl>(), d_slot_off.as<uint32_t>(), d_slot_w.as<double>(),
                       h.slow_lds};
   }
   // work counters, then one floor key per pair (top-k sink) or the run and
@@ -1518,7 +1513,7 @@ int sncc_refine(sncc_ctx *ctx, const sncc_tmpl *fine, const uint32_t *d_s, const
              kRefineSpanV);
   CHK(pd->d_slow.upload(h.slow, ctx->stream));
   CHK(pd->d_slot_off.upload(h.slot_off, ctx->stream));
-  CHK(pd->d_slot_c.upload(h.slot_c, ctx->stream));
+  CHK(pd->d_slot_w.upload(h.slot_w, ctx->stream));
   if (launch_refine(d_s, d_s2, (long long)(N + 1) * sat_pitch, sat_pitch,
                     fine->d_dev.as<DevTmpl>(), fine->d_geom.as<int4>(), fine->d_c64.as<double>(),
                     pd->slots(), pd->d_pairs.as<PairDesc>(), n_pairs, d_cand, n_cand, radius,
@@ -1592,7 +1587,7 @@ int sncc_threshold_match(sncc_ctx *ctx, const sncc_tmpl *fast, const sncc_tmpl *
   sa.c64 = slow->d_c64.as<double>();
   sa.stmpl = pd->d_slow.as<SlowTmpl>();
   sa.slot_off = pd->d_slot_off.as<uint32_t>();
-  sa.slot_c = pd->d_slot_c.as<double>();
+  sa.slot_w = pd->d_slot_w.as<double>();
   sa.pairs = pd->d_pairs.as<PairDesc>();
   sa.thr = pd->d_thr.as<double>();
   sa.cand = d_cand;

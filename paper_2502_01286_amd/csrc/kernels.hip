@@ -883,6 +883,51 @@ __device__ __forceinline__ void stage_region(__amdgpu_buffer_rsrc_t rs, int P, i
   __builtin_amdgcn_s_waitcnt(0);
 }
 
+// Each staged region row less its first entry (modulo 2^32).  A window's box
+// sums are unchanged, and so is a chain's sum of w D (its slot weights add to
+// zero), while a column difference D = s(y + h, x) - s(y, x) becomes the box
+// sum over rows [y, y + h) and the region's columns left of x, below
+// 255 x rows x pitch.  Needed when the table's own differences, below
+// 255 x h x P, could come near 2^32 (they must stay exact as unsigned
+// integers) or make the FP64 products w D large against c_i F_i: the kernels
+// shift when 255 H P >= 2^27 (relative_rows), where the products stay below
+// 2^27 |w| either way (rho within about 1e-13 of the exact value; a CPU run of
+// both forms on 1280-wide frames gave 5e-14 unshifted, 1e-15 shifted).  A
+// wave shifts the rows it staged (stage_region's rows), after its own loads
+// have landed, so no barrier is needed before; four rows at a time, their
+// first entries read before any row is written.
+// Whether a staged region must be made row-relative (region_relative) for a
+// template of height H on tables of pitch P.
+__device__ __forceinline__ bool relative_rows(int H, int P) {
+  return 255ull * (unsigned long long)H * (unsigned long long)P >= (1ull << 27);
+}
+
+__device__ __forceinline__ void region_relative(uint32_t *region, int nrow, int ncol, int pitch,
+                                                int wave, int lane, int n_waves) {
+  constexpr int G = 4;
+  for (int row0 = wave; row0 < nrow; row0 += G * n_waves) {
+    uint32_t b[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int row = row0 + g * n_waves;
+      b[g] = row < nrow ? region[row * pitch] : 0u;
+    }
+    for (int c = lane; c < ncol; c += 64) {
+      uint32_t v[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int row = row0 + g * n_waves;
+        v[g] = row < nrow ? region[row * pitch + c] : 0u;
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int row = row0 + g * n_waves;
+        if (row < nrow) region[row * pitch + c] = v[g] - b[g];
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ uint32_t lds_at(const uint32_t *region, int byte_off) {
   return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(region) + byte_off);
 }
@@ -907,19 +952,20 @@ __device__ __forceinline__ bool consecutive4(const int (&base)[4]) {
 // the region byte offset of window j's top-left entry.  Lanes run over the
 // template's boundary slots (see SlowTmpl), two 64-slot blocks per step with
 // the next step's slot entries requested ahead; per slot and window two LDS
-// reads give the column difference D, the lane below holds the previous
-// boundary's D, and c_i (D - D_prev) is added to the lane's FP64 sum.  Lane l
-// returns the sum of window l mod 4.  CONSEC: the four windows are
-// consecutive offsets of one row (base[j] = base[0] + 4 j), so one address per
-// slot serves all four reads, with immediate offsets.
+// reads give the column difference D (a region row's shift cancels within a
+// chain) and w D is added to the lane's FP64 sum, which over a chain is the
+// sum of c_i F_i (summation by parts).  Lane l returns the sum of window
+// l mod 4.  CONSEC: the four windows are consecutive offsets of one row
+// (base[j] = base[0] + 4 j), so one address per slot serves all four reads,
+// with immediate offsets.
 template <bool CONSEC>
 __device__ __forceinline__ double staged_num4(const uint32_t *region, const int (&base)[4],
                                               __amdgpu_buffer_rsrc_t rso,
-                                              __amdgpu_buffer_rsrc_t rsc, int n_iter, int lane) {
+                                              __amdgpu_buffer_rsrc_t rsw, int n_iter, int lane) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  auto block = [&](uint32_t o, double c) {
+  auto block = [&](uint32_t o, double w) {
     const int top = (int)(o & 0xffffu), bot = (int)(o >> 16);
-    uint32_t D[4], Dp[4];
+    uint32_t D[4];
     if constexpr (CONSEC) {
       const char *rb = reinterpret_cast<const char *>(region) + base[0];
       const uint32_t *pb = reinterpret_cast<const uint32_t *>(rb + bot);
@@ -931,39 +977,30 @@ __device__ __forceinline__ double staged_num4(const uint32_t *region, const int 
       for (int j = 0; j < 4; ++j)
         D[j] = lds_at(region, base[j] + bot) - lds_at(region, base[j] + top);
     }
-    // the previous boundary's difference (row_shr:1), kept separate moves.
-    // Folded, the compiler writes D - shr(D) as v_subrev_u32_dpp d, D, D,
-    // which on gfx950 computes shr(src1) - src0 instead of src1 - shr(src0)
-    // (a one-wave probe with distinct registers shows the shift applied to
-    // src1): the negated difference.  The empty asm keeps the move separate.
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      Dp[j] = (uint32_t)__builtin_amdgcn_mov_dpp((int)D[j], 0x111, 0xf, 0xf, true);
-    asm volatile("" : "+v"(Dp[0]), "+v"(Dp[1]), "+v"(Dp[2]), "+v"(Dp[3]));
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = __builtin_fma((double)(D[j] - Dp[j]), c, acc[j]);
+    for (int j = 0; j < 4; ++j) acc[j] = __builtin_fma((double)D[j], w, acc[j]);
   };
   auto load_o = [&](int i) {
     return __builtin_amdgcn_raw_buffer_load_b32(rso, lane * 4, min(i, n_iter - 1) * 256, 0);
   };
-  auto load_c = [&](int i) {
+  auto load_w = [&](int i) {
     return __builtin_bit_cast(
-        double, __builtin_amdgcn_raw_buffer_load_b64(rsc, lane * 8, min(i, n_iter - 1) * 512, 0));
+        double, __builtin_amdgcn_raw_buffer_load_b64(rsw, lane * 8, min(i, n_iter - 1) * 512, 0));
   };
   uint32_t o0 = load_o(0), o1 = load_o(1);
-  double c0 = load_c(0), c1 = load_c(1);
+  double w0 = load_w(0), w1 = load_w(1);
   int it = 0;
   for (; it + 2 <= n_iter; it += 2) {
     const uint32_t n0 = load_o(it + 2), n1 = load_o(it + 3);
-    const double m0 = load_c(it + 2), m1 = load_c(it + 3);
-    block(o0, c0);
-    block(o1, c1);
+    const double m0 = load_w(it + 2), m1 = load_w(it + 3);
+    block(o0, w0);
+    block(o1, w1);
     o0 = n0;
     o1 = n1;
-    c0 = m0;
-    c1 = m1;
+    w0 = m0;
+    w1 = m1;
   }
-  if (it < n_iter) block(o0, c0);
+  if (it < n_iter) block(o0, w0);
   return wave_sum4_f64(acc[0], acc[1], acc[2], acc[3], lane);
 }
 
@@ -986,10 +1023,10 @@ template <bool CONSEC>
 __device__ __forceinline__ double staged_rho4(const uint32_t *region, int pitch,
                                               const int (&base)[4], const int (&gof)[4],
                                               __amdgpu_buffer_rsrc_t rso,
-                                              __amdgpu_buffer_rsrc_t rsc, int n_iter,
+                                              __amdgpu_buffer_rsrc_t rsw, int n_iter,
                                               __amdgpu_buffer_rsrc_t rs2, int P4,
                                               const DevTmpl &td, int lane) {
-  const double sum = staged_num4<CONSEC>(region, base, rso, rsc, n_iter, lane);
+  const double sum = staged_num4<CONSEC>(region, base, rso, rsw, n_iter, lane);
   const int jj = lane & 3;
   const int q = jj == 0 ? base[0] : jj == 1 ? base[1] : jj == 2 ? base[2] : base[3];
   const int g = jj == 0 ? gof[0] : jj == 1 ? gof[1] : jj == 2 ? gof[2] : gof[3];
@@ -1003,7 +1040,7 @@ __global__ __launch_bounds__(256) void slow_kernel(
     const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
     int P, int N, const DevTmpl *__restrict__ tmpls, const int4 *__restrict__ geom,
     const double *__restrict__ c64, const SlowTmpl *__restrict__ stmpl,
-    const uint32_t *__restrict__ slot_off, const double *__restrict__ slot_c,
+    const uint32_t *__restrict__ slot_off, const double *__restrict__ slot_w,
     const PairDesc *__restrict__ pairs, const double *__restrict__ thrs,
     const sncc_hit *__restrict__ cand, const int *__restrict__ cand_count, int cand_cap,
     const RunDesc *__restrict__ runs, const int *__restrict__ run_count, int run_cap,
@@ -1045,9 +1082,10 @@ __global__ __launch_bounds__(256) void slow_kernel(
       // region rows [v0, v0 + rows), columns [u0, u0 + pitch), clamped to
       // the table (clamped entries are never read by a window of the run)
       stage_region(rs, P, N, rd.v0, rd.u0, st.rows, st.pitch, st.pitch, region, wave, lane);
+      if (relative_rows(td.H, P)) region_relative(region, st.rows, st.pitch, st.pitch, wave, lane, 4);
       __syncthreads();
       const __amdgpu_buffer_rsrc_t rso = make_rsrc(slot_off + st.tbl, (uint32_t)st.n_iter * 256u);
-      const __amdgpu_buffer_rsrc_t rsc = make_rsrc(slot_c + st.tbl, (uint32_t)st.n_iter * 512u);
+      const __amdgpu_buffer_rsrc_t rsw = make_rsrc(slot_w + st.tbl, (uint32_t)st.n_iter * 512u);
       for (int b = start + wave * kSlowBatch; b < end; b += 4 * kSlowBatch) {
         int su[kSlowBatch], sv[kSlowBatch], base[kSlowBatch], gof[kSlowBatch];
 #pragma unroll
@@ -1061,9 +1099,9 @@ __global__ __launch_bounds__(256) void slow_kernel(
         // lane j < kSlowBatch holds survivor b + j
         const double rho =
             consecutive4(base)
-                ? staged_rho4<true>(region, st.pitch, base, gof, rso, rsc, st.n_iter, rs2, P4,
+                ? staged_rho4<true>(region, st.pitch, base, gof, rso, rsw, st.n_iter, rs2, P4,
                                     td, lane)
-                : staged_rho4<false>(region, st.pitch, base, gof, rso, rsc, st.n_iter, rs2, P4,
+                : staged_rho4<false>(region, st.pitch, base, gof, rso, rsw, st.n_iter, rs2, P4,
                                      td, lane);
         const int jj = lane & 3;
         const int uu = jj == 0 ? su[0] : jj == 1 ? su[1] : jj == 2 ? su[2] : su[3];
@@ -1097,7 +1135,7 @@ int slow_occupancy(int lds_bytes) {
 int launch_slow(const SlowArgs &a, int grid, int lds_bytes, hipStream_t st) {
   hipLaunchKernelGGL(slow_kernel, dim3(grid), dim3(256), lds_bytes, st, a.s, a.s2,
                      a.frame_stride, a.P, a.N, a.tmpls, a.geom, a.c64, a.stmpl, a.slot_off,
-                     a.slot_c, a.pairs, a.thr, a.cand, a.cand_count, a.cand_cap, a.runs,
+                     a.slot_w, a.pairs, a.thr, a.cand, a.cand_count, a.cand_cap, a.runs,
                      a.run_count, a.run_cap, a.work, a.out, a.out_cap, a.out_count);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -1126,7 +1164,7 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
     const uint32_t *__restrict__ s, const uint32_t *__restrict__ s2, long long frame_stride,
     int P, const DevTmpl *__restrict__ tmpls, const int4 *__restrict__ geom,
     const double *__restrict__ c64, const SlowTmpl *__restrict__ stmpl,
-    const uint32_t *__restrict__ slot_off, const double *__restrict__ slot_c,
+    const uint32_t *__restrict__ slot_off, const double *__restrict__ slot_w,
     const PairDesc *__restrict__ pairs, const sncc_match *__restrict__ cand, int n_cand,
     int radius, int N, sncc_match64 *__restrict__ out, int *__restrict__ count) {
   __shared__ uint32_t first[REFINE_CAP / 32];  // bit i: entry i starts a chunk
@@ -1362,9 +1400,10 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
     // [umin, umax + W] of the table, at the region's pitch
     const int nrow = vmax - vmin + td.H + 1, ncol = umax - umin + td.W + 1;
     stage_region(rs, P, N, vmin, umin, nrow, ncol, st.pitch, region, wave, lane, kRefineWaves);
+    if (relative_rows(td.H, P)) region_relative(region, nrow, ncol, st.pitch, wave, lane, kRefineWaves);
     __syncthreads();
     const __amdgpu_buffer_rsrc_t rso = make_rsrc(slot_off + st.tbl, (uint32_t)st.n_iter * 256u);
-    const __amdgpu_buffer_rsrc_t rsc = make_rsrc(slot_c + st.tbl, (uint32_t)st.n_iter * 512u);
+    const __amdgpu_buffer_rsrc_t rsw = make_rsrc(slot_w + st.tbl, (uint32_t)st.n_iter * 512u);
     for (int e0 = wave * 4; e0 < n; e0 += 4 * kRefineWaves) {  // four entries per wave
       int base[4];
 #pragma unroll
@@ -1375,8 +1414,8 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
       }
       // lane j < 4 holds the sum of entry c0 + e0 + j
       const double sum = consecutive4(base)
-                             ? staged_num4<true>(region, base, rso, rsc, st.n_iter, lane)
-                             : staged_num4<false>(region, base, rso, rsc, st.n_iter, lane);
+                             ? staged_num4<true>(region, base, rso, rsw, st.n_iter, lane)
+                             : staged_num4<false>(region, base, rso, rsw, st.n_iter, lane);
       if (lane < 4 && e0 + lane < n) num[e0 + lane] = sum;
     }
     __syncthreads();
@@ -1438,7 +1477,7 @@ int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride,
   hipLaunchKernelGGL(refine_kernel, dim3(n_pairs), dim3(kRefineThreads),
                      kRefineChunk * 8 + np * 4 + slots.lds_bytes,
                      st, s, s2, frame_stride, P, tmpls, geom, c64, slots.tmpl, slots.off,
-                     slots.c, pairs, cand, n_cand, radius, N, out, count);
+                     slots.w, pairs, cand, n_cand, radius, N, out, count);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -139,13 +139,19 @@ struct CompactOut {
 // Slow pass of the two-threshold search.  A template whose region (the
 // table rows and columns that the windows of one run's offsets cover) fits
 // the LDS budget is scored from LDS through a boundary-slot table: its
-// segments as horizontal chains, each chain of L segments taking L + 1
-// consecutive slots inside one 16-lane row (so that a lane finds the
-// previous boundary one lane down), padded to whole waves.  Slot j holds the
-// LDS byte offsets of the boundary column's entries in the chain's top row
-// y and bottom row y + h (relative to the window's top-left entry; bottom in
-// the high 16 bits) and c_i of the segment ending there (0 at a chain's
-// first boundary and in padding slots).
+// segments as horizontal chains (runs of segments with equal y and h, each
+// starting where the previous one ends), a chain of L segments taking L + 1
+// slots, one per boundary column, padded to whole waves.  Along a chain with
+// boundary columns x_0 < ... < x_L and segment constants c_1 .. c_L, the sum
+// of c_i times the segment's box sum (Eq. (11)) equals, by summation by
+// parts, the sum over boundaries of D_j w_j, where D_j is the column
+// difference s(y + h, x_j) - s(y, x_j) and w_0 = -c_1, w_j = c_j - c_(j+1),
+// w_L = c_L.  Since the weights of a chain add to zero, D_j may be taken
+// from any table whose rows are shifted by a constant per row, such as the
+// staged region with each row less its first entry.  Slot j holds the LDS
+// byte offsets of the boundary column's entries in the chain's top row y and
+// bottom row y + h (relative to the window's top-left entry; bottom in the
+// high 16 bits) and w_j (padding slots: offsets 0, w 0).
 struct SlowTmpl {
   int tbl;     // first slot (-1: scored from the global tables)
   int n_iter;  // slots / 64
@@ -157,7 +163,6 @@ struct SlowTmpl {
 // of the frame's table; at most this many words.
 constexpr int kSlowRegionWords = 13312;  // 52 KB
 static_assert(kSlowRegionWords * 4 <= 65536, "slot byte offsets are 16-bit");
-constexpr int kSlowChainMax = 15;        // segments per chain piece (16 slots)
 
 // The refine kernel scores its offsets in chunks: a chunk whose offsets span
 // at most span_u columns and span_v rows is scored from a staged region like
@@ -173,7 +178,7 @@ static_assert(kRefineRegionWords * 4 <= 65536, "slot byte offsets are 16-bit");
 struct SlotTables {
   const SlowTmpl *tmpl;
   const uint32_t *off;
-  const double *c;
+  const double *w;
   int lds_bytes;  // largest region of a staged template (0: none)
 };
 
@@ -187,7 +192,7 @@ struct SlowArgs {
   const double *c64;
   const SlowTmpl *stmpl;
   const uint32_t *slot_off;
-  const double *slot_c;
+  const double *slot_w;
   const PairDesc *pairs;
   const double *thr;        // per template
   const sncc_hit *cand;

@@ -16,7 +16,8 @@
 // every pair's tiles exactly once, the queues must be a permutation of the
 // items, and every LDS read the records imply must stay inside the plan's
 // LDS size; the slow pass's and the refine's slot tables must stay inside
-// their regions.  Exit status 0 when every check holds.
+// their regions and their weighted column differences must give the
+// segments' sums.  Exit status 0 when every check holds.
 
 #include "../../paper_2502_01286_amd/csrc/segment.cpp"
 #include "../../paper_2502_01286_amd/csrc/api.cpp"
@@ -230,19 +231,60 @@ static void check_plan(const sncc_tmpl &tm, const PlanHost &ph, int n_pairs, int
   }
 }
 
+// Slot tables: every slot inside its template's region, and the weighted
+// column differences equal the segment sums.  For a random image g at the
+// region's origin, with each table row shifted by a random constant and then
+// made relative to its first entry as the kernels do, the sum over slots of
+// w (s(bottom) - s(top)) must equal the sum over segments of c_i times the
+// box sum of g (summation by parts along each chain), to FP64 rounding.
 static void check_slots(const sncc_tmpl &tm, const PlanHost &ph) {
+  uint64_t lcg = 0x9e3779b97f4a7c15ull;
+  auto next = [&]() { return (uint32_t)((lcg = lcg * 6364136223846793005ull + 1442695040888963407ull) >> 33); };
   for (int t = 0; t < tm.T; ++t) {
     const SlowTmpl &st = ph.slow[t];
     if (st.tbl < 0) continue;
     const long long region = (long long)st.pitch * st.rows * 4;
     CHECK(region <= (long long)ph.slow_lds, "region %lld > %d", region, ph.slow_lds);
+    bool inside = true;
     for (int i = st.tbl; i < st.tbl + 64 * st.n_iter; ++i) {
       CHECK(i < (int)ph.slot_off.size(), "slot %d beyond the table", i);
-      if (i >= (int)ph.slot_off.size()) break;
+      if (i >= (int)ph.slot_off.size()) return;
       const uint32_t o = ph.slot_off[i];
       const long long top = o & 0xffffu, bot = o >> 16;
       CHECK(top < region && bot < region, "slot %d: %lld %lld of %lld", i, top, bot, region);
+      inside = inside && top < region && bot < region && top % 4 == 0 && bot % 4 == 0;
     }
+    if (!inside) continue;
+    const int P = st.pitch, R = st.rows;
+    std::vector<uint32_t> g((size_t)R * P), tab((size_t)R * P);
+    for (uint32_t &v : g) v = next() & 0xffu;
+    for (int r = 1; r < R; ++r)  // tab[r][c]: sum of g over rows < r and columns < c
+      for (int c = 1; c < P; ++c)
+        tab[(size_t)r * P + c] = tab[(size_t)(r - 1) * P + c] + tab[(size_t)r * P + c - 1] -
+                                 tab[(size_t)(r - 1) * P + c - 1] + g[(size_t)(r - 1) * P + c - 1];
+    for (int r = 0; r < R; ++r) {  // a table row's shift, then the kernels' relative form
+      const uint32_t shift = next();
+      for (int c = 0; c < P; ++c) tab[(size_t)r * P + c] += shift;
+      const uint32_t b = tab[(size_t)r * P];
+      for (int c = 0; c < P; ++c) tab[(size_t)r * P + c] -= b;
+    }
+    double by_slots = 0.0, by_segs = 0.0, scale = 0.0;
+    for (int i = st.tbl; i < st.tbl + 64 * st.n_iter; ++i) {
+      const uint32_t o = ph.slot_off[i];
+      const uint32_t D = tab[(o >> 16) / 4] - tab[(o & 0xffffu) / 4];
+      by_slots += ph.slot_w[i] * (double)D;
+    }
+    const std::vector<Seg> &segs = tm.segs[t];
+    for (size_t i = 0; i < segs.size(); ++i) {
+      const Seg &q = segs[i];
+      int64_t F = 0;
+      for (int y = q.y; y < q.y + q.h; ++y)
+        for (int x = q.x; x < q.x + q.w; ++x) F += g[(size_t)y * P + x];
+      by_segs += tm.c64[t][i] * (double)F;
+      scale += std::fabs(tm.c64[t][i] * (double)F);
+    }
+    CHECK(std::fabs(by_slots - by_segs) <= 1e-9 * (scale + 1.0),
+          "template %d: slots give %.17g, segments %.17g", t, by_slots, by_segs);
   }
 }
 

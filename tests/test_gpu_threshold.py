@@ -181,6 +181,31 @@ def test_staged_and_global_slow_forms_together(S, ctx):
     assert tot_m > 0 and got["n_out"] == tot_m
 
 
+def test_wide_frames_row_relative_regions(S, ctx):
+    """8300-wide frames: the 64-tall template's run regions are made
+    row-relative before scoring (255 H P >= 2^27), the 20-tall template's are
+    not; both against the oracle, with a planted copy of each."""
+    rng = np.random.default_rng(93)
+    M, N = 8300, 80
+    frames = [synth.scene(7700 + i, M, N) for i in range(2)]
+    templates = []
+    for j, (w, h) in enumerate([(24, 64), (24, 20)]):
+        t, _, _ = synth.crop_template(rng, frames[j], w, h, sigma_max=10)
+        templates.append(t)
+        px, py = int(rng.integers(0, M - w + 1)), int(rng.integers(0, N - h + 1))
+        frames[1 - j][py:py + h, px:px + w] = t
+    pairs = [(b, j) for b in range(2) for j in range(2)]
+    print("2 frames 8300x80 x templates 24x64, 24x20", flush=True)
+    got = _run(S, ctx, frames, templates, pairs, cand_cap=1 << 18, out_cap=1 << 18)
+    cands, outs = _split(got["cand"], len(pairs)), _split(got["out"], len(pairs))
+    tot_m = 0
+    for p, (b, j) in enumerate(pairs):
+        res, fa, sl, fmap, tb = _oracle_pair(frames[b], templates[j])
+        _, nm = _compare_pair(cands[p], outs[p], res, sl, fmap, tb)
+        tot_m += nm
+    assert tot_m > 0 and got["n_out"] == tot_m
+
+
 def test_capacity_overflow_counts_and_truncates(S, ctx):
     frames = [synth.scene(7100, 160, 120)]
     rng = np.random.default_rng(5)
