@@ -682,18 +682,56 @@ void plan_slots(const sncc_tmpl *tm, int span_u, int span_v, int max_words, Plan
     st.pitch = pitch;
     st.rows = rows;
     const std::vector<double> &c = tm->c64[t];
+    std::vector<std::pair<uint32_t, double>> raster;
     for (const std::vector<int> &ch : chains) {
       const Seg &g0 = segs[ch[0]];
       const uint32_t top = (uint32_t)(g0.y * pitch), bot = (uint32_t)((g0.y + g0.h) * pitch);
       auto slot = [&](int x) { return ((top + x) * 4) | (((bot + x) * 4) << 16); };  // bytes
       // boundary j: w_j = c_j - c_(j+1), c_0 = c_(L+1) = 0
-      ph.slot_off.push_back(slot(g0.x));
-      ph.slot_w.push_back(-c[ch[0]]);
+      raster.emplace_back(slot(g0.x), -c[ch[0]]);
       for (size_t k = 0; k < ch.size(); ++k) {
         const Seg &g = segs[ch[k]];
-        ph.slot_off.push_back(slot(g.x + g.w));
-        ph.slot_w.push_back(k + 1 < ch.size() ? c[ch[k]] - c[ch[k + 1]] : c[ch[k]]);
+        raster.emplace_back(slot(g.x + g.w), k + 1 < ch.size() ? c[ch[k]] - c[ch[k + 1]] : c[ch[k]]);
       }
+    }
+    // Slot order for the LDS banks (32 banks of 4 bytes per half-wave): each
+    // group of 32 slots first takes, from the next kLook slots in raster
+    // order, those whose top and bottom entries fall in banks the group does
+    // not use yet (a window's base shifts every lane's bank alike), then the
+    // least conflicting ones.  The sum does not depend on the order.
+    constexpr size_t kLook = 512;
+    size_t head = 0;
+    std::vector<char> taken(raster.size(), 0);
+    auto bank = [](uint32_t o, int hi) { return (int)(((hi ? o >> 16 : o & 0xffffu) >> 2) & 31); };
+    while (head < raster.size()) {
+      int used_t[32] = {0}, used_b[32] = {0};
+      int n = 0;
+      auto take = [&](size_t i) {
+        taken[i] = 1;
+        ++used_t[bank(raster[i].first, 0)];
+        ++used_b[bank(raster[i].first, 1)];
+        ph.slot_off.push_back(raster[i].first);
+        ph.slot_w.push_back(raster[i].second);
+        ++n;
+      };
+      for (size_t i = head, seen = 0; i < raster.size() && seen < kLook && n < 32; ++i) {
+        if (taken[i]) continue;
+        ++seen;
+        if (!used_t[bank(raster[i].first, 0)] && !used_b[bank(raster[i].first, 1)]) take(i);
+      }
+      while (n < 32) {
+        size_t best = raster.size();
+        int best_cost = 1 << 30;
+        for (size_t i = head, seen = 0; i < raster.size() && seen < kLook; ++i) {
+          if (taken[i]) continue;
+          ++seen;
+          const int cost = used_t[bank(raster[i].first, 0)] + used_b[bank(raster[i].first, 1)];
+          if (cost < best_cost) best = i, best_cost = cost;
+        }
+        if (best == raster.size()) break;
+        take(best);
+      }
+      while (head < raster.size() && taken[head]) ++head;
     }
     while (ph.slot_off.size() % 64 != 0) {
       ph.slot_off.push_back(0);
