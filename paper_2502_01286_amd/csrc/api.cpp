@@ -694,44 +694,61 @@ void plan_slots(const sncc_tmpl *tm, int span_u, int span_v, int max_words, Plan
         raster.emplace_back(slot(g.x + g.w), k + 1 < ch.size() ? c[ch[k]] - c[ch[k + 1]] : c[ch[k]]);
       }
     }
-    // Slot order for the LDS banks (32 banks of 4 bytes per half-wave): each
-    // group of 32 slots first takes, from the next kLook slots in raster
-    // order, those whose top and bottom entries fall in banks the group does
-    // not use yet (a window's base shifts every lane's bank alike), then the
-    // least conflicting ones.  The sum does not depend on the order.
-    constexpr size_t kLook = 512;
-    size_t head = 0;
-    std::vector<char> taken(raster.size(), 0);
-    auto bank = [](uint32_t o, int hi) { return (int)(((hi ? o >> 16 : o & 0xffffu) >> 2) & 31); };
-    while (head < raster.size()) {
+    // Slot order for the LDS banks (32 banks of 4 bytes per half-wave; a
+    // window's base shifts every lane's bank alike): groups of 32 slots, each
+    // taking first, among the next kWindow slots in raster order, slots of
+    // the banks with the most slots still to place (top plus bottom count),
+    // at most one per top bank and one per bottom bank, then the least
+    // conflicting ones.  The sum does not depend on the order.
+    constexpr size_t kWindow = 4096;
+    auto bank = [&](size_t i, int hi) {
+      const uint32_t o = raster[i].first;
+      return (int)(((hi ? o >> 16 : o & 0xffffu) >> 2) & 31);
+    };
+    int rem_t[32] = {0}, rem_b[32] = {0};
+    for (size_t i = 0; i < raster.size(); ++i) ++rem_t[bank(i, 0)], ++rem_b[bank(i, 1)];
+    std::vector<size_t> pool(raster.size());
+    for (size_t i = 0; i < pool.size(); ++i) pool[i] = i;
+    std::vector<size_t> cand, grp;
+    std::vector<char> in_grp(raster.size(), 0);
+    while (!pool.empty()) {
+      cand.assign(pool.begin(), pool.begin() + std::min(pool.size(), kWindow));
+      std::stable_sort(cand.begin(), cand.end(), [&](size_t x, size_t y) {
+        return rem_t[bank(x, 0)] + rem_b[bank(x, 1)] > rem_t[bank(y, 0)] + rem_b[bank(y, 1)];
+      });
       int used_t[32] = {0}, used_b[32] = {0};
-      int n = 0;
+      grp.clear();
       auto take = [&](size_t i) {
-        taken[i] = 1;
-        ++used_t[bank(raster[i].first, 0)];
-        ++used_b[bank(raster[i].first, 1)];
-        ph.slot_off.push_back(raster[i].first);
-        ph.slot_w.push_back(raster[i].second);
-        ++n;
+        grp.push_back(i);
+        in_grp[i] = 1;
+        ++used_t[bank(i, 0)];
+        ++used_b[bank(i, 1)];
       };
-      for (size_t i = head, seen = 0; i < raster.size() && seen < kLook && n < 32; ++i) {
-        if (taken[i]) continue;
-        ++seen;
-        if (!used_t[bank(raster[i].first, 0)] && !used_b[bank(raster[i].first, 1)]) take(i);
+      for (size_t i : cand) {
+        if (grp.size() == 32) break;
+        if (!used_t[bank(i, 0)] && !used_b[bank(i, 1)]) take(i);
       }
-      while (n < 32) {
+      while (grp.size() < 32) {
         size_t best = raster.size();
         int best_cost = 1 << 30;
-        for (size_t i = head, seen = 0; i < raster.size() && seen < kLook; ++i) {
-          if (taken[i]) continue;
-          ++seen;
-          const int cost = used_t[bank(raster[i].first, 0)] + used_b[bank(raster[i].first, 1)];
+        for (size_t i : cand) {
+          if (in_grp[i]) continue;
+          const int cost = used_t[bank(i, 0)] + used_b[bank(i, 1)];
           if (cost < best_cost) best = i, best_cost = cost;
         }
         if (best == raster.size()) break;
         take(best);
       }
-      while (head < raster.size() && taken[head]) ++head;
+      for (size_t i : grp) {
+        --rem_t[bank(i, 0)];
+        --rem_b[bank(i, 1)];
+        ph.slot_off.push_back(raster[i].first);
+        ph.slot_w.push_back(raster[i].second);
+      }
+      size_t k = 0;
+      for (size_t i : pool)
+        if (!in_grp[i]) pool[k++] = i;
+      pool.resize(k);
     }
     while (ph.slot_off.size() % 64 != 0) {
       ph.slot_off.push_back(0);
