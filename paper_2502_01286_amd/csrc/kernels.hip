@@ -626,16 +626,28 @@ __global__ __launch_bounds__(256) void merge_kernel(const PairDesc *__restrict__
   const PairDesc pd = pairs[p];
   u64 lkey = 0, thr = 0;
   // one load brings the partial lists of g = 64 / k items (lane l holds key
-  // l mod k of item l / k), so the load latency is paid once per g items
+  // l mod k of item l / k), and the next load is issued before the current
+  // keys are used, so its latency overlaps their merge
   const int g = 64 / k;
   auto merge_items = [&](const u64 *part, int ib, int ie) {
-    for (int item = ib; item < ie; item += g) {
+    auto load = [&](int item) -> u64 {
       const int mi = item + lane / k;
-      const u64 mine = lane < g * k && mi < ie ? part[(long long)mi * k + lane % k] : 0;
-      // only keys above the current k-th can enter; the lanes holding them are
-      // visited in lane order (item by item, each item's keys in descending
-      // order), and a key is checked again against the k-th as it rises
+      return lane < g * k && mi < ie ? part[(long long)mi * k + lane % k] : 0;
+    };
+    u64 next = ib < ie ? load(ib) : 0;
+    for (int item = ib; item < ie; item += g) {
+      const u64 mine = next;
+      if (item + g < ie) next = load(item + g);
+      // only keys above the current k-th can enter.  A few are inserted one
+      // by one in lane order, each checked again against the k-th as it
+      // rises; more are sorted across the wave and merged in one step (the
+      // same k best: keys are distinct)
       u64 cand = __ballot(mine > thr);
+      if (__popcll(cand) > 2) {
+        topk_merge_sorted(lkey, wave_sort_desc_u64(mine > thr ? mine : 0ull, lane), k, lane);
+        thr = lane_u64(lkey, k - 1);
+        continue;
+      }
       while (cand) {
         const int l = __ffsll((long long)cand) - 1;
         cand &= cand - 1;
