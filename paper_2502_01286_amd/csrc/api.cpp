@@ -192,6 +192,11 @@ struct PlanHost {
   std::vector<uint32_t> slot_off;
   std::vector<double> slot_w;
   int slow_lds = 0;             // bytes of the largest staged region
+  // refine launch classes: pairs whose region leaves room for four
+  // workgroups per CU first (refine_n_first of them, regions of at most
+  // refine_lds_first bytes), then the others
+  std::vector<int> refine_order;
+  int refine_n_first = 0, refine_lds_first = 0;
   int run_cap = 0;              // (tile, wave) pairs of the plan
   int64_t coarse_evals = 0, n_offsets = 0;
   int64_t computed_evals = 0;  // including offsets of partial edge tiles
@@ -760,6 +765,32 @@ void plan_slots(const sncc_tmpl *tm, int span_u, int span_v, int max_words, Plan
   }
 }
 
+// Refine launch classes over the plan's pairs (after plan_slots of the fine
+// approximations): the offset list of n_cand (2 radius + 1)^2 entries and a
+// region that fits refine_region_budget(np, 4) let four eight-wave
+// workgroups share a CU instead of the three that the largest region allows.
+void plan_refine_order(PlanHost &ph, int n_cand, int radius) {
+  ph.refine_order.clear();
+  ph.refine_n_first = ph.refine_lds_first = 0;
+  const int total = n_cand * (2 * radius + 1) * (2 * radius + 1);
+  int np = 1;
+  while (np < total) np <<= 1;
+  const int budget = refine_region_budget(np, 4);
+  std::vector<int> rest;
+  for (int p = 0; p < (int)ph.pairs.size(); ++p) {
+    const SlowTmpl &st = ph.slow[ph.pairs[p].tmpl];
+    const int region = st.tbl >= 0 ? st.pitch * st.rows * 4 : 0;
+    if (region <= budget) {
+      ph.refine_order.push_back(p);
+      ph.refine_lds_first = std::max(ph.refine_lds_first, region);
+    } else {
+      rest.push_back(p);
+    }
+  }
+  ph.refine_n_first = (int)ph.refine_order.size();
+  ph.refine_order.insert(ph.refine_order.end(), rest.begin(), rest.end());
+}
+
 // Slot tables of the slow approximations for the slow pass, whose runs are
 // one wave's part of kRunCols columns of a tile of shape `tc`, and the run
 // capacity.
@@ -776,7 +807,7 @@ void plan_slow(const sncc_tmpl *slow, const TileCfg &tc, PlanHost &ph) {
 struct PlanDev {
   PlanHost h;
   DevBuf d_tmpls, d_passes, d_ivs, d_recs, d_pairs, d_items, d_order, d_qbeg, d_queue,
-      d_partial, d_thr, d_slow, d_slot_off, d_slot_w, d_runs;
+      d_partial, d_thr, d_slow, d_slot_off, d_slot_w, d_runs, d_refine_order;
   hipEvent_t done = nullptr;
   ~PlanDev() {
     if (done) (void)hipEventDestroy(done);
@@ -798,13 +829,20 @@ struct PlanDev {
       CHK(d_slot_off.upload(h.slot_off, st));
       CHK(d_slot_w.upload(h.slot_w, st));
     }
+    if (!h.refine_order.empty()) CHK(d_refine_order.upload(h.refine_order, st));
     if (h.sink == kSinkCompact)
       CHK(d_runs.reserve(std::max<size_t>(16, (size_t)h.run_cap * sizeof(RunDesc))));
     return SNCC_OK;
   }
   SlotTables slots() {
-    return SlotTables{d_slow.as<SlowTmpl>(), d_slot_off.as<uint32_t>(), d_slot_w.as<double>(),
-                      h.slow_lds};
+    const bool classes = !h.refine_order.empty();
+    return SlotTables{d_slow.as<SlowTmpl>(),
+                      d_slot_off.as<uint32_t>(),
+                      d_slot_w.as<double>(),
+                      h.slow_lds,
+                      classes ? d_refine_order.as<int>() : nullptr,
+                      h.refine_n_first,
+                      h.refine_lds_first};
   }
   // work counters, then one floor key per pair (top-k sink) or the run and
   // slow-pass counters (compacting sink), zeroed per launch
@@ -1566,9 +1604,11 @@ int sncc_refine(sncc_ctx *ctx, const sncc_tmpl *fine, const uint32_t *d_s, const
   CHK(pd->d_pairs.upload(h.pairs, ctx->stream));
   plan_slots(fine, kRefineWideSpanU, kRefineWideSpanV, kRefineRegionWords, h, kRefineSpanU,
              kRefineSpanV);
+  plan_refine_order(h, n_cand, radius);
   CHK(pd->d_slow.upload(h.slow, ctx->stream));
   CHK(pd->d_slot_off.upload(h.slot_off, ctx->stream));
   CHK(pd->d_slot_w.upload(h.slot_w, ctx->stream));
+  CHK(pd->d_refine_order.upload(h.refine_order, ctx->stream));
   if (launch_refine(d_s, d_s2, (long long)(N + 1) * sat_pitch, sat_pitch,
                     fine->d_dev.as<DevTmpl>(), fine->d_geom.as<int4>(), fine->d_c64.as<double>(),
                     pd->slots(), pd->d_pairs.as<PairDesc>(), n_pairs, d_cand, n_cand, radius,
@@ -1960,8 +2000,11 @@ int sncc_batch_create(sncc_ctx *ctx, const sncc_batch_desc *desc, sncc_batch **o
   b->plan.reset(new PlanDev());
   CHK(build_plan(d.coarse, cfg, d.M, d.N, d.sat_pitch, d.n_pairs, b->pairs.data(), d.k, kSinkTopk,
                  ctx->num_cu, b->plan->h, nullptr, split));
-  if (d.fine) plan_slots(d.fine, kRefineWideSpanU, kRefineWideSpanV, kRefineRegionWords, b->plan->h,
-                          kRefineSpanU, kRefineSpanV);
+  if (d.fine) {
+    plan_slots(d.fine, kRefineWideSpanU, kRefineWideSpanV, kRefineRegionWords, b->plan->h,
+               kRefineSpanU, kRefineSpanV);
+    plan_refine_order(b->plan->h, d.k, d.radius);
+  }
   CHK(b->plan->upload(ctx->stream));
   if (any_edge) {
     b->edge.reset(new PlanDev());

@@ -1177,8 +1177,9 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
     int P, const DevTmpl *__restrict__ tmpls, const int4 *__restrict__ geom,
     const double *__restrict__ c64, const SlowTmpl *__restrict__ stmpl,
     const uint32_t *__restrict__ slot_off, const double *__restrict__ slot_w,
-    const PairDesc *__restrict__ pairs, const sncc_match *__restrict__ cand, int n_cand,
-    int radius, int N, sncc_match64 *__restrict__ out, int *__restrict__ count) {
+    const PairDesc *__restrict__ pairs, const int *__restrict__ order,
+    const sncc_match *__restrict__ cand, int n_cand, int radius, int N,
+    sncc_match64 *__restrict__ out, int *__restrict__ count) {
   __shared__ uint32_t first[REFINE_CAP / 32];  // bit i: entry i starts a chunk
   __shared__ int wsum[kRefineWaves];
   __shared__ double best_r[kRefineWaves];
@@ -1188,7 +1189,7 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
   // ints), then the region
   extern __shared__ __align__(16) uint32_t dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int p = blockIdx.x;
+  const int p = order ? order[blockIdx.x] : (int)blockIdx.x;
   const PairDesc pd = pairs[p];
   const DevTmpl td = tmpls[pd.tmpl];
   const SlowTmpl st = stmpl[pd.tmpl];
@@ -1476,6 +1477,14 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
   }
 }
 
+int refine_region_budget(int np, int wgs) {
+  hipFuncAttributes fa;
+  if (hipFuncGetAttributes(&fa, (const void *)refine_kernel) != hipSuccess) return 0;
+  const long long left = (long long)kTileMaxLds / std::max(1, wgs) - (long long)fa.sharedSizeBytes -
+                         kRefineChunk * 8 - (long long)np * 4;
+  return left > 0 ? (int)left : 0;
+}
+
 int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride, int P,
                   const DevTmpl *tmpls, const int4 *geom, const double *c64,
                   const SlotTables &slots, const PairDesc *pairs, int n_pairs,
@@ -1486,10 +1495,20 @@ int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride,
   int np = 1;
   while (np < total) np <<= 1;
   const int N = (int)(frame_stride / P) - 1;
-  hipLaunchKernelGGL(refine_kernel, dim3(n_pairs), dim3(kRefineThreads),
-                     kRefineChunk * 8 + np * 4 + slots.lds_bytes,
-                     st, s, s2, frame_stride, P, tmpls, geom, c64, slots.tmpl, slots.off,
-                     slots.w, pairs, cand, n_cand, radius, N, out, count);
+  const int fixed = kRefineChunk * 8 + np * 4;
+  auto go = [&](int first, int n, int region_bytes) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(refine_kernel, dim3(n), dim3(kRefineThreads), fixed + region_bytes, st, s,
+                       s2, frame_stride, P, tmpls, geom, c64, slots.tmpl, slots.off, slots.w,
+                       pairs, slots.order ? slots.order + first : nullptr, cand, n_cand, radius,
+                       N, out, count);
+  };
+  if (slots.order) {
+    go(0, slots.n_first, slots.lds_first);
+    go(slots.n_first, n_pairs - slots.n_first, slots.lds_bytes);
+  } else {
+    go(0, n_pairs, slots.lds_bytes);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

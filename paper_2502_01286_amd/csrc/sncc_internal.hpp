@@ -180,6 +180,12 @@ struct SlotTables {
   const uint32_t *off;
   const double *w;
   int lds_bytes;  // largest region of a staged template (0: none)
+  // refine launch classes (optional): the pairs in order[0 .. n_first) have
+  // regions of at most lds_first bytes and run in a launch of their own,
+  // which fits more workgroups per CU; order[n_first ..) run in a second one
+  const int *order;
+  int n_first;
+  int lds_first;
 };
 
 struct SlowArgs {
@@ -384,6 +390,9 @@ int launch_map_topk64(const double *map, int pitch, int nu, int nv, int chunk, i
                       Key96 *partial, hipStream_t st);
 int launch_merge64(const PairDesc *pairs, int n_pairs, const Key96 *partial, int k,
                    sncc_match *out, hipStream_t st);
+// Region bytes that leave room for `wgs` refine workgroups per CU when the
+// offset list holds np entries (0 when none fit).
+int refine_region_budget(int np, int wgs);
 int launch_refine(const uint32_t *s, const uint32_t *s2, long long frame_stride,
                   int sat_pitch, const DevTmpl *tmpls, const int4 *geom,
                   const double *c64, const SlotTables &slots, const PairDesc *pairs,

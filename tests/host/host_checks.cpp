@@ -37,6 +37,7 @@ uint32_t *sat_noalloc_addr(int) { return nullptr; }
 int tile_cfg_count() { return kNumCfgs; }
 TileCfg tile_cfg(int i) { return tile_cfg_of(i); }
 int launch_slow(const SlowArgs &, int, int, hipStream_t) { return -1; }
+int refine_region_budget(int np, int wgs) { return kTileMaxLds / wgs - 2048 - 1024 - np * 4; }
 int slow_occupancy(int) { return 1; }
 int launch_tile(int, int, const TileArgs &, int, int, hipStream_t) { return -1; }
 int tile_max_lds() { return kTileMaxLds; }
