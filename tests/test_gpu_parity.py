@@ -396,16 +396,22 @@ def test_map_repeated_calls_match_fresh_contexts(S, ctx):
 
 
 # ------------------------------------------------------------------ refine
-@pytest.mark.parametrize("case", ["default", "large_fine", "radius3", "wide_frame"])
+@pytest.mark.parametrize("case", ["default", "large_fine", "radius3", "wide_frame", "two_classes"])
 def test_refine_parity(S, ctx, case):
     """FP64 refine against the oracle's coarse-fine.  `large_fine` adds a
     130 x 100 template, whose chunk region exceeds the LDS budget (scored from
     the global tables); `radius3` uses +-3 px neighbourhoods; `wide_frame` is
     an 8300-wide frame, where a 64-tall template's staged regions are made
-    row-relative (255 H P >= 2^27) and a 20-tall one's are not."""
+    row-relative (255 H P >= 2^27) and a 20-tall one's are not; `two_classes`
+    pairs a small template with a 90 x 95 one whose chunk region (43 KB)
+    is too large for four workgroups per CU, so the refine runs in two
+    launches."""
     import torch
     if case == "large_fine":
         frames, temps, _, pairs = _multi(71, B=2, M=300, N=220, sides=((24, 30), (130, 100)),
+                                         sigmas=(16, 16))
+    elif case == "two_classes":
+        frames, temps, _, pairs = _multi(74, B=2, M=320, N=240, sides=((24, 30), (90, 95)),
                                          sigmas=(16, 16))
     elif case == "wide_frame":
         frames, temps, _, pairs = _multi(73, B=1, M=8300, N=90, sides=((24, 64), (30, 20)),
