@@ -962,15 +962,16 @@ __device__ __forceinline__ bool consecutive4(const int (&base)[4]) {
 // FP64 sum of c_i F_i over the segments (Eq. (12), first term) for four
 // windows of one template whose table entries are staged in LDS: base[j] is
 // the region byte offset of window j's top-left entry.  Lanes run over the
-// template's boundary slots (see SlowTmpl), two 64-slot blocks per step with
-// the next step's slot entries requested ahead; per slot and window two LDS
+// template's boundary slots (see SlowTmpl), 64-slot blocks whose slot entries
+// are requested ahead; per slot and window two LDS
 // reads give the column difference D (a region row's shift cancels within a
 // chain) and w D is added to the lane's FP64 sum, which over a chain is the
 // sum of c_i F_i (summation by parts).  Lane l returns the sum of window
 // l mod 4.  CONSEC: the four windows are consecutive offsets of one row
 // (base[j] = base[0] + 4 j), so one address per slot serves all four reads,
-// with immediate offsets.
-template <bool CONSEC>
+// with immediate offsets.  DEEP: slot entries four blocks ahead in three
+// register sets (more registers), else one step ahead.
+template <bool CONSEC, bool DEEP>
 __device__ __forceinline__ double staged_num4(const uint32_t *region, const int (&base)[4],
                                               __amdgpu_buffer_rsrc_t rso,
                                               __amdgpu_buffer_rsrc_t rsw, int n_iter, int lane) {
@@ -999,20 +1000,65 @@ __device__ __forceinline__ double staged_num4(const uint32_t *region, const int 
     return __builtin_bit_cast(
         double, __builtin_amdgcn_raw_buffer_load_b64(rsw, lane * 8, min(i, n_iter - 1) * 512, 0));
   };
-  uint32_t o0 = load_o(0), o1 = load_o(1);
-  double w0 = load_w(0), w1 = load_w(1);
-  int it = 0;
-  for (; it + 2 <= n_iter; it += 2) {
-    const uint32_t n0 = load_o(it + 2), n1 = load_o(it + 3);
-    const double m0 = load_w(it + 2), m1 = load_w(it + 3);
-    block(o0, w0);
-    block(o1, w1);
-    o0 = n0;
-    o1 = n1;
-    w0 = m0;
-    w1 = m1;
+  if constexpr (DEEP) {
+    // slot entries in three register sets, each reloaded as soon as its two
+    // blocks are scored and used four blocks later (no register copies, which
+    // would wait for the loads)
+    uint32_t oa0 = load_o(0), oa1 = load_o(1), ob0 = load_o(2), ob1 = load_o(3), oc0 = load_o(4),
+             oc1 = load_o(5);
+    double wa0 = load_w(0), wa1 = load_w(1), wb0 = load_w(2), wb1 = load_w(3), wc0 = load_w(4),
+           wc1 = load_w(5);
+    int it = 0;
+    for (; it + 6 <= n_iter; it += 6) {
+      block(oa0, wa0);
+      block(oa1, wa1);
+      oa0 = load_o(it + 6);
+      oa1 = load_o(it + 7);
+      wa0 = load_w(it + 6);
+      wa1 = load_w(it + 7);
+      // thirds one after another: interleaving all six blocks' LDS reads would
+      // hold them live at once and cost occupancy
+      __builtin_amdgcn_sched_barrier(0);
+      block(ob0, wb0);
+      block(ob1, wb1);
+      ob0 = load_o(it + 8);
+      ob1 = load_o(it + 9);
+      wb0 = load_w(it + 8);
+      wb1 = load_w(it + 9);
+      __builtin_amdgcn_sched_barrier(0);
+      block(oc0, wc0);
+      block(oc1, wc1);
+      oc0 = load_o(it + 10);
+      oc1 = load_o(it + 11);
+      wc0 = load_w(it + 10);
+      wc1 = load_w(it + 11);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // the last n_iter - it < 6 blocks, held in the sets in order
+    if (it < n_iter) block(oa0, wa0);
+    if (it + 1 < n_iter) block(oa1, wa1);
+    if (it + 2 < n_iter) block(ob0, wb0);
+    if (it + 3 < n_iter) block(ob1, wb1);
+    if (it + 4 < n_iter) block(oc0, wc0);
+    if (it + 5 < n_iter) block(oc1, wc1);
+  } else {
+    // one step ahead (the copies into the current registers wait for the
+    // loads): fewer registers, for kernels whose occupancy they limit
+    uint32_t o0 = load_o(0), o1 = load_o(1);
+    double w0 = load_w(0), w1 = load_w(1);
+    int it = 0;
+    for (; it + 2 <= n_iter; it += 2) {
+      const uint32_t n0 = load_o(it + 2), n1 = load_o(it + 3);
+      const double m0 = load_w(it + 2), m1 = load_w(it + 3);
+      block(o0, w0);
+      block(o1, w1);
+      o0 = n0;
+      o1 = n1;
+      w0 = m0;
+      w1 = m1;
+    }
+    if (it < n_iter) block(o0, w0);
   }
-  if (it < n_iter) block(o0, w0);
   return wave_sum4_f64(acc[0], acc[1], acc[2], acc[3], lane);
 }
 
@@ -1038,7 +1084,7 @@ __device__ __forceinline__ double staged_rho4(const uint32_t *region, int pitch,
                                               __amdgpu_buffer_rsrc_t rsw, int n_iter,
                                               __amdgpu_buffer_rsrc_t rs2, int P4,
                                               const DevTmpl &td, int lane) {
-  const double sum = staged_num4<CONSEC>(region, base, rso, rsw, n_iter, lane);
+  const double sum = staged_num4<CONSEC, true>(region, base, rso, rsw, n_iter, lane);
   const int jj = lane & 3;
   const int q = jj == 0 ? base[0] : jj == 1 ? base[1] : jj == 2 ? base[2] : base[3];
   const int g = jj == 0 ? gof[0] : jj == 1 ? gof[1] : jj == 2 ? gof[2] : gof[3];
@@ -1427,8 +1473,8 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
       }
       // lane j < 4 holds the sum of entry c0 + e0 + j
       const double sum = consecutive4(base)
-                             ? staged_num4<true>(region, base, rso, rsw, st.n_iter, lane)
-                             : staged_num4<false>(region, base, rso, rsw, st.n_iter, lane);
+                             ? staged_num4<true, false>(region, base, rso, rsw, st.n_iter, lane)
+                             : staged_num4<false, false>(region, base, rso, rsw, st.n_iter, lane);
       if (lane < 4 && e0 + lane < n) num[e0 + lane] = sum;
     }
     __syncthreads();
