@@ -673,80 +673,66 @@ void plan_slots(const sncc_tmpl *tm, int span_u, int span_v, int max_words, Plan
     }
     if ((long long)pitch * rows > max_words) continue;
     const std::vector<Seg> &segs = tm->segs[t];
-    // whole chains (the slots carry no order constraint), in raster order
-    // of their first segment: a wave's slots then read nearby rows
-    std::vector<std::vector<int>> chains =
-        horizontal_chains(segs, std::numeric_limits<int>::max());
-    std::stable_sort(chains.begin(), chains.end(),
-                     [&](const std::vector<int> &a, const std::vector<int> &b) {
-                       const Seg &x = segs[a[0]], &y = segs[b[0]];
-                       return x.y != y.y ? x.y < y.y : x.x < y.x;
-                     });
+    // corners of the segments with their summed weights (W_p: +c at the
+    // top-left and bottom-right corner of a segment, -c at the other two),
+    // zero sums dropped, in raster order
+    std::map<std::pair<int, int>, double> corner;
+    const std::vector<double> &c = tm->c64[t];
+    for (size_t i = 0; i < segs.size(); ++i) {
+      const Seg &g = segs[i];
+      corner[{g.y, g.x}] += c[i];
+      corner[{g.y + g.h, g.x + g.w}] += c[i];
+      corner[{g.y, g.x + g.w}] -= c[i];
+      corner[{g.y + g.h, g.x}] -= c[i];
+    }
     SlowTmpl st;
     st.tbl = (int)ph.slot_off.size();
     st.pitch = pitch;
     st.rows = rows;
-    const std::vector<double> &c = tm->c64[t];
     std::vector<std::pair<uint32_t, double>> raster;
-    for (const std::vector<int> &ch : chains) {
-      const Seg &g0 = segs[ch[0]];
-      const uint32_t top = (uint32_t)(g0.y * pitch), bot = (uint32_t)((g0.y + g0.h) * pitch);
-      auto slot = [&](int x) { return ((top + x) * 4) | (((bot + x) * 4) << 16); };  // bytes
-      // boundary j: w_j = c_j - c_(j+1), c_0 = c_(L+1) = 0
-      raster.emplace_back(slot(g0.x), -c[ch[0]]);
-      for (size_t k = 0; k < ch.size(); ++k) {
-        const Seg &g = segs[ch[k]];
-        raster.emplace_back(slot(g.x + g.w), k + 1 < ch.size() ? c[ch[k]] - c[ch[k + 1]] : c[ch[k]]);
-      }
-    }
+    for (const auto &e : corner)
+      if (e.second != 0.0)
+        raster.emplace_back((uint32_t)((e.first.first * pitch + e.first.second) * 4), e.second);
     // Slot order for the LDS banks (32 banks of 4 bytes per half-wave; a
     // window's base shifts every lane's bank alike): groups of 32 slots, each
     // taking first, among the next kWindow slots in raster order, slots of
-    // the banks with the most slots still to place (top plus bottom count),
-    // at most one per top bank and one per bottom bank, then the least
-    // conflicting ones.  The sum does not depend on the order.
+    // the banks with the most slots still to place, at most one per bank,
+    // then the least conflicting ones.  The sum does not depend on the order.
     constexpr size_t kWindow = 4096;
-    auto bank = [&](size_t i, int hi) {
-      const uint32_t o = raster[i].first;
-      return (int)(((hi ? o >> 16 : o & 0xffffu) >> 2) & 31);
-    };
-    int rem_t[32] = {0}, rem_b[32] = {0};
-    for (size_t i = 0; i < raster.size(); ++i) ++rem_t[bank(i, 0)], ++rem_b[bank(i, 1)];
+    auto bank = [&](size_t i) { return (int)((raster[i].first >> 2) & 31); };
+    int rem[32] = {0};
+    for (size_t i = 0; i < raster.size(); ++i) ++rem[bank(i)];
     std::vector<size_t> pool(raster.size());
     for (size_t i = 0; i < pool.size(); ++i) pool[i] = i;
     std::vector<size_t> cand, grp;
     std::vector<char> in_grp(raster.size(), 0);
     while (!pool.empty()) {
       cand.assign(pool.begin(), pool.begin() + std::min(pool.size(), kWindow));
-      std::stable_sort(cand.begin(), cand.end(), [&](size_t x, size_t y) {
-        return rem_t[bank(x, 0)] + rem_b[bank(x, 1)] > rem_t[bank(y, 0)] + rem_b[bank(y, 1)];
-      });
-      int used_t[32] = {0}, used_b[32] = {0};
+      std::stable_sort(cand.begin(), cand.end(),
+                       [&](size_t x, size_t y) { return rem[bank(x)] > rem[bank(y)]; });
+      int used[32] = {0};
       grp.clear();
       auto take = [&](size_t i) {
         grp.push_back(i);
         in_grp[i] = 1;
-        ++used_t[bank(i, 0)];
-        ++used_b[bank(i, 1)];
+        ++used[bank(i)];
       };
       for (size_t i : cand) {
         if (grp.size() == 32) break;
-        if (!used_t[bank(i, 0)] && !used_b[bank(i, 1)]) take(i);
+        if (!used[bank(i)]) take(i);
       }
       while (grp.size() < 32) {
         size_t best = raster.size();
         int best_cost = 1 << 30;
         for (size_t i : cand) {
           if (in_grp[i]) continue;
-          const int cost = used_t[bank(i, 0)] + used_b[bank(i, 1)];
-          if (cost < best_cost) best = i, best_cost = cost;
+          if (used[bank(i)] < best_cost) best = i, best_cost = used[bank(i)];
         }
         if (best == raster.size()) break;
         take(best);
       }
       for (size_t i : grp) {
-        --rem_t[bank(i, 0)];
-        --rem_b[bank(i, 1)];
+        --rem[bank(i)];
         ph.slot_off.push_back(raster[i].first);
         ph.slot_w.push_back(raster[i].second);
       }

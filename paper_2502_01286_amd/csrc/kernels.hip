@@ -895,36 +895,31 @@ __device__ __forceinline__ void stage_region(__amdgpu_buffer_rsrc_t rs, int P, i
   __builtin_amdgcn_s_waitcnt(0);
 }
 
-// Each staged region row less its first entry (modulo 2^32).  A window's box
-// sums are unchanged, and so is a chain's sum of w D (its slot weights add to
-// zero), while a column difference D = s(y + h, x) - s(y, x) becomes the box
-// sum over rows [y, y + h) and the region's columns left of x, below
-// 255 x rows x pitch.  Needed when the table's own differences, below
-// 255 x h x P, could come near 2^32 (they must stay exact as unsigned
-// integers) or make the FP64 products w D large against c_i F_i: the kernels
-// shift when 255 H P >= 2^27 (relative_rows), where the products stay below
-// 2^27 |w| either way (rho within about 1e-13 of the exact value; a CPU run of
-// both forms on 1280-wide frames gave 5e-14 unshifted, 1e-15 shifted).  A
-// wave shifts the rows it staged (stage_region's rows), after its own loads
-// have landed, so no barrier is needed before; four rows at a time, their
-// first entries read before any row is written.
-// Whether a staged region must be made row-relative (region_relative) for a
-// template of height H on tables of pitch P.
-__device__ __forceinline__ bool relative_rows(int H, int P) {
-  return 255ull * (unsigned long long)H * (unsigned long long)P >= (1ull << 27);
-}
-
-__device__ __forceinline__ void region_relative(uint32_t *region, int nrow, int ncol, int pitch,
-                                                int wave, int lane, int n_waves) {
+// The staged region made relative in both directions (modulo 2^32): entry
+// (r, c) becomes s(r, c) - s(r, 0) - s(0, c) + s(0, 0), the sum of f over the
+// region's rows [0, r) and columns [0, c), below 255 x rows x pitch, so it is
+// exact as an unsigned 32-bit value for any frame and the FP64 products W s
+// stay small.  Box sums are unchanged, and so is a template's corner sum: its
+// weights add to zero along every row and every column.  s(0, c) comes from
+// the global table (the entries stage_region read), so a wave shifts the rows
+// it staged as soon as its own loads have landed, without a barrier; four
+// rows at a time, their first entries read before any row is written.
+__device__ __forceinline__ void region_relative(__amdgpu_buffer_rsrc_t rs, int P, int N, int v0,
+                                                int u0, uint32_t *region, int nrow, int ncol,
+                                                int pitch, int wave, int lane, int n_waves) {
   constexpr int G = 4;
+  const int gy = min(v0, N) * P;  // the region's first row in the table
+  const uint32_t s00 = __builtin_amdgcn_raw_buffer_load_b32(rs, 0, (gy + min(u0, P - 1)) * 4, 0);
   for (int row0 = wave; row0 < nrow; row0 += G * n_waves) {
     uint32_t b[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const int row = row0 + g * n_waves;
-      b[g] = row < nrow ? region[row * pitch] : 0u;
+      b[g] = row < nrow ? region[row * pitch] - s00 : 0u;
     }
     for (int c = lane; c < ncol; c += 64) {
+      const uint32_t z =
+          __builtin_amdgcn_raw_buffer_load_b32(rs, min(u0 + c, P - 1) * 4, gy * 4, 0);
       uint32_t v[G];
 #pragma unroll
       for (int g = 0; g < G; ++g) {
@@ -934,7 +929,7 @@ __device__ __forceinline__ void region_relative(uint32_t *region, int nrow, int 
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const int row = row0 + g * n_waves;
-        if (row < nrow) region[row * pitch + c] = v[g] - b[g];
+        if (row < nrow) region[row * pitch + c] = v[g] - b[g] - z;
       }
     }
   }
@@ -960,14 +955,13 @@ __device__ __forceinline__ bool consecutive4(const int (&base)[4]) {
 }
 
 // FP64 sum of c_i F_i over the segments (Eq. (12), first term) for four
-// windows of one template whose table entries are staged in LDS: base[j] is
-// the region byte offset of window j's top-left entry.  Lanes run over the
-// template's boundary slots (see SlowTmpl), 64-slot blocks whose slot entries
-// are requested ahead; per slot and window two LDS
-// reads give the column difference D (a region row's shift cancels within a
-// chain) and w D is added to the lane's FP64 sum, which over a chain is the
-// sum of c_i F_i (summation by parts).  Lane l returns the sum of window
-// l mod 4.  CONSEC: the four windows are consecutive offsets of one row
+// windows of one template whose table entries are staged in LDS (made
+// relative by region_relative): base[j] is the region byte offset of window
+// j's top-left entry.  Lanes run over the template's corner slots (see
+// SlowTmpl), 64-slot blocks whose slot entries are requested ahead; per slot
+// and window one LDS read gives the table entry s at the corner and W s is
+// added to the lane's FP64 sum, which over all corners is the sum of c_i F_i.
+// Lane l returns the sum of window l mod 4.  CONSEC: the four windows are consecutive offsets of one row
 // (base[j] = base[0] + 4 j), so one address per slot serves all four reads,
 // with immediate offsets.  DEEP: slot entries four blocks ahead in three
 // register sets (more registers), else one step ahead.
@@ -977,18 +971,15 @@ __device__ __forceinline__ double staged_num4(const uint32_t *region, const int 
                                               __amdgpu_buffer_rsrc_t rsw, int n_iter, int lane) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   auto block = [&](uint32_t o, double w) {
-    const int top = (int)(o & 0xffffu), bot = (int)(o >> 16);
     uint32_t D[4];
     if constexpr (CONSEC) {
-      const char *rb = reinterpret_cast<const char *>(region) + base[0];
-      const uint32_t *pb = reinterpret_cast<const uint32_t *>(rb + bot);
-      const uint32_t *pt = reinterpret_cast<const uint32_t *>(rb + top);
+      const uint32_t *pp =
+          reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(region) + base[0] + o);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) D[j] = pb[j] - pt[j];
+      for (int j = 0; j < 4; ++j) D[j] = pp[j];
     } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        D[j] = lds_at(region, base[j] + bot) - lds_at(region, base[j] + top);
+      for (int j = 0; j < 4; ++j) D[j] = lds_at(region, base[j] + (int)o);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = __builtin_fma((double)D[j], w, acc[j]);
@@ -1140,7 +1131,7 @@ __global__ __launch_bounds__(256) void slow_kernel(
       // region rows [v0, v0 + rows), columns [u0, u0 + pitch), clamped to
       // the table (clamped entries are never read by a window of the run)
       stage_region(rs, P, N, rd.v0, rd.u0, st.rows, st.pitch, st.pitch, region, wave, lane);
-      if (relative_rows(td.H, P)) region_relative(region, st.rows, st.pitch, st.pitch, wave, lane, 4);
+      region_relative(rs, P, N, rd.v0, rd.u0, region, st.rows, st.pitch, st.pitch, wave, lane, 4);
       __syncthreads();
       const __amdgpu_buffer_rsrc_t rso = make_rsrc(slot_off + st.tbl, (uint32_t)st.n_iter * 256u);
       const __amdgpu_buffer_rsrc_t rsw = make_rsrc(slot_w + st.tbl, (uint32_t)st.n_iter * 512u);
@@ -1459,7 +1450,7 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(
     // [umin, umax + W] of the table, at the region's pitch
     const int nrow = vmax - vmin + td.H + 1, ncol = umax - umin + td.W + 1;
     stage_region(rs, P, N, vmin, umin, nrow, ncol, st.pitch, region, wave, lane, kRefineWaves);
-    if (relative_rows(td.H, P)) region_relative(region, nrow, ncol, st.pitch, wave, lane, kRefineWaves);
+    region_relative(rs, P, N, vmin, umin, region, nrow, ncol, st.pitch, wave, lane, kRefineWaves);
     __syncthreads();
     const __amdgpu_buffer_rsrc_t rso = make_rsrc(slot_off + st.tbl, (uint32_t)st.n_iter * 256u);
     const __amdgpu_buffer_rsrc_t rsw = make_rsrc(slot_w + st.tbl, (uint32_t)st.n_iter * 512u);

@@ -138,20 +138,17 @@ struct CompactOut {
 
 // Slow pass of the two-threshold search.  A template whose region (the
 // table rows and columns that the windows of one run's offsets cover) fits
-// the LDS budget is scored from LDS through a boundary-slot table: its
-// segments as horizontal chains (runs of segments with equal y and h, each
-// starting where the previous one ends), a chain of L segments taking L + 1
-// slots, one per boundary column, padded to whole waves.  Along a chain with
-// boundary columns x_0 < ... < x_L and segment constants c_1 .. c_L, the sum
-// of c_i times the segment's box sum (Eq. (11)) equals, by summation by
-// parts, the sum over boundaries of D_j w_j, where D_j is the column
-// difference s(y + h, x_j) - s(y, x_j) and w_0 = -c_1, w_j = c_j - c_(j+1),
-// w_L = c_L.  Since the weights of a chain add to zero, D_j may be taken
-// from any table whose rows are shifted by a constant per row, such as the
-// staged region with each row less its first entry.  Slot j holds the LDS
-// byte offsets of the boundary column's entries in the chain's top row y and
-// bottom row y + h (relative to the window's top-left entry; bottom in the
-// high 16 bits) and w_j (padding slots: offsets 0, w 0).
+// the LDS budget is scored from LDS through a corner-slot table.  By
+// summation by parts in both directions, the sum over segments of c_i times
+// the box sum F_i (Eq. (11)) equals the sum over the template's distinct
+// rectangle corners p of W_p s(p), where s is the sum table at the corner
+// (relative to the window's top-left entry) and W_p collects +c_i for the
+// top-left and bottom-right corners of segment i and -c_i for the other two.
+// The weights add to zero along every row and every column of corners, so s
+// may be taken from a table shifted by a constant per row and per column,
+// such as the staged region made relative to its first row and column.
+// Slot j holds the corner's LDS byte offset (low 16 bits) and W_j; the
+// slots are padded to whole waves (offset 0, weight 0).
 struct SlowTmpl {
   int tbl;     // first slot (-1: scored from the global tables)
   int n_iter;  // slots / 64

@@ -16,8 +16,8 @@
 // every pair's tiles exactly once, the queues must be a permutation of the
 // items, and every LDS read the records imply must stay inside the plan's
 // LDS size; the slow pass's and the refine's slot tables must stay inside
-// their regions and their weighted column differences must give the
-// segments' sums.  Exit status 0 when every check holds.
+// their regions and their weighted corner entries must give the segments'
+// sums.  Exit status 0 when every check holds.
 
 #include "../../paper_2502_01286_amd/csrc/segment.cpp"
 #include "../../paper_2502_01286_amd/csrc/api.cpp"
@@ -233,11 +233,12 @@ static void check_plan(const sncc_tmpl &tm, const PlanHost &ph, int n_pairs, int
 }
 
 // Slot tables: every slot inside its template's region, and the weighted
-// column differences equal the segment sums.  For a random image g at the
-// region's origin, with each table row shifted by a random constant and then
-// made relative to its first entry as the kernels do, the sum over slots of
-// w (s(bottom) - s(top)) must equal the sum over segments of c_i times the
-// box sum of g (summation by parts along each chain), to FP64 rounding.
+// corner entries equal the segment sums.  For a random image g at the
+// region's origin, with each table row and each column shifted by a random
+// constant and then made relative to the first row and column as the kernels
+// do, the sum over slots of W s(corner) must equal the sum over segments of
+// c_i times the box sum of g (summation by parts in both directions), to
+// FP64 rounding.
 static void check_slots(const sncc_tmpl &tm, const PlanHost &ph) {
   uint64_t lcg = 0x9e3779b97f4a7c15ull;
   auto next = [&]() { return (uint32_t)((lcg = lcg * 6364136223846793005ull + 1442695040888963407ull) >> 33); };
@@ -263,17 +264,22 @@ static void check_slots(const sncc_tmpl &tm, const PlanHost &ph) {
       for (int c = 1; c < P; ++c)
         tab[(size_t)r * P + c] = tab[(size_t)(r - 1) * P + c] + tab[(size_t)r * P + c - 1] -
                                  tab[(size_t)(r - 1) * P + c - 1] + g[(size_t)(r - 1) * P + c - 1];
-    for (int r = 0; r < R; ++r) {  // a table row's shift, then the kernels' relative form
+    std::vector<uint32_t> col_shift(P);
+    for (uint32_t &v : col_shift) v = next();
+    for (int r = 0; r < R; ++r) {  // shifts of rows and columns
       const uint32_t shift = next();
-      for (int c = 0; c < P; ++c) tab[(size_t)r * P + c] += shift;
-      const uint32_t b = tab[(size_t)r * P];
-      for (int c = 0; c < P; ++c) tab[(size_t)r * P + c] -= b;
+      for (int c = 0; c < P; ++c) tab[(size_t)r * P + c] += shift + col_shift[c];
     }
+    std::vector<uint32_t> rel(tab.size());  // the kernels' relative form
+    for (int r = 0; r < R; ++r)
+      for (int c = 0; c < P; ++c)
+        rel[(size_t)r * P + c] =
+            tab[(size_t)r * P + c] - tab[(size_t)r * P] - tab[c] + tab[0];
     double by_slots = 0.0, by_segs = 0.0, scale = 0.0;
     for (int i = st.tbl; i < st.tbl + 64 * st.n_iter; ++i) {
       const uint32_t o = ph.slot_off[i];
-      const uint32_t D = tab[(o >> 16) / 4] - tab[(o & 0xffffu) / 4];
-      by_slots += ph.slot_w[i] * (double)D;
+      CHECK((o >> 16) == 0, "slot %d: high half %u", i, o >> 16);
+      by_slots += ph.slot_w[i] * (double)rel[(o & 0xffffu) / 4];
     }
     const std::vector<Seg> &segs = tm.segs[t];
     for (size_t i = 0; i < segs.size(); ++i) {
