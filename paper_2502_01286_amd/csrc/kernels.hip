@@ -907,9 +907,15 @@ __device__ __forceinline__ void stage_region(__amdgpu_buffer_rsrc_t rs, int P, i
 __device__ __forceinline__ void region_relative(__amdgpu_buffer_rsrc_t rs, int P, int N, int v0,
                                                 int u0, uint32_t *region, int nrow, int ncol,
                                                 int pitch, int wave, int lane, int n_waves) {
-  constexpr int G = 4;
+  constexpr int G = 4, ZK = 4;  // rows per group; column chunks whose s(0, c) stay in registers
   const int gy = min(v0, N) * P;  // the region's first row in the table
+  auto row0_entry = [&](int c) {
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, min(u0 + c, P - 1) * 4, gy * 4, 0);
+  };
   const uint32_t s00 = __builtin_amdgcn_raw_buffer_load_b32(rs, 0, (gy + min(u0, P - 1)) * 4, 0);
+  uint32_t zk[ZK];
+#pragma unroll
+  for (int k = 0; k < ZK; ++k) zk[k] = lane + 64 * k < ncol ? row0_entry(lane + 64 * k) : 0u;
   for (int row0 = wave; row0 < nrow; row0 += G * n_waves) {
     uint32_t b[G];
 #pragma unroll
@@ -917,9 +923,7 @@ __device__ __forceinline__ void region_relative(__amdgpu_buffer_rsrc_t rs, int P
       const int row = row0 + g * n_waves;
       b[g] = row < nrow ? region[row * pitch] - s00 : 0u;
     }
-    for (int c = lane; c < ncol; c += 64) {
-      const uint32_t z =
-          __builtin_amdgcn_raw_buffer_load_b32(rs, min(u0 + c, P - 1) * 4, gy * 4, 0);
+    auto shift = [&](int c, uint32_t z) {
       uint32_t v[G];
 #pragma unroll
       for (int g = 0; g < G; ++g) {
@@ -931,7 +935,11 @@ __device__ __forceinline__ void region_relative(__amdgpu_buffer_rsrc_t rs, int P
         const int row = row0 + g * n_waves;
         if (row < nrow) region[row * pitch + c] = v[g] - b[g] - z;
       }
-    }
+    };
+#pragma unroll
+    for (int k = 0; k < ZK; ++k)
+      if (lane + 64 * k < ncol) shift(lane + 64 * k, zk[k]);
+    for (int c = lane + 64 * ZK; c < ncol; c += 64) shift(c, row0_entry(c));
   }
 }
 
