@@ -6,8 +6,8 @@ for b - shr(a)) computes shr(b) - a: the shift lands on the other operand (a
 one-wave probe with distinct registers showed it).  No kernel may contain an
 operand-reversed VOP2 op with a DPP source, and the slow pass and the refine
 kernel, whose slot loops take no value from another lane (summation by
-parts along each chain), may contain no subtraction with a row-shifted DPP
-source.  A compiler change that folds such an operation fails here, on the
+parts over the segments' corners), may contain no subtraction with a
+row-shifted DPP source.  A compiler change that folds such an operation fails here, on the
 CPU, before any GPU run.
 """
 
