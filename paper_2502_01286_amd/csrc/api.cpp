@@ -186,7 +186,7 @@ struct PlanHost {
   std::vector<WorkItem> items;
   std::vector<int> order;       // item indices, queue by queue
   std::vector<int> qbeg;        // nq + 1 offsets into order
-  // boundary-slot tables: of the slow approximations (two-threshold search)
+  // corner-slot tables: of the slow approximations (two-threshold search)
   // or of the fine ones (refine)
   std::vector<SlowTmpl> slow;
   std::vector<uint32_t> slot_off;

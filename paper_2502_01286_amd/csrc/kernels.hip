@@ -804,13 +804,12 @@ int launch_merge64(const PairDesc *pairs, int n_pairs, const Key96 *partial, int
 // of a tile: one pair, a few offset rows) from a counter.
 //
 // Staged form: the workgroup copies the run's region of the frame's table
-// (every entry a window of the run reads) to LDS; each wave then scores four
-// survivors at a time, lanes over the template's boundary slots (see
-// SlowTmpl): per slot two LDS reads give the boundary column's difference
-// D = s(y + h) - s(y) (modulo 2^32), and the lane below in the same chain
-// holds the previous boundary, so F_i = D - D_prev is the segment's box sum
-// (Eq. (11)); c_i F_i is accumulated in FP64 per lane and summed over the
-// wave at the end.  Global form (regions too large for LDS): lanes over the
+// (every entry a window of the run reads) to LDS and makes it relative to its
+// first row and column; each wave then scores four survivors at a time, lanes
+// over the template's corner slots (see SlowTmpl): per slot one LDS read
+// gives the table entry at the corner, W times it is accumulated in FP64 per
+// lane, and the wave's sum is the sum of c_i F_i over the segments (Eq. (12),
+// summation by parts of Eq. (11) over the corners).  Global form (regions too large for LDS): lanes over the
 // run's survivors, each scoring its own offset over the shared segment list
 // with buffer loads whose scalar offset is the segment's corner, blocks of
 // kSlowBlock segments loaded before they are summed in segment order.
