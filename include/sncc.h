@@ -65,8 +65,8 @@ extern "C" {
 
 /* Size of the per-device static carry scratch of sncc_build_sats_noalloc
  * (8 MiB): the call accepts B frames of M x N while
- * 8 * B * (ceil(N/64) * M + N * ceil(M/256) + 2 * ceil(N/64) * ceil(M/256))
- * does not exceed it (e.g. 25 frames 1920x1080, 54 frames 1280x720,
+ * 8 * B * (ceil(N/64) * M + N * ceil(M/256) + ceil(N/64) * ceil(M/256))
+ * does not exceed it (e.g. 25 frames 1920x1080, 55 frames 1280x720,
  * 6 frames 3840x2160). */
 #define SNCC_NOALLOC_SCRATCH_BYTES 8388608
 

@@ -1,12 +1,12 @@
 // HIP kernels for segmented NCC on gfx950 (CDNA4, wave64).
 //
-//  * Sum tables (Eqs. (10), (14)): three launches.  Per 64 x 256 tile,
+//  * Sum tables (Eqs. (10), (14)): two launches.  Per 64 x 256 tile,
 //    sat_totals writes column totals, row totals and the tile total;
-//    sat_prefix turns them into the carries each tile needs (sum of the
-//    rows above per column, of the columns to the left per row, and of the
-//    tiles above-left); sat_scan rebuilds the tile with running column sums
-//    and one wavefront scan per row and writes s and s^2.  f is read twice,
-//    s and s^2 written once: about 10 bytes of HBM traffic per pixel.
+//    sat_scan sums from them the carries its tile needs (the rows above per
+//    column, the columns to the left per row, the tiles above-left), then
+//    rebuilds the tile with running column sums and one wavefront scan per
+//    row and writes s and s^2.  f is read twice, s and s^2 written once:
+//    about 10 bytes of HBM traffic per pixel.
 //  * Scoring (Eqs. (11)-(18)): a persistent kernel pulls work items
 //    (pair, range of offset tiles) from an atomic counter.  For each tile the
 //    rows of the sum table that the template's corner rows touch are staged
@@ -36,7 +36,7 @@ constexpr int SAT_TY = 64;
 constexpr int SAT_TX = 256;
 
 struct SatScratch {
-  uint32_t *colT, *rowT, *T, *corner;
+  uint32_t *colT, *rowT, *T;
   int nTX, nTY;
 };
 
@@ -47,13 +47,12 @@ __host__ __device__ inline SatScratch sat_layout(uint32_t *base, int B, int M, i
   sc.colT = base;                                          // [2][B][nTY][M]
   sc.rowT = sc.colT + (size_t)2 * B * sc.nTY * M;          // [2][B][nTX][N]
   sc.T = sc.rowT + (size_t)2 * B * N * sc.nTX;             // [2][B][nTY][nTX]
-  sc.corner = sc.T + (size_t)2 * B * sc.nTY * sc.nTX;      // [2][B][nTY][nTX]
   return sc;
 }
 
 size_t sat_scratch_words(int B, int M, int N) {
   size_t nTX = (M + SAT_TX - 1) / SAT_TX, nTY = (N + SAT_TY - 1) / SAT_TY;
-  return (size_t)2 * B * (nTY * (size_t)M + (size_t)N * nTX + 2 * nTY * nTX);
+  return (size_t)2 * B * (nTY * (size_t)M + (size_t)N * nTX + nTY * nTX);
 }
 
 // Pixels x0 .. x0 + 3 of a row packed into one word (byte q = pixel x0 + q,
@@ -204,71 +203,6 @@ __global__ __launch_bounds__(256) void sat_totals(const uint8_t *__restrict__ f,
   }
 }
 
-// Exclusive prefix, in place, of n words at p[0], p[stride], ...: the loads
-// of each group of 16 are issued together, then the group is summed.
-__device__ __forceinline__ void excl_prefix_inplace(uint32_t *__restrict__ p, size_t stride,
-                                                    int n) {
-  uint32_t run = 0;
-  for (int i0 = 0; i0 < n; i0 += 16) {
-    uint32_t t[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) t[q] = i0 + q < n ? p[(size_t)(i0 + q) * stride] : 0u;
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-      if (i0 + q < n) {
-        p[(size_t)(i0 + q) * stride] = run;
-        run += t[q];
-      }
-  }
-}
-
-// Carries: exclusive prefix over tile rows of the column totals, over tile
-// columns of the row totals, and the 2-D exclusive prefix of tile totals.
-__global__ __launch_bounds__(256) void sat_prefix(int B, int M, int N,
-                                                  uint32_t *__restrict__ scratch) {
-  SatScratch sc = sat_layout(scratch, B, M, N);
-  const long long job = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long nA = (long long)B * M, nB = (long long)B * N, nC = (long long)B * sc.nTX;
-  if (job < 2 * nA) {
-    const int p = (int)(job / nA);
-    const long long j = job - p * nA;
-    const int b = (int)(j / M), x = (int)(j % M);
-    const size_t plane = (size_t)B * sc.nTY * M;
-    excl_prefix_inplace(sc.colT + p * plane + (size_t)b * sc.nTY * M + x, (size_t)M, sc.nTY);
-  } else if (job < 2 * nA + 2 * nB) {
-    const long long jj = job - 2 * nA;
-    const int p = (int)(jj / nB);
-    const long long j = jj - p * nB;
-    const int b = (int)(j / N), y = (int)(j % N);
-    const size_t plane = (size_t)B * N * sc.nTX;
-    excl_prefix_inplace(sc.rowT + p * plane + (size_t)b * sc.nTX * N + y, (size_t)N, sc.nTX);
-  } else if (job < 2 * nA + 2 * nB + 2 * nC) {
-    const long long jj = job - 2 * nA - 2 * nB;
-    const int p = (int)(jj / nC);
-    const long long j = jj - p * nC;
-    const int b = (int)(j / sc.nTX), J = (int)(j % sc.nTX);
-    const size_t plane = (size_t)B * sc.nTY * sc.nTX;
-    const uint32_t *T = sc.T + p * plane + (size_t)b * sc.nTY * sc.nTX;
-    uint32_t *corner = sc.corner + p * plane + (size_t)b * sc.nTY * sc.nTX;
-    uint32_t acc = 0;
-    for (int I0 = 0; I0 < sc.nTY; I0 += 16) {
-      uint32_t left[16];  // per tile row: the tiles left of column J
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        left[q] = 0;
-        if (I0 + q < sc.nTY)
-          for (int Jp = 0; Jp < J; ++Jp) left[q] += T[(size_t)(I0 + q) * sc.nTX + Jp];
-      }
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (I0 + q < sc.nTY) {
-          corner[(size_t)(I0 + q) * sc.nTX + J] = acc;
-          acc += left[q];
-        }
-    }
-  }
-}
-
 __global__ __launch_bounds__(256) void sat_scan(const uint8_t *__restrict__ f,
                                                 int B, int M, int N, int f_pitch,
                                                 const uint32_t *__restrict__ scratch,
@@ -276,6 +210,7 @@ __global__ __launch_bounds__(256) void sat_scan(const uint8_t *__restrict__ f,
                                                 uint32_t *__restrict__ s2,
                                                 int P) {
   __shared__ uint32_t wcol[SAT_WAVES][8][64];  // per wave: column totals of f, f^2
+  __shared__ uint32_t wcar[SAT_WAVES][8][64];  // per wave: its part of the column carries
   SatScratch sc = sat_layout(const_cast<uint32_t *>(scratch), B, M, N);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int J = blockIdx.x, I = blockIdx.y, b = blockIdx.z;
@@ -314,33 +249,57 @@ __global__ __launch_bounds__(256) void sat_scan(const uint8_t *__restrict__ f,
 #pragma unroll
     for (int q = 0; q < 4; ++q) wcol[w][4 + q][lane] = t2[q];
   }
-  // running column sums start at the sum of all rows above this wave's rows
-  uint32_t cs[4], cs2[4];
+  // The carries, summed here from sat_totals' totals (modulo 2^32, so in any
+  // order): the column totals of the tile rows above (the waves take every
+  // fourth tile row and add their parts through LDS), each row's totals of
+  // the tile columns to its left (lane r: row y0 + r), and the tile totals
+  // above-left (spread over the lanes, then a wave sum).
+  uint32_t cs[4] = {0, 0, 0, 0}, cs2[4] = {0, 0, 0, 0};
   const size_t plane_col = (size_t)B * sc.nTY * M;
+  for (int Ip = w; Ip < I; Ip += SAT_WAVES) {
+    const size_t o = ((size_t)b * sc.nTY + Ip) * M + x0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (x0 + q < M) {
+        cs[q] += sc.colT[o + q];
+        cs2[q] += sc.colT[plane_col + o + q];
+      }
+  }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const size_t o = ((size_t)b * sc.nTY + I) * M + x0 + q;
-    cs[q] = (x0 + q < M) ? sc.colT[o] : 0u;
-    cs2[q] = (x0 + q < M) ? sc.colT[plane_col + o] : 0u;
+    wcar[w][q][lane] = cs[q];
+    wcar[w][4 + q][lane] = cs2[q];
   }
-  // left carry of row y0 + r (held by lane r): tile corner + rows' left sums
   const size_t plane_row = (size_t)B * N * sc.nTX;
   uint32_t rl = 0, rl2 = 0;
-  if (lane < rows) {
-    const size_t o = ((size_t)b * sc.nTX + J) * N + y0 + lane;
-    rl = sc.rowT[o];
-    rl2 = sc.rowT[plane_row + o];
-  }
-  const size_t oc = ((size_t)b * sc.nTY + I) * sc.nTX + J;
+  if (lane < rows)
+    for (int Jp = 0; Jp < J; ++Jp) {
+      const size_t o = ((size_t)b * sc.nTX + Jp) * N + y0 + lane;
+      rl += sc.rowT[o];
+      rl2 += sc.rowT[plane_row + o];
+    }
   const size_t plane_t = (size_t)B * sc.nTY * sc.nTX;
-  const uint32_t L = sc.corner[oc] + wave_incl_scan(rl);
-  const uint32_t L2 = sc.corner[plane_t + oc] + wave_incl_scan(rl2);
+  uint32_t ct = 0, ct2 = 0;
+  for (int e = lane; e < I * J; e += 64) {
+    const int Ip = e / J, Jp = e - Ip * J;
+    const size_t o = ((size_t)b * sc.nTY + Ip) * sc.nTX + Jp;
+    ct += sc.T[o];
+    ct2 += sc.T[plane_t + o];
+  }
+  // left carry of row y0 + r (held by lane r): tile corner + rows' left sums
+  const uint32_t L = wave_sum(ct) + wave_incl_scan(rl);
+  const uint32_t L2 = wave_sum(ct2) + wave_incl_scan(rl2);
   __syncthreads();
-  for (int u = 0; u < w; ++u)
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    cs[q] = 0;
+    cs2[q] = 0;
+  }
+  for (int u = 0; u < SAT_WAVES; ++u)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      cs[q] += wcol[u][q][lane];
-      cs2[q] += wcol[u][4 + q][lane];
+      cs[q] += wcar[u][q][lane] + (u < w ? wcol[u][q][lane] : 0u);
+      cs2[q] += wcar[u][4 + q][lane] + (u < w ? wcol[u][4 + q][lane] : 0u);
     }
 
 #pragma unroll
@@ -405,9 +364,6 @@ int launch_sat(const uint8_t *f, int B, int M, int N, int f_pitch, uint32_t *s,
   dim3 grid(nTX, nTY, B);
   hipLaunchKernelGGL(sat_totals, grid, dim3(64 * SAT_WAVES), 0, st, f, B, M, N, f_pitch,
                      scratch);
-  const long long jobs = 2 * ((long long)B * M + (long long)B * N + (long long)B * nTX);
-  hipLaunchKernelGGL(sat_prefix, dim3((unsigned)((jobs + 255) / 256)), dim3(256), 0, st,
-                     B, M, N, scratch);
   hipLaunchKernelGGL(sat_scan, grid, dim3(64 * SAT_WAVES), 0, st, f, B, M, N, f_pitch, scratch,
                      s, s2, sat_pitch);
   return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -31,7 +31,7 @@ def test_noalloc_sum_tables_match_build_sats():
             frames = [synth.scene(7700 + 10 * case + b, M, N) for b in range(B)]
             f = torch.from_numpy(np.stack(frames)).cuda()
             P = S.sncc_sat_pitch(M)
-            words = 2 * B * (-(-N // 64) * M + N * -(-M // 256) + 2 * -(-N // 64) * -(-M // 256))
+            words = 2 * B * (-(-N // 64) * M + N * -(-M // 256) + -(-N // 64) * -(-M // 256))
             assert 4 * words <= S.SNCC_NOALLOC_SCRATCH_BYTES
             s_ref, s2_ref = _tables(torch, B, M, N, P, 0)
             S.sncc_build_sats(ctx, f, s_ref, s2_ref)
