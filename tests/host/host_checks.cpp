@@ -17,7 +17,8 @@
 // items, and every LDS read the records imply must stay inside the plan's
 // LDS size; the slow pass's and the refine's slot tables must stay inside
 // their regions and their weighted corner entries must give the segments'
-// sums.  Exit status 0 when every check holds.
+// sums; the refine's launch classes must order every pair once, each class
+// within its LDS size.  Exit status 0 when every check holds.
 
 #include "../../paper_2502_01286_amd/csrc/segment.cpp"
 #include "../../paper_2502_01286_amd/csrc/api.cpp"
@@ -295,6 +296,36 @@ static void check_slots(const sncc_tmpl &tm, const PlanHost &ph) {
   }
 }
 
+// Refine launch classes: the order is a permutation of the pairs, the first
+// refine_n_first pairs have regions within refine_lds_first, which is within
+// the four-per-CU budget, and the others' regions exceed that budget.
+static void check_refine_order(PlanHost &ph, int n_cand, int radius) {
+  plan_refine_order(ph, n_cand, radius);
+  const int n = (int)ph.pairs.size();
+  CHECK((int)ph.refine_order.size() == n, "refine order holds %zu of %d pairs",
+        ph.refine_order.size(), n);
+  std::vector<char> seen(n, 0);
+  int np = 1;
+  while (np < n_cand * (2 * radius + 1) * (2 * radius + 1)) np <<= 1;
+  const int budget = refine_region_budget(np, 4);
+  CHECK(ph.refine_lds_first <= budget, "first class region %d > budget %d",
+        ph.refine_lds_first, budget);
+  for (int i = 0; i < (int)ph.refine_order.size(); ++i) {
+    const int p = ph.refine_order[i];
+    CHECK(p >= 0 && p < n && !seen[p], "refine order entry %d: pair %d", i, p);
+    if (p < 0 || p >= n || seen[p]) continue;
+    seen[p] = 1;
+    const SlowTmpl &st = ph.slow[ph.pairs[p].tmpl];
+    const int region = st.tbl >= 0 ? st.pitch * st.rows * 4 : 0;
+    if (i < ph.refine_n_first)
+      CHECK(region <= ph.refine_lds_first, "pair %d region %d above %d", p, region,
+            ph.refine_lds_first);
+    else
+      CHECK(region > budget, "pair %d region %d in the second class within %d", p, region,
+            budget);
+  }
+}
+
 int main(int argc, char **argv) {
   const int iters = argc > 1 ? std::atoi(argv[1]) : 2000;
   std::mt19937_64 rng(argc > 2 ? std::strtoull(argv[2], nullptr, 10) : 1);
@@ -359,6 +390,7 @@ int main(int argc, char **argv) {
         plan_slots(&tm, kRefineWideSpanU, kRefineWideSpanV, kRefineRegionWords, edge_ph,
                    kRefineSpanU, kRefineSpanV);
         check_slots(tm, edge_ph);
+        check_refine_order(edge_ph, 1 + (int)(rng() % 64), (int)(rng() % 3));
         ++n_plan;
       }
     }
