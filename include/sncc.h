@@ -281,7 +281,8 @@ int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index,
                uint8_t *d_degenerate);
 
 /* Forms of sncc_score_frame */
-#define SNCC_FORM_AUTO 0        /* tile-local when allowed and K <= 40         */
+#define SNCC_FORM_AUTO 0        /* tile-local when allowed, K <= 40 and at most
+                                   2^19 offsets (small frames, few segments)   */
 #define SNCC_FORM_TILE_LOCAL 1  /* sum tables built per tile in LDS            */
 #define SNCC_FORM_GLOBAL 2      /* the frame's tables first, then sncc_score   */
 

@@ -227,8 +227,9 @@ def _chk(t, dtype, name, shape=None, min_numel=None):
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if shape is not None:
-        if t.dim() != len(shape) or any(w is not None and int(g) != int(w)
-                                        for g, w in zip(t.shape, shape)):
+        got = tuple(t.shape)
+        if got != shape and (len(got) != len(shape) or any(
+                w is not None and int(g) != int(w) for g, w in zip(got, shape))):
             want = "(" + ", ".join("*" if w is None else str(int(w)) for w in shape) + ")"
             raise ValueError(f"{name} must have shape {want}, got {tuple(t.shape)}")
     if min_numel is not None and t.numel() < int(min_numel):
@@ -272,9 +273,17 @@ def _tables(s, s2, B, N):
 
 
 def _check_pairs(p, B, n_templates=None):
-    if p.size and (p[:, 0].min() < 0 or p[:, 0].max() >= int(B)):
+    if not p.size:
+        return
+    if len(p) <= 8:  # a few pairs: Python's min/max cost less than NumPy's reductions
+        rows = p.tolist()
+        f_lo, f_hi = min(r[0] for r in rows), max(r[0] for r in rows)
+        t_lo, t_hi = min(r[1] for r in rows), max(r[1] for r in rows)
+    else:
+        f_lo, f_hi, t_lo, t_hi = p[:, 0].min(), p[:, 0].max(), p[:, 1].min(), p[:, 1].max()
+    if f_lo < 0 or f_hi >= int(B):
         raise ValueError(f"pair frame index outside [0, {int(B)})")
-    if n_templates is not None and p.size and (p[:, 1].min() < 0 or p[:, 1].max() >= n_templates):
+    if n_templates is not None and (t_lo < 0 or t_hi >= n_templates):
         raise ValueError(f"pair template index outside [0, {n_templates})")
 
 

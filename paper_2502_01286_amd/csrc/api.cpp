@@ -852,7 +852,8 @@ struct PlanDev {
     a.items = d_items.as<WorkItem>();
     a.order = d_order.as<int>();
     a.qbeg = d_qbeg.as<int>();
-    a.nq = (int)h.qbeg.size() - 1;
+    // one workgroup per item: no queues (the kernel takes order[blockIdx])
+    a.nq = h.grid == (int)h.items.size() ? 0 : (int)h.qbeg.size() - 1;
     a.n_items = (int)h.items.size();
     a.queue = d_queue.as<int>();
     a.k = h.k;
@@ -1373,13 +1374,15 @@ int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint32_t *d_
   a.rho = d_rho;
   a.rho_pitch = rho_pitch;
   a.degen = d_degenerate;
-  if (launch_zero(a.queue, a.n_zero, ctx->stream) != 0 ||
+  // the map sink uses no counters but the queues'
+  if ((a.nq != 0 && launch_zero(a.queue, a.n_zero, ctx->stream) != 0) ||
       launch_tile(pd->h.cfg, kSinkMap, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0)
     SNCC_FAIL(SNCC_EDEVICE, "tile launch: %s", hipGetErrorString(hipGetLastError()));
   return SNCC_OK;
 }
 
 constexpr int kTileLocalMaxK = 40;
+constexpr long long kTileLocalMaxOffsets = 1 << 19;
 
 int sncc_score_frame(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint8_t *d_f,
                      int M, int N, int f_pitch, int form, float *d_rho, int rho_pitch,
@@ -1402,11 +1405,15 @@ int sncc_score_frame(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint8_
   if (form == SNCC_FORM_TILE_LOCAL && !local_ok)
     SNCC_FAIL(SNCC_ERANGE, "template %dx%d does not allow the tile-local form", W, H);
   // automatic choice: the tile-local form reads four LDS entries per segment
-  // and offset where the batched kernel's chains read fewer, so it wins only
-  // while building the frame's tables costs more than the segments (measured
-  // on one MI355X: 2x faster at K = 23, 1.2x at K = 12, 0.9x at K = 72)
-  const bool local = form == SNCC_FORM_TILE_LOCAL ||
-                     (form == SNCC_FORM_AUTO && local_ok && tm->K[index] <= kTileLocalMaxK);
+  // and offset where the batched kernel's chains read fewer, and each tile
+  // builds its region's tables, so it wins only on small frames with few
+  // segments, where the launches of the frame's tables dominate (measured on
+  // one MI355X: 640 x 480 at K = 23, 20.8 vs 30 us; 1920 x 1080 at K = 12,
+  // 66.5 vs 46 us, at K = 72, 106 vs 73 us)
+  const bool local =
+      form == SNCC_FORM_TILE_LOCAL ||
+      (form == SNCC_FORM_AUTO && local_ok && tm->K[index] <= kTileLocalMaxK &&
+       (long long)nu * nv <= kTileLocalMaxOffsets);
   const int used = local ? SNCC_FORM_TILE_LOCAL : SNCC_FORM_GLOBAL;
   if (used == SNCC_FORM_TILE_LOCAL) {
     FusedArgs a;

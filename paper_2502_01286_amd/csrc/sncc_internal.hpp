@@ -225,7 +225,7 @@ struct TileArgs {
   const WorkItem *items;
   const int *order;        // execution order of items, queue by queue
   const int *qbeg;         // nq + 1 offsets into order
-  int nq;                  // work queues (1..kMaxQueues)
+  int nq;                  // work queues (1..kMaxQueues; 0: one workgroup per item)
   int n_items;
   int *queue;              // counters at queue[16 j], then (TOPK sink) the
                            // pair floors; kQueueInts + 2 n_pairs ints zeroed

@@ -435,12 +435,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
   // sits at queue[16 j].  A workgroup drains the queue of the chiplet (XCD)
   // it runs on, whose L2 then holds the frame rows that queue's items share,
   // and then the others in turn; every workgroup leaves once it has found
-  // all queues empty.
-  const int home = (int)(__builtin_amdgcn_s_getreg(20 | (3 << 11)) & 15) % nq;
+  // all queues empty.  nq == 0: the grid has one workgroup per item, and
+  // workgroup b runs order[b] and leaves (no counters: a small launch would
+  // otherwise end with each workgroup's round of atomics over every queue).
+  const int home = (int)(__builtin_amdgcn_s_getreg(20 | (3 << 11)) & 15) % max(nq, 1);
   int tried = 0;  // queues found empty (thread 0)
   for (;;) {
     if (threadIdx.x == 0) {
       int got = -1;
+      if (nq == 0 && tried++ == 0) got = order[blockIdx.x];
       while (tried < nq) {
         const int qq = (home + tried) % nq;
         const int i = atomicAdd(queue + 16 * qq, 1);

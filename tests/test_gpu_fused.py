@@ -127,7 +127,8 @@ def test_form_choice_by_size(S, ctx):
         S.sncc_score_frame(ctx, tm, 0, d, rho, form=S.SNCC_FORM_TILE_LOCAL)
     assert e.value.code == S.SNCC_ERANGE
     assert S.sncc_score_frame(ctx, tm, 0, d, rho) == S.SNCC_FORM_GLOBAL
-    # automatic choice: tile-local for few segments, global for many
+    # automatic choice: tile-local for few segments on a small frame
+    # (461 x 653 offsets), global for many
     for sg, want_form in ((40, S.SNCC_FORM_TILE_LOCAL), (2, S.SNCC_FORM_GLOBAL)):
         t2, _, _ = synth.crop_template(rng, f, 48, 40, sigma_max=sg)
         tm2 = lib_templates(S, ctx, [t2], [sg])
@@ -137,6 +138,16 @@ def test_form_choice_by_size(S, ctx):
         assert S.sncc_score_frame(ctx, tm2, 0, d, r2) == want_form
         S.sncc_sync(ctx)
         S.sncc_tmpl_destroy(tm2)
+    # a frame of more than 2^19 offsets takes the global form at any K
+    fb = synth.scene(8301, 1920, 1080)
+    t3, _, _ = synth.crop_template(np.random.default_rng(61), fb, 64, 64, sigma_max=16)
+    tm3 = lib_templates(S, ctx, [t3], [16])
+    assert S.sncc_tmpl_info(tm3, 0)[2] <= 40
+    r3 = torch.zeros((1080 - 64 + 1, 1920 - 64 + 1), dtype=torch.float32, device="cuda")
+    db = torch.from_numpy(fb).cuda()
+    assert S.sncc_score_frame(ctx, tm3, 0, db, r3) == S.SNCC_FORM_GLOBAL
+    S.sncc_sync(ctx)
+    S.sncc_tmpl_destroy(tm3)
     S.sncc_sync(ctx)
     S.sncc_tmpl_destroy(tm)
     ta = O.precompute_template_approximation(t, 16)
