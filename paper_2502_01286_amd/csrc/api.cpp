@@ -1374,7 +1374,8 @@ int sncc_score(sncc_ctx *ctx, const sncc_tmpl *tm, int index, const uint32_t *d_
   a.rho = d_rho;
   a.rho_pitch = rho_pitch;
   a.degen = d_degenerate;
-  // the map sink uses no counters but the queues'
+  // the map sink uses no counters but the queues' (none with one workgroup
+  // per item)
   if ((a.nq != 0 && launch_zero(a.queue, a.n_zero, ctx->stream) != 0) ||
       launch_tile(pd->h.cfg, kSinkMap, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0)
     SNCC_FAIL(SNCC_EDEVICE, "tile launch: %s", hipGetErrorString(hipGetLastError()));
@@ -1485,7 +1486,8 @@ int sncc_topk(sncc_ctx *ctx, const sncc_tmpl *tm, const uint32_t *d_s, const uin
     }, &pd));
     TileArgs a = pd->args(d_s, d_s2, fs, sat_pitch, M, N);
     ctx->n_stages = 0;
-    if (launch_zero(a.queue, a.n_zero, ctx->stream) != 0)
+    // one workgroup per item: no queue counters and no pair floors to reset
+    if (a.nq != 0 && launch_zero(a.queue, a.n_zero, ctx->stream) != 0)
       SNCC_FAIL(SNCC_EDEVICE, "top-k launch: %s", hipGetErrorString(hipGetLastError()));
     ctx->mark(0);
     if (launch_tile(pd->h.cfg, kSinkTopk, a, pd->h.grid, pd->h.lds_bytes, ctx->stream) != 0)

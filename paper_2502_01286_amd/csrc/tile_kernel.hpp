@@ -457,9 +457,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
       // a key below the k-th key of another item of the same pair cannot be
       // in the pair's top k; items publish theirs when they finish.  Every
       // wave's threshold word starts from that floor (no wave reads these
-      // words any more: the previous item's merge passed a barrier)
+      // words any more: the previous item's merge passed a barrier).  With
+      // one workgroup per item (nq == 0) the items run at once and the floors
+      // are neither read nor published, so they need no reset
       uint32_t fl = 0;
-      if (SINK == kSinkTopk && got >= 0)
+      if (SINK == kSinkTopk && got >= 0 && nq != 0)
         fl = (uint32_t)(__hip_atomic_load(pair_floor + items[got].pair, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT) >> 32);
       for (int w = 0; w < NW; ++w) thr_sh[w] = fl;
@@ -515,7 +517,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
         }
         if (lane < k) partial[(long long)item * k + lane] = lkey;
         const u64 kth = lane_u64(lkey, k - 1);
-        if (lane == 0 && kth != 0) atomicMax(pair_floor + it.pair, kth);
+        if (lane == 0 && kth != 0 && nq != 0) atomicMax(pair_floor + it.pair, kth);
       }
     }
   }
