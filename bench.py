@@ -520,9 +520,17 @@ def _oracle_map(ex, n_proc, f, ta):
 
 
 def _events_ms(torch, fn, reps):
+    """Mean time per call of back-to-back calls between two events: at least
+    `reps` calls, more for short calls (about 2 ms in all, at most 200), so
+    that a call of a few microseconds is timed in steady state."""
     fn()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fn()
+    e1.record()
+    torch.cuda.synchronize()
+    reps = max(reps, min(200, int(2.0 / max(e0.elapsed_time(e1), 1e-3))))
     e0.record()
     for _ in range(reps):
         fn()
