@@ -93,6 +93,18 @@ def test_pair_indices_checked_against_frames():
     with pytest.raises(ValueError, match="template index"):
         _check_pairs(np.array([[0, 3]], np.int32), 2, 3)
     _check_pairs(np.array([[1, 2]], np.int32), 2, 3)
+    # a few pairs and many pairs take different code paths; a bad index in
+    # the last row, negative or past the end, is found by both
+    for n in (3, 8, 9, 100):
+        ok = np.zeros((n, 2), np.int32)
+        _check_pairs(ok, 1, 1)
+        for col, bad, what in ((0, -1, "frame"), (0, 1, "frame"), (1, -1, "template"),
+                               (1, 1, "template")):
+            p = ok.copy()
+            p[-1, col] = bad
+            with pytest.raises(ValueError, match=f"{what} index"):
+                _check_pairs(p, 1, 1)
+    _check_pairs(np.zeros((0, 2), np.int32), 1, 1)
 
 
 def test_tmpl_count_rejects_null():
