@@ -198,6 +198,13 @@ static void check_plan(const sncc_tmpl &tm, const PlanHost &ph, int n_pairs, int
   CHECK(!ph.qbeg.empty() && ph.qbeg.front() == 0 && ph.qbeg.back() == (int)ph.order.size(),
         "queue offsets");
   for (size_t q = 1; q < ph.qbeg.size(); ++q) CHECK(ph.qbeg[q] >= ph.qbeg[q - 1], "queues");
+  // launch grid: at most one workgroup per item; with exactly one per item
+  // the kernel takes no queue and workgroup b runs order[b]
+  CHECK(ph.grid >= 1 && (ph.items.empty() || ph.grid <= (int)ph.items.size()),
+        "grid %d for %zu items", ph.grid, ph.items.size());
+  if (ph.grid == (int)ph.items.size())
+    CHECK(ph.order.size() == ph.items.size(), "one item per workgroup: order holds %zu of %zu",
+          ph.order.size(), ph.items.size());
   // LDS reads of the staged records
   const int scale_words = 64 * tc.nw * tc.ru * tc.rv;
   for (int t = 0; t < tm.T; ++t) {
