@@ -63,6 +63,14 @@ namespace {
 // SNCC_TEST_FAIL_ALLOC set to a positive byte count in the environment, every
 // device allocation of at least that many bytes fails as if the device were
 // out of memory (read at each allocation, so a test can set and clear it).
+// With SNCC_TEST_QUEUES=1 in the environment, scoring launches that would run
+// one workgroup per item use the work queues instead (read at each launch), so
+// that a test can compare the two forms on the same call.
+bool queues_forced() {
+  const char *v = std::getenv("SNCC_TEST_QUEUES");
+  return v && v[0] == '1';
+}
+
 bool alloc_fails_by_request(size_t n) {
   const char *v = std::getenv("SNCC_TEST_FAIL_ALLOC");
   if (!v || !*v) return false;
@@ -853,7 +861,7 @@ struct PlanDev {
     a.order = d_order.as<int>();
     a.qbeg = d_qbeg.as<int>();
     // one workgroup per item: no queues (the kernel takes order[blockIdx])
-    a.nq = h.grid == (int)h.items.size() ? 0 : (int)h.qbeg.size() - 1;
+    a.nq = h.grid == (int)h.items.size() && !queues_forced() ? 0 : (int)h.qbeg.size() - 1;
     a.n_items = (int)h.items.size();
     a.queue = d_queue.as<int>();
     a.k = h.k;

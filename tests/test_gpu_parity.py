@@ -361,6 +361,40 @@ def test_topk_repeated_calls_match_fresh_contexts(S, ctx):
         S.sncc_tmpl_destroy(h)
 
 
+def test_one_item_per_workgroup_matches_the_queues(S, ctx, monkeypatch):
+    """Small launches run one workgroup per item without queue counters or
+    pair floors; the same calls through the work queues (forced by the
+    library's SNCC_TEST_QUEUES hook) must give the same maps bit for bit and
+    the same top-k lists."""
+    import torch
+    frames, temps, sigmas, pairs = _multi(91)
+    B, N, M = len(frames), frames[0].shape[0], frames[0].shape[1]
+    _, s, s2 = build_sats(S, ctx, frames)
+    tm = lib_templates(S, ctx, temps, sigmas)
+    W, H, _, _ = S.sncc_tmpl_info(tm, 2)
+
+    def run():
+        out = {}
+        for k in (1, 5, 32):
+            o = torch.zeros((len(pairs), k, 3), dtype=torch.int32, device="cuda")
+            S.sncc_topk(ctx, tm, s, s2, B, M, N, pairs, k, S.SNCC_FP32_KAHAN, o)
+            out[k] = o
+        rho = torch.zeros((N - H + 1, M - W + 1), dtype=torch.float32, device="cuda")
+        S.sncc_score(ctx, tm, 2, s[1], s2[1], M, N, S.SNCC_FP32_KAHAN, rho)
+        S.sncc_sync(ctx)
+        return {k: v.cpu().numpy() for k, v in out.items()}, rho.cpu().numpy()
+
+    monkeypatch.delenv("SNCC_TEST_QUEUES", raising=False)
+    lists, rho = run()
+    monkeypatch.setenv("SNCC_TEST_QUEUES", "1")
+    lists_q, rho_q = run()
+    monkeypatch.delenv("SNCC_TEST_QUEUES")
+    assert np.array_equal(rho.view(np.uint32), rho_q.view(np.uint32))
+    for k in lists:
+        assert np.array_equal(lists[k], lists_q[k]), k
+    S.sncc_tmpl_destroy(tm)
+
+
 def test_map_repeated_calls_match_fresh_contexts(S, ctx):
     """A context keeps the plan of its last FP32 map call; calls that change
     the template index, the template set or the tables must give exactly what
